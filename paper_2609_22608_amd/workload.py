@@ -1,0 +1,384 @@
+"""Seeded synthetic workloads for the edge-timing path.
+
+This module only draws random numbers and arranges them into the arrays that
+both the GPU library and the FP64 checker consume.  It holds none of the
+method's arithmetic (no cubic, no dynamics, no limit ratios, no distances):
+every array it returns is an *input*.  All floating-point values are rounded
+to FP32 once, here, so that both consumers read identical bits (doubles that
+are exactly FP32-representable, except the DH twist angles, which are exact
+multiples of pi/2 handled as such by both sides).
+
+One exception is documented: goal candidates are placed by an inverse
+construction (pick a goal configuration, place the object's flight through a
+point of the blade edge), which needs the blade pose.  That pose comes from a
+small forward-kinematics routine private to this module
+(``_synth_fk``).  It only positions inputs; neither the kernels nor the
+checker call it, and no expected value depends on it.
+
+Workload recipes follow the paper's experimental setup (Sec. V: 7-DOF arm,
+B candidates x M parents, ballistic flights, obstacles) at the sizes of the
+five benchmark shapes used by this project (see ``CONFIGS``).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Dict, Optional
+
+import numpy as np
+
+DOF = 7
+STATE = 2 * DOF  # (q, qd)
+
+# Modified-DH twist angles alpha_{i-1} for joints 1..7 (a Panda/FR3-like
+# pattern: every twist is 0 or +-pi/2).
+ALPHA_7DOF = np.array([0.0, -math.pi / 2, math.pi / 2, math.pi / 2,
+                       -math.pi / 2, math.pi / 2, math.pi / 2])
+
+KIND_FREE = 0
+KIND_GOAL = 1
+
+
+def _f32(x):
+    """Round to FP32 and return FP64 holding the same value."""
+    return np.asarray(x, dtype=np.float32).astype(np.float64)
+
+
+# ---------------------------------------------------------------------------
+# Arm
+# ---------------------------------------------------------------------------
+
+def make_arm(seed: int = 0, n_spheres: int = 40, w_max: float = 300.0,
+             armature: bool = True, friction: bool = True,
+             sphere_r=(0.04, 0.08), alpha=None) -> Dict[str, np.ndarray]:
+    """Seeded synthetic 7-DOF revolute arm (modified DH).
+
+    Joint i's frame is Rx(alpha_{i-1}) Tx(a_{i-1}) Rz(q_i) Tz(d_i).  Link
+    lengths a, d ~ U[0.05, 0.35] m, masses U[0.5, 4] kg, diagonal inertias
+    about the COM U[0.005, 0.05] kg m^2 (resampled until the triangle
+    inequality holds), joint limits +-2.8 rad, velocity limits U[2.0, 2.6]
+    rad/s and torque limits U[12, 87] N m (both sorted from proximal to
+    distal), power limit ``w_max``.  Reflected rotor inertia and the sigmoid
+    friction parameters of Eq. (5) are synthetic (the identified values the
+    paper adopts are not printed).  ``acc`` is the braking deceleration that
+    defines the position-dependent velocity taper.
+    """
+    rng = np.random.default_rng(seed)
+    n = DOF
+    alpha = ALPHA_7DOF.copy() if alpha is None else np.asarray(alpha, np.float64)
+    a = rng.uniform(0.05, 0.35, n)
+    d = rng.uniform(0.05, 0.35, n)
+    a[0] = 0.0  # first axis through the base origin
+    tool = np.array([0.0, 0.0, 0.10])
+    # segment of link i: origin of frame i+1 expressed in frame i
+    seg = np.zeros((n, 3))
+    for i in range(n - 1):
+        seg[i] = (a[i + 1], -math.sin(alpha[i + 1]) * d[i + 1],
+                  math.cos(alpha[i + 1]) * d[i + 1])
+    seg[n - 1] = tool
+    seg = np.where(np.abs(seg) < 1e-12, 0.0, seg)
+    m = rng.uniform(0.5, 4.0, n)
+    lam = rng.uniform(0.3, 0.7, n)
+    rc = lam[:, None] * seg + rng.uniform(-0.02, 0.02, (n, 3))
+    inertia = np.zeros((n, 3))
+    for i in range(n):
+        while True:
+            v = rng.uniform(0.005, 0.05, 3)
+            if v[0] + v[1] >= v[2] and v[1] + v[2] >= v[0] and v[0] + v[2] >= v[1]:
+                inertia[i] = v
+                break
+    im = np.sort(rng.uniform(0.01, 0.1, n))[::-1] if armature else np.zeros(n)
+    psi1 = rng.uniform(0.1, 0.6, n) if friction else np.zeros(n)
+    psi2 = rng.uniform(5.0, 50.0, n)
+    psi3 = rng.uniform(-0.05, 0.05, n)
+    qdmax = np.sort(rng.uniform(2.0, 2.6, n))[::-1]
+    taumax = np.sort(rng.uniform(12.0, 87.0, n))[::-1]
+    # collision spheres, split over links 1..7 in proportion to segment length
+    seglen = np.linalg.norm(seg, axis=1)
+    share = seglen / seglen.sum() * n_spheres
+    cnt = np.maximum(1, np.floor(share).astype(int))
+    while cnt.sum() < n_spheres:
+        cnt[np.argmax(share - cnt)] += 1
+    while cnt.sum() > n_spheres:
+        cnt[np.argmax(cnt)] -= 1
+    sph_link, sph = [], []
+    for i in range(n):
+        for j in range(cnt[i]):
+            c = (j + 0.5) / cnt[i] * seg[i]
+            sph_link.append(i + 1)
+            sph.append([c[0], c[1], c[2], rng.uniform(*sphere_r)])
+    arm = dict(
+        n=n,
+        alpha=alpha,
+        a=_f32(a), d=_f32(d), m=_f32(m), rc=_f32(rc), I=_f32(inertia),
+        Im=_f32(im), psi1=_f32(psi1), psi2=_f32(psi2), psi3=_f32(psi3),
+        qmin=_f32(np.full(n, -2.8)), qmax=_f32(np.full(n, 2.8)),
+        qdmax=_f32(qdmax), taumax=_f32(taumax), acc=_f32(np.full(n, 10.0)),
+        wmax=float(np.float32(w_max)), g=_f32([0.0, 0.0, -9.81]),
+        tool=_f32(tool),
+        sph_link=np.asarray(sph_link, np.int32), sph=_f32(np.asarray(sph)),
+        # blade (input synthesis only): 0.30 m edge along x7 from the tool
+        # point, cutting direction y7
+        blade_base=_f32(tool), blade_dir=_f32([1.0, 0.0, 0.0]),
+        blade_len=0.30, blade_normal=_f32([0.0, 1.0, 0.0]),
+    )
+    return arm
+
+
+def reach(arm) -> float:
+    """Sum of link segment lengths (an upper bound of the arm's reach)."""
+    tot = abs(arm["d"][0])
+    for i in range(1, arm["n"]):
+        tot += math.hypot(arm["a"][i], arm["d"][i])
+    return float(tot + np.linalg.norm(arm["tool"]))
+
+
+# ---------------------------------------------------------------------------
+# Travel-time grid
+# ---------------------------------------------------------------------------
+
+def t_grid(n_t: int, t_min: float, t_max: float) -> np.ndarray:
+    """Geometric grid of candidate travel times, endpoints included, FP32."""
+    j = np.arange(n_t, dtype=np.float64)
+    return _f32(t_min * (t_max / t_min) ** (j / (n_t - 1)))
+
+
+# ---------------------------------------------------------------------------
+# States
+# ---------------------------------------------------------------------------
+
+def uniform_states(arm, n: int, rng, qd_scale: float = 0.5) -> np.ndarray:
+    """(q, qd) uniform within the joint box, qd within qd_scale * qdmax."""
+    q = rng.uniform(arm["qmin"], arm["qmax"], (n, DOF))
+    qd = rng.uniform(-qd_scale * arm["qdmax"], qd_scale * arm["qdmax"], (n, DOF))
+    return _f32(np.concatenate([q, qd], axis=1))
+
+
+def make_tree(arm, n: int, seed: int, qd_scale: float = 0.5):
+    """Tree nodes: states uniform within the limits (qd scaled), and a
+    time-to-come t_n ~ U[0, 0.3] s.  Returns (states [n][14], t [n])."""
+    rng = np.random.default_rng([seed, 1])
+    x = uniform_states(arm, n, rng, qd_scale)
+    t = _f32(rng.uniform(0.0, 0.3, n))
+    return x, t
+
+
+def _dh(alpha, a, d, q):
+    """4x4 homogeneous transforms Rx(alpha) Tx(a) Rz(q) Tz(d), batched over q."""
+    ca, sa = math.cos(alpha), math.sin(alpha)
+    if abs(ca) < 1e-12:
+        ca = 0.0
+    if abs(sa) < 1e-12:
+        sa = 0.0
+    cq, sq = np.cos(q), np.sin(q)
+    T = np.zeros(q.shape + (4, 4))
+    T[..., 0, 0] = cq
+    T[..., 0, 1] = -sq
+    T[..., 0, 3] = a
+    T[..., 1, 0] = sq * ca
+    T[..., 1, 1] = cq * ca
+    T[..., 1, 2] = -sa
+    T[..., 1, 3] = -sa * d
+    T[..., 2, 0] = sq * sa
+    T[..., 2, 1] = cq * sa
+    T[..., 2, 2] = ca
+    T[..., 2, 3] = ca * d
+    T[..., 3, 3] = 1.0
+    return T
+
+
+def _synth_fk(arm, q):
+    """Flange pose (4x4) for configurations q [n][7]; goal synthesis only."""
+    T = np.broadcast_to(np.eye(4), q.shape[:-1] + (4, 4)).copy()
+    for i in range(arm["n"]):
+        T = T @ _dh(arm["alpha"][i], arm["a"][i], arm["d"][i], q[..., i])
+    return T
+
+
+def _blade_point(arm, q, c):
+    T = _synth_fk(arm, q)
+    local = arm["blade_base"] + (c * arm["blade_len"])[..., None] * arm["blade_dir"]
+    return np.einsum("...ij,...j->...i", T[..., :3, :3], local) + T[..., :3, 3], T
+
+
+def goal_states(arm, n: int, rng, t_arr=(0.2, 0.8), launch=(4.0, 7.0),
+                cone_deg: float = 30.0, blade_speed=(0.5, 2.0), g=9.81):
+    """Goal candidates by inverse construction.
+
+    A goal configuration q_g is drawn in the joint box; the contact point p
+    lies on the 0.30 m blade edge; the arrival time is U[t_arr]; the object's
+    velocity at arrival points into the blade within ``cone_deg`` of the
+    cutting direction and the flight is the ballistic arc of Eq. (1) through
+    p with launch speed U[launch]; the blade moves along its cutting
+    direction at U[blade_speed] m/s and qd_g = J^+ v_ee.  Samples whose qd_g
+    leaves the velocity box, whose contact point is below 5 cm or whose arc
+    has no real launch solution are redrawn.
+
+    Returns (states [n][14], T_req [n], flight dict of per-sample arrays).
+    """
+    out_x, out_t, fl = [], [], {k: [] for k in ("x0", "v0", "t_fall", "v_rel")}
+    gvec = np.array([0.0, 0.0, -g])
+    cos_cone = math.cos(math.radians(cone_deg))
+    need = n
+    while need > 0:
+        m = max(64, 2 * need)
+        q = rng.uniform(0.9 * arm["qmin"], 0.9 * arm["qmax"], (m, DOF))
+        c = rng.uniform(0.0, 1.0, m)
+        p, T = _blade_point(arm, q, c)
+        nb = np.einsum("...ij,j->...i", T[..., :3, :3], arm["blade_normal"])
+        # positional Jacobian of the contact point by central differences
+        J = np.zeros((m, 3, DOF))
+        h = 1e-6
+        for j in range(DOF):
+            dq = np.zeros(DOF)
+            dq[j] = h
+            pp, _ = _blade_point(arm, q + dq, c)
+            pm, _ = _blade_point(arm, q - dq, c)
+            J[:, :, j] = (pp - pm) / (2 * h)
+        bs = rng.uniform(*blade_speed, m)
+        v_ee = bs[:, None] * nb
+        qd = np.einsum("nij,nj->ni", np.linalg.pinv(J), v_ee)
+        # object velocity direction: cone about -n_b
+        ct = rng.uniform(cos_cone, 1.0, m)
+        st = np.sqrt(1 - ct * ct)
+        ph = rng.uniform(0, 2 * math.pi, m)
+        e1 = np.cross(nb, np.array([0.0, 0.0, 1.0]))
+        bad = np.linalg.norm(e1, axis=1) < 1e-6
+        e1[bad] = np.cross(nb[bad], np.array([1.0, 0.0, 0.0]))
+        e1 /= np.linalg.norm(e1, axis=1, keepdims=True)
+        e2 = np.cross(nb, e1)
+        dirv = -ct[:, None] * nb + st[:, None] * (np.cos(ph)[:, None] * e1 + np.sin(ph)[:, None] * e2)
+        ta = rng.uniform(*t_arr, m)
+        s = rng.uniform(*launch, m)
+        gT = gvec[None, :] * ta[:, None]
+        dg = np.einsum("ni,ni->n", dirv, gT)
+        disc = dg * dg - np.einsum("ni,ni->n", gT, gT) + s * s
+        lam = dg + np.sqrt(np.maximum(disc, 0.0))
+        xd_T = lam[:, None] * dirv
+        v0 = xd_T - gT
+        x0 = p - v0 * ta[:, None] - 0.5 * gvec[None, :] * ta[:, None] ** 2
+        # fall time: later root of x_z(t) = 0
+        aa, bb, cc = 0.5 * gvec[2], v0[:, 2], x0[:, 2]
+        dd = np.maximum(bb * bb - 4 * aa * cc, 0.0)
+        t_fall = (-bb - np.sqrt(dd)) / (2 * aa)
+        v_rel = np.linalg.norm(v_ee - xd_T, axis=1)
+        ok = ((disc > 0) & (lam > 0) & (p[:, 2] > 0.05)
+              & np.all(np.abs(qd) <= arm["qdmax"], axis=1) & (t_fall > ta))
+        idx = np.nonzero(ok)[0][:need]
+        out_x.append(np.concatenate([q[idx], qd[idx]], axis=1))
+        out_t.append(ta[idx])
+        fl["x0"].append(x0[idx])
+        fl["v0"].append(v0[idx])
+        fl["t_fall"].append(t_fall[idx])
+        fl["v_rel"].append(v_rel[idx])
+        need -= len(idx)
+    x = _f32(np.concatenate(out_x))
+    t = _f32(np.concatenate(out_t))
+    flight = {k: _f32(np.concatenate(v)) for k, v in fl.items()}
+    return x, t, flight
+
+
+def make_candidates(arm, b: int, goal_frac: float, seed: int, qd_scale: float = 0.5):
+    """Candidate batch: a fraction ``goal_frac`` of goal samples (inverse
+    construction, first), the rest uniform.  Returns a dict with ``x``
+    [b][14], ``kind`` [b] (0 free, 1 goal), ``t_req`` [b] (0 for free) and
+    per-goal flight data (x0, v0, t_fall, v_rel; zeros for free samples)."""
+    rng = np.random.default_rng([seed, 2])
+    n_goal = int(round(goal_frac * b))
+    xs = np.zeros((b, STATE))
+    kind = np.zeros(b, np.int32)
+    t_req = np.zeros(b)
+    flight = dict(x0=np.zeros((b, 3)), v0=np.zeros((b, 3)), t_fall=np.zeros(b), v_rel=np.zeros(b))
+    if n_goal:
+        xg, tg, fg = goal_states(arm, n_goal, rng)
+        xs[:n_goal] = xg
+        kind[:n_goal] = KIND_GOAL
+        t_req[:n_goal] = tg
+        for k in flight:
+            flight[k][:n_goal] = fg[k]
+    xs[n_goal:] = uniform_states(arm, b - n_goal, rng, qd_scale)
+    return dict(x=_f32(xs), kind=kind, t_req=_f32(t_req),
+                flight={k: _f32(v) for k, v in flight.items()})
+
+
+def make_obstacles(arm, n_obs: int, seed: int, r=(0.05, 0.15)) -> np.ndarray:
+    """Obstacle spheres [n_obs][4] = (centre xyz, radius): centres 0.25-0.8 of
+    the reach from the base, z >= 0, clear of the base column (links 0-1)."""
+    rng = np.random.default_rng([seed, 3])
+    R = reach(arm)
+    col_r = 0.15 + abs(arm["a"][1])
+    col_h = float(arm["d"][0]) + 0.1
+    out = []
+    while len(out) < n_obs:
+        rad = rng.uniform(*r)
+        dist = rng.uniform(0.25 * R, 0.8 * R)
+        v = rng.normal(size=3)
+        v[2] = abs(v[2])
+        v /= np.linalg.norm(v)
+        cpos = dist * v
+        if math.hypot(cpos[0], cpos[1]) < col_r + rad and cpos[2] < col_h + rad:
+            continue
+        out.append([cpos[0], cpos[1], cpos[2], rad])
+    return _f32(np.asarray(out).reshape(n_obs, 4))
+
+
+# ---------------------------------------------------------------------------
+# Benchmark shapes
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass(frozen=True)
+class Shape:
+    name: str
+    n_nodes: int
+    batch: int
+    k: int
+    n_t: int
+    t_min: float
+    t_max: float
+    samples: int
+    n_obs: int
+    goal_frac: float
+    obs_r: tuple = (0.05, 0.15)
+    w_max: float = 300.0
+
+
+CONFIGS = {
+    # plain method, tiny: 256-node tree, 64 uniform candidates, k=4,
+    # 32 durations over 0.02-1.0 s, 16 samples, no obstacles
+    "tiny": Shape("tiny", 256, 64, 4, 32, 0.02, 1.0, 16, 0, 0.0),
+    # one planning iteration: 16,384 nodes, 4,096 candidates (half goal),
+    # k=8, 64 durations x 32 samples, 5 obstacles
+    "iteration": Shape("iteration", 16384, 4096, 8, 64, 0.02, 1.0, 32, 5, 0.5),
+    # stress: 262,144 nodes, 65,536 candidates (30% goal), k=16,
+    # 128 durations over 0.01-1.2 s x 64 samples, 20 obstacles
+    "stress": Shape("stress", 262144, 65536, 16, 128, 0.01, 1.2, 64, 20, 0.3, (0.03, 0.2)),
+}
+
+
+def make_workload(shape: Shape, seed: int, arm_seed: int = 0, arm=None):
+    """Complete seeded input set for one shape."""
+    arm = make_arm(arm_seed, w_max=shape.w_max) if arm is None else arm
+    tree_x, tree_t = make_tree(arm, shape.n_nodes, seed)
+    cand = make_candidates(arm, shape.batch, shape.goal_frac, seed)
+    obs = make_obstacles(arm, shape.n_obs, seed, shape.obs_r)
+    grid = t_grid(shape.n_t, shape.t_min, shape.t_max)
+    return dict(shape=shape, arm=arm, tree_x=tree_x, tree_t=tree_t, cand=cand,
+                obs=obs, grid=grid, samples=shape.samples, k=shape.k)
+
+
+def make_problem_set(n_problems: int, seed: int, arm_seed: int = 0,
+                     nodes=(1024, 65536), batch=(256, 8192), k: int = 8,
+                     n_t: int = 64, samples: int = 32, max_obs: int = 5,
+                     goal_frac: float = 0.5):
+    """Many independent planning problems of uneven size: tree sizes and
+    batch sizes log-uniform in the given ranges, 0..max_obs obstacles."""
+    rng = np.random.default_rng([seed, 4])
+    arm = make_arm(arm_seed)
+    probs = []
+    for p in range(n_problems):
+        nn = int(round(math.exp(rng.uniform(math.log(nodes[0]), math.log(nodes[1])))))
+        bb = int(round(math.exp(rng.uniform(math.log(batch[0]), math.log(batch[1])))))
+        no = int(rng.integers(0, max_obs + 1))
+        sh = Shape(f"p{p}", nn, bb, k, n_t, 0.02, 1.0, samples, no, goal_frac)
+        probs.append(make_workload(sh, seed * 1000 + p, arm=arm))
+    return arm, probs
