@@ -1,0 +1,177 @@
+"""Benchmark: validated edges/s of the edge timing and validation step.
+
+One step = one pass of the hot path over one batch: brute-force kNN parents
+for every candidate, then minimum-time search + post-checks of every
+(candidate, parent) edge.  Inputs are generated once, copied to HBM, and
+stay resident; the timed region is bracketed by device synchronisation and
+HIP events on the stream the library launches on.
+
+Prints one JSON line (see the project's benchmark contract).
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "validated edges/s (7-DOF, 64 T x 32 samples); MLP-window vs exact speedup"
+# FLOP of one evaluation point (cubic + sin/cos + RNEA + armature + friction +
+# ratios) in the kernel's formulation; see the design notes for the count
+F_EVAL = 1295
+PEAK_FP32 = 157.3e12  # MI355X FP32 vector peak (packed), FLOP/s
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--seed", type=int, default=101)
+    p.add_argument("--modes", default="plain,screen")
+    p.add_argument("--cpu-sample", type=int, default=512, help="queries in the CPU oracle sample")
+    p.add_argument("--no-cpu", action="store_true")
+    p.add_argument("--profile", action="store_true", help="few steps, no CPU leg (under rocprofv3)")
+    return p.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+
+    from paper_2609_22608_amd import fn, workload as W
+
+    if args.profile:
+        args.steps, args.warmup, args.no_cpu = min(args.steps, 5), 1, True
+    sh = W.CONFIGS["iteration"]
+    wl = W.make_workload(sh, seed=args.seed)
+    E = sh.batch * sh.k
+    ctx = fn.Context(wl["arm"], sh.n_nodes, sh.batch, sh.k)
+    tree, ld, n = fn.tree_soa(wl["tree_x"])
+    cand = fn.dev(wl["cand"]["x"])
+    grid = fn.dev(wl["grid"])
+    obs = fn.dev(wl["obs"])
+    idx = torch.empty((sh.batch, sh.k), dtype=torch.int32, device="cuda")
+    out = dict(j=torch.empty(E, dtype=torch.int16, device="cuda"),
+               status=torch.empty(E, dtype=torch.int16, device="cuda"),
+               margin=torch.empty(E, dtype=torch.float32, device="cuda"),
+               rho=None, work=torch.empty(E, dtype=torch.int32, device="cuda"))
+    stream = torch.cuda.current_stream()
+    modes = {"plain": fn.SEARCH_PLAIN, "screen": fn.SEARCH_SCREEN}
+    forms = {}
+    for name in args.modes.split(","):
+        mode = modes[name]
+
+        def step():
+            ctx.plan_knn(tree, ld, n, cand, sh.k, out_idx=idx, want_d2=False)
+            ev[0].record(stream)
+            ctx.edge_time_batch(tree, ld, n, cand, idx, grid, sh.samples, obs, mode=mode, out=out)
+            ev[1].record(stream)
+
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        edge_ms = []
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        t0.record(stream)
+        for _ in range(args.steps):
+            step()
+            # events of the edge call of this step (read after the loop)
+            edge_ms.append((ev[0], ev[1]))
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        t1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        ms = t0.elapsed_time(t1) / args.steps
+        e_ms = float(np.mean([a.elapsed_time(b) for a, b in edge_ms]))
+        work = int(out["work"].sum().item())
+        flop = work * F_EVAL
+        forms[name] = dict(edges_per_s=E / (ms * 1e-3), ms_per_step=ms, edge_call_ms=e_ms,
+                           evaluations=work, wall_s=wall,
+                           fp32_tflops=flop / (e_ms * 1e-3) / 1e12,
+                           recheck64=int(((out["status"].cpu().numpy().astype(np.uint16)
+                                           & fn.S_RECHECK64) > 0).sum()))
+    best = min(forms, key=lambda k: forms[k]["ms_per_step"])
+    bf = forms[best]
+    res = {
+        "metric": METRIC,
+        "value": bf["edges_per_s"],
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": bf["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "one planning iteration: 16,384-node tree, 4,096 candidates "
+                               "(half goal), k=8, 64 T x 32 samples, 5 obstacles, 7-DOF arm",
+                   "search": best, "edges": E, "seed": args.seed},
+        "forms": forms,
+        "roofline": {"bound": "alu", "kernel": "edge_time_kernel",
+                     "achieved": bf["fp32_tflops"], "peak": PEAK_FP32 / 1e12,
+                     "unit": "TFLOP/s", "frac": bf["fp32_tflops"] * 1e12 / PEAK_FP32,
+                     "traffic": None,
+                     "flop_per_eval": F_EVAL, "evaluations": bf["evaluations"]},
+    }
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample)
+    print(json.dumps(res), flush=True)
+    ctx.close()
+
+
+def cpu_baseline(wl, n_queries):
+    """The FP64 oracle on the host cores: kNN + plain search of a bounded
+    sample of the same workload's candidates."""
+    import oracle as O
+
+    sh = wl["shape"]
+    rng = np.random.default_rng(0)
+    rows = np.sort(rng.choice(sh.batch, n_queries, replace=False))
+    A = O.make_oarm(wl["arm"])
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    threads = max(1, min(threads, 16))
+    chunks = np.array_split(rows, threads * 4)
+
+    def job(r):
+        idx, _ = O.plan_knn(wl["tree_x"], wl["cand"]["x"][r], sh.k)
+        x0, x1, ok = O.edges_of(wl["tree_x"], wl["cand"]["x"][r], idx)
+        O.edge_time(A, x0, x1, wl["grid"], sh.samples, wl["obs"], parent_ok=ok, scan=1)
+        return len(x0)
+
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(threads) as ex:
+        edges = sum(ex.map(job, chunks))
+    dt = time.perf_counter() - t0
+    cpu = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": edges / dt, "unit": "edges/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n_queries} of {sh.batch} candidates ({edges} edges), kNN over the full "
+                      f"{sh.n_nodes}-node tree + plain ascending search, FP64, {dt:.1f} s wall",
+            "cpu": cpu}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,237 @@
+/*
+ * fruitninja.h -- C ABI of the MI355X (gfx950) edge-timing library
+ * (libfruitninja.so).
+ *
+ * The library implements the batched inner loop of the FRUITNINJA planner
+ * ("Becoming a Fruit Ninja", Sec. IV-E and Algorithm 1): for every pair of a
+ * candidate state and one of its nearest tree nodes it builds the cubic edge
+ * of Eq. (6), searches a grid of travel times for the first one whose torque
+ * and power ratios of Eq. (7) are within limits (Def. 6, Def. 7), using the
+ * torque model of Eqs. (4)-(5), and checks the velocity taper, position
+ * limits and clearance at that time.
+ *
+ * Conventions shared by every call
+ *  - Pointers marked "device" are device memory (e.g. torch tensors'
+ *    data_ptr()); "host" pointers are read during the call only.  The caller
+ *    owns every buffer and keeps it alive until the stream has finished.
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = the default stream)
+ *    and the call returns without synchronising.  No call allocates device
+ *    memory except fn_create and fn_mlp_create.
+ *  - Arguments are checked on the host before anything is enqueued.  A
+ *    negative return code (FN_E_*) means nothing was enqueued;
+ *    fn_last_error() then returns a message (thread-local).  No exception
+ *    crosses the ABI.  Data conditions (NaN inputs, a padded parent) are not
+ *    errors: they set per-edge status bits.
+ *  - A state is 14 floats: joint positions q[7] then velocities qd[7].
+ *  - The tree is structure-of-arrays: tree[c * ld + n] is coordinate c of
+ *    node n (c = 0..13), ld >= n_nodes rounded up to a multiple of 4, ld a
+ *    multiple of 4, the base 16-byte aligned.
+ *  - Calls on one context must not overlap in time across streams (they
+ *    share the context's scratch buffers).
+ */
+#ifndef FRUITNINJA_H
+#define FRUITNINJA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FN_DOF 7
+#define FN_STATE 14
+#define FN_MAX_SPHERES 64
+#define FN_MAX_OBS 64
+#define FN_MAX_SAMPLES 64
+#define FN_MAX_NT 256
+#define FN_MAX_K 32
+
+/* return codes */
+enum {
+  FN_OK = 0,
+  FN_E_ARG = -1,         /* bad pointer or value */
+  FN_E_SHAPE = -2,       /* size out of range or beyond the context's caps */
+  FN_E_UNSUPPORTED = -3, /* arm or option this build does not handle */
+  FN_E_HIP = -4,         /* HIP runtime error (message has the HIP text) */
+  FN_E_NOMEM = -5,       /* device allocation failed (create calls only) */
+  FN_E_STATE = -6        /* wrong object state (e.g. untrained surrogate) */
+};
+
+/* per-edge status bits.  An edge is valid (Alg. 1: ok_p) iff its T index
+ * is >= 0 and none of NONE, VEL, POS, COLL, BAD_INPUT, NO_PARENT is set. */
+enum {
+  FN_S_NONE = 1,        /* no grid slot with rho_tau <= 1 and rho_P <= 1 (Def. 7) */
+  FN_S_VEL = 2,         /* velocity taper violated at the searched T (Def. 6 rho_v) */
+  FN_S_POS = 4,         /* joint position limit crossed along the edge */
+  FN_S_COLL = 8,        /* arm sphere closer than the margin to an obstacle */
+  FN_S_RECHECK64 = 16,  /* informational: a ratio within 1e-3 of 1 was decided in FP64 */
+  FN_S_WIN_HIT = 32,    /* informational: windowed search certified inside its window */
+  FN_S_WIN_MISS = 64,   /* informational: window missed; the exact scan finished it */
+  FN_S_BAD_INPUT = 128, /* a non-finite state or duration */
+  FN_S_NO_PARENT = 512  /* padded parent index (-1): no edge */
+};
+#define FN_S_DECISION (FN_S_NONE | FN_S_VEL | FN_S_POS | FN_S_COLL | FN_S_BAD_INPUT | FN_S_NO_PARENT)
+
+/* dynamics terms of Eq. (4) */
+enum { FN_T_RIGID = 1, FN_T_ARMATURE = 2, FN_T_FRICTION = 4, FN_T_GRAVITY = 8, FN_T_ALL = 15 };
+
+/* search modes of edge_time_batch */
+enum {
+  FN_SEARCH_PLAIN = 0,  /* ascending scan, every sample of every slot, stop at the first feasible */
+  FN_SEARCH_SCREEN = 1, /* endpoint samples of all slots first; full slots only where they pass */
+  FN_SEARCH_WINDOW = 2  /* learned window: endpoint certificate below it, window, exact fallback */
+};
+
+/* Arm description (host, FP64).  Modified DH: joint i's frame is
+ * Rx(alpha[i]) Tx(a[i]) Rz(q_i) Tz(d[i]) relative to frame i-1; every alpha
+ * must be 0 or +-pi/2 (within 1e-9).  Link i's mass m, COM rc (frame i) and
+ * diagonal inertia about the COM (frame i); reflected rotor inertia Im and
+ * the friction parameters psi1..3 of Eq. (5); joint limits, velocity limit
+ * qdmax with braking deceleration acc (velocity taper
+ * min(qdmax, sqrt(2 acc dist)), dist = distance to the limit the motion
+ * heads for), torque limits, power limit wmax (Def. 1); gravity g (base
+ * frame); collision spheres: link index 1..7, centre in that link's frame
+ * and radius (Sec. IV-E). */
+typedef struct {
+  int32_t n; /* must be 7 */
+  int32_t terms; /* FN_T_* bits, normally FN_T_ALL */
+  double alpha[7], a[7], d[7];
+  double m[7], rc[7][3], inertia[7][3];
+  double Im[7], psi1[7], psi2[7], psi3[7];
+  double qmin[7], qmax[7], qdmax[7], taumax[7], acc[7];
+  double wmax;
+  double g[3];
+  int32_t n_spheres;
+  int32_t sphere_link[FN_MAX_SPHERES];
+  double sphere[FN_MAX_SPHERES][4];
+} fn_arm_desc;
+
+/* Capacities fixed at creation; every scratch buffer is sized from them. */
+typedef struct {
+  int32_t max_nodes;   /* largest tree */
+  int32_t max_batch;   /* largest candidate batch B */
+  int32_t max_k;       /* largest k (<= FN_MAX_K) */
+  int64_t max_edges;   /* largest number of edges per edge_time_batch / edge_check call */
+} fn_caps;
+
+typedef struct fn_ctx fn_ctx;
+
+/* Creates a context on the current HIP device: copies the arm, derives its
+ * FP32 and FP64 constant blocks on the device, and allocates scratch for the
+ * caps.  Returns FN_OK and *out, or FN_E_ARG / FN_E_UNSUPPORTED (n != 7, a
+ * twist that is not 0 or +-pi/2, more than FN_MAX_SPHERES spheres) /
+ * FN_E_NOMEM / FN_E_HIP. */
+int fn_create(const fn_arm_desc* arm /*host*/, const fn_caps* caps /*host*/, fn_ctx** out);
+/* Frees the context (synchronises the device first). NULL is a no-op. */
+void fn_destroy(fn_ctx* ctx);
+/* Message of the last nonzero return on this thread ("" if none). */
+const char* fn_last_error(void);
+/* Library version string. */
+const char* fn_version(void);
+
+/* ------------------------------------------------------------------ */
+/* plan_knn -- Parents(T, x, M) of Alg. 1 (Sec. IV-E, "brute-force     */
+/* parallel scan"): the k nearest tree nodes of every query by plain   */
+/* Euclidean distance in the 14-D state space.                         */
+/* ------------------------------------------------------------------ */
+/* tree: device SoA (see conventions), n_nodes >= 0 nodes;
+ * queries: device [B][14] float; out_idx: device [B][k] int32, sorted by
+ * (d^2, node index); out_d2: device [B][k] float or NULL.  Ranking is exact:
+ * an FP32 scan selects candidates and every candidate near the k-th
+ * distance is re-ranked with d^2 = sum_{c=0..13} (x_c - y_c)^2 in FP64,
+ * summed in order c = 0..13 with separately rounded products and sums;
+ * out_d2 is that FP64 value rounded to float.  With fewer than k nodes the
+ * tail is padded with -1 (d^2 = +inf).  Returns FN_E_SHAPE if B > max_batch,
+ * k > max_k, k < 1 or n_nodes > max_nodes. */
+int plan_knn(fn_ctx* ctx, const float* tree, int64_t ld, int32_t n_nodes, const float* queries,
+             int32_t B, int32_t k, int32_t* out_idx, float* out_d2, void* stream);
+
+/* Search grid (Sec. IV-D after Def. 7 / Alg. 1 free-candidate branch):
+ * grid: device [n_t] float, strictly increasing, > 0; samples S: the
+ * evaluation times are t_s = T * s / (S-1), s = 0..S-1 (2 <= S <= 64). */
+typedef struct {
+  const float* grid; /* device */
+  int32_t n_t;
+  int32_t samples;
+  int32_t mode;      /* FN_SEARCH_* */
+  int32_t win_half;  /* window mode: slots win_lo .. win_lo + 2*win_half */
+  const int16_t* j_max;  /* device [E] or NULL: search slots 0..j_max only (t_best bound) */
+  const int16_t* win_lo; /* device [E], window mode only: lowest slot of the window,
+                            n_t = "predicted infeasible" */
+} fn_search;
+
+/* Obstacle spheres (world frame): device [n][4] = (x, y, z, radius). */
+typedef struct {
+  const float* spheres; /* device, may be NULL when n == 0 */
+  int32_t n;            /* 0 .. FN_MAX_OBS */
+  float margin;         /* clearance margin, metres (>= 0) */
+} fn_obstacles;
+
+/* Per-edge outputs (device, length E each).  rho4 (nullable): (rho_tauP at
+ * the result slot (at the last slot when none), rho_v, rho_q, rho_c) where
+ * rho_c = max (r_a + r_o + margin)/distance.  margin: the smallest
+ * |rho - 1| over the ratios the decision rests on.  work (nullable): number
+ * of (slot, sample) evaluations of Eq. (4) performed for the edge. */
+typedef struct {
+  int16_t* j;          /* T index (first feasible slot) or -1 */
+  uint16_t* status;    /* FN_S_* bits */
+  float* margin;
+  float* rho4;         /* [E][4] or NULL */
+  int32_t* work;       /* or NULL */
+} fn_edge_out;
+
+/* ------------------------------------------------------------------ */
+/* edge_time_batch -- the minimum feasible time of every (candidate,   */
+/* parent) edge on the grid (Def. 7, Alg. 1 free branch), then the     */
+/* velocity taper (Def. 6 rho_v, exact extremum), position limits and  */
+/* clearance (Sec. IV-E) at that time.                                 */
+/* ------------------------------------------------------------------ */
+/* Edge e = b * k + i goes from tree node nbr[b][i] (x0) to candidate b (x1).
+ * cand: device [B][14]; nbr: device [B][k] int32 (-1 = padding).  Every
+ * mode returns the first slot j with rho_tau(T_j) <= 1 and rho_P(T_j) <= 1
+ * among 0..j_max; the modes differ only in the work done.  Ratios are
+ * evaluated in FP32; any ratio within 1e-3 of 1 is re-evaluated in FP64
+ * before it decides.  Returns FN_E_SHAPE for B*k > max_edges, n_t out of
+ * 1..FN_MAX_NT, S out of 2..FN_MAX_SAMPLES, too many obstacles; FN_E_ARG for
+ * NULL required pointers or window mode without win_lo. */
+int edge_time_batch(fn_ctx* ctx, const float* tree, int64_t ld, int32_t n_nodes,
+                    const float* cand, int32_t B, const int32_t* nbr, int32_t k,
+                    const fn_search* search, const fn_obstacles* obs, const fn_edge_out* out,
+                    void* stream);
+
+/* ------------------------------------------------------------------ */
+/* edge_check -- one fixed duration per edge: the goal-candidate branch */
+/* of Alg. 1 (T = T_req - t_p) and the full-resolution recheck of a    */
+/* sent plan (Sec. IV-E).                                              */
+/* ------------------------------------------------------------------ */
+/* x0, x1: device [E][14]; T: device [E]; S samples as above.  out_status:
+ * device [E] (NONE when rho_tau or rho_P > 1 or T <= 0, VEL, POS, COLL,
+ * BAD_INPUT); out_rho5: device [E][5] = (rho_tau, rho_P, rho_v, rho_q,
+ * rho_c); out_tau: device [E][S][7] torques of Eq. (4) at the samples, or
+ * NULL.  FP32 arithmetic (no FP64 recheck here). */
+int edge_check(fn_ctx* ctx, const float* x0, const float* x1, const float* T, int64_t E,
+               int32_t S, const fn_obstacles* obs, uint16_t* out_status, float* out_rho5,
+               float* out_tau, void* stream);
+
+/* ------------------------------------------------------------------ */
+/* risk_score -- the objective J of Eq. (2) with the terms of Eq. (3)   */
+/* (Sec. IV-B) for n rendezvous nodes; evaluated in FP64.              */
+/* ------------------------------------------------------------------ */
+typedef struct {
+  double gz;          /* vertical gravity of Eq. (1) (negative) */
+  int32_t sigma_mode; /* 0: sigma^2 = sp^2 + (sv t)^2 + (sa t^2 / 2)^2;  1: sigma = s0 + s1 t */
+  double sp, sv, sa, s0, s1;
+  double wv, vtarget, wp, wr, wx, r, nu0, lam; /* weights and constants of Eqs. (2)-(3) */
+} fn_risk;
+
+/* T: arrival times; v_rel: relative blade-object speed; nu: peak velocity
+ * fraction; vz0: vertical launch speed of the flight; t_fall: time the
+ * flight leaves reach (all device [n] float).  out_J: device [n] float. */
+int risk_score(fn_ctx* ctx, const fn_risk* w /*host*/, const float* T, const float* v_rel,
+               const float* nu, const float* vz0, const float* t_fall, int32_t n, float* out_J,
+               void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FRUITNINJA_H */

@@ -1,0 +1,51 @@
+// fn_ctx.h -- host-side context shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fn_internal.h"
+
+namespace fn {
+
+// kNN: most node chunks one query tile is split into
+constexpr int KNN_MAX_SPLIT = 64;
+
+struct Digits {
+  int v[NJ];
+};
+
+// An edge whose decision hit a ratio within BAND of 1: the FP64 stage
+// resumes it at slot j (phase 0) or redoes its post-checks (phase 1).
+struct QEntry {
+  int32_t edge;
+  int16_t j;
+  int16_t phase;
+  float margin;
+  int32_t work;
+};
+
+int fail(int code, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* where);
+
+__global__ void zero_i32_kernel(int32_t* p, int n);
+
+// entries of the kNN partial-list scratch for these caps
+size_t knn_scratch_entries(int max_batch, int max_k);
+// list length a kNN launch uses for k
+inline int knn_k1(int k) { return k <= 16 ? k + 1 : 33; }
+
+}  // namespace fn
+
+struct fn_ctx {
+  int device;
+  int pattern;  // twist pattern code or PAT_GENERIC
+  fn_caps caps;
+  fn_arm_desc desc;  // host copy, spheres sorted by link
+  fn::ArmConst<float>* arm32;
+  fn::ArmConst<double>* arm64;
+  float* knn_d;
+  int32_t* knn_i;
+  int32_t* q_count;  // [0]: queue length
+  fn::QEntry* queue;
+};

@@ -1,0 +1,570 @@
+// fn_edge.hip -- minimum feasible time of every edge on the T grid (Def. 7,
+// Algorithm 1 free-candidate branch), the post-checks at that time (Def. 6
+// rho_v, position limits, clearance of Sec. IV-E), and the fixed-duration
+// check of the goal branch.
+//
+// One wavefront per edge.  The 64 lanes are mapped over (slot, sample)
+// pairs: a pass evaluates G = 64 / Sw slots at once (Sw = S rounded up to a
+// power of two), every lane one point of Eq. (4) along the cubic of Eq. (6).
+// A slot's ratio is the max over its lane group (xor shuffles); slots are
+// decided in ascending order, so the first feasible slot of the grid is the
+// result whatever order the work is done in.
+//
+// Search modes (same result, different work):
+//  PLAIN  -- ascending passes over full slots, stop at the first feasible.
+//  SCREEN -- first the two endpoint samples (u = 0, 1) of every slot, 32
+//            slots per pass; a slot whose endpoint ratio exceeds 1 + BAND is
+//            infeasible for certain and never evaluated in full.  Then full
+//            passes over the remaining slots in ascending order.
+//  WINDOW -- the surrogate's window [lo, lo + 2h]: slots below it are
+//            screened (the certificate), the window is evaluated in full, the
+//            slots above it are screened only if the window holds no
+//            feasible slot.  "Hit" = nothing below the window needed a full
+//            evaluation and the result lies in the window.
+//
+// Every FP32 ratio within BAND of 1 that a decision rests on sends the edge
+// to the FP64 stage (edge_recheck), which resumes it from that slot.
+#include <hip/hip_runtime.h>
+
+#include "fn_ctx.h"
+
+namespace fn {
+
+struct EdgeArgs {
+  const float* __restrict__ tree;
+  int64_t ld;
+  int n_nodes;
+  const float* __restrict__ cand;
+  const int32_t* __restrict__ nbr;
+  int k;
+  int64_t E;
+  const float* __restrict__ grid;
+  int n_t, S, Sw, mode, win_half;
+  const int16_t* __restrict__ j_max;
+  const int16_t* __restrict__ win_lo;
+  const float* __restrict__ obs;
+  int n_obs;
+  float margin_c;
+  int16_t* out_j;
+  uint16_t* out_st;
+  float* out_m;
+  float* out_rho;
+  int32_t* out_work;
+  int32_t* q_count;
+  QEntry* queue;
+};
+
+// queue phase bits
+constexpr int PH_POST = 1;        // only the post-checks are left
+constexpr int PH_BELOW_FULL = 2;  // window mode: a slot below the window was evaluated in full
+
+template <typename R>
+__device__ __forceinline__ bool load_edge(const EdgeArgs& a, int64_t e, EdgeState<R>& S,
+                                          int& status) {
+  const int64_t b = e / a.k;
+  const int p = a.nbr[e];
+  status = 0;
+  if (p < 0) {
+    status = FN_S_NO_PARENT;
+    return false;
+  }
+  if (p >= a.n_nodes) {
+    status = FN_S_BAD_INPUT;
+    return false;
+  }
+  bool finite = true;
+#pragma unroll
+  for (int i = 0; i < NJ; ++i) {
+    const float q0 = a.tree[(size_t)i * a.ld + p];
+    const float v0 = a.tree[(size_t)(NJ + i) * a.ld + p];
+    const float q1 = a.cand[b * FN_STATE + i];
+    const float v1 = a.cand[b * FN_STATE + NJ + i];
+    finite = finite && isfinite(q0) && isfinite(v0) && isfinite(q1) && isfinite(v1);
+    S.q0[i] = R(q0);
+    S.qd0[i] = R(v0);
+    S.dq[i] = R(q1) - R(q0);
+    S.d2[i] = R(v1) - R(v0);
+  }
+  if (!finite) status = FN_S_BAD_INPUT;
+  return finite;
+}
+
+__device__ __forceinline__ float lane_u(int lane, int Sw, int S) {
+  const int s = lane & (Sw - 1);
+  return s < S ? float(s) / float(S - 1) : 0.f;
+}
+
+// Post-checks at duration T (Def. 6 rho_v; position limits; clearance):
+// returns (rho_v, rho_q, rho_c) in every lane.
+template <typename R, int PAT>
+__device__ void post_checks(const ArmConst<R>& A, const EdgeState<R>& E, R T, int S,
+                            const float* __restrict__ obs, int n_obs, float margin_c, R& rv,
+                            R& rq, R& rc) {
+  const int lane = lane_id();
+  R v = 0, q = 0;
+  if (lane < NJ) joint_post(A, E, lane, T, v, q);
+  // clearance: one sample per lane
+  R best = 0;
+  if (n_obs > 0 && lane < S) {
+    const R u = R(lane) / R(S - 1);
+    R sg[NJ], sd[NJ], sdd[NJ], sn[NJ], cs[NJ];
+    cubic_point(E, T, R(1) / T, u, sg, sd, sdd);
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) sincos_r(sg[i], sn[i], cs[i]);
+    sphere_centres<R, PAT>(A, sn, cs, [&](int k, R x, R y, R z) {
+      for (int o = 0; o < n_obs; ++o) {
+        const R dx = x - R(obs[4 * o]), dy = y - R(obs[4 * o + 1]), dz = z - R(obs[4 * o + 2]);
+        const R need = A.sphr[k] + R(obs[4 * o + 3]) + R(margin_c);
+        const R d2 = dx * dx + dy * dy + dz * dz;
+        const R r2 = d2 > R(0) ? need * need / d2 : R(INFINITY);
+        best = rmax(best, r2);
+      }
+    });
+  }
+  if constexpr (sizeof(R) == 4) {
+    rv = wave_max(float(v));
+    rq = wave_max(float(q));
+    rc = sqrtf(wave_max(float(best)));
+  } else {
+    rv = wave_max(double(v));
+    rq = wave_max(double(q));
+    rc = sqrt(wave_max(double(best)));
+  }
+}
+
+__device__ __forceinline__ bool near_one(float r) { return fabsf(r - 1.f) <= BAND; }
+
+// Final status bits from the post-check ratios.
+template <typename R>
+__device__ __forceinline__ int post_status(R rv, R rq, R rc) {
+  int st = 0;
+  if (rv > R(1)) st |= FN_S_VEL;
+  if (rq > R(1)) st |= FN_S_POS;
+  if (rc > R(1)) st |= FN_S_COLL;
+  return st;
+}
+
+__device__ __forceinline__ void write_out(const EdgeArgs& a, int64_t e, int j, int st, float m,
+                                          float r0, float r1, float r2, float r3, int work) {
+  if (lane_id() == 0) {
+    a.out_j[e] = (int16_t)j;
+    a.out_st[e] = (uint16_t)st;
+    a.out_m[e] = m;
+    if (a.out_rho) {
+      a.out_rho[4 * e + 0] = r0;
+      a.out_rho[4 * e + 1] = r1;
+      a.out_rho[4 * e + 2] = r2;
+      a.out_rho[4 * e + 3] = r3;
+    }
+    if (a.out_work) a.out_work[e] = work;
+  }
+}
+
+__device__ __forceinline__ void push_queue(const EdgeArgs& a, int64_t e, int j, int phase,
+                                           float m, int work) {
+  if (lane_id() == 0) {
+    const int slot = atomicAdd(a.q_count, 1);
+    QEntry q;
+    q.edge = (int32_t)e;
+    q.j = (int16_t)j;
+    q.phase = (int16_t)phase;
+    q.margin = m;
+    q.work = work;
+    a.queue[slot] = q;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP32 search kernel
+// ---------------------------------------------------------------------------
+template <int PAT>
+__global__ __launch_bounds__(256) void edge_time_kernel(EdgeArgs a,
+                                                        const ArmConst<float>* __restrict__ Ap) {
+  __shared__ float s_end_all[4][FN_MAX_NT];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t e = (int64_t)blockIdx.x * 4 + wave;
+  if (e >= a.E) return;
+  const ArmConst<float>& A = *Ap;
+  const int lane = lane_id();
+  float* s_end = s_end_all[wave];
+
+  EdgeState<float> ES;
+  int st0;
+  if (!load_edge(a, e, ES, st0)) {
+    write_out(a, e, -1, st0, st0 == FN_S_NO_PARENT ? INFINITY : 0.f, 0, 0, 0, 0, 0);
+    return;
+  }
+  int jmax = a.n_t - 1;
+  if (a.j_max) jmax = min(jmax, (int)a.j_max[e]);
+  if (jmax < 0) {
+    write_out(a, e, -1, FN_S_NONE, INFINITY, 0, 0, 0, 0, 0);
+    return;
+  }
+  const int S = a.S, Sw = a.Sw, G = WAVE / Sw;
+  const int g = lane / Sw;
+  const float u = lane_u(lane, Sw, S);
+  const bool s_ok = (lane & (Sw - 1)) < S;
+
+  for (int j = lane; j < a.n_t; j += WAVE) s_end[j] = -1.f;  // -1: not screened
+  __builtin_amdgcn_wave_barrier();
+
+  int work = 0;
+  float marg = INFINITY;  // over fully evaluated slots up to the result
+  float last = 0.f;
+  int jstar = -1;
+  float rho_star = 0.f;
+  bool below_full = false;
+
+  // endpoint screen of slots [lo, hi]: 32 slots per pass, lane = (slot, end)
+  auto screen = [&](int lo, int hi) {
+    for (int j0 = lo; j0 <= hi; j0 += WAVE / 2) {
+      const int j = j0 + (lane >> 1);
+      const bool act = j <= hi;
+      float r = 0.f;
+      if (act) {
+        const float T = a.grid[j];
+        r = eval_rho<float, PAT>(A, ES, T, 1.f / T, (lane & 1) ? 1.f : 0.f);
+      }
+      r = fmaxf(r, __shfl_xor(r, 1));
+      if (act && (lane & 1) == 0) s_end[j] = r;
+      work += __popcll(__ballot(act));
+    }
+    __builtin_amdgcn_wave_barrier();
+  };
+  // certified-infeasible margin of screened slots below `lim`
+  auto cert_margin = [&](int lim) {
+    float m = INFINITY;
+    for (int j = lane; j < lim; j += WAVE) {
+      const float r = s_end[j];
+      if (r > 1.f + BAND) m = fminf(m, r - 1.f);
+    }
+    return wave_min(m);
+  };
+  // ascending full evaluation of [lo, hi]; screened slots that are certified
+  // are skipped.  Returns 0: not found, 1: found, 2: sent to the FP64 stage.
+  auto scan = [&](int lo, int hi, bool track_below) -> int {
+    int j = lo;
+    while (j <= hi) {
+      // next G slots that are not certified infeasible; lane group g takes
+      // the g-th of them
+      int my = -1, cnt = 0;
+      while (cnt < G && j <= hi) {
+        if (s_end[j] > 1.f + BAND) {
+          ++j;
+          continue;
+        }
+        if (cnt == g) my = j;
+        ++cnt;
+        ++j;
+      }
+      if (cnt == 0) break;
+      if (track_below) below_full = true;
+      float r = 0.f;
+      const bool act = my >= 0 && s_ok;
+      if (act) {
+        const float T = a.grid[my];
+        r = eval_rho<float, PAT>(A, ES, T, 1.f / T, u);
+      }
+      work += __popcll(__ballot(act));
+      r = group_max(r, Sw);
+      for (int q = 0; q < cnt; ++q) {
+        const float rho = __shfl(r, q * Sw);
+        const int jq = __shfl(my, q * Sw);
+        if (near_one(rho)) {
+          const float m = fminf(marg, cert_margin(jq));
+          push_queue(a, e, jq, below_full ? PH_BELOW_FULL : 0, m, work);
+          return 2;
+        }
+        marg = fminf(marg, fabsf(rho - 1.f));
+        last = rho;
+        if (rho <= 1.f) {
+          jstar = jq;
+          rho_star = rho;
+          return 1;
+        }
+      }
+    }
+    return 0;
+  };
+
+  int res = 0;
+  int wlo = 0, whi = -1;
+  if (a.mode == FN_SEARCH_PLAIN) {
+    res = scan(0, jmax, false);
+  } else if (a.mode == FN_SEARCH_SCREEN) {
+    screen(0, jmax);
+    res = scan(0, jmax, false);
+  } else {
+    wlo = min(max((int)a.win_lo[e], 0), jmax + 1);
+    whi = min(wlo + 2 * a.win_half, jmax);
+    if (wlo > 0) {
+      screen(0, wlo - 1);
+      res = scan(0, wlo - 1, true);
+    }
+    if (res == 0 && wlo <= jmax) res = scan(wlo, whi, false);
+    if (res == 0 && whi < jmax) {
+      screen(whi + 1, jmax);
+      res = scan(whi + 1, jmax, false);
+    }
+  }
+  if (res == 2) return;
+  int winbits = 0;
+  if (a.mode == FN_SEARCH_WINDOW) {
+    const bool hit = !below_full && ((jstar >= wlo && jstar <= whi) || (jstar < 0 && wlo > jmax));
+    winbits = hit ? FN_S_WIN_HIT : FN_S_WIN_MISS;
+  }
+  if (jstar < 0) {
+    const float m = fminf(marg, cert_margin(jmax + 1));
+    // ratio of the last slot: its full value, else its screened endpoint value
+    const float lastv = s_end[jmax] > 1.f + BAND ? s_end[jmax] : last;
+    write_out(a, e, -1, FN_S_NONE | winbits, m, lastv, 0, 0, 0, work);
+    return;
+  }
+  float rv, rq, rc;
+  const float T = a.grid[jstar];
+  post_checks<float, PAT>(A, ES, T, S, a.obs, a.n_obs, a.margin_c, rv, rq, rc);
+  float m = fminf(marg, cert_margin(jstar));
+  if (near_one(rv) || near_one(rq) || (a.n_obs > 0 && near_one(rc))) {
+    push_queue(a, e, jstar, PH_POST | (below_full ? PH_BELOW_FULL : 0), m, work);
+    return;
+  }
+  m = fminf(m, fminf(fabsf(rv - 1.f), fminf(fabsf(rq - 1.f), fabsf(rc - 1.f))));
+  write_out(a, e, jstar, post_status(rv, rq, rc) | winbits, m, rho_star, rv, rq, rc, work);
+}
+
+// ---------------------------------------------------------------------------
+// FP64 stage: every queued edge resumes at its slot with full slots in
+// ascending order; a slot whose FP32 ratio is within BAND of 1 is decided by
+// its FP64 ratio; post-checks are done in FP64.
+// ---------------------------------------------------------------------------
+template <int PAT>
+__global__ __launch_bounds__(64) void edge_recheck_kernel(EdgeArgs a,
+                                                          const ArmConst<float>* __restrict__ Ap,
+                                                          const ArmConst<double>* __restrict__ Dp) {
+  const int n = *a.q_count;
+  const ArmConst<float>& A = *Ap;
+  const ArmConst<double>& D = *Dp;
+  const int lane = lane_id();
+  for (int qi = blockIdx.x; qi < n; qi += gridDim.x) {
+    const QEntry q = a.queue[qi];
+    const int64_t e = q.edge;
+    EdgeState<float> ES;
+    EdgeState<double> ED;
+    int st0;
+    load_edge(a, e, ES, st0);
+    load_edge(a, e, ED, st0);
+    int jmax = a.n_t - 1;
+    if (a.j_max) jmax = min(jmax, (int)a.j_max[e]);
+    const int S = a.S;
+    int work = q.work;
+    float marg = q.margin;
+    int jstar = -1;
+    double rho_star = 0;
+    float last = 0;
+    if (q.phase & PH_POST) {
+      jstar = q.j;
+      const double T = a.grid[jstar];
+      rho_star = 0;
+      // the slot ratio itself is reported from FP32 (it was outside the band)
+      const float Tf = a.grid[jstar];
+      float r = 0.f;
+      if (lane < S) r = eval_rho<float, PAT>(A, ES, Tf, 1.f / Tf, float(lane) / float(S - 1));
+      rho_star = wave_max(r);
+      (void)T;
+    } else {
+      for (int j = q.j; j <= jmax; ++j) {
+        const float Tf = a.grid[j];
+        float r = 0.f;
+        if (lane < S) r = eval_rho<float, PAT>(A, ES, Tf, 1.f / Tf, float(lane) / float(S - 1));
+        float rho = wave_max(r);
+        work += S;
+        double rho_d = rho;
+        if (near_one(rho)) {
+          const double T = (double)Tf;
+          double rd = 0.0;
+          if (lane < S) rd = eval_rho<double, PAT>(D, ED, T, 1.0 / T, double(lane) / double(S - 1));
+          rho_d = wave_max(rd);
+        }
+        marg = fminf(marg, (float)fabs(rho_d - 1.0));
+        last = (float)rho_d;
+        if (rho_d <= 1.0) {
+          jstar = j;
+          rho_star = rho_d;
+          break;
+        }
+      }
+    }
+    int winbits = 0;
+    if (a.mode == FN_SEARCH_WINDOW) {
+      const int wlo = min(max((int)a.win_lo[e], 0), jmax + 1);
+      const int whi = min(wlo + 2 * a.win_half, jmax);
+      const bool below = (q.phase & PH_BELOW_FULL) != 0;
+      const bool hit = !below && ((jstar >= wlo && jstar <= whi) || (jstar < 0 && wlo > jmax));
+      winbits = hit ? FN_S_WIN_HIT : FN_S_WIN_MISS;
+    }
+    if (jstar < 0) {
+      write_out(a, e, -1, FN_S_NONE | FN_S_RECHECK64 | winbits, marg, last, 0, 0, 0, work);
+      continue;
+    }
+    double rv, rq, rc;
+    post_checks<double, PAT>(D, ED, (double)a.grid[jstar], S, a.obs, a.n_obs, a.margin_c, rv, rq,
+                             rc);
+    const float m = fminf(marg, (float)fmin(fabs(rv - 1.0), fmin(fabs(rq - 1.0), fabs(rc - 1.0))));
+    write_out(a, e, jstar, post_status(rv, rq, rc) | FN_S_RECHECK64 | winbits, m, (float)rho_star,
+              (float)rv, (float)rq, (float)rc, work);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fixed-duration check (goal branch of Algorithm 1; recheck of a sent plan)
+// ---------------------------------------------------------------------------
+template <int PAT>
+__global__ __launch_bounds__(256) void edge_check_kernel(const float* __restrict__ x0,
+                                                         const float* __restrict__ x1,
+                                                         const float* __restrict__ Tv, int64_t E,
+                                                         int S, const float* __restrict__ obs,
+                                                         int n_obs, float margin_c,
+                                                         const ArmConst<float>* __restrict__ Ap,
+                                                         uint16_t* out_st, float* out_rho,
+                                                         float* out_tau) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t e = (int64_t)blockIdx.x * 4 + wave;
+  if (e >= E) return;
+  const ArmConst<float>& A = *Ap;
+  const int lane = lane_id();
+  EdgeState<float> ES;
+  bool finite = true;
+#pragma unroll
+  for (int i = 0; i < NJ; ++i) {
+    const float q0 = x0[e * FN_STATE + i], v0 = x0[e * FN_STATE + NJ + i];
+    const float q1 = x1[e * FN_STATE + i], v1 = x1[e * FN_STATE + NJ + i];
+    finite = finite && isfinite(q0) && isfinite(v0) && isfinite(q1) && isfinite(v1);
+    ES.q0[i] = q0;
+    ES.qd0[i] = v0;
+    ES.dq[i] = q1 - q0;
+    ES.d2[i] = v1 - v0;
+  }
+  const float T = Tv[e];
+  int st = 0;
+  if (!finite || !isfinite(T)) st = FN_S_BAD_INPUT;
+  else if (!(T > 0.f)) st = FN_S_NONE;
+  if (st) {
+    if (lane == 0) {
+      out_st[e] = (uint16_t)st;
+      for (int r = 0; r < 5; ++r) out_rho[5 * e + r] = 0.f;
+    }
+    if (out_tau)
+      for (int t = lane; t < S * NJ; t += WAVE) out_tau[(size_t)e * S * NJ + t] = 0.f;
+    return;
+  }
+  const float invT = 1.f / T;
+  float rt_all = 0.f, rp_all = 0.f;
+  for (int s0 = 0; s0 < S; s0 += WAVE) {
+    const int s = s0 + lane;
+    if (s < S) {
+      float tau[NJ], rt, rp;
+      eval_point<float, PAT>(A, ES, T, invT, float(s) / float(S - 1), rt, rp, tau);
+      rt_all = fmaxf(rt_all, rt);
+      rp_all = fmaxf(rp_all, rp);
+      if (out_tau)
+#pragma unroll
+        for (int i = 0; i < NJ; ++i) out_tau[((size_t)e * S + s) * NJ + i] = tau[i];
+    }
+  }
+  const float rt = wave_max(rt_all), rp = wave_max(rp_all);
+  float rv, rq, rc;
+  post_checks<float, PAT>(A, ES, T, S, obs, n_obs, margin_c, rv, rq, rc);
+  if (lane == 0) {
+    int s2 = post_status(rv, rq, rc);
+    if (rt > 1.f || rp > 1.f) s2 |= FN_S_NONE;
+    out_st[e] = (uint16_t)s2;
+    out_rho[5 * e + 0] = rt;
+    out_rho[5 * e + 1] = rp;
+    out_rho[5 * e + 2] = rv;
+    out_rho[5 * e + 3] = rq;
+    out_rho[5 * e + 4] = rc;
+  }
+}
+
+static int pow2_at_least(int s) {
+  int w = 1;
+  while (w < s) w <<= 1;
+  return w;
+}
+
+int check_obstacles(const fn_obstacles* obs, const char* who) {
+  if (!obs) return FN_OK;
+  if (obs->n < 0 || obs->n > FN_MAX_OBS) return fail(FN_E_SHAPE, "%s: %d obstacles (max %d)", who, obs->n, FN_MAX_OBS);
+  if (obs->n > 0 && !obs->spheres) return fail(FN_E_ARG, "%s: NULL obstacle array", who);
+  if (!(obs->margin >= 0.f)) return fail(FN_E_ARG, "%s: clearance margin must be >= 0", who);
+  return FN_OK;
+}
+
+}  // namespace fn
+
+using namespace fn;
+
+extern "C" int edge_time_batch(fn_ctx* c, const float* tree, int64_t ld, int32_t n_nodes,
+                               const float* cand, int32_t B, const int32_t* nbr, int32_t k,
+                               const fn_search* sr, const fn_obstacles* obs,
+                               const fn_edge_out* out, void* stream) {
+  if (!c || !sr || !out) return fail(FN_E_ARG, "edge_time_batch: NULL context, search or out");
+  if (B < 0 || k < 1 || k > FN_MAX_K) return fail(FN_E_SHAPE, "edge_time_batch: B = %d, k = %d", B, k);
+  const int64_t E = (int64_t)B * k;
+  if (E > c->caps.max_edges) return fail(FN_E_SHAPE, "edge_time_batch: %lld edges (cap %lld)", (long long)E, (long long)c->caps.max_edges);
+  if (n_nodes < 0) return fail(FN_E_SHAPE, "edge_time_batch: n_nodes = %d", n_nodes);
+  if (sr->n_t < 1 || sr->n_t > FN_MAX_NT) return fail(FN_E_SHAPE, "edge_time_batch: n_t = %d (1..%d)", sr->n_t, FN_MAX_NT);
+  if (sr->samples < 2 || sr->samples > FN_MAX_SAMPLES) return fail(FN_E_SHAPE, "edge_time_batch: S = %d (2..%d)", sr->samples, FN_MAX_SAMPLES);
+  if (sr->mode < FN_SEARCH_PLAIN || sr->mode > FN_SEARCH_WINDOW) return fail(FN_E_ARG, "edge_time_batch: mode %d", sr->mode);
+  if (sr->mode == FN_SEARCH_WINDOW && (!sr->win_lo || sr->win_half < 0)) return fail(FN_E_ARG, "edge_time_batch: window mode needs win_lo and win_half >= 0");
+  int rc = check_obstacles(obs, "edge_time_batch");
+  if (rc) return rc;
+  if (E == 0) return FN_OK;
+  if (!cand || !nbr || !sr->grid || !out->j || !out->status || !out->margin || (n_nodes > 0 && !tree))
+    return fail(FN_E_ARG, "edge_time_batch: NULL array");
+  if (ld < n_nodes) return fail(FN_E_ARG, "edge_time_batch: ld < n_nodes");
+  EdgeArgs a;
+  a.tree = tree; a.ld = ld; a.n_nodes = n_nodes; a.cand = cand; a.nbr = nbr; a.k = k; a.E = E;
+  a.grid = sr->grid; a.n_t = sr->n_t; a.S = sr->samples; a.Sw = pow2_at_least(sr->samples);
+  a.mode = sr->mode; a.win_half = sr->win_half; a.j_max = sr->j_max; a.win_lo = sr->win_lo;
+  a.obs = obs ? obs->spheres : nullptr; a.n_obs = obs ? obs->n : 0; a.margin_c = obs ? obs->margin : 0.f;
+  a.out_j = out->j; a.out_st = out->status; a.out_m = out->margin; a.out_rho = out->rho4;
+  a.out_work = out->work; a.q_count = c->q_count; a.queue = c->queue;
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, s, c->q_count, 1);
+  const dim3 grid((unsigned)((E + 3) / 4));
+  if (c->pattern == PAT_FR3) {
+    hipLaunchKernelGGL(edge_time_kernel<PAT_FR3>, grid, dim3(256), 0, s, a, c->arm32);
+    hipLaunchKernelGGL(edge_recheck_kernel<PAT_FR3>, dim3(256), dim3(64), 0, s, a, c->arm32, c->arm64);
+  } else {
+    hipLaunchKernelGGL(edge_time_kernel<PAT_GENERIC>, grid, dim3(256), 0, s, a, c->arm32);
+    hipLaunchKernelGGL(edge_recheck_kernel<PAT_GENERIC>, dim3(256), dim3(64), 0, s, a, c->arm32, c->arm64);
+  }
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? FN_OK : hip_fail(e, "edge_time_batch launch");
+}
+
+extern "C" int edge_check(fn_ctx* c, const float* x0, const float* x1, const float* T, int64_t E,
+                          int32_t S, const fn_obstacles* obs, uint16_t* out_status,
+                          float* out_rho5, float* out_tau, void* stream) {
+  if (!c) return fail(FN_E_ARG, "edge_check: NULL context");
+  if (E < 0 || E > c->caps.max_edges) return fail(FN_E_SHAPE, "edge_check: E = %lld (cap %lld)", (long long)E, (long long)c->caps.max_edges);
+  if (S < 2 || S > 4096) return fail(FN_E_SHAPE, "edge_check: S = %d (2..4096)", S);
+  int rc = check_obstacles(obs, "edge_check");
+  if (rc) return rc;
+  if (S > FN_MAX_SAMPLES && obs && obs->n > 0)
+    return fail(FN_E_SHAPE, "edge_check: clearance needs S <= %d", FN_MAX_SAMPLES);
+  if (E == 0) return FN_OK;
+  if (!x0 || !x1 || !T || !out_status || !out_rho5) return fail(FN_E_ARG, "edge_check: NULL array");
+  hipStream_t s = (hipStream_t)stream;
+  const dim3 grid((unsigned)((E + 3) / 4));
+  const float* ob = obs ? obs->spheres : nullptr;
+  const int no = obs ? obs->n : 0;
+  const float mg = obs ? obs->margin : 0.f;
+  if (c->pattern == PAT_FR3)
+    hipLaunchKernelGGL(edge_check_kernel<PAT_FR3>, grid, dim3(256), 0, s, x0, x1, T, E, S, ob, no, mg, c->arm32, out_status, out_rho5, out_tau);
+  else
+    hipLaunchKernelGGL(edge_check_kernel<PAT_GENERIC>, grid, dim3(256), 0, s, x0, x1, T, E, S, ob, no, mg, c->arm32, out_status, out_rho5, out_tau);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? FN_OK : hip_fail(e, "edge_check launch");
+}

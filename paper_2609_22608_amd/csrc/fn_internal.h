@@ -1,0 +1,396 @@
+// fn_internal.h -- device-side building blocks of the edge-timing library:
+// the per-context arm constant block, the cubic edge of Eq. (6), the torque
+// model of Eqs. (4)-(5) as recursive Newton-Euler in link frames, and the
+// ratios of Eq. (7).  Everything is templated on the arithmetic type so that
+// the FP32 bulk path and the FP64 near-limit recheck share one formulation.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/fruitninja.h"
+
+namespace fn {
+
+constexpr int NJ = 7;
+constexpr int WAVE = 64;
+// A ratio within BAND of 1 is not decided in FP32.
+constexpr float BAND = 1e-3f;
+
+// Twist pattern of a modified-DH arm as 7 base-4 digits: 0: alpha = 0,
+// 1: +pi/2, 2: -pi/2.  PAT_GENERIC selects runtime cos/sin of alpha.
+constexpr int PAT_GENERIC = -1;
+constexpr int pat_digit(int pat, int i) {
+  int p = pat;
+  for (int k = 0; k < i; ++k) p /= 4;
+  return p % 4;
+}
+// 0, -pi/2, +pi/2, +pi/2, -pi/2, +pi/2, +pi/2 (Panda/FR3-like chain)
+constexpr int PAT_FR3 = 0 + 2 * 4 + 1 * 16 + 1 * 64 + 2 * 256 + 1 * 1024 + 1 * 4096;
+
+template <typename R>
+struct ArmConst {
+  int32_t terms;
+  int32_t pattern;        // twist pattern code (or -1 when some twist is general)
+  R ca[NJ], sa[NJ];       // cos / sin of alpha_{i-1}
+  R px[NJ], py[NJ], pz[NJ];  // origin of frame i in frame i-1
+  R m[NJ];
+  R rcx[NJ], rcy[NJ], rcz[NJ];
+  R Ix[NJ], Iy[NJ], Iz[NJ];
+  R Im[NJ];
+  R psi1[NJ], psi2[NJ], psi3[NJ];
+  R fk2[NJ];              // -psi2 * log2(e)
+  R f0[NJ];               // psi1 / (1 + exp(-psi2 psi3)): friction at rest, subtracted
+  R inv_taumax[NJ];
+  R inv_wmax;
+  R qmin[NJ], qmax[NJ], qcen[NJ], inv_qhalf[NJ], qdmax[NJ], two_acc[NJ];
+  R vd0[3];               // base acceleration: -g when gravity is on
+  int32_t nsph;
+  int32_t sph_link[FN_MAX_SPHERES];
+  R sphx[FN_MAX_SPHERES], sphy[FN_MAX_SPHERES], sphz[FN_MAX_SPHERES], sphr[FN_MAX_SPHERES];
+};
+
+// ---------------------------------------------------------------------------
+// scalar helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void sincos_r(float x, float& s, float& c) {
+  // v_sin_f32 / v_cos_f32 take revolutions
+  const float r = x * 0.15915494309189535f;
+  s = __builtin_amdgcn_sinf(r);
+  c = __builtin_amdgcn_cosf(r);
+}
+__device__ __forceinline__ void sincos_r(double x, double& s, double& c) {
+  s = sin(x);
+  c = cos(x);
+}
+__device__ __forceinline__ float logistic_neg(float k2x) {
+  // 1 / (1 + 2^(k2x)) with k2x = -psi2 (qd + psi3) log2(e)
+  return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(k2x));
+}
+__device__ __forceinline__ double logistic_neg(double k2x) {
+  return 1.0 / (1.0 + exp2(k2x));
+}
+template <typename R>
+__device__ __forceinline__ R rabs(R x) { return x < R(0) ? -x : x; }
+template <typename R>
+__device__ __forceinline__ R rmax(R a, R b) { return a > b ? a : b; }
+
+// ---------------------------------------------------------------------------
+// Rotation by ^{i-1}R_i = Rx(alpha) Rz(theta) and its transpose, with the
+// twist folded in at compile time when it is 0 or +-pi/2.
+// ---------------------------------------------------------------------------
+template <typename R, int PAT, int I>
+__device__ __forceinline__ void rotT(const ArmConst<R>& A, R c, R s, R vx, R vy, R vz, R& ox,
+                                     R& oy, R& oz) {
+  // u = Rx(alpha)^T v
+  R ux = vx, uy, uz;
+  if constexpr (PAT != PAT_GENERIC && pat_digit(PAT, I) == 0) {
+    uy = vy; uz = vz;
+  } else if constexpr (PAT != PAT_GENERIC && pat_digit(PAT, I) == 1) {
+    uy = vz; uz = -vy;
+  } else if constexpr (PAT != PAT_GENERIC && pat_digit(PAT, I) == 2) {
+    uy = -vz; uz = vy;
+  } else {
+    const R ca = A.ca[I], sa = A.sa[I];
+    uy = ca * vy + sa * vz;
+    uz = ca * vz - sa * vy;
+  }
+  // o = Rz(theta)^T u
+  ox = c * ux + s * uy;
+  oy = c * uy - s * ux;
+  oz = uz;
+}
+template <typename R, int PAT, int I>
+__device__ __forceinline__ void rot(const ArmConst<R>& A, R c, R s, R vx, R vy, R vz, R& ox,
+                                    R& oy, R& oz) {
+  // u = Rz(theta) v ; o = Rx(alpha) u
+  const R ux = c * vx - s * vy;
+  const R uy = s * vx + c * vy;
+  const R uz = vz;
+  ox = ux;
+  if constexpr (PAT != PAT_GENERIC && pat_digit(PAT, I) == 0) {
+    oy = uy; oz = uz;
+  } else if constexpr (PAT != PAT_GENERIC && pat_digit(PAT, I) == 1) {
+    oy = -uz; oz = uy;
+  } else if constexpr (PAT != PAT_GENERIC && pat_digit(PAT, I) == 2) {
+    oy = uz; oz = -uy;
+  } else {
+    const R ca = A.ca[I], sa = A.sa[I];
+    oy = ca * uy - sa * uz;
+    oz = sa * uy + ca * uz;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Eq. (4): rigid-body inverse dynamics by recursive Newton-Euler in link
+// frames (outward: angular velocity/acceleration and linear acceleration of
+// every frame, Newton-Euler force/moment of every link about its COM;
+// inward: force and moment transmitted at every joint), plus armature and
+// the sigmoid friction of Eq. (5).  sn/cs: sin/cos of q.
+// ---------------------------------------------------------------------------
+template <typename R, int PAT>
+__device__ __forceinline__ void rnea(const ArmConst<R>& A, const R* sn, const R* cs,
+                                     const R* qd, const R* qdd, R* tau) {
+  const bool rigid = (A.terms & FN_T_RIGID) != 0;
+  R Fx[NJ], Fy[NJ], Fz[NJ], Nx[NJ], Ny[NJ], Nz[NJ];
+  R wx = 0, wy = 0, wz = 0, ax = 0, ay = 0, az = 0;  // w_{i-1}, wd_{i-1}
+  R vx = A.vd0[0], vy = A.vd0[1], vz = A.vd0[2];      // vd_{i-1}
+#pragma unroll
+  for (int i = 0; i < NJ; ++i) {
+    const R c = cs[i], s = sn[i];
+    const R px = A.px[i], py = A.py[i], pz = A.pz[i];
+    // t = wd x p + w x (w x p) + vd   (frame i-1)
+    const R wpx = wy * pz - wz * py, wpy = wz * px - wx * pz, wpz = wx * py - wy * px;
+    const R tx = (ay * pz - az * py) + (wy * wpz - wz * wpy) + vx;
+    const R ty = (az * px - ax * pz) + (wz * wpx - wx * wpz) + vy;
+    const R tz = (ax * py - ay * px) + (wx * wpy - wy * wpx) + vz;
+    R nvx, nvy, nvz, rwx, rwy, rwz, rax, ray, raz;
+    switch (i) {  // compile-time link index after unrolling
+#define FN_ROT3(II)                                              \
+  case II:                                                       \
+    rotT<R, PAT, II>(A, c, s, tx, ty, tz, nvx, nvy, nvz);        \
+    rotT<R, PAT, II>(A, c, s, wx, wy, wz, rwx, rwy, rwz);        \
+    rotT<R, PAT, II>(A, c, s, ax, ay, az, rax, ray, raz);        \
+    break;
+      FN_ROT3(0) FN_ROT3(1) FN_ROT3(2) FN_ROT3(3) FN_ROT3(4) FN_ROT3(5) FN_ROT3(6)
+#undef FN_ROT3
+    }
+    const R q1 = qd[i];
+    wx = rwx; wy = rwy; wz = rwz + q1;
+    ax = rax + rwy * q1; ay = ray - rwx * q1; az = raz + qdd[i];
+    vx = nvx; vy = nvy; vz = nvz;
+    // COM acceleration and the link's Newton-Euler wrench
+    const R rx = A.rcx[i], ry = A.rcy[i], rz = A.rcz[i];
+    const R wrx = wy * rz - wz * ry, wry = wz * rx - wx * rz, wrz = wx * ry - wy * rx;
+    const R cx = (ay * rz - az * ry) + (wy * wrz - wz * wry) + vx;
+    const R cy = (az * rx - ax * rz) + (wz * wrx - wx * wrz) + vy;
+    const R cz = (ax * ry - ay * rx) + (wx * wry - wy * wrx) + vz;
+    const R mm = A.m[i];
+    Fx[i] = mm * cx; Fy[i] = mm * cy; Fz[i] = mm * cz;
+    const R Iwx = A.Ix[i] * wx, Iwy = A.Iy[i] * wy, Iwz = A.Iz[i] * wz;
+    Nx[i] = A.Ix[i] * ax + (wy * Iwz - wz * Iwy);
+    Ny[i] = A.Iy[i] * ay + (wz * Iwx - wx * Iwz);
+    Nz[i] = A.Iz[i] * az + (wx * Iwy - wy * Iwx);
+  }
+  R fx = 0, fy = 0, fz = 0, nx = 0, ny = 0, nz = 0;  // f_{i+1}, n_{i+1} in frame i+1
+#pragma unroll
+  for (int i = NJ - 1; i >= 0; --i) {
+    R Rfx = 0, Rfy = 0, Rfz = 0, Rnx = 0, Rny = 0, Rnz = 0;
+    if (i + 1 < NJ) {
+      const R c = cs[i + 1], s = sn[i + 1];
+      switch (i + 1) {
+#define FN_ROT2(II)                                              \
+  case II:                                                       \
+    rot<R, PAT, II>(A, c, s, fx, fy, fz, Rfx, Rfy, Rfz);         \
+    rot<R, PAT, II>(A, c, s, nx, ny, nz, Rnx, Rny, Rnz);         \
+    break;
+        FN_ROT2(1) FN_ROT2(2) FN_ROT2(3) FN_ROT2(4) FN_ROT2(5) FN_ROT2(6)
+#undef FN_ROT2
+      }
+      // + p_{i+1} x (R f_{i+1})
+      const R px = A.px[i + 1], py = A.py[i + 1], pz = A.pz[i + 1];
+      Rnx += py * Rfz - pz * Rfy;
+      Rny += pz * Rfx - px * Rfz;
+      Rnz += px * Rfy - py * Rfx;
+    }
+    const R rx = A.rcx[i], ry = A.rcy[i], rz = A.rcz[i];
+    fx = Rfx + Fx[i]; fy = Rfy + Fy[i]; fz = Rfz + Fz[i];
+    nx = Nx[i] + Rnx + (ry * Fz[i] - rz * Fy[i]);
+    ny = Ny[i] + Rny + (rz * Fx[i] - rx * Fz[i]);
+    nz = Nz[i] + Rnz + (rx * Fy[i] - ry * Fx[i]);
+    tau[i] = rigid ? nz : R(0);
+  }
+  const bool arm = (A.terms & FN_T_ARMATURE) != 0;
+  const bool fric = (A.terms & FN_T_FRICTION) != 0;
+#pragma unroll
+  for (int i = 0; i < NJ; ++i) {
+    if (arm) tau[i] += A.Im[i] * qdd[i];
+    if (fric) tau[i] += A.psi1[i] * logistic_neg(A.fk2[i] * (qd[i] + A.psi3[i])) - A.f0[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Eq. (6) in the normalised time u = t / T:
+//   sigma = q0 + u (qd0 T + u (A2 + u A3)),  A2 = 3 d1 - d2 T,  A3 = d2 T - 2 d1,
+//   d1 = q1 - q0 - qd0 T,  d2 = qd1 - qd0.
+// ---------------------------------------------------------------------------
+template <typename R>
+struct EdgeState {
+  R q0[NJ], qd0[NJ], dq[NJ], d2[NJ];  // dq = q1 - q0
+};
+
+template <typename R>
+__device__ __forceinline__ void cubic_point(const EdgeState<R>& E, R T, R invT, R u, R* sg,
+                                            R* sd, R* sdd) {
+  const R invT2 = invT * invT;
+#pragma unroll
+  for (int i = 0; i < NJ; ++i) {
+    const R v0T = E.qd0[i] * T;
+    const R d1 = E.dq[i] - v0T;
+    const R A2 = R(3) * d1 - E.d2[i] * T;
+    const R A3 = E.d2[i] * T - R(2) * d1;
+    sg[i] = E.q0[i] + u * (v0T + u * (A2 + u * A3));
+    sd[i] = E.qd0[i] + u * (R(2) * A2 + R(3) * A3 * u) * invT;
+    sdd[i] = (R(2) * A2 + R(6) * A3 * u) * invT2;
+  }
+}
+
+// One evaluation point of Def. 6: torque ratio max_i |tau_i| / taumax_i and
+// power ratio |sum_i tau_i sd_i| / W_max at normalised time u of duration T.
+template <typename R, int PAT>
+__device__ __forceinline__ void eval_point(const ArmConst<R>& A, const EdgeState<R>& E, R T,
+                                           R invT, R u, R& rt, R& rp, R* tau_out) {
+  R sg[NJ], sd[NJ], sdd[NJ], sn[NJ], cs[NJ], tau[NJ];
+  cubic_point(E, T, invT, u, sg, sd, sdd);
+#pragma unroll
+  for (int i = 0; i < NJ; ++i) sincos_r(sg[i], sn[i], cs[i]);
+  rnea<R, PAT>(A, sn, cs, sd, sdd, tau);
+  R t = 0, pw = 0;
+#pragma unroll
+  for (int i = 0; i < NJ; ++i) {
+    t = rmax(t, rabs(tau[i]) * A.inv_taumax[i]);
+    pw += tau[i] * sd[i];
+    if (tau_out) tau_out[i] = tau[i];
+  }
+  rt = t;
+  rp = rabs(pw) * A.inv_wmax;
+}
+template <typename R, int PAT>
+__device__ __forceinline__ R eval_rho(const ArmConst<R>& A, const EdgeState<R>& E, R T, R invT,
+                                      R u) {
+  R rt, rp;
+  eval_point<R, PAT>(A, E, T, invT, u, rt, rp, nullptr);
+  return rmax(rt, rp);
+}
+
+// Velocity taper of Def. 1 (braking law) and the ratio |v| / taper.
+template <typename R>
+__device__ __forceinline__ R vel_ratio(const ArmConst<R>& A, int i, R q, R v) {
+  if (v == R(0)) return R(0);
+  const R dist = v >= R(0) ? (A.qmax[i] - q) : (q - A.qmin[i]);
+  R lim = sqrt(A.two_acc[i] * rmax(R(0), dist));
+  lim = lim < A.qdmax[i] ? lim : A.qdmax[i];
+  if (!(lim > R(0))) return R(INFINITY);
+  return rabs(v) / lim;
+}
+
+// rho_v and rho_q of joint i at duration T (exact extrema of the cubic).
+template <typename R>
+__device__ __forceinline__ void joint_post(const ArmConst<R>& A, const EdgeState<R>& E, int i, R T,
+                                           R& rv, R& rq) {
+  const R invT = R(1) / T;
+  const R c0 = E.q0[i], c1 = E.qd0[i];
+  const R d1 = E.dq[i] - c1 * T;
+  const R c2 = (R(3) * d1 * invT - E.d2[i]) * invT;
+  const R c3 = (E.d2[i] - R(2) * d1 * invT) * invT * invT;
+  auto pos = [&](R t) { return c0 + t * (c1 + t * (c2 + t * c3)); };
+  auto vel = [&](R t) { return c1 + t * (R(2) * c2 + R(3) * c3 * t); };
+  // velocity peaks: t = 0, t = T, vertex of the quadratic velocity
+  rv = rmax(vel_ratio(A, i, pos(R(0)), vel(R(0))), vel_ratio(A, i, pos(T), vel(T)));
+  if (c3 != R(0)) {
+    const R tv = -c2 / (R(3) * c3);
+    if (tv > R(0) && tv < T) rv = rmax(rv, vel_ratio(A, i, pos(tv), vel(tv)));
+  }
+  // position extrema: endpoints and real roots of the velocity in (0, T)
+  auto pr = [&](R t) { return rabs(pos(t) - A.qcen[i]) * A.inv_qhalf[i]; };
+  rq = rmax(pr(R(0)), pr(T));
+  const R qa = R(3) * c3, qb = R(2) * c2, qc = c1;
+  if (qa == R(0)) {
+    if (qb != R(0)) {
+      const R t = -qc / qb;
+      if (t >= R(0) && t <= T) rq = rmax(rq, pr(t));
+    }
+  } else {
+    const R disc = qb * qb - R(4) * qa * qc;
+    if (disc >= R(0)) {
+      const R sq = sqrt(disc);
+      const R qq = R(-0.5) * (qb + (qb >= R(0) ? sq : -sq));
+      if (qq != R(0)) {
+        const R t1 = qq / qa, t2 = qc / qq;
+        if (t1 >= R(0) && t1 <= T) rq = rmax(rq, pr(t1));
+        if (t2 >= R(0) && t2 <= T) rq = rmax(rq, pr(t2));
+      }
+    }
+  }
+}
+
+// World-frame centres of the collision spheres at configuration (sn, cs),
+// streamed: fn(k, x, y, z) is called for every sphere k in order.
+template <typename R, int PAT, typename F>
+__device__ __forceinline__ void sphere_centres(const ArmConst<R>& A, const R* sn, const R* cs,
+                                               F&& fn) {
+  // columns of the world rotation of frame i and its origin
+  R r00 = 1, r01 = 0, r02 = 0, r10 = 0, r11 = 1, r12 = 0, r20 = 0, r21 = 0, r22 = 1;
+  R ox = 0, oy = 0, oz = 0;
+  int k = 0;
+#pragma unroll
+  for (int i = 0; i < NJ; ++i) {
+    // origin_i = origin_{i-1} + R_{i-1} p_i
+    const R px = A.px[i], py = A.py[i], pz = A.pz[i];
+    ox += r00 * px + r01 * py + r02 * pz;
+    oy += r10 * px + r11 * py + r12 * pz;
+    oz += r20 * px + r21 * py + r22 * pz;
+    // R_i = R_{i-1} Rx(alpha) Rz(theta): apply to the rows
+    R a0, a1, a2, b0, b1, b2, c0, c1, c2;  // rows after Rx
+    switch (i) {
+#define FN_RX(II)                                                             \
+  case II:                                                                   \
+    if constexpr (PAT != PAT_GENERIC && pat_digit(PAT, II) == 0) {            \
+      a0 = r00; a1 = r01; a2 = r02; b0 = r10; b1 = r11; b2 = r12;             \
+      c0 = r20; c1 = r21; c2 = r22;                                           \
+    } else if constexpr (PAT != PAT_GENERIC && pat_digit(PAT, II) == 1) {     \
+      a0 = r00; a1 = r02; a2 = -r01; b0 = r10; b1 = r12; b2 = -r11;           \
+      c0 = r20; c1 = r22; c2 = -r21;                                          \
+    } else if constexpr (PAT != PAT_GENERIC && pat_digit(PAT, II) == 2) {     \
+      a0 = r00; a1 = -r02; a2 = r01; b0 = r10; b1 = -r12; b2 = r11;           \
+      c0 = r20; c1 = -r22; c2 = r21;                                          \
+    } else {                                                                  \
+      const R ca = A.ca[II], sa = A.sa[II];                                   \
+      a0 = r00; a1 = r01 * ca + r02 * sa; a2 = r02 * ca - r01 * sa;           \
+      b0 = r10; b1 = r11 * ca + r12 * sa; b2 = r12 * ca - r11 * sa;           \
+      c0 = r20; c1 = r21 * ca + r22 * sa; c2 = r22 * ca - r21 * sa;           \
+    }                                                                         \
+    break;
+      FN_RX(0) FN_RX(1) FN_RX(2) FN_RX(3) FN_RX(4) FN_RX(5) FN_RX(6)
+#undef FN_RX
+    }
+    const R c = cs[i], s = sn[i];
+    r00 = a0 * c + a1 * s; r01 = a1 * c - a0 * s; r02 = a2;
+    r10 = b0 * c + b1 * s; r11 = b1 * c - b0 * s; r12 = b2;
+    r20 = c0 * c + c1 * s; r21 = c1 * c - c0 * s; r22 = c2;
+    // spheres of link i+1 (sorted by link on the host)
+    while (k < A.nsph && A.sph_link[k] == i + 1) {
+      const R lx = A.sphx[k], ly = A.sphy[k], lz = A.sphz[k];
+      fn(k, ox + r00 * lx + r01 * ly + r02 * lz, oy + r10 * lx + r11 * ly + r12 * lz,
+         oz + r20 * lx + r21 * ly + r22 * lz);
+      ++k;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// wave helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o));
+  return v;
+}
+// max over aligned groups of `width` lanes (width a power of two <= 64)
+__device__ __forceinline__ float group_max(float v, int width) {
+  for (int o = 1; o < width; o <<= 1) v = fmaxf(v, __shfl_xor(v, o));
+  return v;
+}
+
+}  // namespace fn

@@ -1,0 +1,255 @@
+"""ctypes binding of libfruitninja.so (include/fruitninja.h).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  PyTorch provides device memory and the current stream.  The
+library must have been built (``python -m paper_2609_22608_amd.build`` or
+``__graft_entry__.build()``); loading fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfruitninja.so")
+
+FN_OK, FN_E_ARG, FN_E_SHAPE, FN_E_UNSUPPORTED, FN_E_HIP, FN_E_NOMEM, FN_E_STATE = 0, -1, -2, -3, -4, -5, -6
+S_NONE, S_VEL, S_POS, S_COLL, S_RECHECK64, S_WIN_HIT, S_WIN_MISS, S_BAD_INPUT, S_NO_PARENT = \
+    1, 2, 4, 8, 16, 32, 64, 128, 512
+S_DECISION = S_NONE | S_VEL | S_POS | S_COLL | S_BAD_INPUT | S_NO_PARENT
+T_RIGID, T_ARMATURE, T_FRICTION, T_GRAVITY, T_ALL = 1, 2, 4, 8, 15
+SEARCH_PLAIN, SEARCH_SCREEN, SEARCH_WINDOW = 0, 1, 2
+MAX_SPHERES = 64
+
+
+class FnError(RuntimeError):
+    pass
+
+
+class ArmDesc(C.Structure):
+    _fields_ = [
+        ("n", C.c_int32), ("terms", C.c_int32),
+        ("alpha", C.c_double * 7), ("a", C.c_double * 7), ("d", C.c_double * 7),
+        ("m", C.c_double * 7), ("rc", (C.c_double * 3) * 7), ("inertia", (C.c_double * 3) * 7),
+        ("Im", C.c_double * 7), ("psi1", C.c_double * 7), ("psi2", C.c_double * 7),
+        ("psi3", C.c_double * 7),
+        ("qmin", C.c_double * 7), ("qmax", C.c_double * 7), ("qdmax", C.c_double * 7),
+        ("taumax", C.c_double * 7), ("acc", C.c_double * 7),
+        ("wmax", C.c_double), ("g", C.c_double * 3),
+        ("n_spheres", C.c_int32), ("sphere_link", C.c_int32 * MAX_SPHERES),
+        ("sphere", (C.c_double * 4) * MAX_SPHERES),
+    ]
+
+
+class Caps(C.Structure):
+    _fields_ = [("max_nodes", C.c_int32), ("max_batch", C.c_int32), ("max_k", C.c_int32),
+                ("max_edges", C.c_int64)]
+
+
+class Search(C.Structure):
+    _fields_ = [("grid", C.c_void_p), ("n_t", C.c_int32), ("samples", C.c_int32),
+                ("mode", C.c_int32), ("win_half", C.c_int32), ("j_max", C.c_void_p),
+                ("win_lo", C.c_void_p)]
+
+
+class Obstacles(C.Structure):
+    _fields_ = [("spheres", C.c_void_p), ("n", C.c_int32), ("margin", C.c_float)]
+
+
+class EdgeOut(C.Structure):
+    _fields_ = [("j", C.c_void_p), ("status", C.c_void_p), ("margin", C.c_void_p),
+                ("rho4", C.c_void_p), ("work", C.c_void_p)]
+
+
+class Risk(C.Structure):
+    _fields_ = [("gz", C.c_double), ("sigma_mode", C.c_int32), ("sp", C.c_double),
+                ("sv", C.c_double), ("sa", C.c_double), ("s0", C.c_double), ("s1", C.c_double),
+                ("wv", C.c_double), ("vtarget", C.c_double), ("wp", C.c_double),
+                ("wr", C.c_double), ("wx", C.c_double), ("r", C.c_double), ("nu0", C.c_double),
+                ("lam", C.c_double)]
+
+
+_lib = None
+_lock = threading.Lock()
+
+
+def lib():
+    """Loads libfruitninja.so; raises if it has not been built."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise FnError(f"{LIB_PATH} is missing: build it first "
+                              "(python -m paper_2609_22608_amd.build)")
+            L = C.CDLL(LIB_PATH)
+            vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+            L.fn_last_error.restype = C.c_char_p
+            L.fn_version.restype = C.c_char_p
+            L.fn_create.argtypes = [C.POINTER(ArmDesc), C.POINTER(Caps), C.POINTER(vp)]
+            L.fn_destroy.argtypes = [vp]
+            L.plan_knn.argtypes = [vp, vp, i64, i32, vp, i32, i32, vp, vp, vp]
+            L.edge_time_batch.argtypes = [vp, vp, i64, i32, vp, i32, vp, i32, C.POINTER(Search),
+                                          C.POINTER(Obstacles), C.POINTER(EdgeOut), vp]
+            L.edge_check.argtypes = [vp, vp, vp, vp, i64, i32, C.POINTER(Obstacles), vp, vp, vp, vp]
+            L.risk_score.argtypes = [vp, C.POINTER(Risk), vp, vp, vp, vp, vp, i32, vp, vp]
+            _lib = L
+    return _lib
+
+
+def _check(rc, what):
+    if rc != FN_OK:
+        raise FnError(f"{what} failed ({rc}): {lib().fn_last_error().decode()}")
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def arm_desc(arm, terms: int = T_ALL) -> ArmDesc:
+    """Packs a workload arm dict into the library's fn_arm_desc."""
+    d = ArmDesc()
+    d.n = int(arm["n"])
+    d.terms = terms
+    for i in range(7):
+        d.alpha[i] = float(arm["alpha"][i])
+        d.a[i] = float(arm["a"][i])
+        d.d[i] = float(arm["d"][i])
+        d.m[i] = float(arm["m"][i])
+        for r in range(3):
+            d.rc[i][r] = float(arm["rc"][i][r])
+            d.inertia[i][r] = float(arm["I"][i][r])
+        for key in ("Im", "psi1", "psi2", "psi3", "qmin", "qmax", "qdmax", "taumax", "acc"):
+            getattr(d, key)[i] = float(arm[key][i])
+    d.wmax = float(arm["wmax"])
+    for r in range(3):
+        d.g[r] = float(arm["g"][r])
+    ns = len(arm["sph_link"])
+    if ns > MAX_SPHERES:
+        raise FnError(f"{ns} spheres (max {MAX_SPHERES})")
+    d.n_spheres = ns
+    for k in range(ns):
+        d.sphere_link[k] = int(arm["sph_link"][k])
+        for r in range(4):
+            d.sphere[k][r] = float(arm["sph"][k][r])
+    return d
+
+
+def tree_soa(states, device="cuda", capacity=None):
+    """Structure-of-arrays device copy of tree states [n][14] -> [14][ld]
+    (ld a multiple of 4, padding zero).  Returns (tensor, ld, n)."""
+    x = np.asarray(states, np.float32)
+    n = x.shape[0]
+    cap = max(n, capacity or 0)
+    ld = max(4, (cap + 3) // 4 * 4)
+    soa = np.zeros((14, ld), np.float32)
+    soa[:, :n] = x.T
+    return torch.from_numpy(soa).to(device), ld, n
+
+
+def dev(x, dtype=torch.float32, device="cuda"):
+    return torch.as_tensor(np.ascontiguousarray(x)).to(device=device, dtype=dtype).contiguous()
+
+
+class Context:
+    """An fn_ctx on the current device."""
+
+    def __init__(self, arm, max_nodes, max_batch, max_k, max_edges=None, terms: int = T_ALL):
+        torch.cuda.init()
+        self._desc = arm_desc(arm, terms)
+        caps = Caps(int(max_nodes), int(max_batch), int(max_k),
+                    int(max_edges if max_edges is not None else max_batch * max_k))
+        self.caps = caps
+        h = C.c_void_p()
+        _check(lib().fn_create(C.byref(self._desc), C.byref(caps), C.byref(h)), "fn_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().fn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- plan_knn -----------------------------------------------------------
+    def plan_knn(self, tree, ld, n_nodes, queries, k, out_idx=None, out_d2=None, want_d2=True):
+        B = queries.shape[0]
+        if out_idx is None:
+            out_idx = torch.empty((B, k), dtype=torch.int32, device=queries.device)
+        if out_d2 is None and want_d2:
+            out_d2 = torch.empty((B, k), dtype=torch.float32, device=queries.device)
+        _check(lib().plan_knn(self.h, _ptr(tree), ld, n_nodes, _ptr(queries), B, k,
+                              _ptr(out_idx), _ptr(out_d2), _stream()), "plan_knn")
+        return out_idx, out_d2
+
+    # -- edge_time_batch ------------------------------------------------------
+    def edge_time_batch(self, tree, ld, n_nodes, cand, nbr, grid, samples, obs=None,
+                        margin=0.0, mode=SEARCH_PLAIN, j_max=None, win_lo=None, win_half=4,
+                        out=None, want_rho=True, want_work=True):
+        B, k = nbr.shape
+        E = B * k
+        d = cand.device
+        if out is None:
+            out = dict(j=torch.empty(E, dtype=torch.int16, device=d),
+                       status=torch.empty(E, dtype=torch.int16, device=d),
+                       margin=torch.empty(E, dtype=torch.float32, device=d),
+                       rho=torch.empty((E, 4), dtype=torch.float32, device=d) if want_rho else None,
+                       work=torch.empty(E, dtype=torch.int32, device=d) if want_work else None)
+        s = Search(C.c_void_p(grid.data_ptr()), grid.shape[0], int(samples), int(mode),
+                   int(win_half), None if j_max is None else C.c_void_p(j_max.data_ptr()),
+                   None if win_lo is None else C.c_void_p(win_lo.data_ptr()))
+        o = Obstacles(None if obs is None or obs.shape[0] == 0 else C.c_void_p(obs.data_ptr()),
+                      0 if obs is None else obs.shape[0], float(margin))
+        eo = EdgeOut(out["j"].data_ptr(), out["status"].data_ptr(), out["margin"].data_ptr(),
+                     None if out["rho"] is None else out["rho"].data_ptr(),
+                     None if out["work"] is None else out["work"].data_ptr())
+        _check(lib().edge_time_batch(self.h, _ptr(tree), ld, n_nodes, _ptr(cand), B, _ptr(nbr), k,
+                                     C.byref(s), C.byref(o), C.byref(eo), _stream()),
+               "edge_time_batch")
+        return out
+
+    # -- edge_check -----------------------------------------------------------
+    def edge_check(self, x0, x1, T, samples, obs=None, margin=0.0, want_tau=False):
+        E = x0.shape[0]
+        d = x0.device
+        st = torch.empty(E, dtype=torch.int16, device=d)
+        rho = torch.empty((E, 5), dtype=torch.float32, device=d)
+        tau = torch.empty((E, samples, 7), dtype=torch.float32, device=d) if want_tau else None
+        o = Obstacles(None if obs is None or obs.shape[0] == 0 else C.c_void_p(obs.data_ptr()),
+                      0 if obs is None else obs.shape[0], float(margin))
+        _check(lib().edge_check(self.h, _ptr(x0), _ptr(x1), _ptr(T), E, int(samples), C.byref(o),
+                                _ptr(st), _ptr(rho), _ptr(tau), _stream()), "edge_check")
+        return dict(status=st, rho=rho, tau=tau)
+
+    # -- risk_score -----------------------------------------------------------
+    def risk_score(self, w: Risk, T, v_rel, nu, vz0, t_fall, out=None):
+        n = T.shape[0]
+        if out is None:
+            out = torch.empty(n, dtype=torch.float32, device=T.device)
+        _check(lib().risk_score(self.h, C.byref(w), _ptr(T), _ptr(v_rel), _ptr(nu), _ptr(vz0),
+                                _ptr(t_fall), n, _ptr(out), _stream()), "risk_score")
+        return out
+
+
+PAPER_RISK = dict(wv=0.20, vtarget=9.0, wp=8.0, wr=8.0, wx=1.0, r=0.09, nu0=0.90, lam=1.2)
+
+
+def make_risk(gz=-9.81, sigma_mode=0, sp=0.0048, sv=0.0186, sa=0.0, s0=0.01, s1=0.05, **w):
+    r = Risk()
+    r.gz, r.sigma_mode, r.sp, r.sv, r.sa, r.s0, r.s1 = gz, sigma_mode, sp, sv, sa, s0, s1
+    ww = dict(PAPER_RISK)
+    ww.update(w)
+    for key, v in ww.items():
+        setattr(r, key, v)
+    return r

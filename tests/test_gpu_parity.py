@@ -1,0 +1,314 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle on
+the same seeded inputs.
+
+Bar: kNN indices bit-exact; T index and decision status bits bit-exact on
+every edge whose oracle margin exceeds 1e-3 (and reported for the rest);
+torques within 1e-4 relative (|dtau| <= 1e-4 max(|tau|, 1e-2 taumax)).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2609_22608_amd import workload as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2609_22608_amd import fn  # noqa: E402
+
+
+def _ctx(wl, B=None, k=None, N=None):
+    sh = wl["shape"]
+    return fn.Context(wl["arm"], N or sh.n_nodes, B or sh.batch, k or sh.k)
+
+
+def _decision(st):
+    return st.astype(np.int64) & fn.S_DECISION
+
+
+def compare_edges(gpu, ref, sel_idx=None, label=""):
+    gj = gpu["j"].cpu().numpy().astype(np.int64)
+    gs = _decision(gpu["status"].cpu().numpy().astype(np.uint16))
+    if sel_idx is not None:
+        gj, gs = gj[sel_idx], gs[sel_idx]
+    rj = ref["j"].astype(np.int64)
+    rs = ref["status"].astype(np.int64)
+    strict = ref["margin"] > 1e-3
+    bad = strict & ((gj != rj) | (gs != rs))
+    loose = (~strict) & ((gj != rj) | (gs != rs))
+    print(f"{label}: {len(rj)} edges, strict {strict.sum()}, mismatches strict {bad.sum()}, "
+          f"near-limit mismatches {loose.sum()}")
+    assert bad.sum() == 0, f"{label}: {bad.sum()} strict mismatches at {np.nonzero(bad)[0][:10]}"
+    return gj, gs
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    return W.make_workload(W.CONFIGS["tiny"], seed=1)
+
+
+@pytest.fixture(scope="module")
+def iteration():
+    return W.make_workload(W.CONFIGS["iteration"], seed=101)
+
+
+# ------------------------------------------------------------------ kNN
+
+def test_knn_tiny_exact(tiny):
+    sh = tiny["shape"]
+    ctx = _ctx(tiny)
+    tree, ld, n = fn.tree_soa(tiny["tree_x"])
+    q = fn.dev(tiny["cand"]["x"])
+    idx, d2 = ctx.plan_knn(tree, ld, n, q, sh.k)
+    ridx, rd2 = O.plan_knn(tiny["tree_x"], tiny["cand"]["x"], sh.k)
+    assert np.array_equal(idx.cpu().numpy(), ridx)
+    assert np.array_equal(d2.cpu().numpy(), rd2.astype(np.float32))
+
+
+@pytest.mark.parametrize("k", [1, 4, 8, 16, 20])
+def test_knn_iteration_exact_sampled(iteration, k):
+    """Full tree of 16,384 nodes, 4,096 queries; 256 sampled queries checked."""
+    sh = iteration["shape"]
+    ctx = _ctx(iteration, k=max(k, sh.k))
+    tree, ld, n = fn.tree_soa(iteration["tree_x"])
+    q = fn.dev(iteration["cand"]["x"])
+    idx, d2 = ctx.plan_knn(tree, ld, n, q, k)
+    rows = np.random.default_rng(k).choice(sh.batch, 256, replace=False)
+    ridx, rd2 = O.plan_knn(iteration["tree_x"], iteration["cand"]["x"][rows], k)
+    assert np.array_equal(idx.cpu().numpy()[rows], ridx)
+    assert np.array_equal(d2.cpu().numpy()[rows], rd2.astype(np.float32))
+
+
+def test_knn_ties_duplicates_and_padding():
+    rng = np.random.default_rng(3)
+    arm = W.make_arm(0)
+    nodes = W.uniform_states(arm, 301, rng)
+    nodes[17] = nodes[3]
+    nodes[250] = nodes[3]
+    nodes[41] = nodes[40]
+    nodes[100:140] = nodes[100]  # a block of 40 identical nodes (forces the exact rescan)
+    qs = W.uniform_states(arm, 70, rng)
+    qs[5] = nodes[3]
+    qs[6] = nodes[40]
+    qs[7] = nodes[100]
+    ctx = fn.Context(arm, 400, 128, 16)
+    tree, ld, n = fn.tree_soa(nodes)
+    for k in (3, 8, 16):
+        idx, d2 = ctx.plan_knn(tree, ld, n, fn.dev(qs), k)
+        ridx, rd2 = O.plan_knn(nodes, qs, k)
+        assert np.array_equal(idx.cpu().numpy(), ridx), k
+        assert np.array_equal(d2.cpu().numpy(), rd2.astype(np.float32)), k
+    # fewer nodes than k: padding
+    tree, ld, n = fn.tree_soa(nodes[:5])
+    idx, d2 = ctx.plan_knn(tree, ld, n, fn.dev(qs[:3]), 8)
+    ridx, _ = O.plan_knn(nodes[:5], qs[:3], 8)
+    assert np.array_equal(idx.cpu().numpy(), ridx)
+    assert np.isinf(d2.cpu().numpy()[:, 5:]).all()
+    # empty tree
+    tree, ld, n = fn.tree_soa(np.zeros((0, 14), np.float32))
+    idx, _ = ctx.plan_knn(tree, ld, 0, fn.dev(qs[:2]), 4)
+    assert (idx.cpu().numpy() == -1).all()
+
+
+# ------------------------------------------------------------------ edge timing
+
+def _run_edges(ctx, wl, idx, mode, **kw):
+    sh = wl["shape"]
+    tree, ld, n = fn.tree_soa(wl["tree_x"])
+    cand = fn.dev(wl["cand"]["x"])
+    grid = fn.dev(wl["grid"])
+    obs = fn.dev(wl["obs"]) if len(wl["obs"]) else None
+    out = ctx.edge_time_batch(tree, ld, n, cand, idx, grid, sh.samples, obs, mode=mode, **kw)
+    torch.cuda.synchronize()
+    return out
+
+
+@pytest.mark.parametrize("mode", [fn.SEARCH_PLAIN, fn.SEARCH_SCREEN])
+def test_edge_time_tiny_all_edges(tiny, mode):
+    sh = tiny["shape"]
+    ctx = _ctx(tiny)
+    ridx, _ = O.plan_knn(tiny["tree_x"], tiny["cand"]["x"], sh.k)
+    idx = fn.dev(ridx, torch.int32)
+    out = _run_edges(ctx, tiny, idx, mode)
+    x0, x1, ok = O.edges_of(tiny["tree_x"], tiny["cand"]["x"], ridx)
+    ref = O.edge_time(O.make_oarm(tiny["arm"]), x0, x1, tiny["grid"], sh.samples, parent_ok=ok)
+    gj, gs = compare_edges(out, ref, label=f"tiny mode {mode}")
+    rho = out["rho"].cpu().numpy()
+    f = gj >= 0
+    # ratios at the result slot within FP32 accuracy
+    assert np.allclose(rho[f, 0], ref["rho"][f, 0], rtol=1e-4)
+    assert np.allclose(rho[f, 1:3], ref["rho"][f, 1:3], rtol=1e-4)
+    if mode == fn.SEARCH_PLAIN:
+        m = out["margin"].cpu().numpy()
+        fin = np.isfinite(ref["margin"])
+        assert np.allclose(m[fin], ref["margin"][fin], rtol=2e-3, atol=2e-5)
+        # work = evaluated lanes: whole passes of 64 / S slots up to the result
+        work = out["work"].cpu().numpy()
+        st = out["status"].cpu().numpy().astype(np.uint16)
+        ok = (st & (fn.S_RECHECK64 | fn.S_NO_PARENT | fn.S_BAD_INPUT)) == 0
+        G = 64 // 16
+        assert (work[ok] >= ref["nslots"][ok] * sh.samples).all()
+        assert (work[ok] < (ref["nslots"][ok] + G) * sh.samples).all()
+
+
+@pytest.mark.parametrize("mode", [fn.SEARCH_PLAIN, fn.SEARCH_SCREEN])
+def test_edge_time_iteration_sampled(iteration, mode):
+    """Full one-iteration shape (32,768 edges, 64 T x 32 samples, 5 obstacles)
+    on the GPU; 384 sampled edges checked against the oracle."""
+    sh = iteration["shape"]
+    ctx = _ctx(iteration)
+    tree, ld, n = fn.tree_soa(iteration["tree_x"])
+    cand = fn.dev(iteration["cand"]["x"])
+    idx, _ = ctx.plan_knn(tree, ld, n, cand, sh.k)
+    out = _run_edges(ctx, iteration, idx, mode)
+    nbr = idx.cpu().numpy()
+    E = nbr.size
+    sel = np.random.default_rng(7 + mode).choice(E, 384, replace=False)
+    x0, x1, ok = O.edges_of(iteration["tree_x"], iteration["cand"]["x"], nbr)
+    ref = O.edge_time(O.make_oarm(iteration["arm"]), x0[sel], x1[sel], iteration["grid"],
+                      sh.samples, iteration["obs"], parent_ok=ok[sel])
+    compare_edges(out, ref, sel, label=f"iteration mode {mode}")
+
+
+def test_modes_agree_full_iteration(iteration):
+    """All search modes give identical results on every edge of the batch."""
+    sh = iteration["shape"]
+    ctx = _ctx(iteration)
+    tree, ld, n = fn.tree_soa(iteration["tree_x"])
+    cand = fn.dev(iteration["cand"]["x"])
+    idx, _ = ctx.plan_knn(tree, ld, n, cand, sh.k)
+    a = _run_edges(ctx, iteration, idx, fn.SEARCH_PLAIN)
+    b = _run_edges(ctx, iteration, idx, fn.SEARCH_SCREEN)
+    rng = np.random.default_rng(0)
+    wl = torch.as_tensor(rng.integers(0, sh.n_t + 1, idx.numel()).astype(np.int16)).cuda()
+    c = _run_edges(ctx, iteration, idx, fn.SEARCH_WINDOW, win_lo=wl, win_half=4)
+    ja, jb, jc = (x["j"].cpu().numpy() for x in (a, b, c))
+    sa, sb, sc = (_decision(x["status"].cpu().numpy().astype(np.uint16)) for x in (a, b, c))
+    assert np.array_equal(ja, jb) and np.array_equal(sa, sb)
+    assert np.array_equal(ja, jc) and np.array_equal(sa, sc)
+    wa, wb = a["work"].cpu().numpy(), b["work"].cpu().numpy()
+    print(f"work plain {wa.sum()} screen {wb.sum()} ({wa.sum() / max(1, wb.sum()):.2f}x)")
+    assert wb.sum() < wa.sum()
+
+
+def test_edge_time_bad_input_and_padding(tiny):
+    sh = tiny["shape"]
+    ctx = _ctx(tiny)
+    ridx, _ = O.plan_knn(tiny["tree_x"], tiny["cand"]["x"], sh.k)
+    ridx = ridx.copy()
+    ridx[0, 1] = -1
+    cx = tiny["cand"]["x"].copy()
+    cx[2, 9] = np.nan
+    wl = dict(tiny)
+    wl["cand"] = dict(tiny["cand"], x=cx)
+    out = _run_edges(ctx, wl, fn.dev(ridx, torch.int32), fn.SEARCH_PLAIN)
+    st = out["status"].cpu().numpy().astype(np.uint16)
+    j = out["j"].cpu().numpy()
+    assert st[1] == fn.S_NO_PARENT and j[1] == -1
+    assert (st[2 * sh.k:3 * sh.k] == fn.S_BAD_INPUT).all()
+    # neighbours untouched
+    x0, x1, ok = O.edges_of(tiny["tree_x"], cx, ridx)
+    ref = O.edge_time(O.make_oarm(tiny["arm"]), x0, x1, tiny["grid"], sh.samples, parent_ok=ok)
+    compare_edges(out, ref, label="bad-input batch")
+
+
+def test_edge_time_jmax(tiny):
+    sh = tiny["shape"]
+    ctx = _ctx(tiny)
+    ridx, _ = O.plan_knn(tiny["tree_x"], tiny["cand"]["x"], sh.k)
+    jm = np.random.default_rng(1).integers(-1, sh.n_t, ridx.size).astype(np.int16)
+    out = _run_edges(ctx, tiny, fn.dev(ridx, torch.int32), fn.SEARCH_SCREEN,
+                     j_max=fn.dev(jm, torch.int16))
+    x0, x1, ok = O.edges_of(tiny["tree_x"], tiny["cand"]["x"], ridx)
+    ref = O.edge_time(O.make_oarm(tiny["arm"]), x0, x1, tiny["grid"], sh.samples, parent_ok=ok,
+                      jmax=jm)
+    compare_edges(out, ref, label="jmax")
+
+
+@pytest.mark.parametrize("S", [2, 5, 16, 64])
+def test_edge_time_sample_counts(tiny, S):
+    sh = tiny["shape"]
+    ctx = _ctx(tiny)
+    ridx, _ = O.plan_knn(tiny["tree_x"], tiny["cand"]["x"], sh.k)
+    tree, ld, n = fn.tree_soa(tiny["tree_x"])
+    out = ctx.edge_time_batch(tree, ld, n, fn.dev(tiny["cand"]["x"]), fn.dev(ridx, torch.int32),
+                              fn.dev(tiny["grid"]), S, mode=fn.SEARCH_PLAIN)
+    torch.cuda.synchronize()
+    x0, x1, ok = O.edges_of(tiny["tree_x"], tiny["cand"]["x"], ridx)
+    ref = O.edge_time(O.make_oarm(tiny["arm"]), x0, x1, tiny["grid"], S, parent_ok=ok)
+    compare_edges(out, ref, label=f"S={S}")
+
+
+# ------------------------------------------------------------------ fixed-T check
+
+def test_edge_check_torques_and_ratios(iteration):
+    sh = iteration["shape"]
+    ctx = _ctx(iteration)
+    rng = np.random.default_rng(5)
+    E = 200
+    x0 = iteration["tree_x"][rng.integers(0, sh.n_nodes, E)]
+    x1 = iteration["cand"]["x"][rng.integers(0, sh.batch, E)]
+    T = W._f32(rng.uniform(0.05, 1.0, E))
+    T[0] = -0.1
+    obs = fn.dev(iteration["obs"])
+    out = ctx.edge_check(fn.dev(x0), fn.dev(x1), fn.dev(T), sh.samples, obs, want_tau=True)
+    torch.cuda.synchronize()
+    A = O.make_oarm(iteration["arm"])
+    ref = O.edge_check(A, x0, x1, T, sh.samples, iteration["obs"], want_tau=True)
+    tau = out["tau"].cpu().numpy().astype(np.float64)[1:]
+    rt = ref["tau"][1:]
+    tmax = iteration["arm"]["taumax"]
+    scale = np.maximum(np.abs(rt), 1e-2 * tmax)
+    err = np.abs(tau - rt) / scale
+    load = np.max(np.abs(rt) / tmax, axis=2)  # peak torque ratio of each sample
+    for lo, hi in ((0, 1), (1, 10), (10, 100), (100, 1e9)):
+        m = (load >= lo) & (load < hi)
+        if m.any():
+            print(f"samples with peak ratio in [{lo},{hi}): {m.sum()}, max rel err "
+                  f"{err[m].max():.2e}, p99 {np.quantile(err[m], 0.99):.2e}")
+    w = np.unravel_index(np.argmax(err), err.shape)
+    print("worst", w, "T", T[1:][w[0]], "tau_ref", rt[w[0], w[1]], "tau_gpu", tau[w[0], w[1]])
+    assert err[load <= 10].max() <= 1e-4
+    rho = out["rho"].cpu().numpy()
+    assert np.allclose(rho[1:], ref["rho"][1:], rtol=1e-4, atol=1e-6)
+    st = out["status"].cpu().numpy().astype(np.uint16)
+    strict = np.all(np.abs(ref["rho"] - 1) > 1e-3, axis=1)
+    assert np.array_equal(st[strict] & fn.S_DECISION, ref["status"][strict])
+    assert st[0] == fn.S_NONE
+
+
+# ------------------------------------------------------------------ risk
+
+def test_risk_score():
+    ctx = fn.Context(W.make_arm(0), 16, 16, 4)
+    rng = np.random.default_rng(2)
+    n = 1000
+    T = W._f32(rng.uniform(0.1, 1.0, n))
+    tf = W._f32(T + rng.uniform(-0.3, 0.5, n))
+    vr = W._f32(rng.uniform(0, 12, n))
+    nu = W._f32(rng.uniform(0.5, 1.3, n))
+    vz = W._f32(rng.uniform(1, 6, n))
+    for mode in (0, 1):
+        w = fn.make_risk(sigma_mode=mode, sp=0.0054, sv=0.0406, sa=0.2)
+        J = ctx.risk_score(w, fn.dev(T), fn.dev(vr), fn.dev(nu), fn.dev(vz), fn.dev(tf))
+        torch.cuda.synchronize()
+        R = O.make_orisk(sigma_mode=mode, sp=0.0054, sv=0.0406, sa=0.2)
+        ref = O.risk_score(R, T, vr, nu, vz, tf)
+        assert np.allclose(J.cpu().numpy(), ref, rtol=1e-6, atol=1e-5)
+
+
+def test_errors_are_returned_not_thrown(tiny):
+    ctx = _ctx(tiny)
+    tree, ld, n = fn.tree_soa(tiny["tree_x"])
+    q = fn.dev(tiny["cand"]["x"])
+    with pytest.raises(fn.FnError, match="k ="):
+        ctx.plan_knn(tree, ld, n, q, 99)
+    with pytest.raises(fn.FnError, match="S ="):
+        ctx.edge_time_batch(tree, ld, n, q, torch.zeros((64, 4), dtype=torch.int32, device="cuda"),
+                            fn.dev(tiny["grid"]), 65)
+    with pytest.raises(fn.FnError, match="window"):
+        ctx.edge_time_batch(tree, ld, n, q, torch.zeros((64, 4), dtype=torch.int32, device="cuda"),
+                            fn.dev(tiny["grid"]), 16, mode=fn.SEARCH_WINDOW)
