@@ -63,23 +63,22 @@ __device__ void fill_arm(const fn_arm_desc* d, const int* digits, int pattern, A
     }
     A->ca[i] = R(ca);
     A->sa[i] = R(sa);
-    A->px[i] = R(d->a[i]);
-    A->py[i] = R(-sa * d->d[i]);
-    A->pz[i] = R(ca * d->d[i]);
-    A->m[i] = R(d->m[i]);
-    A->rcx[i] = R(d->rc[i][0]);
-    A->rcy[i] = R(d->rc[i][1]);
-    A->rcz[i] = R(d->rc[i][2]);
-    A->Ix[i] = R(d->inertia[i][0]);
-    A->Iy[i] = R(d->inertia[i][1]);
-    A->Iz[i] = R(d->inertia[i][2]);
-    A->Im[i] = R(d->Im[i]);
-    A->psi1[i] = R(d->psi1[i]);
-    A->psi2[i] = R(d->psi2[i]);
-    A->psi3[i] = R(d->psi3[i]);
-    A->fk2[i] = R(-d->psi2[i] * 1.4426950408889634);
-    A->f0[i] = R(d->psi1[i] / (1.0 + exp(-d->psi2[i] * d->psi3[i])));
-    A->inv_taumax[i] = R(1.0 / d->taumax[i]);
+    A->L[i].px = R(d->a[i]);
+    A->L[i].py = R(-sa * d->d[i]);
+    A->L[i].pz = R(ca * d->d[i]);
+    A->L[i].m = R(d->m[i]);
+    A->L[i].rcx = R(d->rc[i][0]);
+    A->L[i].rcy = R(d->rc[i][1]);
+    A->L[i].rcz = R(d->rc[i][2]);
+    A->L[i].Ix = R(d->inertia[i][0]);
+    A->L[i].Iy = R(d->inertia[i][1]);
+    A->L[i].Iz = R(d->inertia[i][2]);
+    A->L[i].Im = R(d->Im[i]);
+    A->L[i].psi1 = R(d->psi1[i]);
+    A->L[i].psi3 = R(d->psi3[i]);
+    A->L[i].fk2 = R(-d->psi2[i] * 1.4426950408889634);
+    A->L[i].f0 = R(d->psi1[i] / (1.0 + exp(-d->psi2[i] * d->psi3[i])));
+    A->L[i].inv_taumax = R(1.0 / d->taumax[i]);
     A->qmin[i] = R(d->qmin[i]);
     A->qmax[i] = R(d->qmax[i]);
     A->qcen[i] = R(0.5 * (d->qmax[i] + d->qmin[i]));

@@ -102,7 +102,17 @@ __device__ void post_checks(const ArmConst<R>& A, const EdgeState<R>& E, R T, in
                             R& rq, R& rc) {
   const int lane = lane_id();
   R v = 0, q = 0;
-  if (lane < NJ) joint_post(A, E, lane, T, v, q);
+  // lane i < 7 checks joint i (register selects keep the edge state in VGPRs)
+  R q0 = 0, qd0 = 0, dq = 0, d2v = 0;
+#pragma unroll
+  for (int i = 0; i < NJ; ++i)
+    if (lane == i) {
+      q0 = E.q0[i];
+      qd0 = E.qd0[i];
+      dq = E.dq[i];
+      d2v = E.d2[i];
+    }
+  if (lane < NJ) joint_post(A, lane, q0, qd0, dq, d2v, T, v, q);
   // clearance: one sample per lane
   R best = 0;
   if (n_obs > 0 && lane < S) {
@@ -176,7 +186,42 @@ __device__ __forceinline__ void push_queue(const EdgeArgs& a, int64_t e, int j, 
 
 // ---------------------------------------------------------------------------
 // FP32 search kernel
+//
+// The search of every mode is a short list of stages, each a slot range
+// that is either screened (endpoint samples) or scanned (full slots in
+// ascending order, certified slots skipped):
+//   PLAIN : scan [0, jmax]
+//   SCREEN: screen [0, jmax], scan [0, jmax]
+//   WINDOW: screen [0, lo-1], scan [0, lo-1], scan [lo, hi],
+//           screen [hi+1, jmax], scan [hi+1, jmax]
+// One loop walks the stages so that the evaluation of Eq. (4) has a single
+// call site.
 // ---------------------------------------------------------------------------
+enum { ST_SCREEN = 0, ST_SCAN = 1, ST_END = 2 };
+
+__device__ __forceinline__ void stage_of(int mode, int st, int jmax, int lo, int hi, int& type,
+                                         int& a, int& b, bool& below) {
+  below = false;
+  type = ST_END;
+  a = 0;
+  b = -1;
+  if (mode == FN_SEARCH_PLAIN) {
+    if (st == 0) { type = ST_SCAN; a = 0; b = jmax; }
+  } else if (mode == FN_SEARCH_SCREEN) {
+    if (st == 0) { type = ST_SCREEN; a = 0; b = jmax; }
+    if (st == 1) { type = ST_SCAN; a = 0; b = jmax; }
+  } else {
+    switch (st) {
+      case 0: type = ST_SCREEN; a = 0; b = lo - 1; break;
+      case 1: type = ST_SCAN; a = 0; b = lo - 1; below = true; break;
+      case 2: type = ST_SCAN; a = lo; b = hi; break;
+      case 3: type = ST_SCREEN; a = hi + 1; b = jmax; break;
+      case 4: type = ST_SCAN; a = hi + 1; b = jmax; break;
+      default: break;
+    }
+  }
+}
+
 template <int PAT>
 __global__ __launch_bounds__(256) void edge_time_kernel(EdgeArgs a,
                                                         const ArmConst<float>* __restrict__ Ap) {
@@ -202,11 +247,17 @@ __global__ __launch_bounds__(256) void edge_time_kernel(EdgeArgs a,
   }
   const int S = a.S, Sw = a.Sw, G = WAVE / Sw;
   const int g = lane / Sw;
-  const float u = lane_u(lane, Sw, S);
+  const float u_full = lane_u(lane, Sw, S);
   const bool s_ok = (lane & (Sw - 1)) < S;
 
   for (int j = lane; j < a.n_t; j += WAVE) s_end[j] = -1.f;  // -1: not screened
   __builtin_amdgcn_wave_barrier();
+
+  int wlo = 0, whi = -1;
+  if (a.mode == FN_SEARCH_WINDOW) {
+    wlo = min(max((int)a.win_lo[e], 0), jmax + 1);
+    whi = min(wlo + 2 * a.win_half, jmax);
+  }
 
   int work = 0;
   float marg = INFINITY;  // over fully evaluated slots up to the result
@@ -214,41 +265,31 @@ __global__ __launch_bounds__(256) void edge_time_kernel(EdgeArgs a,
   int jstar = -1;
   float rho_star = 0.f;
   bool below_full = false;
+  bool queued = false;
 
-  // endpoint screen of slots [lo, hi]: 32 slots per pass, lane = (slot, end)
-  auto screen = [&](int lo, int hi) {
-    for (int j0 = lo; j0 <= hi; j0 += WAVE / 2) {
-      const int j = j0 + (lane >> 1);
-      const bool act = j <= hi;
-      float r = 0.f;
-      if (act) {
-        const float T = a.grid[j];
-        r = eval_rho<float, PAT>(A, ES, T, 1.f / T, (lane & 1) ? 1.f : 0.f);
-      }
-      r = fmaxf(r, __shfl_xor(r, 1));
-      if (act && (lane & 1) == 0) s_end[j] = r;
-      work += __popcll(__ballot(act));
+  int stage = 0, type, sa, sb;
+  bool below;
+  stage_of(a.mode, stage, jmax, wlo, whi, type, sa, sb, below);
+  int j = sa;
+  while (type != ST_END) {
+    if (j > sb) {
+      ++stage;
+      stage_of(a.mode, stage, jmax, wlo, whi, type, sa, sb, below);
+      j = sa;
+      continue;
     }
-    __builtin_amdgcn_wave_barrier();
-  };
-  // certified-infeasible margin of screened slots below `lim`
-  auto cert_margin = [&](int lim) {
-    float m = INFINITY;
-    for (int j = lane; j < lim; j += WAVE) {
-      const float r = s_end[j];
-      if (r > 1.f + BAND) m = fminf(m, r - 1.f);
-    }
-    return wave_min(m);
-  };
-  // ascending full evaluation of [lo, hi]; screened slots that are certified
-  // are skipped.  Returns 0: not found, 1: found, 2: sent to the FP64 stage.
-  auto scan = [&](int lo, int hi, bool track_below) -> int {
-    int j = lo;
-    while (j <= hi) {
-      // next G slots that are not certified infeasible; lane group g takes
-      // the g-th of them
-      int my = -1, cnt = 0;
-      while (cnt < G && j <= hi) {
+    // lanes of this pass: slot `my` (or -1) and normalised time u
+    int my = -1, cnt = 0;
+    float u = u_full;
+    if (type == ST_SCREEN) {
+      const int jj = j + (lane >> 1);
+      my = jj <= sb ? jj : -1;
+      u = (lane & 1) ? 1.f : 0.f;
+      cnt = min(WAVE / 2, sb - j + 1);
+      j += WAVE / 2;
+    } else {
+      // next G slots not certified infeasible; lane group g takes the g-th
+      while (cnt < G && j <= sb) {
         if (s_end[j] > 1.f + BAND) {
           ++j;
           continue;
@@ -257,64 +298,62 @@ __global__ __launch_bounds__(256) void edge_time_kernel(EdgeArgs a,
         ++cnt;
         ++j;
       }
-      if (cnt == 0) break;
-      if (track_below) below_full = true;
-      float r = 0.f;
-      const bool act = my >= 0 && s_ok;
-      if (act) {
-        const float T = a.grid[my];
-        r = eval_rho<float, PAT>(A, ES, T, 1.f / T, u);
+      if (cnt == 0) continue;  // range exhausted
+      if (!s_ok) my = -1;
+      if (below) below_full = true;
+    }
+    const bool act = my >= 0;
+    float r = 0.f;
+    if (act) {
+      const float T = a.grid[my];
+      r = eval_rho<float, PAT>(A, ES, T, __builtin_amdgcn_rcpf(T), u);
+    }
+    work += __popcll(__ballot(act));
+    if (type == ST_SCREEN) {
+      r = fmaxf(r, __shfl_xor(r, 1));
+      if (act && (lane & 1) == 0) s_end[my] = r;
+      __builtin_amdgcn_wave_barrier();
+      continue;
+    }
+    r = group_max(r, Sw);
+    bool done = false;
+    for (int q = 0; q < cnt; ++q) {
+      const float rho = __shfl(r, q * Sw);
+      const int jq = __shfl(my, q * Sw);
+      if (near_one(rho)) {
+        // decided in FP64: hand the edge over at slot jq
+        float m = INFINITY;
+        for (int t = lane; t < jq; t += WAVE)
+          if (s_end[t] > 1.f + BAND) m = fminf(m, s_end[t] - 1.f);
+        m = fminf(marg, wave_min(m));
+        push_queue(a, e, jq, below_full ? PH_BELOW_FULL : 0, m, work);
+        queued = done = true;
+        break;
       }
-      work += __popcll(__ballot(act));
-      r = group_max(r, Sw);
-      for (int q = 0; q < cnt; ++q) {
-        const float rho = __shfl(r, q * Sw);
-        const int jq = __shfl(my, q * Sw);
-        if (near_one(rho)) {
-          const float m = fminf(marg, cert_margin(jq));
-          push_queue(a, e, jq, below_full ? PH_BELOW_FULL : 0, m, work);
-          return 2;
-        }
-        marg = fminf(marg, fabsf(rho - 1.f));
-        last = rho;
-        if (rho <= 1.f) {
-          jstar = jq;
-          rho_star = rho;
-          return 1;
-        }
+      marg = fminf(marg, fabsf(rho - 1.f));
+      last = rho;
+      if (rho <= 1.f) {
+        jstar = jq;
+        rho_star = rho;
+        done = true;
+        break;
       }
     }
-    return 0;
-  };
-
-  int res = 0;
-  int wlo = 0, whi = -1;
-  if (a.mode == FN_SEARCH_PLAIN) {
-    res = scan(0, jmax, false);
-  } else if (a.mode == FN_SEARCH_SCREEN) {
-    screen(0, jmax);
-    res = scan(0, jmax, false);
-  } else {
-    wlo = min(max((int)a.win_lo[e], 0), jmax + 1);
-    whi = min(wlo + 2 * a.win_half, jmax);
-    if (wlo > 0) {
-      screen(0, wlo - 1);
-      res = scan(0, wlo - 1, true);
-    }
-    if (res == 0 && wlo <= jmax) res = scan(wlo, whi, false);
-    if (res == 0 && whi < jmax) {
-      screen(whi + 1, jmax);
-      res = scan(whi + 1, jmax, false);
-    }
+    if (done) break;
   }
-  if (res == 2) return;
+  if (queued) return;
+  // certified-infeasible margin of the screened slots below the result
+  const int lim = jstar >= 0 ? jstar : jmax + 1;
+  float mc = INFINITY;
+  for (int t = lane; t < lim; t += WAVE)
+    if (s_end[t] > 1.f + BAND) mc = fminf(mc, s_end[t] - 1.f);
+  float m = fminf(marg, wave_min(mc));
   int winbits = 0;
   if (a.mode == FN_SEARCH_WINDOW) {
     const bool hit = !below_full && ((jstar >= wlo && jstar <= whi) || (jstar < 0 && wlo > jmax));
     winbits = hit ? FN_S_WIN_HIT : FN_S_WIN_MISS;
   }
   if (jstar < 0) {
-    const float m = fminf(marg, cert_margin(jmax + 1));
     // ratio of the last slot: its full value, else its screened endpoint value
     const float lastv = s_end[jmax] > 1.f + BAND ? s_end[jmax] : last;
     write_out(a, e, -1, FN_S_NONE | winbits, m, lastv, 0, 0, 0, work);
@@ -323,7 +362,6 @@ __global__ __launch_bounds__(256) void edge_time_kernel(EdgeArgs a,
   float rv, rq, rc;
   const float T = a.grid[jstar];
   post_checks<float, PAT>(A, ES, T, S, a.obs, a.n_obs, a.margin_c, rv, rq, rc);
-  float m = fminf(marg, cert_margin(jstar));
   if (near_one(rv) || near_one(rq) || (a.n_obs > 0 && near_one(rc))) {
     push_queue(a, e, jstar, PH_POST | (below_full ? PH_BELOW_FULL : 0), m, work);
     return;

@@ -28,20 +28,25 @@ constexpr int pat_digit(int pat, int i) {
 // 0, -pi/2, +pi/2, +pi/2, -pi/2, +pi/2, +pi/2 (Panda/FR3-like chain)
 constexpr int PAT_FR3 = 0 + 2 * 4 + 1 * 16 + 1 * 64 + 2 * 256 + 1 * 1024 + 1 * 4096;
 
+// Per-link constants, contiguous so that one scalar load fetches a link.
+template <typename R>
+struct alignas(16 * sizeof(R)) LinkConst {
+  R px, py, pz;     // origin of frame i in frame i-1
+  R m;
+  R rcx, rcy, rcz;  // COM in frame i
+  R Ix, Iy, Iz;     // diagonal inertia about the COM
+  R Im;             // reflected rotor inertia
+  R psi1, fk2, psi3;  // friction: fk2 = -psi2 log2(e)
+  R f0;             // psi1 / (1 + exp(-psi2 psi3)): friction at rest, subtracted
+  R inv_taumax;
+};
+
 template <typename R>
 struct ArmConst {
+  LinkConst<R> L[NJ];
   int32_t terms;
   int32_t pattern;        // twist pattern code (or -1 when some twist is general)
   R ca[NJ], sa[NJ];       // cos / sin of alpha_{i-1}
-  R px[NJ], py[NJ], pz[NJ];  // origin of frame i in frame i-1
-  R m[NJ];
-  R rcx[NJ], rcy[NJ], rcz[NJ];
-  R Ix[NJ], Iy[NJ], Iz[NJ];
-  R Im[NJ];
-  R psi1[NJ], psi2[NJ], psi3[NJ];
-  R fk2[NJ];              // -psi2 * log2(e)
-  R f0[NJ];               // psi1 / (1 + exp(-psi2 psi3)): friction at rest, subtracted
-  R inv_taumax[NJ];
   R inv_wmax;
   R qmin[NJ], qmax[NJ], qcen[NJ], inv_qhalf[NJ], qdmax[NJ], two_acc[NJ];
   R vd0[3];               // base acceleration: -g when gravity is on
@@ -138,7 +143,7 @@ __device__ __forceinline__ void rnea(const ArmConst<R>& A, const R* sn, const R*
 #pragma unroll
   for (int i = 0; i < NJ; ++i) {
     const R c = cs[i], s = sn[i];
-    const R px = A.px[i], py = A.py[i], pz = A.pz[i];
+    const R px = A.L[i].px, py = A.L[i].py, pz = A.L[i].pz;
     // t = wd x p + w x (w x p) + vd   (frame i-1)
     const R wpx = wy * pz - wz * py, wpy = wz * px - wx * pz, wpz = wx * py - wy * px;
     const R tx = (ay * pz - az * py) + (wy * wpz - wz * wpy) + vx;
@@ -160,17 +165,17 @@ __device__ __forceinline__ void rnea(const ArmConst<R>& A, const R* sn, const R*
     ax = rax + rwy * q1; ay = ray - rwx * q1; az = raz + qdd[i];
     vx = nvx; vy = nvy; vz = nvz;
     // COM acceleration and the link's Newton-Euler wrench
-    const R rx = A.rcx[i], ry = A.rcy[i], rz = A.rcz[i];
+    const R rx = A.L[i].rcx, ry = A.L[i].rcy, rz = A.L[i].rcz;
     const R wrx = wy * rz - wz * ry, wry = wz * rx - wx * rz, wrz = wx * ry - wy * rx;
     const R cx = (ay * rz - az * ry) + (wy * wrz - wz * wry) + vx;
     const R cy = (az * rx - ax * rz) + (wz * wrx - wx * wrz) + vy;
     const R cz = (ax * ry - ay * rx) + (wx * wry - wy * wrx) + vz;
-    const R mm = A.m[i];
+    const R mm = A.L[i].m;
     Fx[i] = mm * cx; Fy[i] = mm * cy; Fz[i] = mm * cz;
-    const R Iwx = A.Ix[i] * wx, Iwy = A.Iy[i] * wy, Iwz = A.Iz[i] * wz;
-    Nx[i] = A.Ix[i] * ax + (wy * Iwz - wz * Iwy);
-    Ny[i] = A.Iy[i] * ay + (wz * Iwx - wx * Iwz);
-    Nz[i] = A.Iz[i] * az + (wx * Iwy - wy * Iwx);
+    const R Iwx = A.L[i].Ix * wx, Iwy = A.L[i].Iy * wy, Iwz = A.L[i].Iz * wz;
+    Nx[i] = A.L[i].Ix * ax + (wy * Iwz - wz * Iwy);
+    Ny[i] = A.L[i].Iy * ay + (wz * Iwx - wx * Iwz);
+    Nz[i] = A.L[i].Iz * az + (wx * Iwy - wy * Iwx);
   }
   R fx = 0, fy = 0, fz = 0, nx = 0, ny = 0, nz = 0;  // f_{i+1}, n_{i+1} in frame i+1
 #pragma unroll
@@ -188,12 +193,12 @@ __device__ __forceinline__ void rnea(const ArmConst<R>& A, const R* sn, const R*
 #undef FN_ROT2
       }
       // + p_{i+1} x (R f_{i+1})
-      const R px = A.px[i + 1], py = A.py[i + 1], pz = A.pz[i + 1];
+      const R px = A.L[i + 1].px, py = A.L[i + 1].py, pz = A.L[i + 1].pz;
       Rnx += py * Rfz - pz * Rfy;
       Rny += pz * Rfx - px * Rfz;
       Rnz += px * Rfy - py * Rfx;
     }
-    const R rx = A.rcx[i], ry = A.rcy[i], rz = A.rcz[i];
+    const R rx = A.L[i].rcx, ry = A.L[i].rcy, rz = A.L[i].rcz;
     fx = Rfx + Fx[i]; fy = Rfy + Fy[i]; fz = Rfz + Fz[i];
     nx = Nx[i] + Rnx + (ry * Fz[i] - rz * Fy[i]);
     ny = Ny[i] + Rny + (rz * Fx[i] - rx * Fz[i]);
@@ -204,8 +209,8 @@ __device__ __forceinline__ void rnea(const ArmConst<R>& A, const R* sn, const R*
   const bool fric = (A.terms & FN_T_FRICTION) != 0;
 #pragma unroll
   for (int i = 0; i < NJ; ++i) {
-    if (arm) tau[i] += A.Im[i] * qdd[i];
-    if (fric) tau[i] += A.psi1[i] * logistic_neg(A.fk2[i] * (qd[i] + A.psi3[i])) - A.f0[i];
+    if (arm) tau[i] += A.L[i].Im * qdd[i];
+    if (fric) tau[i] += A.L[i].psi1 * logistic_neg(A.L[i].fk2 * (qd[i] + A.L[i].psi3)) - A.L[i].f0;
   }
 }
 
@@ -248,7 +253,7 @@ __device__ __forceinline__ void eval_point(const ArmConst<R>& A, const EdgeState
   R t = 0, pw = 0;
 #pragma unroll
   for (int i = 0; i < NJ; ++i) {
-    t = rmax(t, rabs(tau[i]) * A.inv_taumax[i]);
+    t = rmax(t, rabs(tau[i]) * A.L[i].inv_taumax);
     pw += tau[i] * sd[i];
     if (tau_out) tau_out[i] = tau[i];
   }
@@ -274,15 +279,17 @@ __device__ __forceinline__ R vel_ratio(const ArmConst<R>& A, int i, R q, R v) {
   return rabs(v) / lim;
 }
 
-// rho_v and rho_q of joint i at duration T (exact extrema of the cubic).
+// rho_v and rho_q of one joint at duration T (exact extrema of the cubic):
+// boundary state (q0, qd0), dq = q1 - q0, d2 = qd1 - qd0; i indexes the
+// joint's limits.
 template <typename R>
-__device__ __forceinline__ void joint_post(const ArmConst<R>& A, const EdgeState<R>& E, int i, R T,
-                                           R& rv, R& rq) {
+__device__ __forceinline__ void joint_post(const ArmConst<R>& A, int i, R q0, R qd0, R dq, R d2v,
+                                           R T, R& rv, R& rq) {
   const R invT = R(1) / T;
-  const R c0 = E.q0[i], c1 = E.qd0[i];
-  const R d1 = E.dq[i] - c1 * T;
-  const R c2 = (R(3) * d1 * invT - E.d2[i]) * invT;
-  const R c3 = (E.d2[i] - R(2) * d1 * invT) * invT * invT;
+  const R c0 = q0, c1 = qd0;
+  const R d1 = dq - c1 * T;
+  const R c2 = (R(3) * d1 * invT - d2v) * invT;
+  const R c3 = (d2v - R(2) * d1 * invT) * invT * invT;
   auto pos = [&](R t) { return c0 + t * (c1 + t * (c2 + t * c3)); };
   auto vel = [&](R t) { return c1 + t * (R(2) * c2 + R(3) * c3 * t); };
   // velocity peaks: t = 0, t = T, vertex of the quadratic velocity
@@ -326,7 +333,7 @@ __device__ __forceinline__ void sphere_centres(const ArmConst<R>& A, const R* sn
 #pragma unroll
   for (int i = 0; i < NJ; ++i) {
     // origin_i = origin_{i-1} + R_{i-1} p_i
-    const R px = A.px[i], py = A.py[i], pz = A.pz[i];
+    const R px = A.L[i].px, py = A.L[i].py, pz = A.L[i].pz;
     ox += r00 * px + r01 * py + r02 * pz;
     oy += r10 * px + r11 * py + r12 * pz;
     oz += r20 * px + r21 * py + r22 * pz;
