@@ -90,6 +90,10 @@ __device__ void fill_arm(const fn_arm_desc* d, const int* digits, int pattern, A
   const bool grav = (d->terms & FN_T_GRAVITY) != 0;
   for (int r = 0; r < 3; ++r) A->vd0[r] = grav ? R(-d->g[r]) : R(0);
   A->nsph = d->n_spheres;
+  // spheres arrive sorted by link: prefix offsets per link
+  for (int i = 0; i <= NJ; ++i) A->sph_first[i] = 0;
+  for (int k = 0; k < d->n_spheres; ++k) A->sph_first[d->sphere_link[k]] += 1;
+  for (int i = 1; i <= NJ; ++i) A->sph_first[i] += A->sph_first[i - 1];
   for (int k = 0; k < d->n_spheres; ++k) {
     A->sph_link[k] = d->sphere_link[k];
     A->sphx[k] = R(d->sphere[k][0]);
@@ -214,6 +218,7 @@ extern "C" int fn_create(const fn_arm_desc* arm, const fn_caps* caps, fn_ctx** o
   const size_t kl = knn_scratch_entries(caps->max_batch, caps->max_k);
   FN_ALLOC(c->knn_d, kl * sizeof(float));
   FN_ALLOC(c->knn_i, kl * sizeof(int32_t));
+  FN_ALLOC(c->knn_y, knn_scratch_entries(caps->max_batch, 0) * sizeof(float));
   // near-limit queue: counter + one entry per edge
   FN_ALLOC(c->q_count, 64 * sizeof(int32_t));
   FN_ALLOC(c->queue, (size_t)(caps->max_edges > 0 ? caps->max_edges : 1) * sizeof(QEntry));
@@ -243,6 +248,7 @@ extern "C" void fn_destroy(fn_ctx* c) {
   (void)hipFree(c->arm64);
   (void)hipFree(c->knn_d);
   (void)hipFree(c->knn_i);
+  (void)hipFree(c->knn_y);
   (void)hipFree(c->q_count);
   (void)hipFree(c->queue);
   delete c;

@@ -46,6 +46,7 @@ struct fn_ctx {
   fn::ArmConst<double>* arm64;
   float* knn_d;
   int32_t* knn_i;
+  float* knn_y;  // per (query, chunk): max |y|^2 of the chunk
   int32_t* q_count;  // [0]: queue length
   fn::QEntry* queue;
 };

@@ -113,23 +113,31 @@ __device__ void post_checks(const ArmConst<R>& A, const EdgeState<R>& E, R T, in
       d2v = E.d2[i];
     }
   if (lane < NJ) joint_post(A, lane, q0, qd0, dq, d2v, T, v, q);
-  // clearance: one sample per lane
+  // clearance: lane = (sample, sphere part); the parts split each link's
+  // spheres so that all 64 lanes work when S < 64
   R best = 0;
-  if (n_obs > 0 && lane < S) {
-    const R u = R(lane) / R(S - 1);
-    R sg[NJ], sd[NJ], sdd[NJ], sn[NJ], cs[NJ];
-    cubic_point(E, T, R(1) / T, u, sg, sd, sdd);
+  if (n_obs > 0) {
+    int Sw = 1;
+    while (Sw < S) Sw <<= 1;
+    const int nparts = Sw >= WAVE ? 1 : WAVE / Sw;
+    const int s = lane & (Sw - 1), part = lane / Sw;
+    if (s < S && part < nparts) {
+      const R u = R(s) / R(S - 1);
+      R sg[NJ], sd[NJ], sdd[NJ], sn[NJ], cs[NJ];
+      cubic_point(E, T, R(1) / T, u, sg, sd, sdd);
 #pragma unroll
-    for (int i = 0; i < NJ; ++i) sincos_r(sg[i], sn[i], cs[i]);
-    sphere_centres<R, PAT>(A, sn, cs, [&](int k, R x, R y, R z) {
-      for (int o = 0; o < n_obs; ++o) {
-        const R dx = x - R(obs[4 * o]), dy = y - R(obs[4 * o + 1]), dz = z - R(obs[4 * o + 2]);
-        const R need = A.sphr[k] + R(obs[4 * o + 3]) + R(margin_c);
-        const R d2 = dx * dx + dy * dy + dz * dz;
-        const R r2 = d2 > R(0) ? need * need / d2 : R(INFINITY);
-        best = rmax(best, r2);
-      }
-    });
+      for (int i = 0; i < NJ; ++i) sincos_r(sg[i], sn[i], cs[i]);
+      sphere_centres<R, PAT>(A, sn, cs, part, nparts, [&](int k, R x, R y, R z) {
+        const R ra = A.sphr[k] + R(margin_c);
+        for (int o = 0; o < n_obs; ++o) {
+          const R dx = x - R(obs[4 * o]), dy = y - R(obs[4 * o + 1]), dz = z - R(obs[4 * o + 2]);
+          const R need = ra + R(obs[4 * o + 3]);
+          const R d2 = dx * dx + dy * dy + dz * dz;
+          const R r2 = d2 > R(0) ? fdiv(need * need, d2) : R(INFINITY);
+          best = rmax(best, r2);
+        }
+      });
+    }
   }
   if constexpr (sizeof(R) == 4) {
     rv = wave_max(float(v));
@@ -222,10 +230,41 @@ __device__ __forceinline__ void stage_of(int mode, int st, int jmax, int lo, int
   }
 }
 
+// Slots still to be evaluated in full: bit j of word j / 64.
+struct SlotMask {
+  uint64_t w0, w1, w2, w3;
+  __device__ __forceinline__ uint64_t get(int i) const {
+    return i == 0 ? w0 : i == 1 ? w1 : i == 2 ? w2 : w3;
+  }
+  __device__ __forceinline__ void clear(int i, uint64_t m) {
+    if (i == 0) w0 &= ~m;
+    else if (i == 1) w1 &= ~m;
+    else if (i == 2) w2 &= ~m;
+    else w3 &= ~m;
+  }
+  // lowest set slot in [j, hi], or -1
+  __device__ __forceinline__ int next(int j, int hi) const {
+    while (j <= hi) {
+      const int w = j >> 6;
+      const uint64_t bits = get(w) & (~0ull << (j & 63));
+      if (bits) {
+        const int t = (w << 6) + __ffsll((long long)bits) - 1;
+        return t <= hi ? t : -1;
+      }
+      j = (w + 1) << 6;
+    }
+    return -1;
+  }
+};
+
 template <int PAT>
 __global__ __launch_bounds__(256) void edge_time_kernel(EdgeArgs a,
                                                         const ArmConst<float>* __restrict__ Ap) {
   __shared__ float s_end_all[4][FN_MAX_NT];
+  __shared__ float s_T[FN_MAX_NT];
+  // the block's four edges share the grid: stage it once
+  for (int t = threadIdx.x; t < a.n_t; t += blockDim.x) s_T[t] = a.grid[t];
+  __syncthreads();
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t e = (int64_t)blockIdx.x * 4 + wave;
   if (e >= a.E) return;
@@ -252,6 +291,7 @@ __global__ __launch_bounds__(256) void edge_time_kernel(EdgeArgs a,
 
   for (int j = lane; j < a.n_t; j += WAVE) s_end[j] = -1.f;  // -1: not screened
   __builtin_amdgcn_wave_barrier();
+  SlotMask todo{~0ull, ~0ull, ~0ull, ~0ull};
 
   int wlo = 0, whi = -1;
   if (a.mode == FN_SEARCH_WINDOW) {
@@ -282,21 +322,23 @@ __global__ __launch_bounds__(256) void edge_time_kernel(EdgeArgs a,
     int my = -1, cnt = 0;
     float u = u_full;
     if (type == ST_SCREEN) {
-      const int jj = j + (lane >> 1);
+      // lane l: slot j + (l & 31), endpoint u = 0 (l < 32) or u = 1
+      const int jj = j + (lane & 31);
       my = jj <= sb ? jj : -1;
-      u = (lane & 1) ? 1.f : 0.f;
+      u = lane >= 32 ? 1.f : 0.f;
       cnt = min(WAVE / 2, sb - j + 1);
       j += WAVE / 2;
     } else {
-      // next G slots not certified infeasible; lane group g takes the g-th
-      while (cnt < G && j <= sb) {
-        if (s_end[j] > 1.f + BAND) {
-          ++j;
-          continue;
+      // next G slots still to be evaluated; lane group g takes the g-th
+      while (cnt < G) {
+        const int t = todo.next(j, sb);
+        if (t < 0) {
+          j = sb + 1;
+          break;
         }
-        if (cnt == g) my = j;
+        if (cnt == g) my = t;
         ++cnt;
-        ++j;
+        j = t + 1;
       }
       if (cnt == 0) continue;  // range exhausted
       if (!s_ok) my = -1;
@@ -305,14 +347,20 @@ __global__ __launch_bounds__(256) void edge_time_kernel(EdgeArgs a,
     const bool act = my >= 0;
     float r = 0.f;
     if (act) {
-      const float T = a.grid[my];
+      const float T = s_T[my];
       r = eval_rho<float, PAT>(A, ES, T, __builtin_amdgcn_rcpf(T), u);
     }
     work += __popcll(__ballot(act));
     if (type == ST_SCREEN) {
-      r = fmaxf(r, __shfl_xor(r, 1));
-      if (act && (lane & 1) == 0) s_end[my] = r;
-      __builtin_amdgcn_wave_barrier();
+      r = fmaxf(r, __shfl_xor(r, 32));
+      if (act && lane < 32) s_end[my] = r;
+      // slots certified infeasible leave the to-do mask: bit t of the ballot
+      // is slot j0 + t, and the pass may straddle two 64-slot words
+      const int j0 = j - WAVE / 2;
+      const uint64_t bits = __ballot(act && lane < 32 && r > 1.f + BAND) & 0xffffffffull;
+      const int w0 = j0 >> 6, sh = j0 & 63;
+      todo.clear(w0, bits << sh);
+      if (sh > 32) todo.clear(w0 + 1, bits >> (64 - sh));
       continue;
     }
     r = group_max(r, Sw);
@@ -342,6 +390,7 @@ __global__ __launch_bounds__(256) void edge_time_kernel(EdgeArgs a,
     if (done) break;
   }
   if (queued) return;
+  __builtin_amdgcn_wave_barrier();
   // certified-infeasible margin of the screened slots below the result
   const int lim = jstar >= 0 ? jstar : jmax + 1;
   float mc = INFINITY;
@@ -360,7 +409,7 @@ __global__ __launch_bounds__(256) void edge_time_kernel(EdgeArgs a,
     return;
   }
   float rv, rq, rc;
-  const float T = a.grid[jstar];
+  const float T = s_T[jstar];
   post_checks<float, PAT>(A, ES, T, S, a.obs, a.n_obs, a.margin_c, rv, rq, rc);
   if (near_one(rv) || near_one(rq) || (a.n_obs > 0 && near_one(rc))) {
     push_queue(a, e, jstar, PH_POST | (below_full ? PH_BELOW_FULL : 0), m, work);
@@ -524,6 +573,10 @@ __global__ __launch_bounds__(256) void edge_check_kernel(const float* __restrict
   }
 }
 
+// waves of the FP64 stage: one per queued edge up to 4096 (the queue
+// length is known only on the device)
+static unsigned recheck_waves(int64_t E) { return (unsigned)(E < 4096 ? (E > 0 ? E : 1) : 4096); }
+
 static int pow2_at_least(int s) {
   int w = 1;
   while (w < s) w <<= 1;
@@ -573,10 +626,10 @@ extern "C" int edge_time_batch(fn_ctx* c, const float* tree, int64_t ld, int32_t
   const dim3 grid((unsigned)((E + 3) / 4));
   if (c->pattern == PAT_FR3) {
     hipLaunchKernelGGL(edge_time_kernel<PAT_FR3>, grid, dim3(256), 0, s, a, c->arm32);
-    hipLaunchKernelGGL(edge_recheck_kernel<PAT_FR3>, dim3(256), dim3(64), 0, s, a, c->arm32, c->arm64);
+    hipLaunchKernelGGL(edge_recheck_kernel<PAT_FR3>, dim3(recheck_waves(E)), dim3(64), 0, s, a, c->arm32, c->arm64);
   } else {
     hipLaunchKernelGGL(edge_time_kernel<PAT_GENERIC>, grid, dim3(256), 0, s, a, c->arm32);
-    hipLaunchKernelGGL(edge_recheck_kernel<PAT_GENERIC>, dim3(256), dim3(64), 0, s, a, c->arm32, c->arm64);
+    hipLaunchKernelGGL(edge_recheck_kernel<PAT_GENERIC>, dim3(recheck_waves(E)), dim3(64), 0, s, a, c->arm32, c->arm64);
   }
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? FN_OK : hip_fail(e, "edge_time_batch launch");

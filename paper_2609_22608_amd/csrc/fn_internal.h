@@ -51,6 +51,7 @@ struct ArmConst {
   R qmin[NJ], qmax[NJ], qcen[NJ], inv_qhalf[NJ], qdmax[NJ], two_acc[NJ];
   R vd0[3];               // base acceleration: -g when gravity is on
   int32_t nsph;
+  int32_t sph_first[NJ + 1];  // spheres of link i+1: [sph_first[i], sph_first[i+1])
   int32_t sph_link[FN_MAX_SPHERES];
   R sphx[FN_MAX_SPHERES], sphy[FN_MAX_SPHERES], sphz[FN_MAX_SPHERES], sphr[FN_MAX_SPHERES];
 };
@@ -77,6 +78,9 @@ __device__ __forceinline__ double logistic_neg(double k2x) {
 }
 template <typename R>
 __device__ __forceinline__ R rabs(R x) { return x < R(0) ? -x : x; }
+// a / b: hardware reciprocal (1 ulp) in FP32, IEEE division in FP64
+__device__ __forceinline__ float fdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double fdiv(double a, double b) { return a / b; }
 template <typename R>
 __device__ __forceinline__ R rmax(R a, R b) { return a > b ? a : b; }
 
@@ -322,14 +326,15 @@ __device__ __forceinline__ void joint_post(const ArmConst<R>& A, int i, R q0, R 
 }
 
 // World-frame centres of the collision spheres at configuration (sn, cs),
-// streamed: fn(k, x, y, z) is called for every sphere k in order.
+// streamed link by link: fn(k, x, y, z) is called for the spheres
+// k = first + part, first + part + nparts, ... of every link, so that
+// `nparts` lane groups share the spheres of one pose.
 template <typename R, int PAT, typename F>
 __device__ __forceinline__ void sphere_centres(const ArmConst<R>& A, const R* sn, const R* cs,
-                                               F&& fn) {
-  // columns of the world rotation of frame i and its origin
+                                               int part, int nparts, F&& fn) {
+  // world rotation of frame i (rows) and its origin
   R r00 = 1, r01 = 0, r02 = 0, r10 = 0, r11 = 1, r12 = 0, r20 = 0, r21 = 0, r22 = 1;
   R ox = 0, oy = 0, oz = 0;
-  int k = 0;
 #pragma unroll
   for (int i = 0; i < NJ; ++i) {
     // origin_i = origin_{i-1} + R_{i-1} p_i
@@ -337,7 +342,7 @@ __device__ __forceinline__ void sphere_centres(const ArmConst<R>& A, const R* sn
     ox += r00 * px + r01 * py + r02 * pz;
     oy += r10 * px + r11 * py + r12 * pz;
     oz += r20 * px + r21 * py + r22 * pz;
-    // R_i = R_{i-1} Rx(alpha) Rz(theta): apply to the rows
+    // R_i = R_{i-1} Rx(alpha) Rz(theta)
     R a0, a1, a2, b0, b1, b2, c0, c1, c2;  // rows after Rx
     switch (i) {
 #define FN_RX(II)                                                             \
@@ -365,12 +370,10 @@ __device__ __forceinline__ void sphere_centres(const ArmConst<R>& A, const R* sn
     r00 = a0 * c + a1 * s; r01 = a1 * c - a0 * s; r02 = a2;
     r10 = b0 * c + b1 * s; r11 = b1 * c - b0 * s; r12 = b2;
     r20 = c0 * c + c1 * s; r21 = c1 * c - c0 * s; r22 = c2;
-    // spheres of link i+1 (sorted by link on the host)
-    while (k < A.nsph && A.sph_link[k] == i + 1) {
+    for (int k = A.sph_first[i] + part; k < A.sph_first[i + 1]; k += nparts) {
       const R lx = A.sphx[k], ly = A.sphy[k], lz = A.sphz[k];
       fn(k, ox + r00 * lx + r01 * ly + r02 * lz, oy + r10 * lx + r11 * ly + r12 * lz,
          oz + r20 * lx + r21 * ly + r22 * lz);
-      ++k;
     }
   }
 }

@@ -1,11 +1,10 @@
 // fn_knn.hip -- Parents(T, x, M) of Algorithm 1: brute-force k nearest tree
 // nodes by Euclidean distance in the 14-D state space (Sec. IV-E).
 //
-// Stage 1 (knn_scan): one wavefront per (64 queries, node chunk).  Each lane
-// holds one query in VGPRs; the chunk's nodes are wave-uniform and arrive
-// through the scalar cache as float4 rows of the SoA tree, so every
-// distance costs 14 subtractions and 14 FMAs with SGPR operands.  Each lane
-// keeps its chunk's k+1 smallest FP32 keys (d^2, index).
+// Stage 1 (knn_scan): one wavefront per (4 queries, node chunk); lanes run
+// over the chunk's nodes with coalesced loads of the SoA tree rows, every
+// distance costs 14 subtractions and 14 FMAs, and each query keeps its
+// chunk's k+1 smallest FP32 keys (d^2, index) spread over lanes 0..k.
 // Stage 2 (knn_merge): one wavefront per query merges the chunk lists.  The
 // FP32 k-th key bounds a band that provably holds the exact top-k; every
 // candidate in the band is re-ranked with the FP64 distance summed in the
@@ -19,75 +18,120 @@
 namespace fn {
 
 constexpr int KNN_TARGET_WAVES = 4096;
-constexpr float KNN_BAND = 1e-5f;  // >> FP32 relative error of a 14-term sum of squares
+constexpr float KNN_BAND = 1e-6f;  // slack for rounding the band itself
+constexpr float KNN_EPS = 4e-6f;   // |d32 - d| <= KNN_EPS (|x| + |y|)^2 (twice the FP32 bound)
 
 __device__ __forceinline__ bool key_less(float d, int i, float d2, int i2) {
   return d < d2 || (d == d2 && (unsigned)i < (unsigned)i2);
 }
 
-template <int K1>
+// lane r takes lane r-1's value (DPP wave shift; lane 0 gets 0)
+__device__ __forceinline__ float wave_shr1(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x138,
+                                                            0xf, 0xf, true));
+}
+__device__ __forceinline__ int wave_shr1(int v) {
+  return __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true);
+}
+
+// One wavefront per (QG queries, node chunk).  Lanes run over 64 nodes at
+// a time (coalesced loads of the SoA rows).  The FP32 screening distance is
+// |x|^2 + |y|^2 - 2 x.y (14 FMAs per pair, |y|^2 shared by the QG queries);
+// its absolute error is below 4e-6 (|x| + |y|)^2, a bound the merge carries
+// into the band it re-ranks exactly.  Every query's k+1 best keys
+// (d^2, index) live distributed over lanes 0..K1-1; the K1-th is a
+// wave-uniform threshold, so a node costs a ballot unless it beats it.
+template <int K1, int QG>
 __global__ __launch_bounds__(256) void knn_scan(const float* __restrict__ tree, int64_t ld,
                                                 int n_nodes, const float* __restrict__ qs, int B,
-                                                int n_qtiles, int n_split, int chunk,
+                                                int n_groups, int n_split, int chunk,
                                                 float* __restrict__ out_d,
-                                                int32_t* __restrict__ out_i) {
+                                                int32_t* __restrict__ out_i,
+                                                float* __restrict__ out_y2) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int pair = blockIdx.x * 4 + wave;
-  if (pair >= n_qtiles * n_split) return;
-  const int qt = pair / n_split, ch = pair - qt * n_split;
+  if (pair >= n_groups * n_split) return;
+  // the wavefronts of a block share a node chunk (L1 reuse), each with its
+  // own query group
+  const int ch = pair / n_groups, grp = pair - ch * n_groups;
   const int lane = threadIdx.x & 63;
-  const int b = qt * 64 + lane;
-  const int bq = b < B ? b : B - 1;
-  float x[FN_STATE];
+  float xm2[QG][FN_STATE], xx[QG];
 #pragma unroll
-  for (int c = 0; c < FN_STATE; ++c) x[c] = qs[(size_t)bq * FN_STATE + c];
-  float ld_d[K1];
-  int ld_i[K1];
-#pragma unroll
-  for (int r = 0; r < K1; ++r) {
-    ld_d[r] = INFINITY;
-    ld_i[r] = -1;
-  }
-  const int n_pad = (n_nodes + 3) & ~3;
-  const int n0 = ch * chunk;
-  const int n1 = min(n0 + chunk, n_pad);
-  for (int n = n0; n < n1; n += 4) {
-    float d[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int q = 0; q < QG; ++q) {
+    const int b = min(grp * QG + q, B - 1);
+    float s2 = 0.f;
 #pragma unroll
     for (int c = 0; c < FN_STATE; ++c) {
-      const float4 y = *reinterpret_cast<const float4*>(tree + (size_t)c * ld + n);
-      float t;
-      t = x[c] - y.x; d[0] = fmaf(t, t, d[0]);
-      t = x[c] - y.y; d[1] = fmaf(t, t, d[1]);
-      t = x[c] - y.z; d[2] = fmaf(t, t, d[2]);
-      t = x[c] - y.w; d[3] = fmaf(t, t, d[3]);
+      const float v = qs[(size_t)b * FN_STATE + c];
+      xm2[q][c] = -2.f * v;
+      s2 = fmaf(v, v, s2);
     }
+    xx[q] = s2;
+  }
+  float Ld[QG];
+  int Li[QG];
+  float th_d[QG];
+  int th_i[QG];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int idx = n + u;
-      const float dd = d[u];
-      if (idx < n_nodes && key_less(dd, idx, ld_d[K1 - 1], ld_i[K1 - 1])) {
-        // insert into the sorted list (entries shift up from the back)
+  for (int q = 0; q < QG; ++q) {
+    Ld[q] = INFINITY;
+    Li[q] = -1;
+    th_d[q] = INFINITY;
+    th_i[q] = -1;
+  }
+  float y2max = 0.f;
+  const int n0 = ch * chunk;
+  const int n1 = min(n0 + chunk, n_nodes);
+  for (int nb = n0; nb < n1; nb += WAVE) {
+    const int node = nb + lane;
+    const bool valid = node < n1;
+    const int nc = valid ? node : n1 - 1;
+    float y[FN_STATE];
+    float yy = 0.f;
 #pragma unroll
-        for (int r = K1 - 1; r >= 1; --r) {
-          const bool shift = key_less(dd, idx, ld_d[r - 1], ld_i[r - 1]);
-          const bool here = key_less(dd, idx, ld_d[r], ld_i[r]);
-          ld_d[r] = shift ? ld_d[r - 1] : (here ? dd : ld_d[r]);
-          ld_i[r] = shift ? ld_i[r - 1] : (here ? idx : ld_i[r]);
-        }
-        if (key_less(dd, idx, ld_d[0], ld_i[0])) {
-          ld_d[0] = dd;
-          ld_i[0] = idx;
-        }
+    for (int c = 0; c < FN_STATE; ++c) {
+      y[c] = tree[(size_t)c * ld + nc];
+      yy = fmaf(y[c], y[c], yy);
+    }
+    y2max = fmaxf(y2max, yy);
+#pragma unroll
+    for (int q = 0; q < QG; ++q) {
+      float d = yy + xx[q];
+#pragma unroll
+      for (int c = 0; c < FN_STATE; ++c) d = fmaf(xm2[q][c], y[c], d);
+      d = valid ? d : INFINITY;
+      // nodes arrive in increasing index, so an equal distance never beats
+      // the threshold entry
+      uint64_t mask = __ballot(d < th_d[q]);
+      while (mask) {
+        const int src = __ffsll((long long)mask) - 1;
+        mask &= mask - 1;
+        const float dd = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, d), src));
+        const int ii = nb + src;
+        if (!key_less(dd, ii, th_d[q], th_i[q])) continue;
+        // insert into the distributed sorted list (lane r holds entry r)
+        const float pd = wave_shr1(Ld[q]);
+        const int pi = wave_shr1(Li[q]);
+        const bool lt_here = key_less(dd, ii, Ld[q], Li[q]);
+        const bool lt_prev = lane > 0 && key_less(dd, ii, pd, pi);
+        Ld[q] = lane >= K1 ? INFINITY : lt_prev ? pd : lt_here ? dd : Ld[q];
+        Li[q] = lane >= K1 ? -1 : lt_prev ? pi : lt_here ? ii : Li[q];
+        th_d[q] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, Ld[q]), K1 - 1));
+        th_i[q] = __builtin_amdgcn_readlane(Li[q], K1 - 1);
       }
     }
   }
-  if (b < B) {
-    const size_t base = ((size_t)b * n_split + ch) * K1;
+  y2max = wave_max(y2max);
 #pragma unroll
-    for (int r = 0; r < K1; ++r) {
-      out_d[base + r] = ld_d[r];
-      out_i[base + r] = ld_i[r];
+  for (int q = 0; q < QG; ++q) {
+    const int b = grp * QG + q;
+    if (b < B) {
+      if (lane < K1) {
+        const size_t base = ((size_t)b * n_split + ch) * K1;
+        out_d[base + lane] = Ld[q];
+        out_i[base + lane] = Li[q];
+      }
+      if (lane == 0) out_y2[(size_t)b * n_split + ch] = y2max;
     }
   }
 }
@@ -135,6 +179,7 @@ __global__ __launch_bounds__(64) void knn_merge(const float* __restrict__ tree, 
                                                 int k, int n_split,
                                                 const float* __restrict__ in_d,
                                                 const int32_t* __restrict__ in_i,
+                                                const float* __restrict__ in_y2,
                                                 int32_t* __restrict__ out_idx,
                                                 float* __restrict__ out_d2) {
   const int b = blockIdx.x;
@@ -176,7 +221,18 @@ __global__ __launch_bounds__(64) void knn_merge(const float* __restrict__ tree, 
     th_d = bd;
     th_i = bi;
   }
-  const float band = th_d < 0.f ? INFINITY : th_d * (1.0f + KNN_BAND) + 1e-30f;
+  // absolute error bound of the FP32 screening distances of this query:
+  // 4e-6 (|x| + max |y|)^2, max over every chunk (the whole tree)
+  float y2 = 0.f;
+  for (int c2 = lane; c2 < n_split; c2 += 64) y2 = fmaxf(y2, in_y2[(size_t)b * n_split + c2]);
+  y2 = wave_max(y2);
+  double xn = 0.0;
+#pragma unroll
+  for (int c = 0; c < FN_STATE; ++c) xn += x[c] * x[c];
+  const float rad = (float)sqrt(xn) + sqrtf(y2);
+  const float eps = KNN_EPS * rad * rad;
+  // every exact top-k node has a screening key within th + 2 eps
+  const float band = th_i < 0 ? INFINITY : th_d + 2.f * eps + fabsf(th_d) * KNN_BAND + 1e-30f;
 
   // (b) a chunk whose (k+1)-th entry is inside the band may have cut near ties
   int over = 0;
@@ -266,27 +322,30 @@ __global__ __launch_bounds__(64) void knn_merge(const float* __restrict__ tree, 
   }
 }
 
+constexpr int KNN_QG = 4;  // queries per scan wavefront
+
 template <int K1>
 static void launch_knn(fn_ctx* c, const float* tree, int64_t ld, int n_nodes, const float* qs,
                        int B, int k, int32_t* out_idx, float* out_d2, hipStream_t s) {
-  const int n_qtiles = (B + 63) / 64;
-  const int n_pad = (n_nodes + 3) & ~3;
-  int n_split = (KNN_TARGET_WAVES + n_qtiles - 1) / n_qtiles;
+  const int n_groups = (B + KNN_QG - 1) / KNN_QG;
+  // enough wavefronts to fill the chip, chunks of at least 512 nodes
+  int n_split = (KNN_TARGET_WAVES + n_groups - 1) / n_groups;
   n_split = min(n_split, KNN_MAX_SPLIT);
-  n_split = max(1, min(n_split, (n_pad + 63) / 64));
-  int chunk = (n_pad + n_split - 1) / n_split;
-  chunk = max(4, (chunk + 3) & ~3);  // an empty tree still gets one (empty) chunk
-  n_split = max(1, (n_pad + chunk - 1) / chunk);
-  const int pairs = n_qtiles * n_split;
-  hipLaunchKernelGGL(knn_scan<K1>, dim3((pairs + 3) / 4), dim3(256), 0, s, tree, ld, n_nodes, qs,
-                     B, n_qtiles, n_split, chunk, c->knn_d, c->knn_i);
+  n_split = max(1, min(n_split, n_nodes / 512));
+  int chunk = (n_nodes + n_split - 1) / n_split;
+  chunk = max(WAVE, (chunk + WAVE - 1) / WAVE * WAVE);
+  n_split = max(1, (n_nodes + chunk - 1) / chunk);
+  const int pairs = n_groups * n_split;
+  hipLaunchKernelGGL((knn_scan<K1, KNN_QG>), dim3((pairs + 3) / 4), dim3(256), 0, s, tree, ld,
+                     n_nodes, qs, B, n_groups, n_split, chunk, c->knn_d, c->knn_i, c->knn_y);
   hipLaunchKernelGGL(knn_merge<K1>, dim3(B), dim3(64), 0, s, tree, ld, n_nodes, qs, k, n_split,
-                     c->knn_d, c->knn_i, out_idx, out_d2);
+                     c->knn_d, c->knn_i, c->knn_y, out_idx, out_d2);
 }
 
 size_t knn_scratch_entries(int max_batch, int max_k) {
-  const size_t qt = (size_t)(max_batch + 63) / 64;
-  return (size_t)64 * (KNN_TARGET_WAVES + qt) * knn_k1(max_k);
+  // B * n_split <= QG * n_groups * ceil(TARGET / n_groups) <= QG * (TARGET + n_groups)
+  const size_t groups = (size_t)(max_batch + KNN_QG - 1) / KNN_QG;
+  return (size_t)KNN_QG * (KNN_TARGET_WAVES + groups) * (max_k > 0 ? knn_k1(max_k) : 1);
 }
 
 }  // namespace fn
