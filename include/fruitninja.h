@@ -65,9 +65,11 @@ enum {
   FN_S_POS = 4,         /* joint position limit crossed along the edge */
   FN_S_COLL = 8,        /* arm sphere closer than the margin to an obstacle */
   FN_S_RECHECK64 = 16,  /* informational: a ratio within 1e-3 of 1 was decided in FP64 */
-  FN_S_WIN_HIT = 32,    /* informational: windowed search certified inside its window */
-  FN_S_WIN_MISS = 64,   /* informational: window missed; the exact scan finished it */
+  FN_S_WIN_HIT = 32,    /* informational: the result lies in the predicted window */
+  FN_S_WIN_MISS = 64,   /* informational: it does not; the exact scan found it elsewhere */
   FN_S_BAD_INPUT = 128, /* a non-finite state or duration */
+  FN_S_WIN_BELOW = 256, /* informational: a slot below the window passed the endpoint screen
+                           and was evaluated in full */
   FN_S_NO_PARENT = 512  /* padded parent index (-1): no edge */
 };
 #define FN_S_DECISION (FN_S_NONE | FN_S_VEL | FN_S_POS | FN_S_COLL | FN_S_BAD_INPUT | FN_S_NO_PARENT)
@@ -83,8 +85,8 @@ enum {
 };
 
 /* Arm description (host, FP64).  Modified DH: joint i's frame is
- * Rx(alpha[i]) Tx(a[i]) Rz(q_i) Tz(d[i]) relative to frame i-1; every alpha
- * must be 0 or +-pi/2 (within 1e-9).  Link i's mass m, COM rc (frame i) and
+ * Rx(alpha[i]) Tx(a[i]) Rz(q_i) Tz(d[i]) relative to frame i-1.  Link i's
+ * mass m, COM rc (frame i) and
  * diagonal inertia about the COM (frame i); reflected rotor inertia Im and
  * the friction parameters psi1..3 of Eq. (5); joint limits, velocity limit
  * qdmax with braking deceleration acc (velocity taper
@@ -118,9 +120,10 @@ typedef struct fn_ctx fn_ctx;
 
 /* Creates a context on the current HIP device: copies the arm, derives its
  * FP32 and FP64 constant blocks on the device, and allocates scratch for the
- * caps.  Returns FN_OK and *out, or FN_E_ARG / FN_E_UNSUPPORTED (n != 7, a
- * twist that is not 0 or +-pi/2, more than FN_MAX_SPHERES spheres) /
- * FN_E_NOMEM / FN_E_HIP. */
+ * caps.  Twists of 0 or +-pi/2 select kernels with the rotations folded in
+ * at compile time; other twists use a general kernel.  Returns FN_OK and
+ * *out, or FN_E_ARG / FN_E_UNSUPPORTED (n != 7, more than FN_MAX_SPHERES
+ * spheres) / FN_E_NOMEM / FN_E_HIP. */
 int fn_create(const fn_arm_desc* arm /*host*/, const fn_caps* caps /*host*/, fn_ctx** out);
 /* Frees the context (synchronises the device first). NULL is a no-op. */
 void fn_destroy(fn_ctx* ctx);
@@ -230,6 +233,79 @@ typedef struct {
 int risk_score(fn_ctx* ctx, const fn_risk* w /*host*/, const float* T, const float* v_rel,
                const float* nu, const float* vz0, const float* t_fall, int32_t n, float* out_J,
                void* stream);
+
+
+/* ------------------------------------------------------------------ */
+/* Learned T-window surrogate.  A 4-layer MLP 28 -> 256 -> 256 -> 256  */
+/* -> 2 (SiLU after the first three layers) maps an edge's boundary    */
+/* states (the inputs of Eq. (6)) to (standardised log T*, feasibility */
+/* logit), where T* is the result of Def. 7 on the grid.  BF16 weights  */
+/* and activations on MFMA with FP32 accumulation; FP32 master weights  */
+/* and Adam.  Its prediction only narrows edge_time_batch's work        */
+/* (FN_SEARCH_WINDOW); results stay exact.                             */
+/* ------------------------------------------------------------------ */
+typedef struct fn_mlp fn_mlp;
+
+/* Training configuration: epochs over the data, minibatch rows (multiple
+ * of 8, <= 8192), Adam learning rate (cosine decay to 0 over the run when
+ * cosine != 0), betas, eps, shuffling seed, and the T grid the slot labels
+ * index (device [n_t]). */
+typedef struct {
+  int32_t epochs, batch;
+  float lr, beta1, beta2, eps;
+  int32_t cosine;
+  uint64_t seed;
+  const float* grid;
+  int32_t n_t;
+} fn_train_cfg;
+
+/* Creates a network on the context's device with weights drawn
+ * U(-1/sqrt(fan_in), 1/sqrt(fan_in)) from SplitMix64(seed); Adam state 0. */
+int fn_mlp_create(fn_ctx* ctx, uint64_t seed, fn_mlp** out);
+void fn_mlp_destroy(fn_mlp* mlp);
+/* Number of parameters in the logical layout W1[256][28], b1[256],
+ * W2[256][256], b2, W3[256][256], b3, W4[2][256], b4[2] (row-major). */
+int fn_mlp_param_count(void);
+/* Host copy in/out of the FP32 parameters (logical layout; set resets the
+ * Adam state).  FN_E_SHAPE if count differs from fn_mlp_param_count(). */
+int fn_mlp_set_params(fn_mlp* mlp, const float* host, int64_t count);
+int fn_mlp_get_params(const fn_mlp* mlp, float* host, int64_t count);
+/* Checkpoint: parameters, Adam moments and step count (binary file). */
+int fn_mlp_save(const fn_mlp* mlp, const char* path);
+int fn_mlp_load(fn_ctx* ctx, const char* path, fn_mlp** out);
+
+/* Surrogate inputs of every edge: X[e] = (state of tree node nbr[e], state
+ * of candidate e / k) as 28 floats (zeros for a padded parent).
+ * Arguments as edge_time_batch; X: device [B*k][28]. */
+int edge_features(fn_ctx* ctx, const float* tree, int64_t ld, int32_t n_nodes, const float* cand,
+                  int32_t B, const int32_t* nbr, int32_t k, float* X, void* stream);
+
+/* Trains on N rows: X device [N][28] raw edge states; y_j device [N] the
+ * exact search's slot index (-1 = no feasible slot).  Inputs are
+ * normalised inside ((q - centre)/half-range, qd/qdmax); the regression
+ * target is (log T_j - mu)/s mapping [log T_0, log T_last] to [-1, 1].
+ * Loss per minibatch: mean squared error of output 0 over rows with a slot
+ * + binary cross-entropy with logits of output 1.  out_epoch_loss: device
+ * [epochs][3] (mean total, squared-error and cross-entropy terms) or NULL.
+ * Each epoch visits floor(N / batch) minibatches of a permutation
+ * i -> (a i + c) mod N drawn from the seed. */
+int surrogate_train(fn_ctx* ctx, fn_mlp* mlp, const float* X, const int16_t* y_j, int64_t N,
+                    const fn_train_cfg* cfg, float* out_epoch_loss, void* stream);
+
+/* Loss and gradient of one batch without updating (N <= 8192, multiple of
+ * 8): out_grad device [fn_mlp_param_count()] (logical layout), out_loss3
+ * device [3] or NULL. */
+int surrogate_grad(fn_ctx* ctx, fn_mlp* mlp, const float* X, const int16_t* y_j, int32_t N,
+                   const float* grid, int32_t n_t, float* out_grad, float* out_loss3,
+                   void* stream);
+
+/* Inference on N rows: out device [N][2] = (standardised log T*, logit) or
+ * NULL; out_win_lo device [N] or NULL: lowest slot of the window, i.e. the
+ * grid slot nearest the predicted T* minus `half` (clamped at 0), or n_t
+ * (predicted infeasible) when the logit is below logit_min. */
+int surrogate_infer(fn_ctx* ctx, const fn_mlp* mlp, const float* X, int64_t N, const float* grid,
+                    int32_t n_t, int32_t half, float logit_min, float* out, int16_t* out_win_lo,
+                    void* stream);
 
 #ifdef __cplusplus
 }

@@ -19,8 +19,8 @@
 //  WINDOW -- the surrogate's window [lo, lo + 2h]: slots below it are
 //            screened (the certificate), the window is evaluated in full, the
 //            slots above it are screened only if the window holds no
-//            feasible slot.  "Hit" = nothing below the window needed a full
-//            evaluation and the result lies in the window.
+//            feasible slot.  "Hit" = the result lies in the window (or the
+//            network predicted no feasible slot and there is none).
 //
 // Every FP32 ratio within BAND of 1 that a decision rests on sends the edge
 // to the FP64 stage (edge_recheck), which resumes it from that slot.
@@ -399,8 +399,10 @@ __global__ __launch_bounds__(256) void edge_time_kernel(EdgeArgs a,
   float m = fminf(marg, wave_min(mc));
   int winbits = 0;
   if (a.mode == FN_SEARCH_WINDOW) {
-    const bool hit = !below_full && ((jstar >= wlo && jstar <= whi) || (jstar < 0 && wlo > jmax));
-    winbits = hit ? FN_S_WIN_HIT : FN_S_WIN_MISS;
+    // hit: the result lies in the predicted window (or none was predicted
+    // and none exists); BELOW: a slot under the window needed a full pass
+    const bool hit = (jstar >= 0 && jstar >= wlo && jstar <= whi) || (jstar < 0 && wlo > jmax);
+    winbits = (hit ? FN_S_WIN_HIT : FN_S_WIN_MISS) | (below_full ? FN_S_WIN_BELOW : 0);
   }
   if (jstar < 0) {
     // ratio of the last slot: its full value, else its screened endpoint value
@@ -486,8 +488,8 @@ __global__ __launch_bounds__(64) void edge_recheck_kernel(EdgeArgs a,
       const int wlo = min(max((int)a.win_lo[e], 0), jmax + 1);
       const int whi = min(wlo + 2 * a.win_half, jmax);
       const bool below = (q.phase & PH_BELOW_FULL) != 0;
-      const bool hit = !below && ((jstar >= wlo && jstar <= whi) || (jstar < 0 && wlo > jmax));
-      winbits = hit ? FN_S_WIN_HIT : FN_S_WIN_MISS;
+      const bool hit = (jstar >= 0 && jstar >= wlo && jstar <= whi) || (jstar < 0 && wlo > jmax);
+      winbits = (hit ? FN_S_WIN_HIT : FN_S_WIN_MISS) | (below ? FN_S_WIN_BELOW : 0);
     }
     if (jstar < 0) {
       write_out(a, e, -1, FN_S_NONE | FN_S_RECHECK64 | winbits, marg, last, 0, 0, 0, work);

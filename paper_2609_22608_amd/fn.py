@@ -18,8 +18,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfruitninja.so")
 
 FN_OK, FN_E_ARG, FN_E_SHAPE, FN_E_UNSUPPORTED, FN_E_HIP, FN_E_NOMEM, FN_E_STATE = 0, -1, -2, -3, -4, -5, -6
-S_NONE, S_VEL, S_POS, S_COLL, S_RECHECK64, S_WIN_HIT, S_WIN_MISS, S_BAD_INPUT, S_NO_PARENT = \
-    1, 2, 4, 8, 16, 32, 64, 128, 512
+S_NONE, S_VEL, S_POS, S_COLL, S_RECHECK64, S_WIN_HIT, S_WIN_MISS, S_BAD_INPUT, S_WIN_BELOW, \
+    S_NO_PARENT = 1, 2, 4, 8, 16, 32, 64, 128, 256, 512
 S_DECISION = S_NONE | S_VEL | S_POS | S_COLL | S_BAD_INPUT | S_NO_PARENT
 T_RIGID, T_ARMATURE, T_FRICTION, T_GRAVITY, T_ALL = 1, 2, 4, 8, 15
 SEARCH_PLAIN, SEARCH_SCREEN, SEARCH_WINDOW = 0, 1, 2
@@ -65,6 +65,13 @@ class EdgeOut(C.Structure):
                 ("rho4", C.c_void_p), ("work", C.c_void_p)]
 
 
+class TrainCfg(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float),
+                ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+                ("cosine", C.c_int32), ("seed", C.c_uint64), ("grid", C.c_void_p),
+                ("n_t", C.c_int32)]
+
+
 class Risk(C.Structure):
     _fields_ = [("gz", C.c_double), ("sigma_mode", C.c_int32), ("sp", C.c_double),
                 ("sv", C.c_double), ("sa", C.c_double), ("s0", C.c_double), ("s1", C.c_double),
@@ -96,6 +103,17 @@ def lib():
                                           C.POINTER(Obstacles), C.POINTER(EdgeOut), vp]
             L.edge_check.argtypes = [vp, vp, vp, vp, i64, i32, C.POINTER(Obstacles), vp, vp, vp, vp]
             L.risk_score.argtypes = [vp, C.POINTER(Risk), vp, vp, vp, vp, vp, i32, vp, vp]
+            L.fn_mlp_create.argtypes = [vp, C.c_uint64, C.POINTER(vp)]
+            L.fn_mlp_destroy.argtypes = [vp]
+            L.fn_mlp_param_count.restype = C.c_int
+            L.fn_mlp_set_params.argtypes = [vp, vp, i64]
+            L.fn_mlp_get_params.argtypes = [vp, vp, i64]
+            L.fn_mlp_save.argtypes = [vp, C.c_char_p]
+            L.fn_mlp_load.argtypes = [vp, C.c_char_p, C.POINTER(vp)]
+            L.edge_features.argtypes = [vp, vp, i64, i32, vp, i32, vp, i32, vp, vp]
+            L.surrogate_train.argtypes = [vp, vp, vp, vp, i64, C.POINTER(TrainCfg), vp, vp]
+            L.surrogate_grad.argtypes = [vp, vp, vp, vp, i32, vp, i32, vp, vp, vp]
+            L.surrogate_infer.argtypes = [vp, vp, vp, i64, vp, i32, i32, C.c_float, vp, vp, vp]
             _lib = L
     return _lib
 
@@ -240,6 +258,91 @@ class Context:
         _check(lib().risk_score(self.h, C.byref(w), _ptr(T), _ptr(v_rel), _ptr(nu), _ptr(vz0),
                                 _ptr(t_fall), n, _ptr(out), _stream()), "risk_score")
         return out
+
+
+class Surrogate:
+    """An fn_mlp (the learned T-window network) bound to a Context."""
+
+    def __init__(self, ctx: Context, seed: int = 0, handle=None):
+        self.ctx = ctx
+        if handle is None:
+            handle = C.c_void_p()
+            _check(lib().fn_mlp_create(ctx.h, C.c_uint64(seed), C.byref(handle)), "fn_mlp_create")
+        self.h = handle
+
+    @classmethod
+    def load(cls, ctx: Context, path: str):
+        h = C.c_void_p()
+        _check(lib().fn_mlp_load(ctx.h, path.encode(), C.byref(h)), "fn_mlp_load")
+        return cls(ctx, handle=h)
+
+    def save(self, path: str):
+        torch.cuda.synchronize()
+        _check(lib().fn_mlp_save(self.h, path.encode()), "fn_mlp_save")
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().fn_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def param_count() -> int:
+        return lib().fn_mlp_param_count()
+
+    def set_params(self, flat):
+        a = np.ascontiguousarray(flat, np.float32)
+        _check(lib().fn_mlp_set_params(self.h, a.ctypes.data_as(C.c_void_p), a.size),
+               "fn_mlp_set_params")
+
+    def get_params(self):
+        torch.cuda.synchronize()
+        a = np.zeros(self.param_count(), np.float32)
+        _check(lib().fn_mlp_get_params(self.h, a.ctypes.data_as(C.c_void_p), a.size),
+               "fn_mlp_get_params")
+        return a
+
+    def grad(self, X, y_j, grid):
+        g = torch.empty(self.param_count(), dtype=torch.float32, device=X.device)
+        l3 = torch.empty(3, dtype=torch.float32, device=X.device)
+        _check(lib().surrogate_grad(self.ctx.h, self.h, _ptr(X), _ptr(y_j), X.shape[0],
+                                    _ptr(grid), grid.shape[0], _ptr(g), _ptr(l3), _stream()),
+               "surrogate_grad")
+        return g, l3
+
+    def train(self, X, y_j, grid, epochs=20, batch=4096, lr=1e-3, beta1=0.9, beta2=0.999,
+              eps=1e-8, cosine=True, seed=0):
+        cfg = TrainCfg(int(epochs), int(batch), float(lr), float(beta1), float(beta2), float(eps),
+                       int(bool(cosine)), int(seed), grid.data_ptr(), grid.shape[0])
+        losses = torch.zeros((epochs, 3), dtype=torch.float32, device=X.device)
+        _check(lib().surrogate_train(self.ctx.h, self.h, _ptr(X), _ptr(y_j), X.shape[0],
+                                     C.byref(cfg), _ptr(losses), _stream()), "surrogate_train")
+        return losses
+
+    def infer(self, X, grid, half=4, logit_min=0.0, want_out=True, win_lo=None, out=None):
+        N = X.shape[0]
+        if out is None and want_out:
+            out = torch.empty((N, 2), dtype=torch.float32, device=X.device)
+        if win_lo is None:
+            win_lo = torch.empty(N, dtype=torch.int16, device=X.device)
+        _check(lib().surrogate_infer(self.ctx.h, self.h, _ptr(X), N, _ptr(grid), grid.shape[0],
+                                     int(half), float(logit_min), _ptr(out), _ptr(win_lo),
+                                     _stream()), "surrogate_infer")
+        return out, win_lo
+
+
+def edge_features(ctx: Context, tree, ld, n_nodes, cand, nbr, out=None):
+    B, k = nbr.shape
+    if out is None:
+        out = torch.empty((B * k, 28), dtype=torch.float32, device=cand.device)
+    _check(lib().edge_features(ctx.h, _ptr(tree), ld, n_nodes, _ptr(cand), B, _ptr(nbr), k,
+                               _ptr(out), _stream()), "edge_features")
+    return out
 
 
 PAPER_RISK = dict(wv=0.20, vtarget=9.0, wp=8.0, wr=8.0, wx=1.0, r=0.09, nu0=0.90, lam=1.2)
