@@ -35,7 +35,12 @@ def parse():
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--seed", type=int, default=101)
-    p.add_argument("--modes", default="plain,screen")
+    p.add_argument("--modes", default="plain,screen,window")
+    p.add_argument("--surrogate", default=None, help="checkpoint to load instead of training")
+    p.add_argument("--train-batches", type=int, default=32,
+                   help="one-iteration batches labelled for the surrogate (32 x 32,768 edges)")
+    p.add_argument("--train-epochs", type=int, default=8)
+    p.add_argument("--half", type=int, default=4)
     p.add_argument("--cpu-sample", type=int, default=512, help="queries in the CPU oracle sample")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--profile", action="store_true", help="few steps, no CPU leg (under rocprofv3)")
@@ -67,18 +72,34 @@ def main():
                margin=torch.empty(E, dtype=torch.float32, device="cuda"),
                rho=None, work=torch.empty(E, dtype=torch.int32, device="cuda"))
     stream = torch.cuda.current_stream()
-    modes = {"plain": fn.SEARCH_PLAIN, "screen": fn.SEARCH_SCREEN}
+    modes = {"plain": fn.SEARCH_PLAIN, "screen": fn.SEARCH_SCREEN, "window": fn.SEARCH_WINDOW}
+    wanted = args.modes.split(",")
+    surrogate_info = None
+    net = None
+    if "window" in wanted:
+        net, surrogate_info = surrogate(args, ctx, wl["arm"], sh, fn, W, torch)
+    feats = torch.empty((E, 28), dtype=torch.float32, device="cuda")
+    win = torch.empty(E, dtype=torch.int16, device="cuda")
     forms = {}
-    for name in args.modes.split(","):
+    for name in wanted:
         mode = modes[name]
 
         def step():
             ctx.plan_knn(tree, ld, n, cand, sh.k, out_idx=idx, want_d2=False)
             ev[0].record(stream)
-            ctx.edge_time_batch(tree, ld, n, cand, idx, grid, sh.samples, obs, mode=mode, out=out)
+            if mode == fn.SEARCH_WINDOW:
+                fn.edge_features(ctx, tree, ld, n, cand, idx, out=feats)
+                net.infer(feats, grid, half=args.half, want_out=False, win_lo=win)
+                ev[2].record(stream)
+                ctx.edge_time_batch(tree, ld, n, cand, idx, grid, sh.samples, obs, mode=mode,
+                                    win_lo=win, win_half=args.half, out=out)
+            else:
+                ev[2].record(stream)
+                ctx.edge_time_batch(tree, ld, n, cand, idx, grid, sh.samples, obs, mode=mode,
+                                    out=out)
             ev[1].record(stream)
 
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
         for _ in range(args.warmup):
             step()
         torch.cuda.synchronize()
@@ -90,22 +111,36 @@ def main():
         t0.record(stream)
         for _ in range(args.steps):
             step()
-            # events of the edge call of this step (read after the loop)
-            edge_ms.append((ev[0], ev[1]))
-            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            edge_ms.append(ev)
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
         t1.record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - w0
         ms = t0.elapsed_time(t1) / args.steps
-        e_ms = float(np.mean([a.elapsed_time(b) for a, b in edge_ms]))
+        e_ms = float(np.mean([a[2].elapsed_time(a[1]) for a in edge_ms]))
         work = int(out["work"].sum().item())
         flop = work * F_EVAL
-        forms[name] = dict(edges_per_s=E / (ms * 1e-3), ms_per_step=ms, edge_call_ms=e_ms,
-                           evaluations=work, wall_s=wall,
-                           fp32_tflops=flop / (e_ms * 1e-3) / 1e12,
-                           recheck64=int(((out["status"].cpu().numpy().astype(np.uint16)
-                                           & fn.S_RECHECK64) > 0).sum()))
+        st = out["status"].cpu().numpy().astype(np.uint16)
+        jj = out["j"].cpu().numpy()
+        f = dict(edges_per_s=E / (ms * 1e-3), ms_per_step=ms, edge_search_ms=e_ms,
+                 evaluations=work, wall_s=wall,
+                 fp32_tflops=flop / (e_ms * 1e-3) / 1e12,
+                 recheck64=int(((st & fn.S_RECHECK64) > 0).sum()))
+        if mode == fn.SEARCH_WINDOW:
+            pre = float(np.mean([a[0].elapsed_time(a[2]) for a in edge_ms]))
+            feas = jj >= 0
+            miss = (st & fn.S_WIN_MISS) > 0
+            f.update(features_infer_ms=pre,
+                     miss_rate_feasible=float(miss[feas].mean()) if feas.any() else None,
+                     miss_rate_all=float(miss.mean()),
+                     below_window_rate=float(((st & fn.S_WIN_BELOW) > 0).mean()))
+        forms[name] = f
     best = min(forms, key=lambda k: forms[k]["ms_per_step"])
+    speed = {}
+    if "window" in forms and "plain" in forms:
+        speed["window_vs_plain"] = forms["window"]["edges_per_s"] / forms["plain"]["edges_per_s"]
+    if "window" in forms and "screen" in forms:
+        speed["window_vs_screen"] = forms["window"]["edges_per_s"] / forms["screen"]["edges_per_s"]
     bf = forms[best]
     res = {
         "metric": METRIC,
@@ -124,16 +159,53 @@ def main():
                                "(half goal), k=8, 64 T x 32 samples, 5 obstacles, 7-DOF arm",
                    "search": best, "edges": E, "seed": args.seed},
         "forms": forms,
+        "speedup": speed,
+        "surrogate": surrogate_info,
         "roofline": {"bound": "alu", "kernel": "edge_time_kernel",
-                     "achieved": bf["fp32_tflops"], "peak": PEAK_FP32 / 1e12,
+                     "form": best, "achieved": bf["fp32_tflops"], "peak": PEAK_FP32 / 1e12,
                      "unit": "TFLOP/s", "frac": bf["fp32_tflops"] * 1e12 / PEAK_FP32,
                      "traffic": None,
                      "flop_per_eval": F_EVAL, "evaluations": bf["evaluations"]},
     }
+    if args.profile:
+        # a plain device copy of known size (256 MiB) for calibrating the
+        # HBM traffic counters
+        a = torch.empty(64 << 20, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample)
     print(json.dumps(res), flush=True)
     ctx.close()
+
+
+def surrogate(args, ctx, arm, sh, fn, W, torch):
+    """The T-window network: loaded from a checkpoint, or trained here on
+    one-iteration batches with seeds disjoint from the benchmark's."""
+    if args.surrogate and os.path.exists(args.surrogate):
+        return fn.Surrogate.load(ctx, args.surrogate), {"checkpoint": args.surrogate}
+    t0 = time.perf_counter()
+    grid = fn.dev(W.t_grid(sh.n_t, sh.t_min, sh.t_max))
+    Xs, ys = [], []
+    for seed in range(1000, 1000 + args.train_batches):
+        w = W.make_workload(sh, seed=seed, arm=arm)
+        tree, ld, n = fn.tree_soa(w["tree_x"])
+        cand = fn.dev(w["cand"]["x"])
+        idx, _ = ctx.plan_knn(tree, ld, n, cand, sh.k, want_d2=False)
+        o = ctx.edge_time_batch(tree, ld, n, cand, idx, grid, sh.samples, fn.dev(w["obs"]),
+                                mode=fn.SEARCH_SCREEN, want_rho=False, want_work=False)
+        Xs.append(fn.edge_features(ctx, tree, ld, n, cand, idx))
+        ys.append(o["j"].clone())
+    X, y = torch.cat(Xs), torch.cat(ys)
+    net = fn.Surrogate(ctx, seed=1)
+    losses = net.train(X, y, grid, epochs=args.train_epochs, batch=4096, lr=1e-3)
+    torch.cuda.synchronize()
+    L = losses.cpu().numpy()
+    return net, {"train_edges": int(X.shape[0]), "epochs": args.train_epochs,
+                 "seeds": f"1000..{999 + args.train_batches}",
+                 "loss_first_last": [float(L[0, 0]), float(L[-1, 0])],
+                 "setup_s": time.perf_counter() - t0}
 
 
 def cpu_baseline(wl, n_queries):

@@ -201,11 +201,11 @@ __global__ __launch_bounds__(1024) void mlp_loss(const float* __restrict__ Y,
     lm += d * d;
     lb += fmaxf(y1, 0.f) - y1 * f + log1pf(__expf(-fabsf(y1)));
     const float g0 = 2.f * d / nf, g1 = (sigmoidf_(y1) - f) / (float)rows;
-    for (int c = 0; c < NOUT_P; ++c) {
-      const float g = c == 0 ? g0 : (c == 1 ? g1 : 0.f);
-      dYf[(size_t)r * NOUT_P + c] = g;
-      dYb[(size_t)r * NOUT_P + c] = (bf16)g;
-    }
+    // columns 2.. of dY stay zero (cleared when the network is created)
+    dYf[(size_t)r * NOUT_P] = g0;
+    dYf[(size_t)r * NOUT_P + 1] = g1;
+    dYb[(size_t)r * NOUT_P] = (bf16)g0;
+    dYb[(size_t)r * NOUT_P + 1] = (bf16)g1;
   }
   sm[threadIdx.x] = lm;
   sb[threadIdx.x] = lb;
@@ -225,13 +225,30 @@ __global__ __launch_bounds__(1024) void mlp_loss(const float* __restrict__ Y,
   }
 }
 
-// column sums of a [rows][ncol] FP32 matrix, in row order (bias gradients)
-__global__ void mlp_colsum(const float* __restrict__ D, int rows, int ncol, int ld,
-                           float* __restrict__ out) {
+// column sums of a [rows][ncol] FP32 matrix (bias gradients), two passes
+// with a fixed order: row chunks of COLSUM_ROWS give partial sums, then the
+// partials are added in chunk order
+constexpr int COLSUM_ROWS = 32;
+__global__ void mlp_colsum_part(const float* __restrict__ D, int rows, int ncol, int ld,
+                                float* __restrict__ part) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r0 = blockIdx.y * COLSUM_ROWS;
+  if (c >= ncol) return;
+  float v[COLSUM_ROWS];
+#pragma unroll
+  for (int r = 0; r < COLSUM_ROWS; ++r) v[r] = r0 + r < rows ? D[(size_t)(r0 + r) * ld + c] : 0.f;
+  float s = 0.f;
+#pragma unroll
+  for (int r = 0; r < COLSUM_ROWS; ++r) s += v[r];
+  part[(size_t)blockIdx.y * ncol + c] = s;
+}
+__global__ void mlp_colsum_final(const float* __restrict__ part, int chunks, int ncol,
+                                 float* __restrict__ out) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncol) return;
   float s = 0.f;
-  for (int r = 0; r < rows; ++r) s += D[(size_t)r * ld + c];
+#pragma unroll 16
+  for (int z = 0; z < chunks; ++z) s += part[(size_t)z * ncol + c];
   out[c] = s;
 }
 
@@ -360,7 +377,7 @@ struct fn_mlp {
   int64_t step;
   int rows;               // workspace rows
   bf16 *Xb, *H1, *H2, *H3, *dYb, *dZb0, *dZb1;
-  float *Z1, *Z2, *Z3, *Y, *dYf, *dZf0, *dZf1, *tgt, *feas, *part, *acc3;
+  float *Z1, *Z2, *Z3, *Y, *dYf, *dZf0, *dZf1, *tgt, *feas, *part, *acc3, *colpart;
   int* nf;
 };
 
@@ -377,6 +394,7 @@ static int mlp_alloc(fn_mlp* n) {
   A(n->Z1, R * W * 4) A(n->Z2, R * W * 4) A(n->Z3, R * W * 4) A(n->Y, R * NOUT_P * 4)
   A(n->dYf, R * NOUT_P * 4) A(n->dZf0, R * W * 4) A(n->dZf1, R * W * 4) A(n->tgt, R * 4)
   A(n->feas, R * 4) A(n->part, (size_t)MAX_SPLIT * W * W * 4) A(n->acc3, 64 * 4) A(n->nf, 64 * 4)
+  A(n->colpart, ((R + COLSUM_ROWS - 1) / COLSUM_ROWS) * W * 4)
 #undef A
   return e == hipSuccess ? FN_OK : fail(FN_E_NOMEM, "fn_mlp: hipMalloc: %s", hipGetErrorString(e));
 }
@@ -386,7 +404,7 @@ extern "C" void fn_mlp_destroy(fn_mlp* n) {
   (void)hipDeviceSynchronize();
   void* ps[] = {n->p, n->m, n->v, n->g, n->wb, n->Xb, n->H1, n->H2, n->H3, n->dYb, n->dZb0,
                 n->dZb1, n->Z1, n->Z2, n->Z3, n->Y, n->dYf, n->dZf0, n->dZf1, n->tgt, n->feas,
-                n->part, n->acc3, n->nf};
+                n->part, n->acc3, n->nf, n->colpart};
   for (void* q : ps)
     if (q) (void)hipFree(q);
   delete n;
@@ -463,6 +481,11 @@ extern "C" int fn_mlp_create(fn_ctx* ctx, uint64_t seed, fn_mlp** out) {
     fn_mlp_destroy(n);
     return rc;
   }
+  if (hipMemset(n->dYf, 0, (size_t)n->rows * NOUT_P * 4) != hipSuccess ||
+      hipMemset(n->dYb, 0, (size_t)n->rows * NOUT_P * 2) != hipSuccess) {
+    fn_mlp_destroy(n);
+    return fail(FN_E_HIP, "fn_mlp_create: clear");
+  }
   // U(-1/sqrt(fan_in), 1/sqrt(fan_in)) from SplitMix64
   std::vector<float> h(NP_LOG);
   uint64_t s = seed;
@@ -509,7 +532,11 @@ static void mlp_wgrad(fn_mlp* n, const bf16* dZb, const float* dZf, int ldz, con
                              nullptr, nullptr, splits, stride);
   hipLaunchKernelGGL(mlp_reduce_splits, dim3((stride + 255) / 256), dim3(256), 0, s, n->part, used,
                      stride, (int)stride, gW);
-  hipLaunchKernelGGL(mlp_colsum, dim3((nout + 255) / 256), dim3(256), 0, s, dZf, rows, nout, ldz, gb);
+  const int chunks = (rows + COLSUM_ROWS - 1) / COLSUM_ROWS;
+  hipLaunchKernelGGL(mlp_colsum_part, dim3((nout + 63) / 64, chunks), dim3(64), 0, s, dZf, rows,
+                     nout, ldz, n->colpart);
+  hipLaunchKernelGGL(mlp_colsum_final, dim3((nout + 255) / 256), dim3(256), 0, s, n->colpart, chunks,
+                     nout, gb);
 }
 
 // Backward pass of the prepared batch (n->dY*): fills n->g.
