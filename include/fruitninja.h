@@ -113,7 +113,9 @@ typedef struct {
   int32_t max_nodes;   /* largest tree */
   int32_t max_batch;   /* largest candidate batch B */
   int32_t max_k;       /* largest k (<= FN_MAX_K) */
-  int64_t max_edges;   /* largest number of edges per edge_time_batch / edge_check call */
+  int64_t max_edges;   /* largest number of edges per edge_time_batch / edge_check call, and
+                          of all problems of a batched iteration together */
+  int32_t max_problems; /* most problems in a batched iteration (0: no batched iterations) */
 } fn_caps;
 
 typedef struct fn_ctx fn_ctx;
@@ -306,6 +308,82 @@ int surrogate_grad(fn_ctx* ctx, fn_mlp* mlp, const float* X, const int16_t* y_j,
 int surrogate_infer(fn_ctx* ctx, const fn_mlp* mlp, const float* X, int64_t N, const float* grid,
                     int32_t n_t, int32_t half, float logit_min, float* out, int16_t* out_win_lo,
                     void* stream);
+
+/* ------------------------------------------------------------------ */
+/* Launch mappings chosen by the autotuner                             */
+/* ------------------------------------------------------------------ */
+/* kNN: the scan is split into node chunks until about knn_target_waves
+ * wavefronts run (chunks of at least knn_min_chunk nodes).  0 keeps the
+ * default (4096 wavefronts, 512 nodes).  Applies to later plan_knn calls
+ * and fn_batch_prepare.  Errors: FN_E_ARG when knn_target_waves is outside
+ * [0, 16384] or knn_min_chunk is negative or not a multiple of 64. */
+typedef struct {
+  int32_t knn_target_waves;
+  int32_t knn_min_chunk;
+} fn_tuning;
+int fn_set_tuning(fn_ctx* ctx, const fn_tuning* t /*host*/);
+
+/* ------------------------------------------------------------------ */
+/* Batched planning iteration (Algorithm 1, one round for many         */
+/* problems): Parents for every candidate, the edge of every           */
+/* (candidate, parent) pair -- free candidates searched on the grid,   */
+/* goal candidates checked once at T = t_req - t(parent) -- then each  */
+/* candidate attached to the valid parent with the smallest            */
+/* t(parent) + T (ties: lower kNN rank), appended to its tree in       */
+/* candidate order, and every attached goal node scored with J of      */
+/* Eq. (2).  All problems share k, the grid, S and the arm; each has   */
+/* its own tree, candidates and obstacles.                             */
+/* ------------------------------------------------------------------ */
+typedef struct {
+  float* tree;           /* device SoA [14][ld]; the first *n_nodes nodes are valid */
+  int64_t ld;            /* node capacity, a multiple of 4 */
+  int32_t* n_nodes;      /* device counter; grows by the attached candidates (capped at ld) */
+  float* t_node;         /* device [ld] time-to-come of each node */
+  int32_t* parent;       /* device [ld] parent node (-1: root) */
+  float* nu;             /* device [ld] peak velocity fraction on the path to the node */
+  const float* cand;     /* device [B][14] candidates of this round */
+  const int32_t* kind;   /* device [B]: 0 free, 1 goal */
+  const float* t_req;    /* device [B] required arrival time of a goal */
+  const float* v_rel;    /* device [B] relative blade-object speed of a goal */
+  const float* vz0;      /* device [B] vertical launch speed of the goal's flight */
+  const float* t_fall;   /* device [B] time the goal's flight leaves reach */
+  int32_t B;
+  const float* obs;      /* device [n_obs][4] obstacle spheres, or NULL */
+  int32_t n_obs;
+  int32_t* nbr;          /* device out [B][k] parents */
+  int16_t* out_j;        /* device out [B*k] slot (free) or 0 (goal feasible at t_req - t_p), -1 */
+  uint16_t* out_status;  /* device out [B*k] FN_S_* bits */
+  float* out_margin;     /* device out [B*k] */
+  float* out_rho4;       /* device out [B*k][4] */
+  float* out_T;          /* device out [B*k] duration of the result */
+  int32_t* out_node;     /* device out [B] index of the attached node, -1 if none */
+  float* out_J;          /* device out [B] J of an attached goal node, -inf otherwise */
+  float* out_best;       /* device out [2]: best J among this round's goal nodes, its node (as float) */
+} fn_problem;
+
+typedef struct {
+  int32_t n_problems;
+  const fn_problem* problems; /* host array */
+  int32_t k;
+  const float* grid;          /* device [n_t] */
+  int32_t n_t, samples, mode; /* mode FN_SEARCH_PLAIN or FN_SEARCH_SCREEN */
+  float margin;               /* clearance margin */
+  fn_risk risk;
+} fn_problem_set;
+
+/* Uploads the problem tables (synchronous).  Sizes and pointers stay fixed
+ * until the next prepare; tree contents and node counts are read on the
+ * device at every launch.  FN_E_SHAPE beyond max_problems / max_edges /
+ * max_batch (sum of B). */
+int fn_batch_prepare(fn_ctx* ctx, const fn_problem_set* ps);
+/* Enqueues one iteration for the prepared problems: 5 kernels for kNN, the
+ * edge search and its FP64 stage, 1 for attachment and scoring. */
+int fn_batch_launch(fn_ctx* ctx, void* stream);
+/* Captures fn_batch_launch on `stream` into a HIP graph (replaces a
+ * previous one); fn_graph_launch replays it.  Memory is cleared by kernels,
+ * not memset nodes. */
+int fn_graph_capture(fn_ctx* ctx, void* stream);
+int fn_graph_launch(fn_ctx* ctx, void* stream);
 
 #ifdef __cplusplus
 }

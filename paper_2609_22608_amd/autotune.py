@@ -1,0 +1,146 @@
+"""Launch-mapping autotuner for the planner's kernels.
+
+The kNN scan splits the tree into node chunks so that enough wavefronts run
+to fill the 256 compute units; how many, and how small a chunk may get, is a
+trade between occupancy and the cost of merging partial lists, and the best
+point moves with the tree size, the batch size and (for a batched round) the
+number of problems.  The edge search has two exact forms (plain ascending
+scan and endpoint-screened scan) whose ratio moves with the workload's
+feasibility mix.  This module times the candidates on the device with HIP
+events on the launching stream, keeps the fastest, and caches the choice
+per shape in a JSON file so later runs skip the search.
+
+Every candidate computes the same result (the mapping changes only the
+order of independent work; the merge is exact), so tuning is safe at any
+time; the tests check that results do not depend on the tuning.
+"""
+from __future__ import annotations
+
+import json
+import os
+from dataclasses import dataclass
+
+import torch
+
+from . import fn
+
+# (target wavefronts, minimum chunk of nodes per wavefront)
+KNN_CANDIDATES = ((1024, 256), (2048, 256), (2048, 512), (4096, 512), (4096, 1024),
+                  (8192, 512), (8192, 1024), (16384, 1024))
+
+
+@dataclass
+class Choice:
+    knn_target_waves: int
+    knn_min_chunk: int
+    mode: int
+    ms: float
+
+    def as_dict(self):
+        return dict(knn_target_waves=self.knn_target_waves, knn_min_chunk=self.knn_min_chunk,
+                    mode=self.mode, ms=self.ms)
+
+
+class Cache:
+    """JSON cache {key: choice}; key names the shape, the device and the
+    library version so a rebuilt library or another card retunes."""
+
+    def __init__(self, path: str | None):
+        self.path = path
+        self.data = {}
+        if path and os.path.exists(path):
+            with open(path) as f:
+                self.data = json.load(f)
+
+    def get(self, key):
+        d = self.data.get(key)
+        return None if d is None else Choice(**d)
+
+    def put(self, key, ch: Choice):
+        self.data[key] = ch.as_dict()
+        if self.path:
+            tmp = self.path + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(self.data, f, indent=1, sort_keys=True)
+            os.replace(tmp, self.path)
+
+
+def _device_tag():
+    p = torch.cuda.get_device_properties(torch.cuda.current_device())
+    return f"{p.name}|{getattr(p, 'gcnArchName', '')}|cu{p.multi_processor_count}|{fn.version()}"
+
+
+def _time(run, reps, setup=None):
+    """Median device time of run() over reps calls (events on the current
+    stream); setup() runs before each call, outside the timed events."""
+    s = torch.cuda.current_stream()
+    ts = []
+    for r in range(reps + 1):
+        if setup:
+            setup()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        run()
+        e1.record(s)
+        torch.cuda.synchronize()
+        if r:  # the first call warms up
+            ts.append(e0.elapsed_time(e1))
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def tune_knn(ctx: fn.Context, tree, ld, n_nodes, cand, k, reps=5, cache: Cache | None = None,
+             candidates=KNN_CANDIDATES):
+    """Fastest kNN mapping for one (tree, batch, k); leaves it set on ctx."""
+    B = cand.shape[0]
+    key = f"knn|n{n_nodes}|B{B}|k{k}|{_device_tag()}"
+    hit = cache.get(key) if cache else None
+    if hit is not None:
+        ctx.set_tuning(hit.knn_target_waves, hit.knn_min_chunk)
+        return hit, {}
+    idx = torch.empty((B, k), dtype=torch.int32, device=cand.device)
+    times = {}
+    for tw, mc in candidates:
+        ctx.set_tuning(tw, mc)
+        times[(tw, mc)] = _time(lambda: ctx.plan_knn(tree, ld, n_nodes, cand, k, out_idx=idx,
+                                                     want_d2=False), reps)
+    (tw, mc), ms = min(times.items(), key=lambda kv: kv[1])
+    ch = Choice(tw, mc, -1, ms)
+    ctx.set_tuning(tw, mc)
+    if cache:
+        cache.put(key, ch)
+    return ch, {f"{a}/{b}": v for (a, b), v in times.items()}
+
+
+def tune_batch(bt: fn.Batch, reps=3, cache: Cache | None = None, candidates=KNN_CANDIDATES,
+               modes=(fn.SEARCH_PLAIN, fn.SEARCH_SCREEN)):
+    """Fastest (kNN mapping, search form) for a prepared batched round.
+
+    Each timing restores the initial trees first, so every candidate times
+    the same round.  Leaves the winner prepared on ``bt``."""
+    sig = ";".join(f"{P['n0']}x{P['B']}o{P['n_obs']}" for P in bt.problems)
+    key = f"batch|{sig}|k{bt.k}|nt{bt.grid.shape[0]}|S{bt.samples}|{_device_tag()}"
+    hit = cache.get(key) if cache else None
+    if hit is not None:
+        bt.ctx.set_tuning(hit.knn_target_waves, hit.knn_min_chunk)
+        bt.mode = hit.mode
+        bt.prepare()
+        return hit, {}
+    times = {}
+    for mode in modes:
+        for tw, mc in candidates:
+            bt.ctx.set_tuning(tw, mc)
+            bt.mode = mode
+            bt.prepare()
+            times[(tw, mc, mode)] = _time(bt.launch, reps, setup=bt.reset_trees)
+    (tw, mc, mode), ms = min(times.items(), key=lambda kv: kv[1])
+    ch = Choice(tw, mc, mode, ms)
+    bt.ctx.set_tuning(tw, mc)
+    bt.mode = mode
+    bt.prepare()
+    bt.reset_trees()
+    if cache:
+        cache.put(key, ch)
+    return ch, {f"{a}/{b}/{'plain' if m == fn.SEARCH_PLAIN else 'screen'}": v
+                for (a, b, m), v in times.items()}

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfruitninja.so")
-SOURCES = ["fn_core.hip", "fn_knn.hip", "fn_edge.hip", "fn_mlp.hip"]
+SOURCES = ["fn_core.hip", "fn_knn.hip", "fn_edge.hip", "fn_mlp.hip", "fn_batch.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # no packed FP32 instructions (v_pk_*_f32)

@@ -1,0 +1,422 @@
+// fn_batch.hip -- one round of Algorithm 1 for many planning problems at once.
+//
+// Every stage runs as one launch over all problems: the work item of a
+// wavefront (a kNN query group and node chunk, a query to merge, an edge)
+// is decoded by binary search over per-problem prefix offsets held on the
+// device, so problems of very different sizes share one grid without host
+// round trips.  Sizes are fixed at prepare time (node capacity, batch
+// sizes); node counts are read on the device at every launch, so the whole
+// round can be captured once as a HIP graph and replayed while the trees
+// grow.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <vector>
+
+#include "fn_edge.h"
+#include "fn_knn.h"
+#include "fn_risk.h"
+
+namespace fn {
+
+struct KnnProb {
+  const float* tree;
+  int64_t ld;
+  const int32_t* n_nodes;
+  const float* qs;
+  int B, n_groups, n_split, chunk;
+  int64_t part_off;  // entries into the partial-list scratch
+  int64_t y_off;     // entries into the per-chunk |y|^2 scratch
+  int32_t* nbr;
+};
+
+struct InsProb {
+  float* tree;
+  int64_t ld;
+  int32_t* n_nodes;
+  float* t_node;
+  int32_t* parent;
+  float* nu;
+  const float* cand;
+  const int32_t* kind;
+  const float* v_rel;
+  const float* vz0;
+  const float* t_fall;
+  int B;
+  const int32_t* nbr;
+  const int16_t* j;
+  const uint16_t* status;
+  const float* rho4;
+  const float* T;
+  int32_t* out_node;
+  float* out_J;
+  float* out_best;
+};
+
+// index p with off[p] <= x < off[p + 1] (n problems)
+__device__ __forceinline__ int bsearch_off(const int64_t* __restrict__ off, int n, int64_t x) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= x) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <int K1>
+__global__ __launch_bounds__(256) void batch_knn_scan(const KnnProb* __restrict__ P, int n,
+                                                      const int64_t* __restrict__ pair_off,
+                                                      float* __restrict__ part_d,
+                                                      int32_t* __restrict__ part_i,
+                                                      float* __restrict__ part_y) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t pair = (int64_t)blockIdx.x * 4 + wave;
+  if (pair >= pair_off[n]) return;
+  const int p = bsearch_off(pair_off, n, pair);
+  const KnnProb& q = P[p];
+  const int local = (int)(pair - pair_off[p]);
+  const int ch = local / q.n_groups, grp = local - ch * q.n_groups;
+  knn_scan_item<K1, KNN_QG>(q.tree, q.ld, *q.n_nodes, q.qs, q.B, grp, ch, q.n_split, q.chunk,
+                            part_d + q.part_off, part_i + q.part_off, part_y + q.y_off);
+}
+
+template <int K1>
+__global__ __launch_bounds__(64) void batch_knn_merge(const KnnProb* __restrict__ P, int n,
+                                                      const int64_t* __restrict__ query_off,
+                                                      const float* __restrict__ part_d,
+                                                      const int32_t* __restrict__ part_i,
+                                                      const float* __restrict__ part_y, int k) {
+  const int64_t qg = blockIdx.x;
+  if (qg >= query_off[n]) return;
+  const int p = bsearch_off(query_off, n, qg);
+  const KnnProb& q = P[p];
+  knn_merge_query<K1>(q.tree, q.ld, *q.n_nodes, q.qs, (int)(qg - query_off[p]), k, q.n_split,
+                      part_d + q.part_off, part_i + q.part_off, part_y + q.y_off, q.nbr, nullptr);
+}
+
+template <int PAT>
+__global__ __launch_bounds__(256) void batch_edge_kernel(ProbTable pt, const float* __restrict__ grid,
+                                                         int n_t,
+                                                         const ArmConst<float>* __restrict__ Ap) {
+  __shared__ float s_end_all[4][FN_MAX_NT];
+  __shared__ float s_T[FN_MAX_NT];
+  __shared__ float s_fix[4];
+  for (int t = threadIdx.x; t < n_t; t += blockDim.x) s_T[t] = grid[t];
+  __syncthreads();
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t eg = (int64_t)blockIdx.x * 4 + wave;
+  if (eg >= pt.edge_off[pt.n]) return;
+  const int p = problem_of(pt, eg);
+  search_edge<PAT>(pt.args[p], eg - pt.edge_off[p], eg, *Ap, s_end_all[wave], s_T, &s_fix[wave]);
+}
+
+// Attachment and scoring, one workgroup per problem: candidate b picks the
+// valid parent with the smallest t(parent) + T (ties: lower kNN rank); the
+// attached candidates are appended in candidate order (block prefix sum),
+// and every attached goal node is scored.
+constexpr int INS_THREADS = 256;
+__global__ __launch_bounds__(INS_THREADS) void batch_insert_kernel(const InsProb* __restrict__ P,
+                                                                   int k, fn_risk w) {
+  __shared__ int s_scan[INS_THREADS];
+  __shared__ float s_bj[INS_THREADS];
+  __shared__ int s_bn[INS_THREADS];
+  const InsProb& q = P[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int n0 = *q.n_nodes;
+  __syncthreads();
+  const uint16_t fail = FN_S_NONE | FN_S_VEL | FN_S_POS | FN_S_COLL | FN_S_BAD_INPUT | FN_S_NO_PARENT;
+  int running = 0;
+  float best_j = -INFINITY;
+  int best_n = -1;
+  for (int base = 0; base < q.B; base += INS_THREADS) {
+    const int b = base + tid;
+    int pick = -1;
+    float cost = INFINITY;
+    if (b < q.B) {
+      for (int i = 0; i < k; ++i) {
+        const int64_t e = (int64_t)b * k + i;
+        if (q.j[e] < 0 || (q.status[e] & fail)) continue;
+        const float c = q.t_node[q.nbr[e]] + q.T[e];
+        if (c < cost) {
+          cost = c;
+          pick = i;
+        }
+      }
+    }
+    // exclusive prefix sum of the attach flags (Hillis-Steele, fixed order)
+    s_scan[tid] = pick >= 0 ? 1 : 0;
+    __syncthreads();
+    for (int o = 1; o < INS_THREADS; o <<= 1) {
+      const int v = tid >= o ? s_scan[tid - o] : 0;
+      __syncthreads();
+      s_scan[tid] += v;
+      __syncthreads();
+    }
+    const int incl = s_scan[tid];
+    const int total = s_scan[INS_THREADS - 1];
+    __syncthreads();
+    if (b < q.B) {
+      const int64_t pos = (int64_t)n0 + running + incl - 1;
+      float J = -INFINITY;
+      int node = -1;
+      if (pick >= 0 && pos < q.ld) {
+        node = (int)pos;
+        const int64_t e = (int64_t)b * k + pick;
+        const int par = q.nbr[e];
+        for (int c = 0; c < FN_STATE; ++c) q.tree[(size_t)c * q.ld + pos] = q.cand[(size_t)b * FN_STATE + c];
+        q.t_node[pos] = cost;
+        q.parent[pos] = par;
+        const float nu = fmaxf(q.nu[par], q.rho4[4 * e + 1]);
+        q.nu[pos] = nu;
+        if (q.kind[b] == 1) {
+          J = (float)risk_eval(w, cost, q.v_rel[b], nu, q.vz0[b], q.t_fall[b]);
+          if (J > best_j || (J == best_j && node < best_n)) {
+            best_j = J;
+            best_n = node;
+          }
+        }
+      }
+      q.out_node[b] = node;
+      q.out_J[b] = J;
+    }
+    running += total;
+  }
+  // best goal node of the round (fixed-order tree reduction)
+  s_bj[tid] = best_j;
+  s_bn[tid] = best_n;
+  __syncthreads();
+  for (int o = INS_THREADS / 2; o > 0; o >>= 1) {
+    if (tid < o) {
+      const float a = s_bj[tid], c = s_bj[tid + o];
+      const int an = s_bn[tid], cn = s_bn[tid + o];
+      if (c > a || (c == a && cn >= 0 && (an < 0 || cn < an))) {
+        s_bj[tid] = c;
+        s_bn[tid] = cn;
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    *q.n_nodes = (int)min<int64_t>(q.ld, (int64_t)n0 + running);
+    q.out_best[0] = s_bj[0];
+    q.out_best[1] = (float)s_bn[0];
+  }
+}
+
+}  // namespace fn
+
+using namespace fn;
+
+// Host-side batch state (part of the context).
+struct fn_batch {
+  int n = 0;
+  int K1 = 0, k = 0, n_t = 0, pattern = 0;
+  const float* grid = nullptr;
+  fn_risk risk{};
+  int64_t pairs = 0, queries = 0, edges = 0;
+  // device tables
+  KnnProb* knn = nullptr;
+  InsProb* ins = nullptr;
+  EdgeArgs* args = nullptr;
+  int64_t *pair_off = nullptr, *query_off = nullptr, *edge_off = nullptr;
+  EdgeArgs a0{};  // queue pointers for the FP64 stage
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+int batch_alloc(fn_ctx* c) {
+  const int np = c->caps.max_problems;
+  if (np <= 0) return FN_OK;
+  fn_batch* b = new fn_batch();
+  c->batch = b;
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = hipMalloc((void**)&b->knn, sizeof(KnnProb) * np);
+  if (e == hipSuccess) e = hipMalloc((void**)&b->ins, sizeof(InsProb) * np);
+  if (e == hipSuccess) e = hipMalloc((void**)&b->args, sizeof(EdgeArgs) * np);
+  if (e == hipSuccess) e = hipMalloc((void**)&b->pair_off, sizeof(int64_t) * (np + 1));
+  if (e == hipSuccess) e = hipMalloc((void**)&b->query_off, sizeof(int64_t) * (np + 1));
+  if (e == hipSuccess) e = hipMalloc((void**)&b->edge_off, sizeof(int64_t) * (np + 1));
+  return e == hipSuccess ? FN_OK : fail(FN_E_NOMEM, "fn_create: batch tables: %s", hipGetErrorString(e));
+}
+
+void batch_free(fn_ctx* c) {
+  fn_batch* b = c->batch;
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  void* ps[] = {b->knn, b->ins, b->args, b->pair_off, b->query_off, b->edge_off};
+  for (void* p : ps)
+    if (p) (void)hipFree(p);
+  delete b;
+  c->batch = nullptr;
+}
+
+extern "C" int fn_batch_prepare(fn_ctx* c, const fn_problem_set* ps) {
+  if (!c || !ps || (ps->n_problems > 0 && !ps->problems)) return fail(FN_E_ARG, "fn_batch_prepare: NULL argument");
+  fn_batch* bt = c->batch;
+  if (!bt) return fail(FN_E_STATE, "fn_batch_prepare: context created with max_problems = 0");
+  const int n = ps->n_problems;
+  if (n < 1 || n > c->caps.max_problems) return fail(FN_E_SHAPE, "fn_batch_prepare: %d problems (cap %d)", n, c->caps.max_problems);
+  if (ps->k < 1 || ps->k > c->caps.max_k) return fail(FN_E_SHAPE, "fn_batch_prepare: k = %d", ps->k);
+  if (ps->n_t < 1 || ps->n_t > FN_MAX_NT || !ps->grid) return fail(FN_E_SHAPE, "fn_batch_prepare: n_t = %d", ps->n_t);
+  if (ps->samples < 2 || ps->samples > FN_MAX_SAMPLES) return fail(FN_E_SHAPE, "fn_batch_prepare: S = %d", ps->samples);
+  if (ps->mode != FN_SEARCH_PLAIN && ps->mode != FN_SEARCH_SCREEN) return fail(FN_E_ARG, "fn_batch_prepare: mode must be PLAIN or SCREEN");
+  if (!(ps->margin >= 0.f)) return fail(FN_E_ARG, "fn_batch_prepare: margin");
+  const int K1 = knn_k1(ps->k);
+  const int64_t cap_part = (int64_t)knn_scratch_entries(c->caps.max_batch, c->caps.max_k, c->caps.max_problems);
+  const int64_t cap_y = (int64_t)knn_scratch_entries(c->caps.max_batch, 0, c->caps.max_problems);
+  std::vector<KnnProb> kp(n);
+  std::vector<InsProb> ip(n);
+  std::vector<EdgeArgs> ea(n);
+  std::vector<int64_t> po(n + 1), qo(n + 1), eo(n + 1);
+  int64_t part = 0, ys = 0, sumB = 0;
+  po[0] = qo[0] = eo[0] = 0;
+  int Sw = 1;
+  while (Sw < ps->samples) Sw <<= 1;
+  const int target = std::min(KNN_TARGET_MAX, c->tune.knn_target_waves > 0 ? c->tune.knn_target_waves : 4096);
+  const int minchunk = c->tune.knn_min_chunk > 0 ? c->tune.knn_min_chunk : 512;
+  for (int p = 0; p < n; ++p) {
+    const fn_problem& q = ps->problems[p];
+    if (!q.tree || !q.n_nodes || !q.t_node || !q.parent || !q.nu || !q.cand || !q.kind || !q.t_req ||
+        !q.v_rel || !q.vz0 || !q.t_fall || !q.nbr || !q.out_j || !q.out_status || !q.out_margin ||
+        !q.out_rho4 || !q.out_T || !q.out_node || !q.out_J || !q.out_best)
+      return fail(FN_E_ARG, "fn_batch_prepare: problem %d has a NULL array", p);
+    if (q.B < 1 || q.ld < 4 || (q.ld & 3) != 0 || q.ld > (int64_t)1 << 30)
+      return fail(FN_E_SHAPE, "fn_batch_prepare: problem %d: B = %d, ld = %lld", p, q.B, (long long)q.ld);
+    if (q.n_obs < 0 || q.n_obs > FN_MAX_OBS || (q.n_obs > 0 && !q.obs))
+      return fail(FN_E_SHAPE, "fn_batch_prepare: problem %d: %d obstacles", p, q.n_obs);
+    // kNN geometry from the node capacity (node counts change on the device)
+    const int groups = (q.B + KNN_QG - 1) / KNN_QG;
+    int split = (int)((target / n + groups - 1) / groups);
+    split = std::max(1, std::min(split, std::min(KNN_MAX_SPLIT, (int)(q.ld / minchunk))));
+    int chunk = (int)((q.ld + split - 1) / split);
+    chunk = std::max(WAVE, (chunk + WAVE - 1) / WAVE * WAVE);
+    split = std::max(1, (int)((q.ld + chunk - 1) / chunk));
+    kp[p] = KnnProb{q.tree, q.ld, q.n_nodes, q.cand, q.B, groups, split, chunk, part, ys, q.nbr};
+    part += (int64_t)q.B * split * K1;
+    ys += (int64_t)q.B * split;
+    po[p + 1] = po[p] + (int64_t)groups * split;
+    qo[p + 1] = qo[p] + q.B;
+    eo[p + 1] = eo[p] + (int64_t)q.B * ps->k;
+    sumB += q.B;
+    EdgeArgs& a = ea[p];
+    std::memset(&a, 0, sizeof(a));
+    a.tree = q.tree; a.ld = q.ld; a.n_nodes = 0; a.n_nodes_dev = q.n_nodes;
+    a.cand = q.cand; a.nbr = q.nbr; a.k = ps->k; a.E = (int64_t)q.B * ps->k;
+    a.grid = ps->grid; a.n_t = ps->n_t; a.S = ps->samples; a.Sw = Sw; a.mode = ps->mode;
+    a.win_half = 0; a.j_max = nullptr; a.win_lo = nullptr;
+    a.obs = q.obs; a.n_obs = q.n_obs; a.margin_c = ps->margin;
+    a.out_j = q.out_j; a.out_st = q.out_status; a.out_m = q.out_margin; a.out_rho = q.out_rho4;
+    a.out_work = nullptr; a.q_count = c->q_count; a.queue = c->queue;
+    a.kind = q.kind; a.t_req = q.t_req; a.t_node = q.t_node; a.out_T = q.out_T;
+    ip[p] = InsProb{q.tree, q.ld, q.n_nodes, q.t_node, q.parent, q.nu, q.cand, q.kind, q.v_rel,
+                    q.vz0, q.t_fall, q.B, q.nbr, q.out_j, q.out_status, q.out_rho4, q.out_T,
+                    q.out_node, q.out_J, q.out_best};
+  }
+  if (eo[n] > c->caps.max_edges) return fail(FN_E_SHAPE, "fn_batch_prepare: %lld edges (cap %lld)", (long long)eo[n], (long long)c->caps.max_edges);
+  if (sumB > c->caps.max_batch || part > cap_part || ys > cap_y)
+    return fail(FN_E_SHAPE, "fn_batch_prepare: %lld candidates in total (cap %d)", (long long)sumB, c->caps.max_batch);
+  hipError_t e = hipMemcpy(bt->knn, kp.data(), sizeof(KnnProb) * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(bt->ins, ip.data(), sizeof(InsProb) * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(bt->args, ea.data(), sizeof(EdgeArgs) * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(bt->pair_off, po.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(bt->query_off, qo.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(bt->edge_off, eo.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "fn_batch_prepare: upload");
+  bt->n = n;
+  bt->K1 = K1;
+  bt->k = ps->k;
+  bt->n_t = ps->n_t;
+  bt->grid = ps->grid;
+  bt->risk = ps->risk;
+  bt->pattern = c->pattern;
+  bt->pairs = po[n];
+  bt->queries = qo[n];
+  bt->edges = eo[n];
+  bt->a0 = ea[0];
+  return FN_OK;
+}
+
+template <int K1>
+static void launch_batch_knn(fn_ctx* c, fn_batch* bt, hipStream_t s) {
+  hipLaunchKernelGGL(batch_knn_scan<K1>, dim3((unsigned)((bt->pairs + 3) / 4)), dim3(256), 0, s,
+                     bt->knn, bt->n, bt->pair_off, c->knn_d, c->knn_i, c->knn_y);
+  hipLaunchKernelGGL(batch_knn_merge<K1>, dim3((unsigned)bt->queries), dim3(64), 0, s, bt->knn,
+                     bt->n, bt->query_off, c->knn_d, c->knn_i, c->knn_y, bt->k);
+}
+
+extern "C" int fn_batch_launch(fn_ctx* c, void* stream) {
+  if (!c) return fail(FN_E_ARG, "fn_batch_launch: NULL context");
+  fn_batch* bt = c->batch;
+  if (!bt || bt->n == 0) return fail(FN_E_STATE, "fn_batch_launch: no prepared problem set");
+  hipStream_t s = (hipStream_t)stream;
+  switch (bt->K1) {
+#define FN_K(KK) case KK: launch_batch_knn<KK>(c, bt, s); break;
+    FN_K(2) FN_K(3) FN_K(4) FN_K(5) FN_K(6) FN_K(7) FN_K(8) FN_K(9) FN_K(10) FN_K(11) FN_K(12)
+    FN_K(13) FN_K(14) FN_K(15) FN_K(16) FN_K(17) FN_K(33)
+#undef FN_K
+    default: return fail(FN_E_SHAPE, "fn_batch_launch: k");
+  }
+  hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, s, c->q_count, 1);
+  const ProbTable pt{bt->n, bt->edge_off, bt->args};
+  const dim3 grid((unsigned)((bt->edges + 3) / 4));
+  const unsigned rw = (unsigned)(bt->edges < 4096 ? bt->edges : 4096);
+  if (bt->pattern == PAT_FR3) {
+    hipLaunchKernelGGL(batch_edge_kernel<PAT_FR3>, grid, dim3(256), 0, s, pt, bt->grid, bt->n_t, c->arm32);
+    hipLaunchKernelGGL(edge_recheck_kernel<PAT_FR3>, dim3(rw), dim3(64), 0, s, bt->a0, pt, c->arm32, c->arm64);
+  } else {
+    hipLaunchKernelGGL(batch_edge_kernel<PAT_GENERIC>, grid, dim3(256), 0, s, pt, bt->grid, bt->n_t, c->arm32);
+    hipLaunchKernelGGL(edge_recheck_kernel<PAT_GENERIC>, dim3(rw), dim3(64), 0, s, bt->a0, pt, c->arm32, c->arm64);
+  }
+  hipLaunchKernelGGL(batch_insert_kernel, dim3(bt->n), dim3(INS_THREADS), 0, s, bt->ins, bt->k, bt->risk);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? FN_OK : hip_fail(e, "fn_batch_launch");
+}
+
+extern "C" int fn_graph_capture(fn_ctx* c, void* stream) {
+  if (!c || !c->batch) return fail(FN_E_STATE, "fn_graph_capture: no batch state");
+  fn_batch* bt = c->batch;
+  hipStream_t s = (hipStream_t)stream;
+  if (!s) return fail(FN_E_ARG, "fn_graph_capture: capture needs a non-default stream");
+  if (bt->exec) {
+    (void)hipGraphExecDestroy(bt->exec);
+    bt->exec = nullptr;
+  }
+  if (bt->graph) {
+    (void)hipGraphDestroy(bt->graph);
+    bt->graph = nullptr;
+  }
+  hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_fail(e, "fn_graph_capture: begin");
+  const int rc = fn_batch_launch(c, stream);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(s, &g);
+  if (rc != FN_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return hip_fail(e, "fn_graph_capture: end");
+  e = hipGraphInstantiate(&bt->exec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return hip_fail(e, "fn_graph_capture: instantiate");
+  }
+  bt->graph = g;
+  return FN_OK;
+}
+
+extern "C" int fn_graph_launch(fn_ctx* c, void* stream) {
+  if (!c || !c->batch || !c->batch->exec) return fail(FN_E_STATE, "fn_graph_launch: nothing captured");
+  hipError_t e = hipGraphLaunch(c->batch->exec, (hipStream_t)stream);
+  return e == hipSuccess ? FN_OK : hip_fail(e, "fn_graph_launch");
+}
+
+extern "C" int fn_set_tuning(fn_ctx* c, const fn_tuning* t) {
+  if (!c || !t) return fail(FN_E_ARG, "fn_set_tuning: NULL argument");
+  if (t->knn_target_waves < 0 || t->knn_target_waves > KNN_TARGET_MAX || t->knn_min_chunk < 0 ||
+      (t->knn_min_chunk & 63) != 0)
+    return fail(FN_E_ARG, "fn_set_tuning: target waves in [0, %d], min chunk >= 0 and a multiple of 64", KNN_TARGET_MAX);
+  c->tune = *t;
+  return FN_OK;
+}

@@ -9,6 +9,7 @@
 #include <string>
 
 #include "fn_ctx.h"
+#include "fn_risk.h"
 
 namespace fn {
 
@@ -111,43 +112,11 @@ __global__ void arm_prepare_kernel(const fn_arm_desc* d, Digits dg, int pattern,
   }
 }
 
-// ---------------------------------------------------------------------------
-// Risk objective (Sec. IV-B): J = w_v min(v_rel, v_target) + w_p log P_object
-// + w_r log P_inrange + w_x log P_arm, with P_object = erf(r / (sigma sqrt 2)),
-// P_inrange = Phi((t_fall - T) / sigma_t), sigma_t = sigma / |xdot_z(t_fall)|,
-// log P_arm = -lambda (nu - nu0)_+ T (1 - nu0 / nu).
-// ---------------------------------------------------------------------------
-__device__ double log_phi_dev(double z) {
-  // log Phi(z) = log(erfc(-z / sqrt 2) / 2); below -30 erfc underflows, so the
-  // scaled complementary error function carries the tail:
-  // erfc(x) = erfcx(x) exp(-x^2)
-  if (z > -30.0) return log(0.5 * erfc(-z * 0.70710678118654752));
-  const double x = -z * 0.70710678118654752;
-  return log(0.5 * erfcx(x)) - x * x;
-}
-
 __global__ void risk_kernel(fn_risk w, const float* T, const float* v_rel, const float* nu,
                             const float* vz0, const float* t_fall, int n, float* out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const double t = T[i];
-  double sg;
-  if (w.sigma_mode == 1) {
-    sg = w.s0 + w.s1 * t;
-  } else {
-    const double a = w.sp, b = w.sv * t, c = 0.5 * w.sa * t * t;
-    sg = sqrt(a * a + b * b + c * c);
-  }
-  const double x = w.r / (sg * 1.4142135623730951);
-  const double lpo = x < 0.5 ? log(erf(x)) : log1p(-erfc(x));
-  const double tf = t_fall[i];
-  const double xdz = double(vz0[i]) + w.gz * tf;
-  const double st = sg / fabs(xdz);
-  const double lpr = log_phi_dev((tf - t) / st);
-  const double v = nu[i];
-  const double lpa = v > w.nu0 ? -w.lam * (v - w.nu0) * t * (1.0 - w.nu0 / v) : 0.0;
-  const double vr = fmin(double(v_rel[i]), w.vtarget);
-  out[i] = float(w.wv * vr + w.wp * lpo + w.wr * lpr + w.wx * lpa);
+  out[i] = (float)risk_eval(w, T[i], v_rel[i], nu[i], vz0[i], t_fall[i]);
 }
 
 __global__ void zero_i32_kernel(int32_t* p, int n) {
@@ -178,7 +147,7 @@ extern "C" int fn_create(const fn_arm_desc* arm, const fn_caps* caps, fn_ctx** o
   }
   if (!(arm->wmax > 0)) return fail(FN_E_ARG, "fn_create: wmax must be > 0");
   if (caps->max_nodes < 0 || caps->max_batch < 0 || caps->max_k < 1 || caps->max_k > FN_MAX_K ||
-      caps->max_edges < 0)
+      caps->max_edges < 0 || caps->max_problems < 0 || caps->max_problems > 4096)
     return fail(FN_E_SHAPE, "fn_create: invalid caps");
 
   fn_ctx* c = new fn_ctx();
@@ -215,14 +184,22 @@ extern "C" int fn_create(const fn_arm_desc* arm, const fn_caps* caps, fn_ctx** o
   FN_ALLOC(c->arm32, sizeof(ArmConst<float>));
   FN_ALLOC(c->arm64, sizeof(ArmConst<double>));
   // kNN partial lists of every (query, node chunk)
-  const size_t kl = knn_scratch_entries(caps->max_batch, caps->max_k);
+  const size_t kl = knn_scratch_entries(caps->max_batch, caps->max_k, caps->max_problems);
   FN_ALLOC(c->knn_d, kl * sizeof(float));
   FN_ALLOC(c->knn_i, kl * sizeof(int32_t));
-  FN_ALLOC(c->knn_y, knn_scratch_entries(caps->max_batch, 0) * sizeof(float));
+  FN_ALLOC(c->knn_y, knn_scratch_entries(caps->max_batch, 0, caps->max_problems) * sizeof(float));
   // near-limit queue: counter + one entry per edge
   FN_ALLOC(c->q_count, 64 * sizeof(int32_t));
   FN_ALLOC(c->queue, (size_t)(caps->max_edges > 0 ? caps->max_edges : 1) * sizeof(QEntry));
 #undef FN_ALLOC
+  {
+    const int brc = batch_alloc(c);
+    if (brc) {
+      (void)hipFree(d_desc);
+      fn_destroy(c);
+      return brc;
+    }
+  }
   e = hipMemcpy(d_desc, &c->desc, sizeof(fn_arm_desc), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     (void)hipFree(d_desc);
@@ -244,6 +221,7 @@ extern "C" int fn_create(const fn_arm_desc* arm, const fn_caps* caps, fn_ctx** o
 extern "C" void fn_destroy(fn_ctx* c) {
   if (!c) return;
   (void)hipDeviceSynchronize();
+  batch_free(c);
   (void)hipFree(c->arm32);
   (void)hipFree(c->arm64);
   (void)hipFree(c->knn_d);

@@ -30,15 +30,28 @@ int hip_fail(hipError_t e, const char* where);
 
 __global__ void zero_i32_kernel(int32_t* p, int n);
 
+
+
 // entries of the kNN partial-list scratch for these caps
-size_t knn_scratch_entries(int max_batch, int max_k);
+// Largest kNN scan grid a tuning may ask for (waves); the partial-list
+// scratch is sized for it.
+constexpr int KNN_TARGET_MAX = 16384;
+size_t knn_scratch_entries(int max_batch, int max_k, int max_problems);
 // list length a kNN launch uses for k
 inline int knn_k1(int k) { return k <= 16 ? k + 1 : 33; }
 
 }  // namespace fn
 
+struct fn_ctx;
+int batch_alloc(fn_ctx* c);
+void batch_free(fn_ctx* c);
+
+struct fn_batch;
+
 struct fn_ctx {
   int device;
+  fn_tuning tune;     // launch mappings (0 = defaults)
+  fn_batch* batch;    // batched-iteration state (NULL when max_problems = 0)
   int pattern;  // twist pattern code or PAT_GENERIC
   fn_caps caps;
   fn_arm_desc desc;  // host copy, spheres sorted by link

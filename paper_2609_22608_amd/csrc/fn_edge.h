@@ -1,0 +1,569 @@
+// fn_edge.h -- device side of the edge search: arguments, the per-edge
+// search of one wavefront (minimum feasible time on the T grid, Def. 7,
+// Algorithm 1; post-checks of Def. 6 rho_v, position limits and clearance of
+// Sec. IV-E) and its FP64 stage.  Used by the single-problem kernels
+// (fn_edge.hip) and the batched multi-problem kernels (fn_batch.hip).
+//
+// Search modes (same result, different work):
+//  PLAIN  -- ascending passes over full slots, stop at the first feasible.
+//  SCREEN -- first the two endpoint samples (u = 0, 1) of every slot, 32
+//            slots per pass; a slot whose endpoint ratio exceeds 1 + BAND is
+//            infeasible for certain and never evaluated in full.  Then full
+//            passes over the remaining slots in ascending order.
+//  WINDOW -- the surrogate's window [lo, lo + 2h]: slots below it are
+//            screened (the certificate), the window is evaluated in full, the
+//            slots above it are screened only if the window holds no
+//            feasible slot.  "Hit" = the result lies in the window (or the
+//            network predicted no feasible slot and there is none).
+// Every FP32 ratio within BAND of 1 that a decision rests on sends the edge
+// to the FP64 stage, which resumes it from that slot.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fn_ctx.h"
+
+namespace fn {
+
+struct EdgeArgs {
+  const float* __restrict__ tree;
+  int64_t ld;
+  int n_nodes;
+  const float* __restrict__ cand;
+  const int32_t* __restrict__ nbr;
+  int k;
+  int64_t E;
+  const float* __restrict__ grid;
+  int n_t, S, Sw, mode, win_half;
+  const int16_t* __restrict__ j_max;
+  const int16_t* __restrict__ win_lo;
+  const float* __restrict__ obs;
+  int n_obs;
+  float margin_c;
+  int16_t* out_j;
+  uint16_t* out_st;
+  float* out_m;
+  float* out_rho;
+  int32_t* out_work;
+  int32_t* q_count;
+  QEntry* queue;
+  // batched problems: device node count (overrides n_nodes when set), and the
+  // goal branch of Algorithm 1 -- candidates with kind 1 are checked once at
+  // T = t_req[b] - t_node[parent] instead of searched
+  const int32_t* __restrict__ n_nodes_dev;
+  const int32_t* __restrict__ kind;
+  const float* __restrict__ t_req;
+  const float* __restrict__ t_node;
+  float* out_T;  // duration of the result (grid slot or fixed T), or NULL
+};
+
+__device__ __forceinline__ int nodes_of(const EdgeArgs& a) {
+  return a.n_nodes_dev ? *a.n_nodes_dev : a.n_nodes;
+}
+
+// queue phase bits
+constexpr int PH_POST = 1;        // only the post-checks are left
+constexpr int PH_BELOW_FULL = 2;  // window mode: a slot below the window was evaluated in full
+
+template <typename R>
+__device__ __forceinline__ bool load_edge(const EdgeArgs& a, int64_t e, EdgeState<R>& S,
+                                          int& status) {
+  const int64_t b = e / a.k;
+  const int p = a.nbr[e];
+  status = 0;
+  if (p < 0) {
+    status = FN_S_NO_PARENT;
+    return false;
+  }
+  if (p >= nodes_of(a)) {
+    status = FN_S_BAD_INPUT;
+    return false;
+  }
+  bool finite = true;
+#pragma unroll
+  for (int i = 0; i < NJ; ++i) {
+    const float q0 = a.tree[(size_t)i * a.ld + p];
+    const float v0 = a.tree[(size_t)(NJ + i) * a.ld + p];
+    const float q1 = a.cand[b * FN_STATE + i];
+    const float v1 = a.cand[b * FN_STATE + NJ + i];
+    finite = finite && isfinite(q0) && isfinite(v0) && isfinite(q1) && isfinite(v1);
+    S.q0[i] = R(q0);
+    S.qd0[i] = R(v0);
+    S.dq[i] = R(q1) - R(q0);
+    S.d2[i] = R(v1) - R(v0);
+  }
+  if (!finite) status = FN_S_BAD_INPUT;
+  return finite;
+}
+
+__device__ __forceinline__ float lane_u(int lane, int Sw, int S) {
+  const int s = lane & (Sw - 1);
+  return s < S ? float(s) / float(S - 1) : 0.f;
+}
+
+// Post-checks at duration T (Def. 6 rho_v; position limits; clearance):
+// returns (rho_v, rho_q, rho_c) in every lane.
+template <typename R, int PAT>
+__device__ void post_checks(const ArmConst<R>& A, const EdgeState<R>& E, R T, int S,
+                            const float* __restrict__ obs, int n_obs, float margin_c, R& rv,
+                            R& rq, R& rc) {
+  const int lane = lane_id();
+  R v = 0, q = 0;
+  // lane i < 7 checks joint i (register selects keep the edge state in VGPRs)
+  R q0 = 0, qd0 = 0, dq = 0, d2v = 0;
+#pragma unroll
+  for (int i = 0; i < NJ; ++i)
+    if (lane == i) {
+      q0 = E.q0[i];
+      qd0 = E.qd0[i];
+      dq = E.dq[i];
+      d2v = E.d2[i];
+    }
+  if (lane < NJ) joint_post(A, lane, q0, qd0, dq, d2v, T, v, q);
+  // clearance: lane = (sample, sphere part); the parts split each link's
+  // spheres so that all 64 lanes work when S < 64
+  R best = 0;
+  if (n_obs > 0) {
+    int Sw = 1;
+    while (Sw < S) Sw <<= 1;
+    const int nparts = Sw >= WAVE ? 1 : WAVE / Sw;
+    const int s = lane & (Sw - 1), part = lane / Sw;
+    if (s < S && part < nparts) {
+      const R u = R(s) / R(S - 1);
+      R sg[NJ], sd[NJ], sdd[NJ], sn[NJ], cs[NJ];
+      cubic_point(E, T, R(1) / T, u, sg, sd, sdd);
+#pragma unroll
+      for (int i = 0; i < NJ; ++i) sincos_r(sg[i], sn[i], cs[i]);
+      sphere_centres<R, PAT>(A, sn, cs, part, nparts, [&](int k, R x, R y, R z) {
+        const R ra = A.sphr[k] + R(margin_c);
+        for (int o = 0; o < n_obs; ++o) {
+          const R dx = x - R(obs[4 * o]), dy = y - R(obs[4 * o + 1]), dz = z - R(obs[4 * o + 2]);
+          const R need = ra + R(obs[4 * o + 3]);
+          const R d2 = dx * dx + dy * dy + dz * dz;
+          const R r2 = d2 > R(0) ? fdiv(need * need, d2) : R(INFINITY);
+          best = rmax(best, r2);
+        }
+      });
+    }
+  }
+  if constexpr (sizeof(R) == 4) {
+    rv = wave_max(float(v));
+    rq = wave_max(float(q));
+    rc = sqrtf(wave_max(float(best)));
+  } else {
+    rv = wave_max(double(v));
+    rq = wave_max(double(q));
+    rc = sqrt(wave_max(double(best)));
+  }
+}
+
+__device__ __forceinline__ bool near_one(float r) { return fabsf(r - 1.f) <= BAND; }
+
+// Final status bits from the post-check ratios.
+template <typename R>
+__device__ __forceinline__ int post_status(R rv, R rq, R rc) {
+  int st = 0;
+  if (rv > R(1)) st |= FN_S_VEL;
+  if (rq > R(1)) st |= FN_S_POS;
+  if (rc > R(1)) st |= FN_S_COLL;
+  return st;
+}
+
+__device__ __forceinline__ void write_out(const EdgeArgs& a, int64_t e, int j, int st, float m,
+                                          float r0, float r1, float r2, float r3, int work,
+                                          float T = 0.f) {
+  if (lane_id() == 0) {
+    if (a.out_T) a.out_T[e] = j >= 0 ? T : 0.f;
+    a.out_j[e] = (int16_t)j;
+    a.out_st[e] = (uint16_t)st;
+    a.out_m[e] = m;
+    if (a.out_rho) {
+      a.out_rho[4 * e + 0] = r0;
+      a.out_rho[4 * e + 1] = r1;
+      a.out_rho[4 * e + 2] = r2;
+      a.out_rho[4 * e + 3] = r3;
+    }
+    if (a.out_work) a.out_work[e] = work;
+  }
+}
+
+__device__ __forceinline__ void push_queue(const EdgeArgs& a, int64_t e, int j, int phase,
+                                           float m, int work) {
+  if (lane_id() == 0) {
+    const int slot = atomicAdd(a.q_count, 1);
+    QEntry q;
+    q.edge = (int32_t)e;
+    q.j = (int16_t)j;
+    q.phase = (int16_t)phase;
+    q.margin = m;
+    q.work = work;
+    a.queue[slot] = q;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP32 search kernel
+//
+// The search of every mode is a short list of stages, each a slot range
+// that is either screened (endpoint samples) or scanned (full slots in
+// ascending order, certified slots skipped):
+//   PLAIN : scan [0, jmax]
+//   SCREEN: screen [0, jmax], scan [0, jmax]
+//   WINDOW: screen [0, lo-1], scan [0, lo-1], scan [lo, hi],
+//           screen [hi+1, jmax], scan [hi+1, jmax]
+// One loop walks the stages so that the evaluation of Eq. (4) has a single
+// call site.
+// ---------------------------------------------------------------------------
+enum { ST_SCREEN = 0, ST_SCAN = 1, ST_END = 2 };
+
+__device__ __forceinline__ void stage_of(int mode, int st, int jmax, int lo, int hi, int& type,
+                                         int& a, int& b, bool& below) {
+  below = false;
+  type = ST_END;
+  a = 0;
+  b = -1;
+  if (mode == FN_SEARCH_PLAIN) {
+    if (st == 0) { type = ST_SCAN; a = 0; b = jmax; }
+  } else if (mode == FN_SEARCH_SCREEN) {
+    if (st == 0) { type = ST_SCREEN; a = 0; b = jmax; }
+    if (st == 1) { type = ST_SCAN; a = 0; b = jmax; }
+  } else {
+    switch (st) {
+      case 0: type = ST_SCREEN; a = 0; b = lo - 1; break;
+      case 1: type = ST_SCAN; a = 0; b = lo - 1; below = true; break;
+      case 2: type = ST_SCAN; a = lo; b = hi; break;
+      case 3: type = ST_SCREEN; a = hi + 1; b = jmax; break;
+      case 4: type = ST_SCAN; a = hi + 1; b = jmax; break;
+      default: break;
+    }
+  }
+}
+
+// Slots still to be evaluated in full: bit j of word j / 64.
+struct SlotMask {
+  uint64_t w0, w1, w2, w3;
+  __device__ __forceinline__ uint64_t get(int i) const {
+    return i == 0 ? w0 : i == 1 ? w1 : i == 2 ? w2 : w3;
+  }
+  __device__ __forceinline__ void clear(int i, uint64_t m) {
+    if (i == 0) w0 &= ~m;
+    else if (i == 1) w1 &= ~m;
+    else if (i == 2) w2 &= ~m;
+    else w3 &= ~m;
+  }
+  // lowest set slot in [j, hi], or -1
+  __device__ __forceinline__ int next(int j, int hi) const {
+    while (j <= hi) {
+      const int w = j >> 6;
+      const uint64_t bits = get(w) & (~0ull << (j & 63));
+      if (bits) {
+        const int t = (w << 6) + __ffsll((long long)bits) - 1;
+        return t <= hi ? t : -1;
+      }
+      j = (w + 1) << 6;
+    }
+    return -1;
+  }
+};
+
+// Fixed duration of a goal edge (Algorithm 1 goal branch): t_req of the
+// candidate minus the parent's time-to-come.  Returns false for a free edge.
+__device__ __forceinline__ bool fixed_T(const EdgeArgs& a, int64_t e, float& T) {
+  if (!a.kind) return false;
+  const int64_t b = e / a.k;
+  if (a.kind[b] != 1) return false;
+  const int p = a.nbr[e];
+  T = a.t_req[b] - a.t_node[p];
+  return true;
+}
+
+// The search of one edge by one wavefront (see the stage list above).
+// eq: the edge's id in the FP64-stage queue; s_end: this wavefront's
+// FN_MAX_NT floats of LDS; s_T: the grid in LDS; s_fix: one float of LDS.
+template <int PAT>
+__device__ void search_edge(const EdgeArgs& a, int64_t e, int64_t eq, const ArmConst<float>& A,
+                            float* s_end, const float* s_T, float* s_fix) {
+  const int lane = lane_id();
+  EdgeState<float> ES;
+  int st0;
+  if (!load_edge(a, e, ES, st0)) {
+    write_out(a, e, -1, st0, st0 == FN_S_NO_PARENT ? INFINITY : 0.f, 0, 0, 0, 0, 0);
+    return;
+  }
+  // goal edges: one slot at the fixed duration
+  float Tfix;
+  const bool fixed = fixed_T(a, e, Tfix);
+  const float* Tg = s_T;
+  int n_t = a.n_t, mode = a.mode;
+  if (fixed) {
+    if (!isfinite(Tfix)) {
+      write_out(a, e, -1, FN_S_BAD_INPUT, 0.f, 0, 0, 0, 0, 0);
+      return;
+    }
+    if (!(Tfix > 0.f)) {
+      write_out(a, e, -1, FN_S_NONE, INFINITY, 0, 0, 0, 0, 0);
+      return;
+    }
+    if (lane == 0) s_fix[0] = Tfix;
+    __builtin_amdgcn_wave_barrier();
+    Tg = s_fix;
+    n_t = 1;
+    mode = FN_SEARCH_PLAIN;
+  }
+  int jmax = n_t - 1;
+  if (a.j_max && !fixed) jmax = min(jmax, (int)a.j_max[e]);
+  if (jmax < 0) {
+    write_out(a, e, -1, FN_S_NONE, INFINITY, 0, 0, 0, 0, 0);
+    return;
+  }
+  const int S = a.S, Sw = a.Sw, G = WAVE / Sw;
+  const int g = lane / Sw;
+  const float u_full = lane_u(lane, Sw, S);
+  const bool s_ok = (lane & (Sw - 1)) < S;
+
+  for (int j = lane; j < n_t; j += WAVE) s_end[j] = -1.f;  // -1: not screened
+  __builtin_amdgcn_wave_barrier();
+  SlotMask todo{~0ull, ~0ull, ~0ull, ~0ull};
+
+  int wlo = 0, whi = -1;
+  if (mode == FN_SEARCH_WINDOW) {
+    wlo = min(max((int)a.win_lo[e], 0), jmax + 1);
+    whi = min(wlo + 2 * a.win_half, jmax);
+  }
+
+  int work = 0;
+  float marg = INFINITY;  // over fully evaluated slots up to the result
+  float last = 0.f;
+  int jstar = -1;
+  float rho_star = 0.f;
+  bool below_full = false;
+  bool queued = false;
+
+  int stage = 0, type, sa, sb;
+  bool below;
+  stage_of(mode, stage, jmax, wlo, whi, type, sa, sb, below);
+  int j = sa;
+  while (type != ST_END) {
+    if (j > sb) {
+      ++stage;
+      stage_of(mode, stage, jmax, wlo, whi, type, sa, sb, below);
+      j = sa;
+      continue;
+    }
+    // lanes of this pass: slot `my` (or -1) and normalised time u
+    int my = -1, cnt = 0;
+    float u = u_full;
+    if (type == ST_SCREEN) {
+      // lane l: slot j + (l & 31), endpoint u = 0 (l < 32) or u = 1
+      const int jj = j + (lane & 31);
+      my = jj <= sb ? jj : -1;
+      u = lane >= 32 ? 1.f : 0.f;
+      cnt = min(WAVE / 2, sb - j + 1);
+      j += WAVE / 2;
+    } else {
+      // next G slots still to be evaluated; lane group g takes the g-th
+      while (cnt < G) {
+        const int t = todo.next(j, sb);
+        if (t < 0) {
+          j = sb + 1;
+          break;
+        }
+        if (cnt == g) my = t;
+        ++cnt;
+        j = t + 1;
+      }
+      if (cnt == 0) continue;  // range exhausted
+      if (!s_ok) my = -1;
+      if (below) below_full = true;
+    }
+    const bool act = my >= 0;
+    float r = 0.f;
+    if (act) {
+      const float T = Tg[my];
+      r = eval_rho<float, PAT>(A, ES, T, __builtin_amdgcn_rcpf(T), u);
+    }
+    work += __popcll(__ballot(act));
+    if (type == ST_SCREEN) {
+      r = fmaxf(r, __shfl_xor(r, 32));
+      if (act && lane < 32) s_end[my] = r;
+      // slots certified infeasible leave the to-do mask: bit t of the ballot
+      // is slot j0 + t, and the pass may straddle two 64-slot words
+      const int j0 = j - WAVE / 2;
+      const uint64_t bits = __ballot(act && lane < 32 && r > 1.f + BAND) & 0xffffffffull;
+      const int w0 = j0 >> 6, sh = j0 & 63;
+      todo.clear(w0, bits << sh);
+      if (sh > 32) todo.clear(w0 + 1, bits >> (64 - sh));
+      continue;
+    }
+    r = group_max(r, Sw);
+    bool done = false;
+    for (int q = 0; q < cnt; ++q) {
+      const float rho = __shfl(r, q * Sw);
+      const int jq = __shfl(my, q * Sw);
+      if (near_one(rho)) {
+        // decided in FP64: hand the edge over at slot jq
+        float m = INFINITY;
+        for (int t = lane; t < jq; t += WAVE)
+          if (s_end[t] > 1.f + BAND) m = fminf(m, s_end[t] - 1.f);
+        m = fminf(marg, wave_min(m));
+        push_queue(a, eq, jq, below_full ? PH_BELOW_FULL : 0, m, work);
+        queued = done = true;
+        break;
+      }
+      marg = fminf(marg, fabsf(rho - 1.f));
+      last = rho;
+      if (rho <= 1.f) {
+        jstar = jq;
+        rho_star = rho;
+        done = true;
+        break;
+      }
+    }
+    if (done) break;
+  }
+  if (queued) return;
+  __builtin_amdgcn_wave_barrier();
+  // certified-infeasible margin of the screened slots below the result
+  const int lim = jstar >= 0 ? jstar : jmax + 1;
+  float mc = INFINITY;
+  for (int t = lane; t < lim; t += WAVE)
+    if (s_end[t] > 1.f + BAND) mc = fminf(mc, s_end[t] - 1.f);
+  float m = fminf(marg, wave_min(mc));
+  int winbits = 0;
+  if (mode == FN_SEARCH_WINDOW) {
+    // hit: the result lies in the predicted window (or none was predicted
+    // and none exists); BELOW: a slot under the window needed a full pass
+    const bool hit = (jstar >= 0 && jstar >= wlo && jstar <= whi) || (jstar < 0 && wlo > jmax);
+    winbits = (hit ? FN_S_WIN_HIT : FN_S_WIN_MISS) | (below_full ? FN_S_WIN_BELOW : 0);
+  }
+  if (jstar < 0) {
+    // ratio of the last slot: its full value, else its screened endpoint value
+    const float lastv = s_end[jmax] > 1.f + BAND ? s_end[jmax] : last;
+    write_out(a, e, -1, FN_S_NONE | winbits, m, lastv, 0, 0, 0, work);
+    return;
+  }
+  float rv, rq, rc;
+  const float T = Tg[jstar];
+  post_checks<float, PAT>(A, ES, T, S, a.obs, a.n_obs, a.margin_c, rv, rq, rc);
+  if (near_one(rv) || near_one(rq) || (a.n_obs > 0 && near_one(rc))) {
+    push_queue(a, eq, jstar, PH_POST | (below_full ? PH_BELOW_FULL : 0), m, work);
+    return;
+  }
+  m = fminf(m, fminf(fabsf(rv - 1.f), fminf(fabsf(rq - 1.f), fabsf(rc - 1.f))));
+  write_out(a, e, jstar, post_status(rv, rq, rc) | winbits, m, rho_star, rv, rq, rc, work, T);
+}
+
+// FP64 stage of one queued edge (one wavefront).
+template <int PAT>
+__device__ void recheck_edge(const EdgeArgs& a, int64_t e, const QEntry& q,
+                             const ArmConst<float>& A, const ArmConst<double>& D, float* s_fix) {
+  const int lane = lane_id();
+  EdgeState<float> ES;
+  EdgeState<double> ED;
+  int st0;
+  load_edge(a, e, ES, st0);
+  load_edge(a, e, ED, st0);
+  float Tfix;
+  const bool fixed = fixed_T(a, e, Tfix);
+  if (fixed && lane == 0) s_fix[0] = Tfix;
+  __builtin_amdgcn_wave_barrier();
+  const float* Tg = fixed ? s_fix : a.grid;
+  int jmax = fixed ? 0 : a.n_t - 1;
+  if (a.j_max && !fixed) jmax = min(jmax, (int)a.j_max[e]);
+  const int S = a.S;
+  int work = q.work;
+  float marg = q.margin;
+  int jstar = -1;
+  double rho_star = 0;
+  float last = 0;
+  if (q.phase & PH_POST) {
+    jstar = q.j;
+    // the slot ratio itself is reported from FP32 (it was outside the band)
+    const float Tf = Tg[jstar];
+    float r = 0.f;
+    if (lane < S)
+      r = eval_rho<float, PAT>(A, ES, Tf, __builtin_amdgcn_rcpf(Tf), float(lane) / float(S - 1));
+    rho_star = wave_max(r);
+  } else {
+    for (int j = q.j; j <= jmax; ++j) {
+      const float Tf = Tg[j];
+      float r = 0.f;
+      if (lane < S)
+        r = eval_rho<float, PAT>(A, ES, Tf, __builtin_amdgcn_rcpf(Tf), float(lane) / float(S - 1));
+      float rho = wave_max(r);
+      work += S;
+      double rho_d = rho;
+      if (near_one(rho)) {
+        const double T = (double)Tf;
+        double rd = 0.0;
+        if (lane < S) rd = eval_rho<double, PAT>(D, ED, T, 1.0 / T, double(lane) / double(S - 1));
+        rho_d = wave_max(rd);
+      }
+      marg = fminf(marg, (float)fabs(rho_d - 1.0));
+      last = (float)rho_d;
+      if (rho_d <= 1.0) {
+        jstar = j;
+        rho_star = rho_d;
+        break;
+      }
+    }
+  }
+  int winbits = 0;
+  if (a.mode == FN_SEARCH_WINDOW && !fixed) {
+    const int wlo = min(max((int)a.win_lo[e], 0), jmax + 1);
+    const int whi = min(wlo + 2 * a.win_half, jmax);
+    const bool below = (q.phase & PH_BELOW_FULL) != 0;
+    const bool hit = (jstar >= 0 && jstar >= wlo && jstar <= whi) || (jstar < 0 && wlo > jmax);
+    winbits = (hit ? FN_S_WIN_HIT : FN_S_WIN_MISS) | (below ? FN_S_WIN_BELOW : 0);
+  }
+  if (jstar < 0) {
+    write_out(a, e, -1, FN_S_NONE | FN_S_RECHECK64 | winbits, marg, last, 0, 0, 0, work);
+    return;
+  }
+  double rv, rq, rc;
+  post_checks<double, PAT>(D, ED, (double)Tg[jstar], S, a.obs, a.n_obs, a.margin_c, rv, rq, rc);
+  const float m = fminf(marg, (float)fmin(fabs(rv - 1.0), fmin(fabs(rq - 1.0), fabs(rc - 1.0))));
+  write_out(a, e, jstar, post_status(rv, rq, rc) | FN_S_RECHECK64 | winbits, m, (float)rho_star,
+            (float)rv, (float)rq, (float)rc, work, Tg[jstar]);
+}
+
+// Several problems in one launch: edge ranges per problem (prefix offsets,
+// n + 1 entries) and each problem's arguments, on the device.
+struct ProbTable {
+  int n;
+  const int64_t* __restrict__ edge_off;
+  const EdgeArgs* __restrict__ args;
+};
+
+// problem of a global edge id (binary search over the offsets)
+__device__ __forceinline__ int problem_of(const ProbTable& pt, int64_t eg) {
+  int lo = 0, hi = pt.n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (pt.edge_off[mid] <= eg) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// FP64 stage over the queue; pt.n == 0: one problem (a).
+template <int PAT>
+__global__ __launch_bounds__(64) void edge_recheck_kernel(EdgeArgs a, ProbTable pt,
+                                                          const ArmConst<float>* __restrict__ Ap,
+                                                          const ArmConst<double>* __restrict__ Dp) {
+  __shared__ float s_fix[1];
+  const int n = *a.q_count;
+  for (int qi = blockIdx.x; qi < n; qi += gridDim.x) {
+    const QEntry q = a.queue[qi];
+    const EdgeArgs* ap = &a;
+    int64_t e = q.edge;
+    if (pt.n > 0) {
+      const int p = problem_of(pt, q.edge);
+      ap = pt.args + p;
+      e -= pt.edge_off[p];
+    }
+    recheck_edge<PAT>(*ap, e, q, *Ap, *Dp, s_fix);
+  }
+}
+
+}  // namespace fn

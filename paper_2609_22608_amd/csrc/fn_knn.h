@@ -1,0 +1,317 @@
+// fn_knn.h -- Parents(T, x, M) of Algorithm 1: brute-force k nearest tree
+// nodes by Euclidean distance in the 14-D state space (Sec. IV-E).
+//
+// Stage 1 (knn_scan): one wavefront per (4 queries, node chunk); lanes run
+// over the chunk's nodes with coalesced loads of the SoA tree rows, every
+// distance costs 14 subtractions and 14 FMAs, and each query keeps its
+// chunk's k+1 smallest FP32 keys (d^2, index) spread over lanes 0..k.
+// Stage 2 (knn_merge): one wavefront per query merges the chunk lists.  The
+// FP32 k-th key bounds a band that provably holds the exact top-k; every
+// candidate in the band is re-ranked with the FP64 distance summed in the
+// reference order (c = 0..13, separately rounded products and sums).  When
+// a chunk's (k+1)-th entry also falls in the band (near ties that the FP32
+// lists may have cut), the query is rescanned exactly in FP64.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fn_ctx.h"
+
+namespace fn {
+
+constexpr int KNN_TARGET_WAVES = 4096;
+constexpr float KNN_BAND = 1e-6f;  // slack for rounding the band itself
+constexpr float KNN_EPS = 4e-6f;   // |d32 - d| <= KNN_EPS (|x| + |y|)^2 (twice the FP32 bound)
+
+__device__ __forceinline__ bool key_less(float d, int i, float d2, int i2) {
+  return d < d2 || (d == d2 && (unsigned)i < (unsigned)i2);
+}
+
+// lane r takes lane r-1's value (DPP wave shift; lane 0 gets 0)
+__device__ __forceinline__ float wave_shr1(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x138,
+                                                            0xf, 0xf, true));
+}
+__device__ __forceinline__ int wave_shr1(int v) {
+  return __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true);
+}
+
+// One wavefront per (QG queries, node chunk).  Lanes run over 64 nodes at
+// a time (coalesced loads of the SoA rows).  The FP32 screening distance is
+// |x|^2 + |y|^2 - 2 x.y (14 FMAs per pair, |y|^2 shared by the QG queries);
+// its absolute error is below 4e-6 (|x| + |y|)^2, a bound the merge carries
+// into the band it re-ranks exactly.  Every query's k+1 best keys
+// (d^2, index) live distributed over lanes 0..K1-1; the K1-th is a
+// wave-uniform threshold, so a node costs a ballot unless it beats it.
+template <int K1, int QG>
+__device__ void knn_scan_item(const float* __restrict__ tree, int64_t ld, int n_nodes,
+                              const float* __restrict__ qs, int B, int grp, int ch, int n_split,
+                              int chunk, float* __restrict__ out_d, int32_t* __restrict__ out_i,
+                              float* __restrict__ out_y2) {
+  const int lane = threadIdx.x & 63;
+  float xm2[QG][FN_STATE], xx[QG];
+#pragma unroll
+  for (int q = 0; q < QG; ++q) {
+    const int b = min(grp * QG + q, B - 1);
+    float s2 = 0.f;
+#pragma unroll
+    for (int c = 0; c < FN_STATE; ++c) {
+      const float v = qs[(size_t)b * FN_STATE + c];
+      xm2[q][c] = -2.f * v;
+      s2 = fmaf(v, v, s2);
+    }
+    xx[q] = s2;
+  }
+  float Ld[QG];
+  int Li[QG];
+  float th_d[QG];
+  int th_i[QG];
+#pragma unroll
+  for (int q = 0; q < QG; ++q) {
+    Ld[q] = INFINITY;
+    Li[q] = -1;
+    th_d[q] = INFINITY;
+    th_i[q] = -1;
+  }
+  float y2max = 0.f;
+  const int n0 = ch * chunk;
+  const int n1 = min(n0 + chunk, n_nodes);
+  for (int nb = n0; nb < n1; nb += WAVE) {
+    const int node = nb + lane;
+    const bool valid = node < n1;
+    const int nc = valid ? node : n1 - 1;
+    float y[FN_STATE];
+    float yy = 0.f;
+#pragma unroll
+    for (int c = 0; c < FN_STATE; ++c) {
+      y[c] = tree[(size_t)c * ld + nc];
+      yy = fmaf(y[c], y[c], yy);
+    }
+    y2max = fmaxf(y2max, yy);
+#pragma unroll
+    for (int q = 0; q < QG; ++q) {
+      float d = yy + xx[q];
+#pragma unroll
+      for (int c = 0; c < FN_STATE; ++c) d = fmaf(xm2[q][c], y[c], d);
+      d = valid ? d : INFINITY;
+      // nodes arrive in increasing index, so an equal distance never beats
+      // the threshold entry
+      uint64_t mask = __ballot(d < th_d[q]);
+      while (mask) {
+        const int src = __ffsll((long long)mask) - 1;
+        mask &= mask - 1;
+        const float dd = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, d), src));
+        const int ii = nb + src;
+        if (!key_less(dd, ii, th_d[q], th_i[q])) continue;
+        // insert into the distributed sorted list (lane r holds entry r)
+        const float pd = wave_shr1(Ld[q]);
+        const int pi = wave_shr1(Li[q]);
+        const bool lt_here = key_less(dd, ii, Ld[q], Li[q]);
+        const bool lt_prev = lane > 0 && key_less(dd, ii, pd, pi);
+        Ld[q] = lane >= K1 ? INFINITY : lt_prev ? pd : lt_here ? dd : Ld[q];
+        Li[q] = lane >= K1 ? -1 : lt_prev ? pi : lt_here ? ii : Li[q];
+        th_d[q] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, Ld[q]), K1 - 1));
+        th_i[q] = __builtin_amdgcn_readlane(Li[q], K1 - 1);
+      }
+    }
+  }
+  y2max = wave_max(y2max);
+#pragma unroll
+  for (int q = 0; q < QG; ++q) {
+    const int b = grp * QG + q;
+    if (b < B) {
+      if (lane < K1) {
+        const size_t base = ((size_t)b * n_split + ch) * K1;
+        out_d[base + lane] = Ld[q];
+        out_i[base + lane] = Li[q];
+      }
+      if (lane == 0) out_y2[(size_t)b * n_split + ch] = y2max;
+    }
+  }
+}
+
+// FP64 squared distance, summed in the reference order with separately
+// rounded operations.
+__device__ __forceinline__ double exact_d2(const float* __restrict__ tree, int64_t ld, int node,
+                                           const double* x) {
+  double d = 0.0;
+#pragma unroll
+  for (int c = 0; c < FN_STATE; ++c) {
+    const double t = __dsub_rn(x[c], (double)tree[(size_t)c * ld + node]);
+    d = __dadd_rn(d, __dmul_rn(t, t));
+  }
+  return d;
+}
+
+__device__ __forceinline__ unsigned long long dkey(double d) {
+  return (unsigned long long)__double_as_longlong(d);
+}
+
+// wave-wide argmin over (d64, idx) keys held one per lane; returns the
+// winning lane's (d, idx) in every lane.
+__device__ __forceinline__ void wave_argmin(double d, int idx, double& wd, int& wi) {
+  unsigned long long k = dkey(d);
+  unsigned long long m = k;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const unsigned long long v = __shfl_xor(m, o);
+    m = v < m ? v : m;
+  }
+  unsigned mi = (k == m) ? (unsigned)idx : 0xffffffffu;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const unsigned v = __shfl_xor(mi, o);
+    mi = v < mi ? v : mi;
+  }
+  wd = __longlong_as_double((long long)m);
+  wi = (int)mi;
+}
+
+template <int K1>
+__device__ void knn_merge_query(const float* __restrict__ tree, int64_t ld, int n_nodes,
+                                const float* __restrict__ qs, int b, int k, int n_split,
+                                const float* __restrict__ in_d, const int32_t* __restrict__ in_i,
+                                const float* __restrict__ in_y2, int32_t* __restrict__ out_idx,
+                                float* __restrict__ out_d2) {
+  const int lane = threadIdx.x & 63;
+  double x[FN_STATE];
+#pragma unroll
+  for (int c = 0; c < FN_STATE; ++c) x[c] = (double)qs[(size_t)b * FN_STATE + c];
+  const int total = n_split * K1;
+  const float* D = in_d + (size_t)b * total;
+  const int32_t* I = in_i + (size_t)b * total;
+
+  // (a) FP32 k-th smallest key among every chunk's first k entries
+  float th_d = -1.f;
+  int th_i = -1;
+  for (int r = 0; r < k; ++r) {
+    float bd = INFINITY;
+    int bi = -1;
+    for (int e = lane; e < total; e += 64) {
+      if (e % K1 >= k) continue;
+      const float d = D[e];
+      const int i = I[e];
+      if (i < 0) continue;
+      const bool after = th_i < 0 ? true : key_less(th_d, th_i, d, i);
+      if (after && key_less(d, i, bd, bi)) {
+        bd = d;
+        bi = i;
+      }
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      const float od = __shfl_xor(bd, o);
+      const int oi = __shfl_xor(bi, o);
+      if (key_less(od, oi, bd, bi)) {
+        bd = od;
+        bi = oi;
+      }
+    }
+    if (bi < 0) break;  // fewer than k nodes in total
+    th_d = bd;
+    th_i = bi;
+  }
+  // absolute error bound of the FP32 screening distances of this query:
+  // 4e-6 (|x| + max |y|)^2, max over every chunk (the whole tree)
+  float y2 = 0.f;
+  for (int c2 = lane; c2 < n_split; c2 += 64) y2 = fmaxf(y2, in_y2[(size_t)b * n_split + c2]);
+  y2 = wave_max(y2);
+  double xn = 0.0;
+#pragma unroll
+  for (int c = 0; c < FN_STATE; ++c) xn += x[c] * x[c];
+  const float rad = (float)sqrt(xn) + sqrtf(y2);
+  const float eps = KNN_EPS * rad * rad;
+  // every exact top-k node has a screening key within th + 2 eps
+  const float band = th_i < 0 ? INFINITY : th_d + 2.f * eps + fabsf(th_d) * KNN_BAND + 1e-30f;
+
+  // (b) a chunk whose (k+1)-th entry is inside the band may have cut near ties
+  int over = 0;
+  for (int e = lane; e < total; e += 64)
+    if (e % K1 == k && I[e] >= 0 && D[e] <= band) over = 1;
+  over = __any(over);
+
+  if (!over) {
+    // (c) FP64 re-rank of the band (computed once into LDS), then k rounds
+    // of wave argmin over (d64, index)
+    __shared__ double s_d[KNN_MAX_SPLIT * (FN_MAX_K + 1)];
+    for (int e = lane; e < total; e += 64) {
+      const int i = I[e];
+      const bool in = (e % K1 < k) && i >= 0 && D[e] <= band;
+      s_d[e] = in ? exact_d2(tree, ld, i, x) : INFINITY;
+    }
+    __syncthreads();
+    double prev_d = -1.0;
+    int prev_i = -1;
+    for (int r = 0; r < k; ++r) {
+      double bd = INFINITY;
+      int bi = 0x7fffffff;
+      for (int e = lane; e < total; e += 64) {
+        const double d = s_d[e];
+        if (!(d < INFINITY)) continue;
+        const int i = I[e];
+        const bool after = prev_i < 0 || d > prev_d || (d == prev_d && i > prev_i);
+        if (after && (d < bd || (d == bd && i < bi))) {
+          bd = d;
+          bi = i;
+        }
+      }
+      double wd;
+      int wi;
+      wave_argmin(bd, bi, wd, wi);
+      if (wi == 0x7fffffff) {
+        wd = INFINITY;
+        wi = -1;
+      } else {
+        prev_d = wd;
+        prev_i = wi;
+      }
+      if (lane == 0) {
+        out_idx[(size_t)b * k + r] = wi;
+        if (out_d2) out_d2[(size_t)b * k + r] = (float)wd;
+      }
+    }
+  } else {
+    // (d) exact FP64 rescan of the whole tree for this query: each lane keeps
+    // a sorted list of its k best, then k rounds of wave argmin over heads
+    double ld_d[FN_MAX_K];
+    int ld_i[FN_MAX_K];
+    for (int r = 0; r < k; ++r) {
+      ld_d[r] = INFINITY;
+      ld_i[r] = 0x7fffffff;
+    }
+    for (int n = lane; n < n_nodes; n += 64) {
+      const double d = exact_d2(tree, ld, n, x);
+      if (d < ld_d[k - 1]) {  // a lane's nodes come in increasing index
+        int r = k - 1;
+        while (r > 0 && d < ld_d[r - 1]) {
+          ld_d[r] = ld_d[r - 1];
+          ld_i[r] = ld_i[r - 1];
+          --r;
+        }
+        ld_d[r] = d;
+        ld_i[r] = n;
+      }
+    }
+    int head = 0;
+    for (int r = 0; r < k; ++r) {
+      const double hd = head < k ? ld_d[head] : INFINITY;
+      const int hi = head < k ? ld_i[head] : 0x7fffffff;
+      double wd;
+      int wi;
+      wave_argmin(hd, hi, wd, wi);
+      if (wi != 0x7fffffff && wi == hi) ++head;
+      if (wi == 0x7fffffff) {
+        wd = INFINITY;
+        wi = -1;
+      }
+      if (lane == 0) {
+        out_idx[(size_t)b * k + r] = wi;
+        if (out_d2) out_d2[(size_t)b * k + r] = (float)wd;
+      }
+    }
+  }
+}
+
+constexpr int KNN_QG = 4;  // queries per scan wavefront
+
+}  // namespace fn

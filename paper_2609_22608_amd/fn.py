@@ -47,7 +47,11 @@ class ArmDesc(C.Structure):
 
 class Caps(C.Structure):
     _fields_ = [("max_nodes", C.c_int32), ("max_batch", C.c_int32), ("max_k", C.c_int32),
-                ("max_edges", C.c_int64)]
+                ("max_edges", C.c_int64), ("max_problems", C.c_int32)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("knn_target_waves", C.c_int32), ("knn_min_chunk", C.c_int32)]
 
 
 class Search(C.Structure):
@@ -78,6 +82,23 @@ class Risk(C.Structure):
                 ("wv", C.c_double), ("vtarget", C.c_double), ("wp", C.c_double),
                 ("wr", C.c_double), ("wx", C.c_double), ("r", C.c_double), ("nu0", C.c_double),
                 ("lam", C.c_double)]
+
+
+class Problem(C.Structure):
+    _fields_ = [("tree", C.c_void_p), ("ld", C.c_int64), ("n_nodes", C.c_void_p),
+                ("t_node", C.c_void_p), ("parent", C.c_void_p), ("nu", C.c_void_p),
+                ("cand", C.c_void_p), ("kind", C.c_void_p), ("t_req", C.c_void_p),
+                ("v_rel", C.c_void_p), ("vz0", C.c_void_p), ("t_fall", C.c_void_p),
+                ("B", C.c_int32), ("obs", C.c_void_p), ("n_obs", C.c_int32), ("nbr", C.c_void_p),
+                ("out_j", C.c_void_p), ("out_status", C.c_void_p), ("out_margin", C.c_void_p),
+                ("out_rho4", C.c_void_p), ("out_T", C.c_void_p), ("out_node", C.c_void_p),
+                ("out_J", C.c_void_p), ("out_best", C.c_void_p)]
+
+
+class ProblemSet(C.Structure):
+    _fields_ = [("n_problems", C.c_int32), ("problems", C.POINTER(Problem)), ("k", C.c_int32),
+                ("grid", C.c_void_p), ("n_t", C.c_int32), ("samples", C.c_int32),
+                ("mode", C.c_int32), ("margin", C.c_float), ("risk", Risk)]
 
 
 _lib = None
@@ -114,6 +135,11 @@ def lib():
             L.surrogate_train.argtypes = [vp, vp, vp, vp, i64, C.POINTER(TrainCfg), vp, vp]
             L.surrogate_grad.argtypes = [vp, vp, vp, vp, i32, vp, i32, vp, vp, vp]
             L.surrogate_infer.argtypes = [vp, vp, vp, i64, vp, i32, i32, C.c_float, vp, vp, vp]
+            L.fn_set_tuning.argtypes = [vp, C.POINTER(Tuning)]
+            L.fn_batch_prepare.argtypes = [vp, C.POINTER(ProblemSet)]
+            L.fn_batch_launch.argtypes = [vp, vp]
+            L.fn_graph_capture.argtypes = [vp, vp]
+            L.fn_graph_launch.argtypes = [vp, vp]
             _lib = L
     return _lib
 
@@ -160,6 +186,10 @@ def arm_desc(arm, terms: int = T_ALL) -> ArmDesc:
     return d
 
 
+def version() -> str:
+    return lib().fn_version().decode()
+
+
 def tree_soa(states, device="cuda", capacity=None):
     """Structure-of-arrays device copy of tree states [n][14] -> [14][ld]
     (ld a multiple of 4, padding zero).  Returns (tensor, ld, n)."""
@@ -179,11 +209,13 @@ def dev(x, dtype=torch.float32, device="cuda"):
 class Context:
     """An fn_ctx on the current device."""
 
-    def __init__(self, arm, max_nodes, max_batch, max_k, max_edges=None, terms: int = T_ALL):
+    def __init__(self, arm, max_nodes, max_batch, max_k, max_edges=None, terms: int = T_ALL,
+                 max_problems: int = 0):
         torch.cuda.init()
         self._desc = arm_desc(arm, terms)
         caps = Caps(int(max_nodes), int(max_batch), int(max_k),
-                    int(max_edges if max_edges is not None else max_batch * max_k))
+                    int(max_edges if max_edges is not None else max_batch * max_k),
+                    int(max_problems))
         self.caps = caps
         h = C.c_void_p()
         _check(lib().fn_create(C.byref(self._desc), C.byref(caps), C.byref(h)), "fn_create")
@@ -199,6 +231,10 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def set_tuning(self, knn_target_waves=0, knn_min_chunk=0):
+        t = Tuning(int(knn_target_waves), int(knn_min_chunk))
+        _check(lib().fn_set_tuning(self.h, C.byref(t)), "fn_set_tuning")
 
     # -- plan_knn -----------------------------------------------------------
     def plan_knn(self, tree, ld, n_nodes, queries, k, out_idx=None, out_d2=None, want_d2=True):
@@ -334,6 +370,84 @@ class Surrogate:
                                      int(half), float(logit_min), _ptr(out), _ptr(win_lo),
                                      _stream()), "surrogate_infer")
         return out, win_lo
+
+
+class Batch:
+    """A batched planning iteration over several problems (fn_problem_set).
+
+    Each problem is a dict of device tensors; ``add_problem`` allocates them
+    from host arrays.  ``prepare`` uploads the tables; ``launch`` enqueues one
+    round; ``capture`` / ``replay`` use a HIP graph."""
+
+    def __init__(self, ctx: Context, grid, samples, k, mode=SEARCH_SCREEN, margin=0.0, risk=None):
+        self.ctx, self.grid, self.samples, self.k = ctx, grid, int(samples), int(k)
+        self.mode, self.margin = int(mode), float(margin)
+        self.risk = risk if risk is not None else make_risk(sigma_mode=1, s0=0.01, s1=0.05)
+        self.problems = []
+
+    def add_problem(self, tree_x, tree_t, cand, obs, capacity):
+        """tree_x [n][14], tree_t [n], cand dict (x, kind, t_req, flight), obs [m][4]."""
+        d = "cuda"
+        n = len(tree_x)
+        tree, ld, _ = tree_soa(tree_x, capacity=capacity)
+        B = len(cand["x"])
+        k = self.k
+        t_node = torch.zeros(ld, dtype=torch.float32, device=d)
+        t_node[:n] = torch.as_tensor(np.asarray(tree_t, np.float32))
+        fl = cand["flight"]
+        P = dict(tree=tree, ld=ld, n0=n, n_nodes=torch.tensor([n], dtype=torch.int32, device=d),
+                 t_node=t_node, t_node0=t_node.clone(), tree0=tree.clone(),
+                 parent=torch.full((ld,), -1, dtype=torch.int32, device=d),
+                 nu=torch.zeros(ld, dtype=torch.float32, device=d),
+                 cand=dev(cand["x"]), kind=dev(cand["kind"], torch.int32), t_req=dev(cand["t_req"]),
+                 v_rel=dev(fl["v_rel"]), vz0=dev(np.asarray(fl["v0"])[:, 2]), t_fall=dev(fl["t_fall"]),
+                 B=B, obs=dev(obs) if len(obs) else None, n_obs=len(obs),
+                 nbr=torch.empty((B, k), dtype=torch.int32, device=d),
+                 out_j=torch.empty(B * k, dtype=torch.int16, device=d),
+                 out_status=torch.empty(B * k, dtype=torch.int16, device=d),
+                 out_margin=torch.empty(B * k, dtype=torch.float32, device=d),
+                 out_rho4=torch.empty((B * k, 4), dtype=torch.float32, device=d),
+                 out_T=torch.empty(B * k, dtype=torch.float32, device=d),
+                 out_node=torch.empty(B, dtype=torch.int32, device=d),
+                 out_J=torch.empty(B, dtype=torch.float32, device=d),
+                 out_best=torch.empty(2, dtype=torch.float32, device=d))
+        self.problems.append(P)
+        return P
+
+    def reset_trees(self):
+        """Back to the initial trees (node counts, times, parents, states)."""
+        for P in self.problems:
+            P["n_nodes"].fill_(P["n0"])
+            P["t_node"].copy_(P["t_node0"])
+            P["tree"].copy_(P["tree0"])
+            P["parent"].fill_(-1)
+            P["nu"].zero_()
+
+    def prepare(self):
+        arr = (Problem * len(self.problems))()
+        for i, P in enumerate(self.problems):
+            q = arr[i]
+            for key in ("tree", "n_nodes", "t_node", "parent", "nu", "cand", "kind", "t_req",
+                        "v_rel", "vz0", "t_fall", "nbr", "out_j", "out_status", "out_margin",
+                        "out_rho4", "out_T", "out_node", "out_J", "out_best"):
+                setattr(q, key, P[key].data_ptr())
+            q.ld, q.B, q.n_obs = P["ld"], P["B"], P["n_obs"]
+            q.obs = None if P["obs"] is None else P["obs"].data_ptr()
+        self._arr = arr
+        ps = ProblemSet(len(self.problems), arr, self.k, self.grid.data_ptr(), self.grid.shape[0],
+                        self.samples, self.mode, self.margin, self.risk)
+        _check(lib().fn_batch_prepare(self.ctx.h, C.byref(ps)), "fn_batch_prepare")
+
+    def launch(self):
+        _check(lib().fn_batch_launch(self.ctx.h, _stream()), "fn_batch_launch")
+
+    def capture(self, stream):
+        with torch.cuda.stream(stream):
+            _check(lib().fn_graph_capture(self.ctx.h, C.c_void_p(stream.cuda_stream)),
+                   "fn_graph_capture")
+
+    def replay(self):
+        _check(lib().fn_graph_launch(self.ctx.h, _stream()), "fn_graph_launch")
 
 
 def edge_features(ctx: Context, tree, ld, n_nodes, cand, nbr, out=None):
