@@ -176,13 +176,16 @@ typedef struct {
  * the result slot (at the last slot when none), rho_v, rho_q, rho_c) where
  * rho_c = max (r_a + r_o + margin)/distance.  margin: the smallest
  * |rho - 1| over the ratios the decision rests on.  work (nullable): number
- * of (slot, sample) evaluations of Eq. (4) performed for the edge. */
+ * of (slot, sample) evaluations of Eq. (4) performed for the edge.
+ * screened (nullable): number of slots whose two endpoint ratios were
+ * evaluated from the endpoint models (screening and window modes). */
 typedef struct {
   int16_t* j;          /* T index (first feasible slot) or -1 */
   uint16_t* status;    /* FN_S_* bits */
   float* margin;
   float* rho4;         /* [E][4] or NULL */
   int32_t* work;       /* or NULL */
+  int16_t* screened;   /* or NULL */
 } fn_edge_out;
 
 /* ------------------------------------------------------------------ */

@@ -95,20 +95,44 @@ __global__ __launch_bounds__(64) void batch_knn_merge(const KnnProb* __restrict_
                       part_d + q.part_off, part_i + q.part_off, part_y + q.y_off, q.nbr, nullptr);
 }
 
+// EDGE_WAVES edges per workgroup (see edge_time_kernel).
 template <int PAT>
-__global__ __launch_bounds__(256) void batch_edge_kernel(ProbTable pt, const float* __restrict__ grid,
-                                                         int n_t,
-                                                         const ArmConst<float>* __restrict__ Ap) {
-  __shared__ float s_end_all[4][FN_MAX_NT];
+__global__ __launch_bounds__(64 * EDGE_WAVES) __attribute__((amdgpu_waves_per_eu(3))) void
+batch_edge_kernel(ProbTable pt, const float* __restrict__ grid, int n_t,
+                  const ArmConst<float>* __restrict__ Ap) {
+  __shared__ float s_end_all[EDGE_WAVES][FN_MAX_NT];
   __shared__ float s_T[FN_MAX_NT];
-  __shared__ float s_fix[4];
+  __shared__ float s_fix[EDGE_WAVES];
+  __shared__ float s_mod[EDGE_WAVES][2 * MODEL_FLOATS];
   for (int t = threadIdx.x; t < n_t; t += blockDim.x) s_T[t] = grid[t];
   __syncthreads();
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t eg = (int64_t)blockIdx.x * 4 + wave;
+  const int64_t eg = (int64_t)blockIdx.x * EDGE_WAVES + wave;
   if (eg >= pt.edge_off[pt.n]) return;
   const int p = problem_of(pt, eg);
-  search_edge<PAT>(pt.args[p], eg - pt.edge_off[p], eg, *Ap, s_end_all[wave], s_T, &s_fix[wave]);
+  search_edge<PAT>(pt.args[p], eg - pt.edge_off[p], eg, *Ap, s_end_all[wave], s_T, &s_fix[wave],
+                   s_mod[wave]);
+}
+
+// Endpoint models of every problem's states: 8 lanes per state, first the
+// parents of all edges (global edge order), then all candidates.
+template <int PAT>
+__global__ __launch_bounds__(256) void batch_model_kernel(ProbTable pt,
+                                                          const int64_t* __restrict__ cand_off,
+                                                          const ArmConst<float>* __restrict__ Ap) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t st = t >> 3;
+  const int role = (int)(t & 7);
+  const int64_t ne = pt.edge_off[pt.n];
+  if (st < ne) {
+    const int p = problem_of(pt, st);
+    model_state<PAT>(pt.args[p], st - pt.edge_off[p], role, *Ap);
+  } else if (st < ne + cand_off[pt.n]) {
+    const int64_t cb = st - ne;
+    const int p = bsearch_off(cand_off, pt.n, cb);
+    const EdgeArgs& a = pt.args[p];
+    model_state<PAT>(a, a.E + (cb - cand_off[p]), role, *Ap);
+  }
 }
 
 // Attachment and scoring, one workgroup per problem: candidate b picks the
@@ -211,7 +235,7 @@ using namespace fn;
 // Host-side batch state (part of the context).
 struct fn_batch {
   int n = 0;
-  int K1 = 0, k = 0, n_t = 0, pattern = 0;
+  int K1 = 0, k = 0, n_t = 0, pattern = 0, mode = 0;
   const float* grid = nullptr;
   fn_risk risk{};
   int64_t pairs = 0, queries = 0, edges = 0;
@@ -308,7 +332,9 @@ extern "C" int fn_batch_prepare(fn_ctx* c, const fn_problem_set* ps) {
     a.win_half = 0; a.j_max = nullptr; a.win_lo = nullptr;
     a.obs = q.obs; a.n_obs = q.n_obs; a.margin_c = ps->margin;
     a.out_j = q.out_j; a.out_st = q.out_status; a.out_m = q.out_margin; a.out_rho = q.out_rho4;
-    a.out_work = nullptr; a.q_count = c->q_count; a.queue = c->queue;
+    a.out_work = nullptr; a.out_scr = nullptr; a.q_count = c->q_count; a.queue = c->queue;
+    a.model_e = c->model_e + eo[p] * MODEL_FLOATS;
+    a.model_c = c->model_c + qo[p] * MODEL_FLOATS;
     a.kind = q.kind; a.t_req = q.t_req; a.t_node = q.t_node; a.out_T = q.out_T;
     ip[p] = InsProb{q.tree, q.ld, q.n_nodes, q.t_node, q.parent, q.nu, q.cand, q.kind, q.v_rel,
                     q.vz0, q.t_fall, q.B, q.nbr, q.out_j, q.out_status, q.out_rho4, q.out_T,
@@ -331,6 +357,7 @@ extern "C" int fn_batch_prepare(fn_ctx* c, const fn_problem_set* ps) {
   bt->grid = ps->grid;
   bt->risk = ps->risk;
   bt->pattern = c->pattern;
+  bt->mode = ps->mode;
   bt->pairs = po[n];
   bt->queries = qo[n];
   bt->edges = eo[n];
@@ -360,13 +387,17 @@ extern "C" int fn_batch_launch(fn_ctx* c, void* stream) {
   }
   hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, s, c->q_count, 1);
   const ProbTable pt{bt->n, bt->edge_off, bt->args};
-  const dim3 grid((unsigned)((bt->edges + 3) / 4));
+  const dim3 grid((unsigned)((bt->edges + EDGE_WAVES - 1) / EDGE_WAVES));
+  const dim3 mgrid((unsigned)(((bt->edges + bt->queries) * 8 + 255) / 256));
+  const bool screens = bt->mode != FN_SEARCH_PLAIN;
   const unsigned rw = (unsigned)(bt->edges < 4096 ? bt->edges : 4096);
   if (bt->pattern == PAT_FR3) {
-    hipLaunchKernelGGL(batch_edge_kernel<PAT_FR3>, grid, dim3(256), 0, s, pt, bt->grid, bt->n_t, c->arm32);
+    if (screens) hipLaunchKernelGGL(batch_model_kernel<PAT_FR3>, mgrid, dim3(256), 0, s, pt, bt->query_off, c->arm32);
+    hipLaunchKernelGGL(batch_edge_kernel<PAT_FR3>, grid, dim3(64 * EDGE_WAVES), 0, s, pt, bt->grid, bt->n_t, c->arm32);
     hipLaunchKernelGGL(edge_recheck_kernel<PAT_FR3>, dim3(rw), dim3(64), 0, s, bt->a0, pt, c->arm32, c->arm64);
   } else {
-    hipLaunchKernelGGL(batch_edge_kernel<PAT_GENERIC>, grid, dim3(256), 0, s, pt, bt->grid, bt->n_t, c->arm32);
+    if (screens) hipLaunchKernelGGL(batch_model_kernel<PAT_GENERIC>, mgrid, dim3(256), 0, s, pt, bt->query_off, c->arm32);
+    hipLaunchKernelGGL(batch_edge_kernel<PAT_GENERIC>, grid, dim3(64 * EDGE_WAVES), 0, s, pt, bt->grid, bt->n_t, c->arm32);
     hipLaunchKernelGGL(edge_recheck_kernel<PAT_GENERIC>, dim3(rw), dim3(64), 0, s, bt->a0, pt, c->arm32, c->arm64);
   }
   hipLaunchKernelGGL(batch_insert_kernel, dim3(bt->n), dim3(INS_THREADS), 0, s, bt->ins, bt->k, bt->risk);

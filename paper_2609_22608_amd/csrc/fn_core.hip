@@ -191,6 +191,8 @@ extern "C" int fn_create(const fn_arm_desc* arm, const fn_caps* caps, fn_ctx** o
   // near-limit queue: counter + one entry per edge
   FN_ALLOC(c->q_count, 64 * sizeof(int32_t));
   FN_ALLOC(c->queue, (size_t)(caps->max_edges > 0 ? caps->max_edges : 1) * sizeof(QEntry));
+  FN_ALLOC(c->model_e, (size_t)caps->max_edges * MODEL_FLOATS * sizeof(float));
+  FN_ALLOC(c->model_c, (size_t)caps->max_batch * MODEL_FLOATS * sizeof(float));
 #undef FN_ALLOC
   {
     const int brc = batch_alloc(c);
@@ -229,6 +231,8 @@ extern "C" void fn_destroy(fn_ctx* c) {
   (void)hipFree(c->knn_y);
   (void)hipFree(c->q_count);
   (void)hipFree(c->queue);
+  (void)hipFree(c->model_e);
+  (void)hipFree(c->model_c);
   delete c;
 }
 

@@ -62,4 +62,8 @@ struct fn_ctx {
   float* knn_y;  // per (query, chunk): max |y|^2 of the chunk
   int32_t* q_count;  // [0]: queue length
   fn::QEntry* queue;
+  // endpoint models: of every edge's parent [max_edges][56], of every
+  // candidate [max_batch][56]
+  float* model_e;
+  float* model_c;
 };

@@ -6,10 +6,13 @@
 //
 // Search modes (same result, different work):
 //  PLAIN  -- ascending passes over full slots, stop at the first feasible.
-//  SCREEN -- first the two endpoint samples (u = 0, 1) of every slot, 32
-//            slots per pass; a slot whose endpoint ratio exceeds 1 + BAND is
-//            infeasible for certain and never evaluated in full.  Then full
-//            passes over the remaining slots in ascending order.
+//  SCREEN -- first the two endpoint samples (u = 0, 1) of every slot, 64
+//            slots per pass, from the endpoint models (the torque there is
+//            affine in the acceleration, so a slot costs two 7x7 products
+//            instead of two Newton-Euler passes); a slot whose endpoint
+//            ratio exceeds 1 + BAND is infeasible for certain and never
+//            evaluated in full.  Then full passes over the remaining slots
+//            in ascending order.
 //  WINDOW -- the surrogate's window [lo, lo + 2h]: slots below it are
 //            screened (the certificate), the window is evaluated in full, the
 //            slots above it are screened only if the window holds no
@@ -45,6 +48,12 @@ struct EdgeArgs {
   float* out_m;
   float* out_rho;
   int32_t* out_work;
+  int16_t* out_scr;  // slots screened by the endpoint models, or NULL
+  // endpoint models (MODEL_FLOATS each): of edge e's parent state at
+  // model_e + e * MODEL_FLOATS, of candidate b at model_c + b * MODEL_FLOATS;
+  // needed by the SCREEN and WINDOW modes
+  float* model_e;
+  float* model_c;
   int32_t* q_count;
   QEntry* queue;
   // batched problems: device node count (overrides n_nodes when set), and the
@@ -239,6 +248,9 @@ __device__ __forceinline__ void stage_of(int mode, int st, int jmax, int lo, int
   }
 }
 
+// Edges (wavefronts) per workgroup of the search kernels.
+constexpr int EDGE_WAVES = 1;
+
 // Slots still to be evaluated in full: bit j of word j / 64.
 struct SlotMask {
   uint64_t w0, w1, w2, w3;
@@ -277,13 +289,51 @@ __device__ __forceinline__ bool fixed_T(const EdgeArgs& a, int64_t e, float& T) 
   return true;
 }
 
+// Endpoint model of one state of an edge launch (8 lanes per state, lane
+// `role`): st < E is the parent of edge st, st = E + b is candidate b.
+// States that no screen reads are skipped: padded or invalid parents and
+// goal candidates (their edges are checked at one fixed duration).
+template <int PAT>
+__device__ __forceinline__ void model_state(const EdgeArgs& a, int64_t st, int role,
+                                            const ArmConst<float>& A) {
+  float q[NJ], qd[NJ];
+  float* dst;
+  if (st < a.E) {
+    const int64_t b = st / a.k;
+    if (a.kind && a.kind[b] == 1) return;
+    const int p = a.nbr[st];
+    if (p < 0 || p >= nodes_of(a)) return;
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) {
+      q[i] = a.tree[(size_t)i * a.ld + p];
+      qd[i] = a.tree[(size_t)(NJ + i) * a.ld + p];
+    }
+    dst = a.model_e + st * MODEL_FLOATS;
+  } else {
+    const int64_t b = st - a.E;
+    if (a.kind && a.kind[b] == 1) return;
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) {
+      q[i] = a.cand[b * FN_STATE + i];
+      qd[i] = a.cand[b * FN_STATE + NJ + i];
+    }
+    dst = a.model_c + b * MODEL_FLOATS;
+  }
+  float out[NJ];
+  model_lane<float, PAT>(A, q, qd, role, out);
+#pragma unroll
+  for (int i = 0; i < NJ; ++i) dst[NJ * role + i] = out[i];
+}
+
 // The search of one edge by one wavefront (see the stage list above).
 // eq: the edge's id in the FP64-stage queue; s_end: this wavefront's
-// FN_MAX_NT floats of LDS; s_T: the grid in LDS; s_fix: one float of LDS.
+// FN_MAX_NT floats of LDS; s_T: the grid in LDS; s_fix: one float of LDS;
+// s_mod: 2 * MODEL_FLOATS floats of LDS.
 template <int PAT>
 __device__ void search_edge(const EdgeArgs& a, int64_t e, int64_t eq, const ArmConst<float>& A,
-                            float* s_end, const float* s_T, float* s_fix) {
+                            float* s_end, const float* s_T, float* s_fix, float* s_mod) {
   const int lane = lane_id();
+  if (a.out_scr && lane == 0) a.out_scr[e] = 0;
   EdgeState<float> ES;
   int st0;
   if (!load_edge(a, e, ES, st0)) {
@@ -322,6 +372,10 @@ __device__ void search_edge(const EdgeArgs& a, int64_t e, int64_t eq, const ArmC
   const bool s_ok = (lane & (Sw - 1)) < S;
 
   for (int j = lane; j < n_t; j += WAVE) s_end[j] = -1.f;  // -1: not screened
+  if (mode != FN_SEARCH_PLAIN && lane < MODEL_FLOATS) {
+    s_mod[lane] = a.model_e[e * MODEL_FLOATS + lane];
+    s_mod[MODEL_FLOATS + lane] = a.model_c[(e / a.k) * MODEL_FLOATS + lane];
+  }
   __builtin_amdgcn_wave_barrier();
   SlotMask todo{~0ull, ~0ull, ~0ull, ~0ull};
 
@@ -331,7 +385,7 @@ __device__ void search_edge(const EdgeArgs& a, int64_t e, int64_t eq, const ArmC
     whi = min(wlo + 2 * a.win_half, jmax);
   }
 
-  int work = 0;
+  int work = 0, scr = 0;
   float marg = INFINITY;  // over fully evaluated slots up to the result
   float last = 0.f;
   int jstar = -1;
@@ -354,12 +408,26 @@ __device__ void search_edge(const EdgeArgs& a, int64_t e, int64_t eq, const ArmC
     int my = -1, cnt = 0;
     float u = u_full;
     if (type == ST_SCREEN) {
-      // lane l: slot j + (l & 31), endpoint u = 0 (l < 32) or u = 1
-      const int jj = j + (lane & 31);
+      // lane l: slot j + l, both endpoints from the models
+      const int j0 = j;
+      const int jj = j + lane;
       my = jj <= sb ? jj : -1;
-      u = lane >= 32 ? 1.f : 0.f;
-      cnt = min(WAVE / 2, sb - j + 1);
-      j += WAVE / 2;
+      j += WAVE;
+      const bool act = my >= 0;
+      float r = 0.f;
+      if (act) {
+        const float T = Tg[my];
+        r = endpoint_ratio(A, ES, s_mod, s_mod + MODEL_FLOATS, T, __builtin_amdgcn_rcpf(T));
+        s_end[my] = r;
+      }
+      scr += __popcll(__ballot(act));
+      // slots certified infeasible leave the to-do mask: bit t of the ballot
+      // is slot j0 + t, and the pass may straddle two 64-slot words
+      const uint64_t bits = __ballot(act && r > 1.f + BAND);
+      const int w0 = j0 >> 6, sh = j0 & 63;
+      todo.clear(w0, bits << sh);
+      if (sh > 0 && w0 < 3) todo.clear(w0 + 1, bits >> (64 - sh));
+      continue;
     } else {
       // next G slots still to be evaluated; lane group g takes the g-th
       while (cnt < G) {
@@ -383,18 +451,6 @@ __device__ void search_edge(const EdgeArgs& a, int64_t e, int64_t eq, const ArmC
       r = eval_rho<float, PAT>(A, ES, T, __builtin_amdgcn_rcpf(T), u);
     }
     work += __popcll(__ballot(act));
-    if (type == ST_SCREEN) {
-      r = fmaxf(r, __shfl_xor(r, 32));
-      if (act && lane < 32) s_end[my] = r;
-      // slots certified infeasible leave the to-do mask: bit t of the ballot
-      // is slot j0 + t, and the pass may straddle two 64-slot words
-      const int j0 = j - WAVE / 2;
-      const uint64_t bits = __ballot(act && lane < 32 && r > 1.f + BAND) & 0xffffffffull;
-      const int w0 = j0 >> 6, sh = j0 & 63;
-      todo.clear(w0, bits << sh);
-      if (sh > 32) todo.clear(w0 + 1, bits >> (64 - sh));
-      continue;
-    }
     r = group_max(r, Sw);
     bool done = false;
     for (int q = 0; q < cnt; ++q) {
@@ -421,6 +477,7 @@ __device__ void search_edge(const EdgeArgs& a, int64_t e, int64_t eq, const ArmC
     }
     if (done) break;
   }
+  if (a.out_scr && lane == 0) a.out_scr[e] = (int16_t)scr;
   if (queued) return;
   __builtin_amdgcn_wave_barrier();
   // certified-infeasible margin of the screened slots below the result

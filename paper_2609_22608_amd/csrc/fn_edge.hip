@@ -13,19 +13,35 @@
 
 namespace fn {
 
+// Endpoint models of every screened state: 8 lanes per state (the E
+// parents, then the B candidates).
 template <int PAT>
-__global__ __launch_bounds__(256) void edge_time_kernel(EdgeArgs a,
-                                                        const ArmConst<float>* __restrict__ Ap) {
-  __shared__ float s_end_all[4][FN_MAX_NT];
+__global__ __launch_bounds__(256) void edge_model_kernel(EdgeArgs a,
+                                                         const ArmConst<float>* __restrict__ Ap) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t st = t >> 3;
+  if (st >= a.E + a.E / a.k) return;
+  model_state<PAT>(a, st, (int)(t & 7), *Ap);
+}
+
+// EDGE_WAVES wavefronts (edges) per workgroup.  Edges take very different
+// times (some stop after the screen, some run several full passes and the
+// post-checks); a one-wave workgroup hands its slot to the next edge as
+// soon as it ends instead of holding it until the slowest of its group
+// ends.  Three waves per SIMD: the register budget of the search.
+template <int PAT>
+__global__ __launch_bounds__(64 * EDGE_WAVES) __attribute__((amdgpu_waves_per_eu(3))) void
+edge_time_kernel(EdgeArgs a, const ArmConst<float>* __restrict__ Ap) {
+  __shared__ float s_end_all[EDGE_WAVES][FN_MAX_NT];
   __shared__ float s_T[FN_MAX_NT];
-  __shared__ float s_fix[4];
-  // the block's four edges share the grid: stage it once
+  __shared__ float s_fix[EDGE_WAVES];
+  __shared__ float s_mod[EDGE_WAVES][2 * MODEL_FLOATS];
   for (int t = threadIdx.x; t < a.n_t; t += blockDim.x) s_T[t] = a.grid[t];
   __syncthreads();
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t e = (int64_t)blockIdx.x * 4 + wave;
+  const int64_t e = (int64_t)blockIdx.x * EDGE_WAVES + wave;
   if (e >= a.E) return;
-  search_edge<PAT>(a, e, e, *Ap, s_end_all[wave], s_T, &s_fix[wave]);
+  search_edge<PAT>(a, e, e, *Ap, s_end_all[wave], s_T, &s_fix[wave], s_mod[wave]);
 }
 
 // ---------------------------------------------------------------------------
@@ -146,15 +162,20 @@ extern "C" int edge_time_batch(fn_ctx* c, const float* tree, int64_t ld, int32_t
   a.mode = sr->mode; a.win_half = sr->win_half; a.j_max = sr->j_max; a.win_lo = sr->win_lo;
   a.obs = obs ? obs->spheres : nullptr; a.n_obs = obs ? obs->n : 0; a.margin_c = obs ? obs->margin : 0.f;
   a.out_j = out->j; a.out_st = out->status; a.out_m = out->margin; a.out_rho = out->rho4;
-  a.out_work = out->work; a.q_count = c->q_count; a.queue = c->queue;
+  a.out_work = out->work; a.out_scr = out->screened; a.q_count = c->q_count; a.queue = c->queue;
+  a.model_e = c->model_e; a.model_c = c->model_c;
   hipStream_t s = (hipStream_t)stream;
   hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, s, c->q_count, 1);
-  const dim3 grid((unsigned)((E + 3) / 4));
+  const dim3 grid((unsigned)((E + EDGE_WAVES - 1) / EDGE_WAVES));
+  const dim3 mgrid((unsigned)(((E + B) * 8 + 255) / 256));
+  const bool screens = sr->mode != FN_SEARCH_PLAIN;
   if (c->pattern == PAT_FR3) {
-    hipLaunchKernelGGL(edge_time_kernel<PAT_FR3>, grid, dim3(256), 0, s, a, c->arm32);
+    if (screens) hipLaunchKernelGGL(edge_model_kernel<PAT_FR3>, mgrid, dim3(256), 0, s, a, c->arm32);
+    hipLaunchKernelGGL(edge_time_kernel<PAT_FR3>, grid, dim3(64 * EDGE_WAVES), 0, s, a, c->arm32);
     hipLaunchKernelGGL(edge_recheck_kernel<PAT_FR3>, dim3(recheck_waves(E)), dim3(64), 0, s, a, ProbTable{0, nullptr, nullptr}, c->arm32, c->arm64);
   } else {
-    hipLaunchKernelGGL(edge_time_kernel<PAT_GENERIC>, grid, dim3(256), 0, s, a, c->arm32);
+    if (screens) hipLaunchKernelGGL(edge_model_kernel<PAT_GENERIC>, mgrid, dim3(256), 0, s, a, c->arm32);
+    hipLaunchKernelGGL(edge_time_kernel<PAT_GENERIC>, grid, dim3(64 * EDGE_WAVES), 0, s, a, c->arm32);
     hipLaunchKernelGGL(edge_recheck_kernel<PAT_GENERIC>, dim3(recheck_waves(E)), dim3(64), 0, s, a, ProbTable{0, nullptr, nullptr}, c->arm32, c->arm64);
   }
   hipError_t e = hipGetLastError();

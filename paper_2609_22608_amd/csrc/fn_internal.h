@@ -137,13 +137,16 @@ __device__ __forceinline__ void rot(const ArmConst<R>& A, R c, R s, R vx, R vy, 
 // inward: force and moment transmitted at every joint), plus armature and
 // the sigmoid friction of Eq. (5).  sn/cs: sin/cos of q.
 // ---------------------------------------------------------------------------
+// Rigid-body part only, with the base acceleration (vd0x, vd0y, vd0z) given:
+// -g for the torque model, 0 for columns of the mass matrix.
 template <typename R, int PAT>
-__device__ __forceinline__ void rnea(const ArmConst<R>& A, const R* sn, const R* cs,
-                                     const R* qd, const R* qdd, R* tau) {
+__device__ __forceinline__ void rnea_rigid(const ArmConst<R>& A, const R* sn, const R* cs,
+                                           const R* qd, const R* qdd, R vd0x, R vd0y, R vd0z,
+                                           R* tau) {
   const bool rigid = (A.terms & FN_T_RIGID) != 0;
   R Fx[NJ], Fy[NJ], Fz[NJ], Nx[NJ], Ny[NJ], Nz[NJ];
   R wx = 0, wy = 0, wz = 0, ax = 0, ay = 0, az = 0;  // w_{i-1}, wd_{i-1}
-  R vx = A.vd0[0], vy = A.vd0[1], vz = A.vd0[2];      // vd_{i-1}
+  R vx = vd0x, vy = vd0y, vz = vd0z;                  // vd_{i-1}
 #pragma unroll
   for (int i = 0; i < NJ; ++i) {
     const R c = cs[i], s = sn[i];
@@ -209,14 +212,61 @@ __device__ __forceinline__ void rnea(const ArmConst<R>& A, const R* sn, const R*
     nz = Nz[i] + Rnz + (rx * Fy[i] - ry * Fx[i]);
     tau[i] = rigid ? nz : R(0);
   }
+}
+
+// Eq. (5) friction of joint i at velocity v, zero at rest.
+template <typename R>
+__device__ __forceinline__ R friction(const ArmConst<R>& A, int i, R v) {
+  return A.L[i].psi1 * logistic_neg(A.L[i].fk2 * (v + A.L[i].psi3)) - A.L[i].f0;
+}
+
+template <typename R, int PAT>
+__device__ __forceinline__ void rnea(const ArmConst<R>& A, const R* sn, const R* cs,
+                                     const R* qd, const R* qdd, R* tau) {
+  rnea_rigid<R, PAT>(A, sn, cs, qd, qdd, A.vd0[0], A.vd0[1], A.vd0[2], tau);
   const bool arm = (A.terms & FN_T_ARMATURE) != 0;
   const bool fric = (A.terms & FN_T_FRICTION) != 0;
 #pragma unroll
   for (int i = 0; i < NJ; ++i) {
     if (arm) tau[i] += A.L[i].Im * qdd[i];
-    if (fric) tau[i] += A.L[i].psi1 * logistic_neg(A.L[i].fk2 * (qd[i] + A.L[i].psi3)) - A.L[i].f0;
+    if (fric) tau[i] += friction(A, i, qd[i]);
   }
 }
+
+// ---------------------------------------------------------------------------
+// Endpoint model.  At u = 0 and u = 1 the cubic's position and velocity are
+// the boundary states, whatever T is; only the acceleration depends on T.
+// The torque of Eq. (4)-(5) is affine in the acceleration,
+//   tau(qdd) = b + (M + diag(Im)) qdd,  b = rigid(q, qd, 0) + friction(qd),
+// so one model per boundary state gives the endpoint torques of every slot.
+// A model is 56 floats: column c of M + diag(Im) at [7c, 7c + 7), b at
+// [49, 56).  Lane `role` 0..6 of a state computes column `role` (unit
+// acceleration, zero velocity, no gravity, no friction); role 7 computes b.
+// ---------------------------------------------------------------------------
+constexpr int MODEL_FLOATS = 56;
+
+template <typename R, int PAT>
+__device__ __forceinline__ void model_lane(const ArmConst<R>& A, const R* q, const R* qd, int role,
+                                           R* out) {
+  R sn[NJ], cs[NJ], v[NJ], acc[NJ];
+#pragma unroll
+  for (int i = 0; i < NJ; ++i) {
+    sincos_r(q[i], sn[i], cs[i]);
+    v[i] = role == NJ ? qd[i] : R(0);
+    acc[i] = i == role ? R(1) : R(0);
+  }
+  const bool col = role < NJ;
+  rnea_rigid<R, PAT>(A, sn, cs, v, acc, col ? R(0) : A.vd0[0], col ? R(0) : A.vd0[1],
+                     col ? R(0) : A.vd0[2], out);
+  const bool arm = (A.terms & FN_T_ARMATURE) != 0;
+  const bool fric = (A.terms & FN_T_FRICTION) != 0;
+#pragma unroll
+  for (int i = 0; i < NJ; ++i) {
+    if (col && arm && i == role) out[i] += A.L[i].Im;
+    if (!col && fric) out[i] += friction(A, i, qd[i]);
+  }
+}
+
 
 // ---------------------------------------------------------------------------
 // Eq. (6) in the normalised time u = t / T:
@@ -270,6 +320,41 @@ __device__ __forceinline__ R eval_rho(const ArmConst<R>& A, const EdgeState<R>& 
   R rt, rp;
   eval_point<R, PAT>(A, E, T, invT, u, rt, rp, nullptr);
   return rmax(rt, rp);
+}
+
+// Larger of the torque and power ratios (Def. 6) at u = 0 and u = 1 of
+// duration T from the two endpoint models (m0: state q0, qd0; m1: state
+// q1, qd1 = qd0 + d2); the models are read from LDS (same address in
+// every lane).
+__device__ __forceinline__ float endpoint_ratio(const ArmConst<float>& A, const EdgeState<float>& E,
+                                                const float* __restrict__ m0,
+                                                const float* __restrict__ m1, float T,
+                                                float invT) {
+  const float invT2 = invT * invT;
+  float a0[NJ], a1[NJ];
+#pragma unroll
+  for (int c = 0; c < NJ; ++c) {
+    // qdd(0) = 2 A2 / T^2, qdd(1) = (2 A2 + 6 A3) / T^2 with A2 = 3 d1 - d2 T,
+    // A3 = d2 T - 2 d1, d1 = dq - qd0 T
+    const float d1 = E.dq[c] - E.qd0[c] * T;
+    const float d2T = E.d2[c] * T;
+    a0[c] = (6.f * d1 - 2.f * d2T) * invT2;
+    a1[c] = (4.f * d2T - 6.f * d1) * invT2;
+  }
+  float r = 0.f, p0 = 0.f, p1 = 0.f;
+#pragma unroll
+  for (int i = 0; i < NJ; ++i) {
+    float t0 = m0[49 + i], t1 = m1[49 + i];
+#pragma unroll
+    for (int c = 0; c < NJ; ++c) {
+      t0 = fmaf(m0[7 * c + i], a0[c], t0);
+      t1 = fmaf(m1[7 * c + i], a1[c], t1);
+    }
+    r = fmaxf(r, fmaxf(fabsf(t0), fabsf(t1)) * A.L[i].inv_taumax);
+    p0 = fmaf(t0, E.qd0[i], p0);
+    p1 = fmaf(t1, E.qd0[i] + E.d2[i], p1);
+  }
+  return fmaxf(r, fmaxf(fabsf(p0), fabsf(p1)) * A.inv_wmax);
 }
 
 // Velocity taper of Def. 1 (braking law) and the ratio |v| / taper.

@@ -66,7 +66,7 @@ class Obstacles(C.Structure):
 
 class EdgeOut(C.Structure):
     _fields_ = [("j", C.c_void_p), ("status", C.c_void_p), ("margin", C.c_void_p),
-                ("rho4", C.c_void_p), ("work", C.c_void_p)]
+                ("rho4", C.c_void_p), ("work", C.c_void_p), ("screened", C.c_void_p)]
 
 
 class TrainCfg(C.Structure):
@@ -259,7 +259,8 @@ class Context:
                        status=torch.empty(E, dtype=torch.int16, device=d),
                        margin=torch.empty(E, dtype=torch.float32, device=d),
                        rho=torch.empty((E, 4), dtype=torch.float32, device=d) if want_rho else None,
-                       work=torch.empty(E, dtype=torch.int32, device=d) if want_work else None)
+                       work=torch.empty(E, dtype=torch.int32, device=d) if want_work else None,
+                       screened=torch.empty(E, dtype=torch.int16, device=d) if want_work else None)
         s = Search(C.c_void_p(grid.data_ptr()), grid.shape[0], int(samples), int(mode),
                    int(win_half), None if j_max is None else C.c_void_p(j_max.data_ptr()),
                    None if win_lo is None else C.c_void_p(win_lo.data_ptr()))
@@ -267,7 +268,8 @@ class Context:
                       0 if obs is None else obs.shape[0], float(margin))
         eo = EdgeOut(out["j"].data_ptr(), out["status"].data_ptr(), out["margin"].data_ptr(),
                      None if out["rho"] is None else out["rho"].data_ptr(),
-                     None if out["work"] is None else out["work"].data_ptr())
+                     None if out["work"] is None else out["work"].data_ptr(),
+                     None if out.get("screened") is None else out["screened"].data_ptr())
         _check(lib().edge_time_batch(self.h, _ptr(tree), ld, n_nodes, _ptr(cand), B, _ptr(nbr), k,
                                      C.byref(s), C.byref(o), C.byref(eo), _stream()),
                "edge_time_batch")
