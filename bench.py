@@ -23,10 +23,27 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "validated edges/s (7-DOF, 64 T x 32 samples); MLP-window vs exact speedup"
-# FLOP of one evaluation point (cubic + sin/cos + RNEA + armature + friction +
-# ratios) in the kernel's formulation; see the design notes for the count
-F_EVAL = 1295
 PEAK_FP32 = 157.3e12  # MI355X FP32 vector peak (packed), FLOP/s
+
+# Algorithmic FLOP per unit in the kernels' formulation (FMA = 2, each
+# transcendental or reciprocal = 1); the design notes derive every count.
+# One evaluation point of Eq. (4)-(7): cubic 169, sin/cos 21, RNEA 1,005,
+# armature 14, friction 56, ratios and power 30.
+F_EVAL = 1295
+# One slot screened from the endpoint models: both endpoint accelerations
+# (79), two 7x7 products with the bias (196), ratios and power (59).
+F_SCREEN = 334
+# One endpoint model (per state): 8 lanes x (sin/cos 21 + rigid RNEA 1,005)
+# + armature 7 + friction 56.
+F_MODEL = 8271
+# Post-checks of one edge at its result: velocity taper and position
+# extrema, 140 per joint; clearance per sample: cubic position 98, sin/cos
+# 21, the frame chain 252, per sphere 19 + 13 per obstacle.
+F_JOINTS = 980
+
+
+def f_post(S, n_obs, n_sph):
+    return F_JOINTS + (S * (371 + n_sph * (19 + 13 * n_obs)) if n_obs > 0 else 0)
 
 
 def parse():
@@ -73,7 +90,8 @@ def main():
     out = dict(j=torch.empty(E, dtype=torch.int16, device="cuda"),
                status=torch.empty(E, dtype=torch.int16, device="cuda"),
                margin=torch.empty(E, dtype=torch.float32, device="cuda"),
-               rho=None, work=torch.empty(E, dtype=torch.int32, device="cuda"))
+               rho=None, work=torch.empty(E, dtype=torch.int32, device="cuda"),
+               screened=torch.empty(E, dtype=torch.int16, device="cuda"))
     stream = torch.cuda.current_stream()
     modes = {"plain": fn.SEARCH_PLAIN, "screen": fn.SEARCH_SCREEN, "window": fn.SEARCH_WINDOW}
     wanted = args.modes.split(",")
@@ -106,6 +124,8 @@ def main():
         for _ in range(args.warmup):
             step()
         torch.cuda.synchronize()
+        ctx.kernel_timing(True)
+        ctx.kernel_times()
         edge_ms = []
         t0 = torch.cuda.Event(enable_timing=True)
         t1 = torch.cuda.Event(enable_timing=True)
@@ -119,15 +139,23 @@ def main():
         t1.record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - w0
+        k_ms = ctx.kernel_times()
+        ctx.kernel_timing(False)
         ms = t0.elapsed_time(t1) / args.steps
         e_ms = float(np.mean([a[2].elapsed_time(a[1]) for a in edge_ms]))
+        kern_ms = float(np.mean(k_ms))
         work = int(out["work"].sum().item())
-        flop = work * F_EVAL
+        scr = int(out["screened"].sum().item())
         st = out["status"].cpu().numpy().astype(np.uint16)
         jj = out["j"].cpu().numpy()
+        n_post = int(((jj >= 0) & ((st & fn.S_RECHECK64) == 0)).sum())
+        n_sph = len(wl["arm"]["sph"])
+        flop = work * F_EVAL + scr * F_SCREEN + n_post * f_post(sh.samples, sh.n_obs, n_sph)
         f = dict(edges_per_s=E / (ms * 1e-3), ms_per_step=ms, edge_search_ms=e_ms,
-                 evaluations=work, wall_s=wall,
-                 fp32_tflops=flop / (e_ms * 1e-3) / 1e12,
+                 edge_time_kernel_ms=kern_ms, evaluations=work, screened_slots=scr,
+                 post_checked=n_post, kernel_gflop=flop / 1e9, wall_s=wall,
+                 fp32_tflops=flop / (kern_ms * 1e-3) / 1e12,
+                 model_states=(E + sh.batch) if mode != fn.SEARCH_PLAIN else 0,
                  recheck64=int(((st & fn.S_RECHECK64) > 0).sum()))
         if mode == fn.SEARCH_WINDOW:
             pre = float(np.mean([a[0].elapsed_time(a[2]) for a in edge_ms]))
@@ -167,8 +195,16 @@ def main():
         "roofline": {"bound": "alu", "kernel": "edge_time_kernel",
                      "form": best, "achieved": bf["fp32_tflops"], "peak": PEAK_FP32 / 1e12,
                      "unit": "TFLOP/s", "frac": bf["fp32_tflops"] * 1e12 / PEAK_FP32,
-                     "traffic": None,
-                     "flop_per_eval": F_EVAL, "evaluations": bf["evaluations"]},
+                     "traffic": traffic_bytes("edge_time_kernel", best),
+                     "kernel_ms": bf["edge_time_kernel_ms"],
+                     "flop_per_launch": bf["kernel_gflop"] * 1e9,
+                     "flop_model": {"eval": F_EVAL, "screened_slot": F_SCREEN,
+                                    "post_checked_edge": f_post(sh.samples, sh.n_obs,
+                                                                len(wl["arm"]["sph"])),
+                                    "model_state": F_MODEL},
+                     "units": {"evaluations": bf["evaluations"],
+                               "screened_slots": bf["screened_slots"],
+                               "post_checked_edges": bf["post_checked"]}},
     }
     if args.batch_problems > 0:
         res["batched_round"] = batched_round(args, fn, W, torch)
@@ -183,6 +219,34 @@ def main():
         res["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample)
     print(json.dumps(res), flush=True)
     ctx.close()
+
+
+def kernel_source_hash():
+    """Hash of the sources the search kernels are built from: a stored
+    traffic figure applies only to the kernel it was measured on."""
+    import hashlib
+
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2609_22608_amd", "csrc")
+    for name in ("fn_internal.h", "fn_ctx.h", "fn_edge.h", "fn_edge.hip"):
+        with open(os.path.join(d, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_bytes(kernel, form):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    rec = t.get(kernel, {})
+    if rec.get("source_hash") != kernel_source_hash() or rec.get("form") != form:
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def batched_round(args, fn, W, torch):

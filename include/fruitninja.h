@@ -134,6 +134,18 @@ const char* fn_last_error(void);
 /* Library version string. */
 const char* fn_version(void);
 
+/* Kernel timing for measurement.  While enabled, every edge_time_batch
+ * call records a pair of HIP events on its stream around its search kernel
+ * (edge_time_kernel), up to FN_MAX_TIMED calls; later calls are not timed.
+ * fn_kernel_times waits for the recorded pairs, writes their elapsed
+ * milliseconds to out_ms (host, up to max entries, *n_out of them) and
+ * clears the list.  Events are created by fn_kernel_timing(ctx, 1) and
+ * freed by fn_kernel_timing(ctx, 0) or fn_destroy.  Errors: FN_E_ARG (NULL
+ * context / out), FN_E_HIP. */
+#define FN_MAX_TIMED 256
+int fn_kernel_timing(fn_ctx* ctx, int enable);
+int fn_kernel_times(fn_ctx* ctx, float* out_ms /*host*/, int32_t max, int32_t* n_out /*host*/);
+
 /* ------------------------------------------------------------------ */
 /* plan_knn -- Parents(T, x, M) of Alg. 1 (Sec. IV-E, "brute-force     */
 /* parallel scan"): the k nearest tree nodes of every query by plain   */

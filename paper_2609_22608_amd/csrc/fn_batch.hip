@@ -96,7 +96,7 @@ __global__ __launch_bounds__(64) void batch_knn_merge(const KnnProb* __restrict_
 }
 
 // EDGE_WAVES edges per workgroup (see edge_time_kernel).
-template <int PAT>
+template <int PAT, int MODE>
 __global__ __launch_bounds__(64 * EDGE_WAVES) __attribute__((amdgpu_waves_per_eu(3))) void
 batch_edge_kernel(ProbTable pt, const float* __restrict__ grid, int n_t,
                   const ArmConst<float>* __restrict__ Ap) {
@@ -104,14 +104,15 @@ batch_edge_kernel(ProbTable pt, const float* __restrict__ grid, int n_t,
   __shared__ float s_T[FN_MAX_NT];
   __shared__ float s_fix[EDGE_WAVES];
   __shared__ float s_mod[EDGE_WAVES][2 * MODEL_FLOATS];
+  __shared__ GeoLDS<float> s_geo[EDGE_WAVES];
   for (int t = threadIdx.x; t < n_t; t += blockDim.x) s_T[t] = grid[t];
   __syncthreads();
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t eg = (int64_t)blockIdx.x * EDGE_WAVES + wave;
   if (eg >= pt.edge_off[pt.n]) return;
   const int p = problem_of(pt, eg);
-  search_edge<PAT>(pt.args[p], eg - pt.edge_off[p], eg, *Ap, s_end_all[wave], s_T, &s_fix[wave],
-                   s_mod[wave]);
+  search_edge<PAT, MODE, true>(pt.args[p], eg - pt.edge_off[p], eg, *Ap, s_end_all[wave], s_T,
+                               &s_fix[wave], s_mod[wave], &s_geo[wave]);
 }
 
 // Endpoint models of every problem's states: 8 lanes per state, first the
@@ -373,6 +374,19 @@ static void launch_batch_knn(fn_ctx* c, fn_batch* bt, hipStream_t s) {
                      bt->n, bt->query_off, c->knn_d, c->knn_i, c->knn_y, bt->k);
 }
 
+// model kernel (screening), search, FP64 stage over all problems
+template <int PAT, int MODE>
+static void launch_batch_search(fn_ctx* c, fn_batch* bt, hipStream_t s) {
+  const ProbTable pt{bt->n, bt->edge_off, bt->args};
+  if (MODE != FN_SEARCH_PLAIN)
+    hipLaunchKernelGGL(batch_model_kernel<PAT>, dim3((unsigned)(((bt->edges + bt->queries) * 8 + 255) / 256)),
+                       dim3(256), 0, s, pt, bt->query_off, c->arm32);
+  hipLaunchKernelGGL((batch_edge_kernel<PAT, MODE>), dim3((unsigned)((bt->edges + EDGE_WAVES - 1) / EDGE_WAVES)),
+                     dim3(64 * EDGE_WAVES), 0, s, pt, bt->grid, bt->n_t, c->arm32);
+  const unsigned rw = (unsigned)(bt->edges < 4096 ? bt->edges : 4096);
+  hipLaunchKernelGGL(edge_recheck_kernel<PAT>, dim3(rw), dim3(64), 0, s, bt->a0, pt, c->arm32, c->arm64);
+}
+
 extern "C" int fn_batch_launch(fn_ctx* c, void* stream) {
   if (!c) return fail(FN_E_ARG, "fn_batch_launch: NULL context");
   fn_batch* bt = c->batch;
@@ -386,19 +400,12 @@ extern "C" int fn_batch_launch(fn_ctx* c, void* stream) {
     default: return fail(FN_E_SHAPE, "fn_batch_launch: k");
   }
   hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, s, c->q_count, 1);
-  const ProbTable pt{bt->n, bt->edge_off, bt->args};
-  const dim3 grid((unsigned)((bt->edges + EDGE_WAVES - 1) / EDGE_WAVES));
-  const dim3 mgrid((unsigned)(((bt->edges + bt->queries) * 8 + 255) / 256));
-  const bool screens = bt->mode != FN_SEARCH_PLAIN;
-  const unsigned rw = (unsigned)(bt->edges < 4096 ? bt->edges : 4096);
   if (bt->pattern == PAT_FR3) {
-    if (screens) hipLaunchKernelGGL(batch_model_kernel<PAT_FR3>, mgrid, dim3(256), 0, s, pt, bt->query_off, c->arm32);
-    hipLaunchKernelGGL(batch_edge_kernel<PAT_FR3>, grid, dim3(64 * EDGE_WAVES), 0, s, pt, bt->grid, bt->n_t, c->arm32);
-    hipLaunchKernelGGL(edge_recheck_kernel<PAT_FR3>, dim3(rw), dim3(64), 0, s, bt->a0, pt, c->arm32, c->arm64);
+    if (bt->mode == FN_SEARCH_PLAIN) launch_batch_search<PAT_FR3, FN_SEARCH_PLAIN>(c, bt, s);
+    else launch_batch_search<PAT_FR3, FN_SEARCH_SCREEN>(c, bt, s);
   } else {
-    if (screens) hipLaunchKernelGGL(batch_model_kernel<PAT_GENERIC>, mgrid, dim3(256), 0, s, pt, bt->query_off, c->arm32);
-    hipLaunchKernelGGL(batch_edge_kernel<PAT_GENERIC>, grid, dim3(64 * EDGE_WAVES), 0, s, pt, bt->grid, bt->n_t, c->arm32);
-    hipLaunchKernelGGL(edge_recheck_kernel<PAT_GENERIC>, dim3(rw), dim3(64), 0, s, bt->a0, pt, c->arm32, c->arm64);
+    if (bt->mode == FN_SEARCH_PLAIN) launch_batch_search<PAT_GENERIC, FN_SEARCH_PLAIN>(c, bt, s);
+    else launch_batch_search<PAT_GENERIC, FN_SEARCH_SCREEN>(c, bt, s);
   }
   hipLaunchKernelGGL(batch_insert_kernel, dim3(bt->n), dim3(INS_THREADS), 0, s, bt->ins, bt->k, bt->risk);
   hipError_t e = hipGetLastError();

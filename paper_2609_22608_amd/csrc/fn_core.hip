@@ -220,9 +220,47 @@ extern "C" int fn_create(const fn_arm_desc* arm, const fn_caps* caps, fn_ctx** o
   return FN_OK;
 }
 
+extern "C" int fn_kernel_timing(fn_ctx* c, int enable) {
+  if (!c) return fail(FN_E_ARG, "fn_kernel_timing: NULL context");
+  if (enable && !c->timing) {
+    for (int i = 0; i < 2 * FN_MAX_TIMED; ++i) {
+      const hipError_t e = hipEventCreate(&c->tev[i]);
+      if (e != hipSuccess) {
+        for (int j = 0; j < i; ++j) (void)hipEventDestroy(c->tev[j]);
+        return hip_fail(e, "fn_kernel_timing: event");
+      }
+    }
+    c->timing = true;
+    c->n_timed = 0;
+  } else if (!enable && c->timing) {
+    (void)hipDeviceSynchronize();
+    for (int i = 0; i < 2 * FN_MAX_TIMED; ++i) (void)hipEventDestroy(c->tev[i]);
+    c->timing = false;
+    c->n_timed = 0;
+  }
+  return FN_OK;
+}
+
+extern "C" int fn_kernel_times(fn_ctx* c, float* out_ms, int32_t max, int32_t* n_out) {
+  if (!c || !n_out || (max > 0 && !out_ms)) return fail(FN_E_ARG, "fn_kernel_times: NULL argument");
+  *n_out = 0;
+  if (!c->timing) return FN_OK;
+  const int n = c->n_timed < max ? c->n_timed : max;
+  for (int i = 0; i < n; ++i) {
+    hipError_t e = hipEventSynchronize(c->tev[2 * i + 1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&out_ms[i], c->tev[2 * i], c->tev[2 * i + 1]);
+    if (e != hipSuccess) return hip_fail(e, "fn_kernel_times");
+  }
+  *n_out = n;
+  c->n_timed = 0;
+  return FN_OK;
+}
+
 extern "C" void fn_destroy(fn_ctx* c) {
   if (!c) return;
   (void)hipDeviceSynchronize();
+  if (c->timing)
+    for (int i = 0; i < 2 * FN_MAX_TIMED; ++i) (void)hipEventDestroy(c->tev[i]);
   batch_free(c);
   (void)hipFree(c->arm32);
   (void)hipFree(c->arm64);

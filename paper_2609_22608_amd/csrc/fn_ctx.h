@@ -66,4 +66,8 @@ struct fn_ctx {
   // candidate [max_batch][56]
   float* model_e;
   float* model_c;
+  // kernel timing: event pairs around the search kernel of timed calls
+  bool timing;
+  int n_timed;
+  hipEvent_t tev[2 * FN_MAX_TIMED];
 };

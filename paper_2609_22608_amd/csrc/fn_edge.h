@@ -110,13 +110,33 @@ __device__ __forceinline__ float lane_u(int lane, int Sw, int S) {
   return s < S ? float(s) / float(S - 1) : 0.f;
 }
 
+// LDS of one wavefront for the clearance check: every sphere as (x, y, z
+// in its link frame, radius + margin), every obstacle as (x, y, z, radius).
+template <typename R>
+struct GeoLDS {
+  R sph[4 * FN_MAX_SPHERES];
+  R obs[4 * FN_MAX_OBS];
+};
+
 // Post-checks at duration T (Def. 6 rho_v; position limits; clearance):
-// returns (rho_v, rho_q, rho_c) in every lane.
+// returns (rho_v, rho_q, rho_c) in every lane.  The sphere and obstacle
+// tables are staged in LDS first, so the (sphere, obstacle) loop reads
+// broadcast LDS instead of waiting on a memory load per pair.
 template <typename R, int PAT>
 __device__ void post_checks(const ArmConst<R>& A, const EdgeState<R>& E, R T, int S,
-                            const float* __restrict__ obs, int n_obs, float margin_c, R& rv,
-                            R& rq, R& rc) {
+                            const float* __restrict__ obs, int n_obs, float margin_c,
+                            GeoLDS<R>* geo, R& rv, R& rq, R& rc) {
   const int lane = lane_id();
+  if (n_obs > 0) {
+    for (int t = lane; t < A.nsph; t += WAVE) {
+      geo->sph[4 * t] = A.sphx[t];
+      geo->sph[4 * t + 1] = A.sphy[t];
+      geo->sph[4 * t + 2] = A.sphz[t];
+      geo->sph[4 * t + 3] = A.sphr[t] + R(margin_c);
+    }
+    for (int t = lane; t < 4 * n_obs; t += WAVE) geo->obs[t] = R(obs[t]);
+    __builtin_amdgcn_wave_barrier();
+  }
   R v = 0, q = 0;
   // lane i < 7 checks joint i (register selects keep the edge state in VGPRs)
   R q0 = 0, qd0 = 0, dq = 0, d2v = 0;
@@ -143,14 +163,16 @@ __device__ void post_checks(const ArmConst<R>& A, const EdgeState<R>& E, R T, in
       cubic_point(E, T, R(1) / T, u, sg, sd, sdd);
 #pragma unroll
       for (int i = 0; i < NJ; ++i) sincos_r(sg[i], sn[i], cs[i]);
-      sphere_centres<R, PAT>(A, sn, cs, part, nparts, [&](int k, R x, R y, R z) {
-        const R ra = A.sphr[k] + R(margin_c);
+      const R* so = geo->obs;
+      sphere_centres<R, PAT>(A, sn, cs, part, nparts, geo->sph, [&](int k, R x, R y, R z) {
+        const R ra = geo->sph[4 * k + 3];
+#pragma unroll 4
         for (int o = 0; o < n_obs; ++o) {
-          const R dx = x - R(obs[4 * o]), dy = y - R(obs[4 * o + 1]), dz = z - R(obs[4 * o + 2]);
-          const R need = ra + R(obs[4 * o + 3]);
+          const R dx = x - so[4 * o], dy = y - so[4 * o + 1], dz = z - so[4 * o + 2];
+          const R need = ra + so[4 * o + 3];
           const R d2 = dx * dx + dy * dy + dz * dz;
-          const R r2 = d2 > R(0) ? fdiv(need * need, d2) : R(INFINITY);
-          best = rmax(best, r2);
+          // d2 = 0 gives +inf (reciprocal of zero; IEEE division in FP64)
+          best = rmax(best, fdiv(need * need, d2));
         }
       });
     }
@@ -328,10 +350,14 @@ __device__ __forceinline__ void model_state(const EdgeArgs& a, int64_t st, int r
 // The search of one edge by one wavefront (see the stage list above).
 // eq: the edge's id in the FP64-stage queue; s_end: this wavefront's
 // FN_MAX_NT floats of LDS; s_T: the grid in LDS; s_fix: one float of LDS;
-// s_mod: 2 * MODEL_FLOATS floats of LDS.
-template <int PAT>
+// s_mod: 2 * MODEL_FLOATS floats of LDS; geo: the clearance tables (LDS).
+// MODE is the search mode (a
+// compile-time constant, so each mode is its own kernel); GOALS: edges of
+// goal candidates (kind 1) are checked at their fixed duration.
+template <int PAT, int MODE, bool GOALS>
 __device__ void search_edge(const EdgeArgs& a, int64_t e, int64_t eq, const ArmConst<float>& A,
-                            float* s_end, const float* s_T, float* s_fix, float* s_mod) {
+                            float* s_end, const float* s_T, float* s_fix, float* s_mod,
+                            GeoLDS<float>* geo) {
   const int lane = lane_id();
   if (a.out_scr && lane == 0) a.out_scr[e] = 0;
   EdgeState<float> ES;
@@ -342,9 +368,9 @@ __device__ void search_edge(const EdgeArgs& a, int64_t e, int64_t eq, const ArmC
   }
   // goal edges: one slot at the fixed duration
   float Tfix;
-  const bool fixed = fixed_T(a, e, Tfix);
+  const bool fixed = GOALS && fixed_T(a, e, Tfix);
   const float* Tg = s_T;
-  int n_t = a.n_t, mode = a.mode;
+  int n_t = a.n_t, mode = MODE;
   if (fixed) {
     if (!isfinite(Tfix)) {
       write_out(a, e, -1, FN_S_BAD_INPUT, 0.f, 0, 0, 0, 0, 0);
@@ -501,7 +527,7 @@ __device__ void search_edge(const EdgeArgs& a, int64_t e, int64_t eq, const ArmC
   }
   float rv, rq, rc;
   const float T = Tg[jstar];
-  post_checks<float, PAT>(A, ES, T, S, a.obs, a.n_obs, a.margin_c, rv, rq, rc);
+  post_checks<float, PAT>(A, ES, T, S, a.obs, a.n_obs, a.margin_c, geo, rv, rq, rc);
   if (near_one(rv) || near_one(rq) || (a.n_obs > 0 && near_one(rc))) {
     push_queue(a, eq, jstar, PH_POST | (below_full ? PH_BELOW_FULL : 0), m, work);
     return;
@@ -513,7 +539,8 @@ __device__ void search_edge(const EdgeArgs& a, int64_t e, int64_t eq, const ArmC
 // FP64 stage of one queued edge (one wavefront).
 template <int PAT>
 __device__ void recheck_edge(const EdgeArgs& a, int64_t e, const QEntry& q,
-                             const ArmConst<float>& A, const ArmConst<double>& D, float* s_fix) {
+                             const ArmConst<float>& A, const ArmConst<double>& D, float* s_fix,
+                             GeoLDS<double>* geo) {
   const int lane = lane_id();
   EdgeState<float> ES;
   EdgeState<double> ED;
@@ -578,7 +605,8 @@ __device__ void recheck_edge(const EdgeArgs& a, int64_t e, const QEntry& q,
     return;
   }
   double rv, rq, rc;
-  post_checks<double, PAT>(D, ED, (double)Tg[jstar], S, a.obs, a.n_obs, a.margin_c, rv, rq, rc);
+  post_checks<double, PAT>(D, ED, (double)Tg[jstar], S, a.obs, a.n_obs, a.margin_c, geo, rv, rq,
+                           rc);
   const float m = fminf(marg, (float)fmin(fabs(rv - 1.0), fmin(fabs(rq - 1.0), fabs(rc - 1.0))));
   write_out(a, e, jstar, post_status(rv, rq, rc) | FN_S_RECHECK64 | winbits, m, (float)rho_star,
             (float)rv, (float)rq, (float)rc, work, Tg[jstar]);
@@ -609,6 +637,7 @@ __global__ __launch_bounds__(64) void edge_recheck_kernel(EdgeArgs a, ProbTable 
                                                           const ArmConst<float>* __restrict__ Ap,
                                                           const ArmConst<double>* __restrict__ Dp) {
   __shared__ float s_fix[1];
+  __shared__ GeoLDS<double> s_geo;
   const int n = *a.q_count;
   for (int qi = blockIdx.x; qi < n; qi += gridDim.x) {
     const QEntry q = a.queue[qi];
@@ -619,7 +648,7 @@ __global__ __launch_bounds__(64) void edge_recheck_kernel(EdgeArgs a, ProbTable 
       ap = pt.args + p;
       e -= pt.edge_off[p];
     }
-    recheck_edge<PAT>(*ap, e, q, *Ap, *Dp, s_fix);
+    recheck_edge<PAT>(*ap, e, q, *Ap, *Dp, s_fix, &s_geo);
   }
 }
 

@@ -29,19 +29,21 @@ __global__ __launch_bounds__(256) void edge_model_kernel(EdgeArgs a,
 // post-checks); a one-wave workgroup hands its slot to the next edge as
 // soon as it ends instead of holding it until the slowest of its group
 // ends.  Three waves per SIMD: the register budget of the search.
-template <int PAT>
+template <int PAT, int MODE>
 __global__ __launch_bounds__(64 * EDGE_WAVES) __attribute__((amdgpu_waves_per_eu(3))) void
 edge_time_kernel(EdgeArgs a, const ArmConst<float>* __restrict__ Ap) {
   __shared__ float s_end_all[EDGE_WAVES][FN_MAX_NT];
   __shared__ float s_T[FN_MAX_NT];
   __shared__ float s_fix[EDGE_WAVES];
   __shared__ float s_mod[EDGE_WAVES][2 * MODEL_FLOATS];
+  __shared__ GeoLDS<float> s_geo[EDGE_WAVES];
   for (int t = threadIdx.x; t < a.n_t; t += blockDim.x) s_T[t] = a.grid[t];
   __syncthreads();
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t e = (int64_t)blockIdx.x * EDGE_WAVES + wave;
   if (e >= a.E) return;
-  search_edge<PAT>(a, e, e, *Ap, s_end_all[wave], s_T, &s_fix[wave], s_mod[wave]);
+  search_edge<PAT, MODE, false>(a, e, e, *Ap, s_end_all[wave], s_T, &s_fix[wave], s_mod[wave],
+                                &s_geo[wave]);
 }
 
 // ---------------------------------------------------------------------------
@@ -56,6 +58,7 @@ __global__ __launch_bounds__(256) void edge_check_kernel(const float* __restrict
                                                          const ArmConst<float>* __restrict__ Ap,
                                                          uint16_t* out_st, float* out_rho,
                                                          float* out_tau) {
+  __shared__ GeoLDS<float> s_geo[4];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t e = (int64_t)blockIdx.x * 4 + wave;
   if (e >= E) return;
@@ -102,7 +105,7 @@ __global__ __launch_bounds__(256) void edge_check_kernel(const float* __restrict
   }
   const float rt = wave_max(rt_all), rp = wave_max(rp_all);
   float rv, rq, rc;
-  post_checks<float, PAT>(A, ES, T, S, obs, n_obs, margin_c, rv, rq, rc);
+  post_checks<float, PAT>(A, ES, T, S, obs, n_obs, margin_c, &s_geo[wave], rv, rq, rc);
   if (lane == 0) {
     int s2 = post_status(rv, rq, rc);
     if (rt > 1.f || rp > 1.f) s2 |= FN_S_NONE;
@@ -118,6 +121,31 @@ __global__ __launch_bounds__(256) void edge_check_kernel(const float* __restrict
 // waves of the FP64 stage: one per queued edge up to 4096 (the queue
 // length is known only on the device)
 static unsigned recheck_waves(int64_t E) { return (unsigned)(E < 4096 ? (E > 0 ? E : 1) : 4096); }
+
+// model kernel (screening modes), search kernel between the timing events,
+// FP64 stage
+template <int PAT, int MODE>
+static void launch_search(fn_ctx* c, const EdgeArgs& a, int ti, hipStream_t s) {
+  const int64_t E = a.E, B = a.E / a.k;
+  if (MODE != FN_SEARCH_PLAIN)
+    hipLaunchKernelGGL(edge_model_kernel<PAT>, dim3((unsigned)(((E + B) * 8 + 255) / 256)),
+                       dim3(256), 0, s, a, c->arm32);
+  if (ti >= 0) (void)hipEventRecord(c->tev[2 * ti], s);
+  hipLaunchKernelGGL((edge_time_kernel<PAT, MODE>), dim3((unsigned)((E + EDGE_WAVES - 1) / EDGE_WAVES)),
+                     dim3(64 * EDGE_WAVES), 0, s, a, c->arm32);
+  if (ti >= 0) (void)hipEventRecord(c->tev[2 * ti + 1], s);
+  hipLaunchKernelGGL(edge_recheck_kernel<PAT>, dim3(recheck_waves(E)), dim3(64), 0, s, a,
+                     ProbTable{0, nullptr, nullptr}, c->arm32, c->arm64);
+}
+
+template <int PAT>
+static void launch_search_mode(fn_ctx* c, const EdgeArgs& a, int ti, hipStream_t s) {
+  switch (a.mode) {
+    case FN_SEARCH_PLAIN: launch_search<PAT, FN_SEARCH_PLAIN>(c, a, ti, s); break;
+    case FN_SEARCH_SCREEN: launch_search<PAT, FN_SEARCH_SCREEN>(c, a, ti, s); break;
+    default: launch_search<PAT, FN_SEARCH_WINDOW>(c, a, ti, s); break;
+  }
+}
 
 static int pow2_at_least(int s) {
   int w = 1;
@@ -166,18 +194,9 @@ extern "C" int edge_time_batch(fn_ctx* c, const float* tree, int64_t ld, int32_t
   a.model_e = c->model_e; a.model_c = c->model_c;
   hipStream_t s = (hipStream_t)stream;
   hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, s, c->q_count, 1);
-  const dim3 grid((unsigned)((E + EDGE_WAVES - 1) / EDGE_WAVES));
-  const dim3 mgrid((unsigned)(((E + B) * 8 + 255) / 256));
-  const bool screens = sr->mode != FN_SEARCH_PLAIN;
-  if (c->pattern == PAT_FR3) {
-    if (screens) hipLaunchKernelGGL(edge_model_kernel<PAT_FR3>, mgrid, dim3(256), 0, s, a, c->arm32);
-    hipLaunchKernelGGL(edge_time_kernel<PAT_FR3>, grid, dim3(64 * EDGE_WAVES), 0, s, a, c->arm32);
-    hipLaunchKernelGGL(edge_recheck_kernel<PAT_FR3>, dim3(recheck_waves(E)), dim3(64), 0, s, a, ProbTable{0, nullptr, nullptr}, c->arm32, c->arm64);
-  } else {
-    if (screens) hipLaunchKernelGGL(edge_model_kernel<PAT_GENERIC>, mgrid, dim3(256), 0, s, a, c->arm32);
-    hipLaunchKernelGGL(edge_time_kernel<PAT_GENERIC>, grid, dim3(64 * EDGE_WAVES), 0, s, a, c->arm32);
-    hipLaunchKernelGGL(edge_recheck_kernel<PAT_GENERIC>, dim3(recheck_waves(E)), dim3(64), 0, s, a, ProbTable{0, nullptr, nullptr}, c->arm32, c->arm64);
-  }
+  const int ti = c->timing && c->n_timed < FN_MAX_TIMED ? c->n_timed++ : -1;
+  if (c->pattern == PAT_FR3) launch_search_mode<PAT_FR3>(c, a, ti, s);
+  else launch_search_mode<PAT_GENERIC>(c, a, ti, s);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? FN_OK : hip_fail(e, "edge_time_batch launch");
 }

@@ -413,10 +413,11 @@ __device__ __forceinline__ void joint_post(const ArmConst<R>& A, int i, R q0, R 
 // World-frame centres of the collision spheres at configuration (sn, cs),
 // streamed link by link: fn(k, x, y, z) is called for the spheres
 // k = first + part, first + part + nparts, ... of every link, so that
-// `nparts` lane groups share the spheres of one pose.
+// `nparts` lane groups share the spheres of one pose.  sph: sphere k's
+// centre in its link frame at sph[4k .. 4k + 2].
 template <typename R, int PAT, typename F>
 __device__ __forceinline__ void sphere_centres(const ArmConst<R>& A, const R* sn, const R* cs,
-                                               int part, int nparts, F&& fn) {
+                                               int part, int nparts, const R* sph, F&& fn) {
   // world rotation of frame i (rows) and its origin
   R r00 = 1, r01 = 0, r02 = 0, r10 = 0, r11 = 1, r12 = 0, r20 = 0, r21 = 0, r22 = 1;
   R ox = 0, oy = 0, oz = 0;
@@ -456,7 +457,7 @@ __device__ __forceinline__ void sphere_centres(const ArmConst<R>& A, const R* sn
     r10 = b0 * c + b1 * s; r11 = b1 * c - b0 * s; r12 = b2;
     r20 = c0 * c + c1 * s; r21 = c1 * c - c0 * s; r22 = c2;
     for (int k = A.sph_first[i] + part; k < A.sph_first[i + 1]; k += nparts) {
-      const R lx = A.sphx[k], ly = A.sphy[k], lz = A.sphz[k];
+      const R lx = sph[4 * k], ly = sph[4 * k + 1], lz = sph[4 * k + 2];
       fn(k, ox + r00 * lx + r01 * ly + r02 * lz, oy + r10 * lx + r11 * ly + r12 * lz,
          oz + r20 * lx + r21 * ly + r22 * lz);
     }

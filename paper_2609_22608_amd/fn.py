@@ -140,6 +140,8 @@ def lib():
             L.fn_batch_launch.argtypes = [vp, vp]
             L.fn_graph_capture.argtypes = [vp, vp]
             L.fn_graph_launch.argtypes = [vp, vp]
+            L.fn_kernel_timing.argtypes = [vp, C.c_int]
+            L.fn_kernel_times.argtypes = [vp, vp, i32, C.POINTER(i32)]
             _lib = L
     return _lib
 
@@ -231,6 +233,17 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def kernel_timing(self, enable=True):
+        """Event pairs around the search kernel of later edge_time_batch calls."""
+        _check(lib().fn_kernel_timing(self.h, int(bool(enable))), "fn_kernel_timing")
+
+    def kernel_times(self, max_n=256):
+        """Elapsed ms of the timed search kernels since the last call (waits)."""
+        buf = (C.c_float * max_n)()
+        n = C.c_int32(0)
+        _check(lib().fn_kernel_times(self.h, buf, max_n, C.byref(n)), "fn_kernel_times")
+        return [buf[i] for i in range(n.value)]
 
     def set_tuning(self, knn_target_waves=0, knn_min_chunk=0):
         t = Tuning(int(knn_target_waves), int(knn_min_chunk))
