@@ -159,7 +159,8 @@ int fn_kernel_times(fn_ctx* ctx, float* out_ms /*host*/, int32_t max, int32_t* n
  * summed in order c = 0..13 with separately rounded products and sums;
  * out_d2 is that FP64 value rounded to float.  With fewer than k nodes the
  * tail is padded with -1 (d^2 = +inf).  Returns FN_E_SHAPE if B > max_batch,
- * k > max_k, k < 1 or n_nodes > max_nodes. */
+ * k > max_k, k < 1, n_nodes > max_nodes or ld > 38,347,920 (the scan's
+ * 32-bit row offsets); FN_E_ARG if ld is not a multiple of 4 or too small. */
 int plan_knn(fn_ctx* ctx, const float* tree, int64_t ld, int32_t n_nodes, const float* queries,
              int32_t B, int32_t k, int32_t* out_idx, float* out_d2, void* stream);
 

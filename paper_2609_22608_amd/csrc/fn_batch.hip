@@ -70,6 +70,7 @@ __global__ __launch_bounds__(256) void batch_knn_scan(const KnnProb* __restrict_
                                                       float* __restrict__ part_d,
                                                       int32_t* __restrict__ part_i,
                                                       float* __restrict__ part_y) {
+  __shared__ KnnBuf<KNN_QG> s_buf[4];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t pair = (int64_t)blockIdx.x * 4 + wave;
   if (pair >= pair_off[n]) return;
@@ -78,7 +79,8 @@ __global__ __launch_bounds__(256) void batch_knn_scan(const KnnProb* __restrict_
   const int local = (int)(pair - pair_off[p]);
   const int ch = local / q.n_groups, grp = local - ch * q.n_groups;
   knn_scan_item<K1, KNN_QG>(q.tree, q.ld, *q.n_nodes, q.qs, q.B, grp, ch, q.n_split, q.chunk,
-                            part_d + q.part_off, part_i + q.part_off, part_y + q.y_off);
+                            part_d + q.part_off, part_i + q.part_off, part_y + q.y_off,
+                            &s_buf[wave]);
 }
 
 template <int K1>
@@ -307,7 +309,7 @@ extern "C" int fn_batch_prepare(fn_ctx* c, const fn_problem_set* ps) {
         !q.v_rel || !q.vz0 || !q.t_fall || !q.nbr || !q.out_j || !q.out_status || !q.out_margin ||
         !q.out_rho4 || !q.out_T || !q.out_node || !q.out_J || !q.out_best)
       return fail(FN_E_ARG, "fn_batch_prepare: problem %d has a NULL array", p);
-    if (q.B < 1 || q.ld < 4 || (q.ld & 3) != 0 || q.ld > (int64_t)1 << 30)
+    if (q.B < 1 || q.ld < 4 || (q.ld & 3) != 0 || q.ld > KNN_MAX_LD)
       return fail(FN_E_SHAPE, "fn_batch_prepare: problem %d: B = %d, ld = %lld", p, q.B, (long long)q.ld);
     if (q.n_obs < 0 || q.n_obs > FN_MAX_OBS || (q.n_obs > 0 && !q.obs))
       return fail(FN_E_SHAPE, "fn_batch_prepare: problem %d: %d obstacles", p, q.n_obs);

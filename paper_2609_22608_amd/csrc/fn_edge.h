@@ -118,27 +118,13 @@ struct GeoLDS {
   R obs[4 * FN_MAX_OBS];
 };
 
-// Post-checks at duration T (Def. 6 rho_v; position limits; clearance):
-// returns (rho_v, rho_q, rho_c) in every lane.  The sphere and obstacle
-// tables are staged in LDS first, so the (sphere, obstacle) loop reads
-// broadcast LDS instead of waiting on a memory load per pair.
-template <typename R, int PAT>
-__device__ void post_checks(const ArmConst<R>& A, const EdgeState<R>& E, R T, int S,
-                            const float* __restrict__ obs, int n_obs, float margin_c,
-                            GeoLDS<R>* geo, R& rv, R& rq, R& rc) {
+// Velocity taper (Def. 6 rho_v) and position limits at duration T, lane
+// i < 7 checking joint i; (rho_v, rho_q) in every lane.
+template <typename R>
+__device__ void joint_checks(const ArmConst<R>& A, const EdgeState<R>& E, R T, R& rv, R& rq) {
   const int lane = lane_id();
-  if (n_obs > 0) {
-    for (int t = lane; t < A.nsph; t += WAVE) {
-      geo->sph[4 * t] = A.sphx[t];
-      geo->sph[4 * t + 1] = A.sphy[t];
-      geo->sph[4 * t + 2] = A.sphz[t];
-      geo->sph[4 * t + 3] = A.sphr[t] + R(margin_c);
-    }
-    for (int t = lane; t < 4 * n_obs; t += WAVE) geo->obs[t] = R(obs[t]);
-    __builtin_amdgcn_wave_barrier();
-  }
   R v = 0, q = 0;
-  // lane i < 7 checks joint i (register selects keep the edge state in VGPRs)
+  // register selects keep the edge state in VGPRs
   R q0 = 0, qd0 = 0, dq = 0, d2v = 0;
 #pragma unroll
   for (int i = 0; i < NJ; ++i)
@@ -149,43 +135,67 @@ __device__ void post_checks(const ArmConst<R>& A, const EdgeState<R>& E, R T, in
       d2v = E.d2[i];
     }
   if (lane < NJ) joint_post(A, lane, q0, qd0, dq, d2v, T, v, q);
-  // clearance: lane = (sample, sphere part); the parts split each link's
-  // spheres so that all 64 lanes work when S < 64
+  rv = wave_max(v);
+  rq = wave_max(q);
+}
+
+// Clearance (Sec. IV-E spheres) at duration T: rho_c = max over samples,
+// arm spheres and obstacles of (r_a + margin + r_o) / distance, in every
+// lane.  The sphere and obstacle tables are staged in LDS first, so the
+// (sphere, obstacle) loop reads broadcast LDS instead of waiting on a
+// memory load per pair.  Lane = (sample, sphere part): the parts split each
+// link's spheres so that all 64 lanes work when S < 64.
+template <typename R, int PAT>
+__device__ void clearance(const ArmConst<R>& A, const EdgeState<R>& E, R T, int S,
+                          const float* __restrict__ obs, int n_obs, float margin_c,
+                          GeoLDS<R>* geo, R& rc) {
+  const int lane = lane_id();
+  for (int t = lane; t < A.nsph; t += WAVE) {
+    geo->sph[4 * t] = A.sphx[t];
+    geo->sph[4 * t + 1] = A.sphy[t];
+    geo->sph[4 * t + 2] = A.sphz[t];
+    geo->sph[4 * t + 3] = A.sphr[t] + R(margin_c);
+  }
+  for (int t = lane; t < 4 * n_obs; t += WAVE) geo->obs[t] = R(obs[t]);
+  __builtin_amdgcn_wave_barrier();
   R best = 0;
-  if (n_obs > 0) {
-    int Sw = 1;
-    while (Sw < S) Sw <<= 1;
-    const int nparts = Sw >= WAVE ? 1 : WAVE / Sw;
-    const int s = lane & (Sw - 1), part = lane / Sw;
-    if (s < S && part < nparts) {
-      const R u = R(s) / R(S - 1);
-      R sg[NJ], sd[NJ], sdd[NJ], sn[NJ], cs[NJ];
-      cubic_point(E, T, R(1) / T, u, sg, sd, sdd);
+  int Sw = 1;
+  while (Sw < S) Sw <<= 1;
+  const int nparts = Sw >= WAVE ? 1 : WAVE / Sw;
+  const int s = lane & (Sw - 1), part = lane / Sw;
+  if (s < S && part < nparts) {
+    const R u = R(s) / R(S - 1);
+    R sg[NJ], sd[NJ], sdd[NJ], sn[NJ], cs[NJ];
+    cubic_point(E, T, R(1) / T, u, sg, sd, sdd);
 #pragma unroll
-      for (int i = 0; i < NJ; ++i) sincos_r(sg[i], sn[i], cs[i]);
-      const R* so = geo->obs;
-      sphere_centres<R, PAT>(A, sn, cs, part, nparts, geo->sph, [&](int k, R x, R y, R z) {
-        const R ra = geo->sph[4 * k + 3];
+    for (int i = 0; i < NJ; ++i) sincos_r(sg[i], sn[i], cs[i]);
+    const R* so = geo->obs;
+    sphere_centres<R, PAT>(A, sn, cs, part, nparts, geo->sph, [&](int k, R x, R y, R z) {
+      const R ra = geo->sph[4 * k + 3];
 #pragma unroll 4
-        for (int o = 0; o < n_obs; ++o) {
-          const R dx = x - so[4 * o], dy = y - so[4 * o + 1], dz = z - so[4 * o + 2];
-          const R need = ra + so[4 * o + 3];
-          const R d2 = dx * dx + dy * dy + dz * dz;
-          // d2 = 0 gives +inf (reciprocal of zero; IEEE division in FP64)
-          best = rmax(best, fdiv(need * need, d2));
-        }
-      });
-    }
+      for (int o = 0; o < n_obs; ++o) {
+        const R dx = x - so[4 * o], dy = y - so[4 * o + 1], dz = z - so[4 * o + 2];
+        const R need = ra + so[4 * o + 3];
+        const R d2 = dx * dx + dy * dy + dz * dz;
+        // d2 = 0 gives +inf (reciprocal of zero; IEEE division in FP64)
+        best = rmax(best, fdiv(need * need, d2));
+      }
+    });
   }
-  if constexpr (sizeof(R) == 4) {
-    rv = wave_max(float(v));
-    rq = wave_max(float(q));
-    rc = sqrtf(wave_max(float(best)));
-  } else {
-    rv = wave_max(double(v));
-    rq = wave_max(double(q));
-    rc = sqrt(wave_max(double(best)));
-  }
+  if constexpr (sizeof(R) == 4) rc = sqrtf(wave_max(float(best)));
+  else rc = sqrt(wave_max(double(best)));
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Post-checks at duration T: (rho_v, rho_q, rho_c) in every lane (rho_c = 0
+// without obstacles).
+template <typename R, int PAT>
+__device__ void post_checks(const ArmConst<R>& A, const EdgeState<R>& E, R T, int S,
+                            const float* __restrict__ obs, int n_obs, float margin_c,
+                            GeoLDS<R>* geo, R& rv, R& rq, R& rc) {
+  joint_checks<R>(A, E, T, rv, rq);
+  rc = R(0);
+  if (n_obs > 0) clearance<R, PAT>(A, E, T, S, obs, n_obs, margin_c, geo, rc);
 }
 
 __device__ __forceinline__ bool near_one(float r) { return fabsf(r - 1.f) <= BAND; }
@@ -540,7 +550,7 @@ __device__ void search_edge(const EdgeArgs& a, int64_t e, int64_t eq, const ArmC
 template <int PAT>
 __device__ void recheck_edge(const EdgeArgs& a, int64_t e, const QEntry& q,
                              const ArmConst<float>& A, const ArmConst<double>& D, float* s_fix,
-                             GeoLDS<double>* geo) {
+                             GeoLDS<float>* geo32, GeoLDS<double>* geo) {
   const int lane = lane_id();
   EdgeState<float> ES;
   EdgeState<double> ED;
@@ -604,9 +614,18 @@ __device__ void recheck_edge(const EdgeArgs& a, int64_t e, const QEntry& q,
     write_out(a, e, -1, FN_S_NONE | FN_S_RECHECK64 | winbits, marg, last, 0, 0, 0, work);
     return;
   }
-  double rv, rq, rc;
-  post_checks<double, PAT>(D, ED, (double)Tg[jstar], S, a.obs, a.n_obs, a.margin_c, geo, rv, rq,
-                           rc);
+  // post-checks in FP32; a ratio within the band of 1 is recomputed in FP64
+  float fv, fq, fc;
+  post_checks<float, PAT>(A, ES, Tg[jstar], S, a.obs, a.n_obs, a.margin_c, geo32, fv, fq, fc);
+  double rv = fv, rq = fq, rc = fc;
+  if (near_one(fv) || near_one(fq)) {
+    double dv, dq;
+    joint_checks<double>(D, ED, (double)Tg[jstar], dv, dq);
+    if (near_one(fv)) rv = dv;
+    if (near_one(fq)) rq = dq;
+  }
+  if (a.n_obs > 0 && near_one(fc))
+    clearance<double, PAT>(D, ED, (double)Tg[jstar], S, a.obs, a.n_obs, a.margin_c, geo, rc);
   const float m = fminf(marg, (float)fmin(fabs(rv - 1.0), fmin(fabs(rq - 1.0), fabs(rc - 1.0))));
   write_out(a, e, jstar, post_status(rv, rq, rc) | FN_S_RECHECK64 | winbits, m, (float)rho_star,
             (float)rv, (float)rq, (float)rc, work, Tg[jstar]);
@@ -637,6 +656,7 @@ __global__ __launch_bounds__(64) void edge_recheck_kernel(EdgeArgs a, ProbTable 
                                                           const ArmConst<float>* __restrict__ Ap,
                                                           const ArmConst<double>* __restrict__ Dp) {
   __shared__ float s_fix[1];
+  __shared__ GeoLDS<float> s_geo32;
   __shared__ GeoLDS<double> s_geo;
   const int n = *a.q_count;
   for (int qi = blockIdx.x; qi < n; qi += gridDim.x) {
@@ -648,7 +668,7 @@ __global__ __launch_bounds__(64) void edge_recheck_kernel(EdgeArgs a, ProbTable 
       ap = pt.args + p;
       e -= pt.edge_off[p];
     }
-    recheck_edge<PAT>(*ap, e, q, *Ap, *Dp, s_fix, &s_geo);
+    recheck_edge<PAT>(*ap, e, q, *Ap, *Dp, s_fix, &s_geo32, &s_geo);
   }
 }
 

@@ -20,6 +20,9 @@
 namespace fn {
 
 constexpr int KNN_TARGET_WAVES = 4096;
+// Largest tree leading dimension: the scan addresses the 14 rows with 32-bit
+// byte offsets (14 * ld * 4 < 2^31).
+constexpr int64_t KNN_MAX_LD = (((int64_t)1 << 31) - 1) / (4 * FN_STATE) / 4 * 4;
 constexpr float KNN_BAND = 1e-6f;  // slack for rounding the band itself
 constexpr float KNN_EPS = 4e-6f;   // |d32 - d| <= KNN_EPS (|x| + |y|)^2 (twice the FP32 bound)
 
@@ -36,18 +39,78 @@ __device__ __forceinline__ int wave_shr1(int v) {
   return __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true);
 }
 
+// Value of lane (lane ^ J) (J a power of two below 64): DPP quad
+// permutations for 1 and 2, LDS swizzle (bit-mask mode, within 32 lanes)
+// for 4..16, LDS permute for 32.
+template <int J>
+__device__ __forceinline__ int lane_xor(int v) {
+  if constexpr (J == 1) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xf, 0xf, true);  // quad_perm 1,0,3,2
+  else if constexpr (J == 2) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xf, 0xf, true);  // 2,3,0,1
+  else if constexpr (J < 32) return __builtin_amdgcn_ds_swizzle(v, (J << 10) | 0x1f);
+  else return __builtin_amdgcn_ds_bpermute((int)((threadIdx.x & 63) ^ 32) << 2, v);
+}
+
+// One compare-exchange stage (block size K, distance J) of the bitonic
+// network over the 64 lanes; keys compare as key_less, branch-free.
+template <int K, int J>
+__device__ __forceinline__ void bitonic_stage(float& d, int& i) {
+  const int lane = threadIdx.x & 63;
+  const float od = __builtin_bit_cast(float, lane_xor<J>(__builtin_bit_cast(int, d)));
+  const int oi = lane_xor<J>(i);
+  const bool eq = od == d;
+  const bool o_less = (od < d) | (eq & ((unsigned)oi < (unsigned)i));
+  const bool s_less = (d < od) | (eq & ((unsigned)i < (unsigned)oi));
+  // the lower lane of a pair keeps the smaller key in an ascending block of
+  // size K, the larger one in a descending block
+  const bool want_min = ((lane & J) == 0) == ((lane & K) == 0);
+  const bool take = want_min ? o_less : s_less;
+  d = take ? od : d;
+  i = take ? oi : i;
+}
+
+template <int K, int J>
+__device__ __forceinline__ void bitonic_merge_steps(float& d, int& i) {
+  bitonic_stage<K, J>(d, i);
+  if constexpr (J > 1) bitonic_merge_steps<K, J / 2>(d, i);
+}
+
+// Sorts the 64 lanes' keys (d, i) ascending by key_less (bitonic network;
+// equal keys stay put).
+__device__ __forceinline__ void wave_sort64(float& d, int& i) {
+  bitonic_merge_steps<2, 1>(d, i);
+  bitonic_merge_steps<4, 2>(d, i);
+  bitonic_merge_steps<8, 4>(d, i);
+  bitonic_merge_steps<16, 8>(d, i);
+  bitonic_merge_steps<32, 16>(d, i);
+  bitonic_merge_steps<64, 32>(d, i);
+}
+
+// LDS of one scan wavefront: per query, a buffer of candidate keys.
+template <int QG>
+struct KnnBuf {
+  float d[QG][WAVE];
+  int32_t i[QG][WAVE];
+};
+
 // One wavefront per (QG queries, node chunk).  Lanes run over 64 nodes at
 // a time (coalesced loads of the SoA rows).  The FP32 screening distance is
 // |x|^2 + |y|^2 - 2 x.y (14 FMAs per pair, |y|^2 shared by the QG queries);
 // its absolute error is below 4e-6 (|x| + |y|)^2, a bound the merge carries
-// into the band it re-ranks exactly.  Every query's k+1 best keys
-// (d^2, index) live distributed over lanes 0..K1-1; the K1-th is a
-// wave-uniform threshold, so a node costs a ballot unless it beats it.
+// into the band it re-ranks exactly.  Every query keeps its chunk's K1
+// best keys (d^2, index) sorted over lanes 0..K1-1 with the K1-th as a
+// wave-uniform threshold.  A node that beats the threshold is appended to
+// the query's LDS buffer (ballot + lane rank); when the list and the buffer
+// fill the 64 lanes they are sorted together and the list and threshold
+// are renewed.  Nodes arrive in increasing index, so a node whose distance
+// equals the threshold never beats it, and every node left out has a key
+// above the chunk's final K1-th key: the list is the chunk's exact FP32
+// top K1 by (d^2, index).
 template <int K1, int QG>
 __device__ void knn_scan_item(const float* __restrict__ tree, int64_t ld, int n_nodes,
                               const float* __restrict__ qs, int B, int grp, int ch, int n_split,
                               int chunk, float* __restrict__ out_d, int32_t* __restrict__ out_i,
-                              float* __restrict__ out_y2) {
+                              float* __restrict__ out_y2, KnnBuf<QG>* buf) {
+  constexpr int CAP = WAVE - K1;  // buffer entries that fit beside the list
   const int lane = threadIdx.x & 63;
   float xm2[QG][FN_STATE], xx[QG];
 #pragma unroll
@@ -65,26 +128,45 @@ __device__ void knn_scan_item(const float* __restrict__ tree, int64_t ld, int n_
   float Ld[QG];
   int Li[QG];
   float th_d[QG];
-  int th_i[QG];
+  int nb[QG];
 #pragma unroll
   for (int q = 0; q < QG; ++q) {
     Ld[q] = INFINITY;
     Li[q] = -1;
     th_d[q] = INFINITY;
-    th_i[q] = -1;
+    nb[q] = 0;
   }
+  // list + buffer of query q sorted together; list and threshold renewed
+  auto merge = [&](int q) {
+    __builtin_amdgcn_wave_barrier();
+    const int t = lane - K1;
+    float d = lane < K1 ? Ld[q] : (t < nb[q] ? buf->d[q][t] : INFINITY);
+    int i = lane < K1 ? Li[q] : (t < nb[q] ? buf->i[q][t] : -1);
+    wave_sort64(d, i);
+    Ld[q] = lane < K1 ? d : INFINITY;
+    Li[q] = lane < K1 ? i : -1;
+    th_d[q] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, d), K1 - 1));
+    nb[q] = 0;
+    __builtin_amdgcn_wave_barrier();
+  };
+  // the tree rows through a buffer resource: row c of node n at byte
+  // offset c * ld * 4 (scalar) + n * 4 (per lane), no 64-bit address math;
+  // the host keeps 14 * ld * 4 below 2^31
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)tree, (short)0, (int)(FN_STATE * ld * 4), 0x00020000);
+  const int row_bytes = (int)ld * 4;
   float y2max = 0.f;
   const int n0 = ch * chunk;
   const int n1 = min(n0 + chunk, n_nodes);
-  for (int nb = n0; nb < n1; nb += WAVE) {
-    const int node = nb + lane;
+  for (int nb0 = n0; nb0 < n1; nb0 += WAVE) {
+    const int node = nb0 + lane;
     const bool valid = node < n1;
     const int nc = valid ? node : n1 - 1;
     float y[FN_STATE];
     float yy = 0.f;
 #pragma unroll
     for (int c = 0; c < FN_STATE; ++c) {
-      y[c] = tree[(size_t)c * ld + nc];
+      y[c] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, nc * 4, c * row_bytes, 0));
       yy = fmaf(y[c], y[c], yy);
     }
     y2max = fmaxf(y2max, yy);
@@ -94,27 +176,30 @@ __device__ void knn_scan_item(const float* __restrict__ tree, int64_t ld, int n_
 #pragma unroll
       for (int c = 0; c < FN_STATE; ++c) d = fmaf(xm2[q][c], y[c], d);
       d = valid ? d : INFINITY;
-      // nodes arrive in increasing index, so an equal distance never beats
-      // the threshold entry
       uint64_t mask = __ballot(d < th_d[q]);
       while (mask) {
-        const int src = __ffsll((long long)mask) - 1;
-        mask &= mask - 1;
-        const float dd = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, d), src));
-        const int ii = nb + src;
-        if (!key_less(dd, ii, th_d[q], th_i[q])) continue;
-        // insert into the distributed sorted list (lane r holds entry r)
-        const float pd = wave_shr1(Ld[q]);
-        const int pi = wave_shr1(Li[q]);
-        const bool lt_here = key_less(dd, ii, Ld[q], Li[q]);
-        const bool lt_prev = lane > 0 && key_less(dd, ii, pd, pi);
-        Ld[q] = lane >= K1 ? INFINITY : lt_prev ? pd : lt_here ? dd : Ld[q];
-        Li[q] = lane >= K1 ? -1 : lt_prev ? pi : lt_here ? ii : Li[q];
-        th_d[q] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, Ld[q]), K1 - 1));
-        th_i[q] = __builtin_amdgcn_readlane(Li[q], K1 - 1);
+        // append the lowest `take` candidates to the buffer
+        const int cnt = (int)__popcll(mask), room = CAP - nb[q];
+        const int take = cnt < room ? cnt : room;
+        const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                                   __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+        const bool in = ((mask >> lane) & 1ull) && rank < take;
+        if (in) {
+          buf->d[q][nb[q] + rank] = d;
+          buf->i[q][nb[q] + rank] = node;
+        }
+        mask &= ~__ballot(in);
+        nb[q] += take;
+        if (nb[q] == CAP) {
+          merge(q);
+          mask &= __ballot(d < th_d[q]);
+        }
       }
     }
   }
+#pragma unroll
+  for (int q = 0; q < QG; ++q)
+    if (nb[q] > 0) merge(q);
   y2max = wave_max(y2max);
 #pragma unroll
   for (int q = 0; q < QG; ++q) {

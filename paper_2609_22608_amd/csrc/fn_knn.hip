@@ -13,13 +13,15 @@ __global__ __launch_bounds__(256) void knn_scan(const float* __restrict__ tree, 
                                                 float* __restrict__ out_d,
                                                 int32_t* __restrict__ out_i,
                                                 float* __restrict__ out_y2) {
+  __shared__ KnnBuf<QG> s_buf[4];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int pair = blockIdx.x * 4 + wave;
   if (pair >= n_groups * n_split) return;
   // the wavefronts of a block share a node chunk (L1 reuse), each with its
   // own query group
   const int ch = pair / n_groups, grp = pair - ch * n_groups;
-  knn_scan_item<K1, QG>(tree, ld, n_nodes, qs, B, grp, ch, n_split, chunk, out_d, out_i, out_y2);
+  knn_scan_item<K1, QG>(tree, ld, n_nodes, qs, B, grp, ch, n_split, chunk, out_d, out_i, out_y2,
+                        &s_buf[wave]);
 }
 
 template <int K1>
@@ -81,6 +83,7 @@ extern "C" int plan_knn(fn_ctx* c, const float* tree, int64_t ld, int32_t n_node
   if (!queries || !out_idx || (n_nodes > 0 && !tree)) return fail(FN_E_ARG, "plan_knn: NULL array");
   const int n_pad = (n_nodes + 3) & ~3;
   if ((ld & 3) != 0 || ld < n_pad) return fail(FN_E_ARG, "plan_knn: ld = %lld (need a multiple of 4 >= %d)", (long long)ld, n_pad);
+  if (ld > KNN_MAX_LD) return fail(FN_E_SHAPE, "plan_knn: ld = %lld (max %lld)", (long long)ld, (long long)KNN_MAX_LD);
   if (((uintptr_t)tree & 15) != 0) return fail(FN_E_ARG, "plan_knn: tree not 16-byte aligned");
   hipStream_t s = (hipStream_t)stream;
   switch (k + 1) {
