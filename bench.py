@@ -75,6 +75,8 @@ def parse():
     p.add_argument("--batch-problems", type=int, default=32,
                    help="problems in the batched-round form (0 skips it)")
     p.add_argument("--no-tune", action="store_true", help="default launch mappings (no autotuning)")
+    p.add_argument("--tune-cache", default=None,
+                   help="JSON cache of tuned launch mappings (read and written)")
     return p.parse_args()
 
 
@@ -111,7 +113,8 @@ def main():
         # launch mapping of the kNN scan for this shape (outside the timed region)
         from paper_2609_22608_amd import autotune
 
-        ch, _ = autotune.tune_knn(ctx, tree, ld, n, cand, sh.k, reps=3)
+        ch, _ = autotune.tune_knn(ctx, tree, ld, n, cand, sh.k, reps=3,
+                                  cache=autotune.Cache(args.tune_cache))
         knn_tuning = ch.as_dict()
     modes = {"plain": fn.SEARCH_PLAIN, "screen": fn.SEARCH_SCREEN, "window": fn.SEARCH_WINDOW}
     wanted = args.modes.split(",")
@@ -296,7 +299,7 @@ def batched_round(args, fn, W, torch):
     bt.prepare()
     tuned = None
     if not args.no_tune:
-        ch, _ = autotune.tune_batch(bt, reps=2)
+        ch, _ = autotune.tune_batch(bt, reps=2, cache=autotune.Cache(args.tune_cache))
         tuned = ch.as_dict()
     stream = torch.cuda.current_stream()
 

@@ -50,39 +50,50 @@ __device__ __forceinline__ int lane_xor(int v) {
   else return __builtin_amdgcn_ds_bpermute((int)((threadIdx.x & 63) ^ 32) << 2, v);
 }
 
+// (d, i) as one unsigned 64-bit key ordered as key_less: the float's bits
+// mapped to an order-preserving unsigned value, then the index (unsigned,
+// so the -1 of a padding entry ranks last).
+__device__ __forceinline__ uint64_t knn_key(float d, int i) {
+  const uint32_t b = __float_as_uint(d + 0.f);  // -0 -> +0, as key_less treats them equal
+  const uint32_t m = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+  return ((uint64_t)m << 32) | (uint32_t)i;
+}
+__device__ __forceinline__ float knn_key_d(uint64_t k) {
+  const uint32_t m = (uint32_t)(k >> 32);
+  return __uint_as_float((m & 0x80000000u) ? (m & 0x7fffffffu) : ~m);
+}
+
 // One compare-exchange stage (block size K, distance J) of the bitonic
-// network over the 64 lanes; keys compare as key_less, branch-free.
+// network over the 64 lanes' keys.
 template <int K, int J>
-__device__ __forceinline__ void bitonic_stage(float& d, int& i) {
+__device__ __forceinline__ void bitonic_stage(uint64_t& key) {
   const int lane = threadIdx.x & 63;
-  const float od = __builtin_bit_cast(float, lane_xor<J>(__builtin_bit_cast(int, d)));
-  const int oi = lane_xor<J>(i);
-  const bool eq = od == d;
-  const bool o_less = (od < d) | (eq & ((unsigned)oi < (unsigned)i));
-  const bool s_less = (d < od) | (eq & ((unsigned)i < (unsigned)oi));
+  const uint64_t o = ((uint64_t)(uint32_t)lane_xor<J>((int)(key >> 32)) << 32) |
+                     (uint32_t)lane_xor<J>((int)(uint32_t)key);
   // the lower lane of a pair keeps the smaller key in an ascending block of
   // size K, the larger one in a descending block
   const bool want_min = ((lane & J) == 0) == ((lane & K) == 0);
-  const bool take = want_min ? o_less : s_less;
-  d = take ? od : d;
-  i = take ? oi : i;
+  key = (want_min ? o < key : key < o) ? o : key;
 }
 
 template <int K, int J>
-__device__ __forceinline__ void bitonic_merge_steps(float& d, int& i) {
-  bitonic_stage<K, J>(d, i);
-  if constexpr (J > 1) bitonic_merge_steps<K, J / 2>(d, i);
+__device__ __forceinline__ void bitonic_merge_steps(uint64_t& key) {
+  bitonic_stage<K, J>(key);
+  if constexpr (J > 1) bitonic_merge_steps<K, J / 2>(key);
 }
 
-// Sorts the 64 lanes' keys (d, i) ascending by key_less (bitonic network;
-// equal keys stay put).
+// Sorts the 64 lanes' keys (d, i) ascending by key_less (bitonic network
+// over 64-bit keys; equal keys stay put).
 __device__ __forceinline__ void wave_sort64(float& d, int& i) {
-  bitonic_merge_steps<2, 1>(d, i);
-  bitonic_merge_steps<4, 2>(d, i);
-  bitonic_merge_steps<8, 4>(d, i);
-  bitonic_merge_steps<16, 8>(d, i);
-  bitonic_merge_steps<32, 16>(d, i);
-  bitonic_merge_steps<64, 32>(d, i);
+  uint64_t key = knn_key(d, i);
+  bitonic_merge_steps<2, 1>(key);
+  bitonic_merge_steps<4, 2>(key);
+  bitonic_merge_steps<8, 4>(key);
+  bitonic_merge_steps<16, 8>(key);
+  bitonic_merge_steps<32, 16>(key);
+  bitonic_merge_steps<64, 32>(key);
+  d = knn_key_d(key);
+  i = (int)(uint32_t)key;
 }
 
 // LDS of one scan wavefront: per query, a buffer of candidate keys.
