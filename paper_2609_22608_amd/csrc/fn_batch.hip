@@ -396,8 +396,8 @@ extern "C" int fn_batch_launch(fn_ctx* c, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   switch (bt->K1) {
 #define FN_K(KK) case KK: launch_batch_knn<KK>(c, bt, s); break;
-    FN_K(2) FN_K(3) FN_K(4) FN_K(5) FN_K(6) FN_K(7) FN_K(8) FN_K(9) FN_K(10) FN_K(11) FN_K(12)
-    FN_K(13) FN_K(14) FN_K(15) FN_K(16) FN_K(17) FN_K(33)
+    FN_K(5) FN_K(6) FN_K(7) FN_K(8) FN_K(9) FN_K(10) FN_K(11) FN_K(12) FN_K(13) FN_K(14) FN_K(15)
+    FN_K(16) FN_K(33)
 #undef FN_K
     default: return fail(FN_E_SHAPE, "fn_batch_launch: k");
   }

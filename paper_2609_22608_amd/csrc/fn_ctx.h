@@ -38,7 +38,9 @@ __global__ void zero_i32_kernel(int32_t* p, int n);
 constexpr int KNN_TARGET_MAX = 16384;
 size_t knn_scratch_entries(int max_batch, int max_k, int max_problems);
 // list length a kNN launch uses for k
-inline int knn_k1(int k) { return k <= 16 ? k + 1 : 33; }
+// (k + 4 spare entries per node chunk, so that near ties at the k-th
+// distance almost never force the exact rescan; 33 for k > 12)
+inline int knn_k1(int k) { return k <= 12 ? k + 4 : 33; }
 
 }  // namespace fn
 

@@ -3,14 +3,16 @@
 //
 // Stage 1 (knn_scan): one wavefront per (4 queries, node chunk); lanes run
 // over the chunk's nodes with coalesced loads of the SoA tree rows, every
-// distance costs 14 subtractions and 14 FMAs, and each query keeps its
-// chunk's k+1 smallest FP32 keys (d^2, index) spread over lanes 0..k.
+// screening distance costs 14 FMAs, and each query keeps its chunk's K1
+// smallest FP32 keys (d^2, index), K1 = k + 4 (33 for k > 12), sorted over
+// lanes 0..K1-1.
 // Stage 2 (knn_merge): one wavefront per query merges the chunk lists.  The
 // FP32 k-th key bounds a band that provably holds the exact top-k; every
-// candidate in the band is re-ranked with the FP64 distance summed in the
+// list entry in the band is re-ranked with the FP64 distance summed in the
 // reference order (c = 0..13, separately rounded products and sums).  When
-// a chunk's (k+1)-th entry also falls in the band (near ties that the FP32
-// lists may have cut), the query is rescanned exactly in FP64.
+// a chunk's last (K1-th) entry also falls in the band, that chunk may hold
+// more in-band nodes than its list, and the query is rescanned exactly in
+// FP64; the spare entries make this rare.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -277,14 +279,14 @@ __device__ void knn_merge_query(const float* __restrict__ tree, int64_t ld, int 
   const float* D = in_d + (size_t)b * total;
   const int32_t* I = in_i + (size_t)b * total;
 
-  // (a) FP32 k-th smallest key among every chunk's first k entries
+  // (a) FP32 k-th smallest key over all chunk lists (each chunk's K1 >= k
+  // smallest keys, so this is the k-th smallest screening key overall)
   float th_d = -1.f;
   int th_i = -1;
   for (int r = 0; r < k; ++r) {
     float bd = INFINITY;
     int bi = -1;
     for (int e = lane; e < total; e += 64) {
-      if (e % K1 >= k) continue;
       const float d = D[e];
       const int i = I[e];
       if (i < 0) continue;
@@ -320,10 +322,11 @@ __device__ void knn_merge_query(const float* __restrict__ tree, int64_t ld, int 
   // every exact top-k node has a screening key within th + 2 eps
   const float band = th_i < 0 ? INFINITY : th_d + 2.f * eps + fabsf(th_d) * KNN_BAND + 1e-30f;
 
-  // (b) a chunk whose (k+1)-th entry is inside the band may have cut near ties
+  // (b) a chunk whose last entry is inside the band may hold more in-band
+  // nodes than its list
   int over = 0;
   for (int e = lane; e < total; e += 64)
-    if (e % K1 == k && I[e] >= 0 && D[e] <= band) over = 1;
+    if (e % K1 == K1 - 1 && I[e] >= 0 && D[e] <= band) over = 1;
   over = __any(over);
 
   if (!over) {
@@ -332,7 +335,7 @@ __device__ void knn_merge_query(const float* __restrict__ tree, int64_t ld, int 
     __shared__ double s_d[KNN_MAX_SPLIT * (FN_MAX_K + 1)];
     for (int e = lane; e < total; e += 64) {
       const int i = I[e];
-      const bool in = (e % K1 < k) && i >= 0 && D[e] <= band;
+      const bool in = i >= 0 && D[e] <= band;
       s_d[e] = in ? exact_d2(tree, ld, i, x) : INFINITY;
     }
     __syncthreads();

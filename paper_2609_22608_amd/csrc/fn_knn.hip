@@ -86,14 +86,12 @@ extern "C" int plan_knn(fn_ctx* c, const float* tree, int64_t ld, int32_t n_node
   if (ld > KNN_MAX_LD) return fail(FN_E_SHAPE, "plan_knn: ld = %lld (max %lld)", (long long)ld, (long long)KNN_MAX_LD);
   if (((uintptr_t)tree & 15) != 0) return fail(FN_E_ARG, "plan_knn: tree not 16-byte aligned");
   hipStream_t s = (hipStream_t)stream;
-  switch (k + 1) {
+  switch (knn_k1(k)) {
 #define FN_K(KK) case KK: launch_knn<KK>(c, tree, ld, n_nodes, queries, B, k, out_idx, out_d2, s); break;
-    FN_K(2) FN_K(3) FN_K(4) FN_K(5) FN_K(6) FN_K(7) FN_K(8) FN_K(9) FN_K(10) FN_K(11) FN_K(12)
-    FN_K(13) FN_K(14) FN_K(15) FN_K(16) FN_K(17)
+    FN_K(5) FN_K(6) FN_K(7) FN_K(8) FN_K(9) FN_K(10) FN_K(11) FN_K(12) FN_K(13) FN_K(14) FN_K(15)
+    FN_K(16) FN_K(33)
 #undef FN_K
-    default:
-      if (k + 1 <= 33) launch_knn<33>(c, tree, ld, n_nodes, queries, B, k, out_idx, out_d2, s);
-      else return fail(FN_E_SHAPE, "plan_knn: k = %d", k);
+    default: return fail(FN_E_SHAPE, "plan_knn: k = %d", k);
   }
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? FN_OK : hip_fail(e, "plan_knn launch");
