@@ -174,6 +174,39 @@ def test_edge_time_iteration_sampled(iteration, mode):
     compare_edges(out, ref, sel, label=f"iteration mode {mode}")
 
 
+def test_stress_shape_sampled(tmp_path):
+    """Full stress shape (262,144 nodes, 65,536 candidates, k = 16, 128 T x 64
+    samples, 20 obstacles: 1,048,576 edges) in the screened form the bench
+    times; 32 sampled candidates (512 edges) checked against the oracle:
+    parents bit-exact, decisions on every strict edge."""
+    import concurrent.futures as cf
+
+    sh = W.CONFIGS["stress"]
+    wl = W.make_workload(sh, seed=7)
+    ctx = _ctx(wl)
+    tree, ld, n = fn.tree_soa(wl["tree_x"])
+    cand = fn.dev(wl["cand"]["x"])
+    idx, d2 = ctx.plan_knn(tree, ld, n, cand, sh.k)
+    out = _run_edges(ctx, wl, idx, fn.SEARCH_SCREEN)
+    rows = np.sort(np.random.default_rng(5).choice(sh.batch, 32, replace=False))
+    ridx, rd2 = O.plan_knn(wl["tree_x"], wl["cand"]["x"][rows], sh.k)
+    assert np.array_equal(idx.cpu().numpy()[rows], ridx)
+    assert np.array_equal(d2.cpu().numpy()[rows], rd2.astype(np.float32))
+    x0, x1, ok = O.edges_of(wl["tree_x"], wl["cand"]["x"][rows], ridx)
+    A = O.make_oarm(wl["arm"])
+    parts = np.array_split(np.arange(len(x0)), 16)
+
+    def job(p):
+        return O.edge_time(A, x0[p], x1[p], wl["grid"], sh.samples, wl["obs"], parent_ok=ok[p])
+
+    with cf.ThreadPoolExecutor(16) as ex:
+        refs = list(ex.map(job, parts))
+    ref = {key: np.concatenate([r[key] for r in refs]) for key in ("j", "status", "margin")}
+    sel = (rows[:, None] * sh.k + np.arange(sh.k)[None, :]).reshape(-1)
+    compare_edges(out, ref, sel, label="stress screen")
+    ctx.close()
+
+
 def test_modes_agree_full_iteration(iteration):
     """All search modes give identical results on every edge of the batch."""
     sh = iteration["shape"]

@@ -1,0 +1,91 @@
+"""Launch mappings do not change results; the autotuner, the kernel timing
+events and the batched round's host-side validation."""
+import numpy as np
+import pytest
+
+from paper_2609_22608_amd import workload as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2609_22608_amd import autotune, fn  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def iteration():
+    sh = W.CONFIGS["iteration"]
+    wl = W.make_workload(sh, seed=303)
+    ctx = fn.Context(wl["arm"], sh.n_nodes, sh.batch, sh.k)
+    tree, ld, n = fn.tree_soa(wl["tree_x"])
+    yield sh, wl, ctx, tree, ld, n, fn.dev(wl["cand"]["x"])
+    ctx.close()
+
+
+def test_knn_result_is_independent_of_the_launch_mapping(iteration):
+    sh, wl, ctx, tree, ld, n, cand = iteration
+    ref = None
+    for tw, mc in ((0, 0), (1024, 256), (16384, 64), (2048, 4096)):
+        ctx.set_tuning(tw, mc)
+        idx, d2 = ctx.plan_knn(tree, ld, n, cand, sh.k)
+        torch.cuda.synchronize()
+        got = (idx.cpu().numpy(), d2.cpu().numpy())
+        if ref is None:
+            ref = got
+        else:
+            assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (tw, mc)
+    ctx.set_tuning(0, 0)
+
+
+def test_autotuner_picks_a_candidate_and_caches_it(iteration, tmp_path):
+    sh, wl, ctx, tree, ld, n, cand = iteration
+    cache = autotune.Cache(str(tmp_path / "t.json"))
+    ch, times = autotune.tune_knn(ctx, tree, ld, n, cand, sh.k, reps=1, cache=cache)
+    assert (ch.knn_target_waves, ch.knn_min_chunk) in autotune.KNN_CANDIDATES
+    assert len(times) == len(autotune.KNN_CANDIDATES) and ch.ms == min(times.values())
+    ch2, times2 = autotune.tune_knn(ctx, tree, ld, n, cand, sh.k, cache=cache)
+    assert ch2 == ch and times2 == {}  # from the cache
+    ctx.set_tuning(0, 0)
+
+
+def test_kernel_timing_events(iteration):
+    sh, wl, ctx, tree, ld, n, cand = iteration
+    idx, _ = ctx.plan_knn(tree, ld, n, cand, sh.k, want_d2=False)
+    grid, obs = fn.dev(wl["grid"]), fn.dev(wl["obs"])
+    ctx.kernel_timing(True)
+    assert ctx.kernel_times() == []
+    for mode in (fn.SEARCH_PLAIN, fn.SEARCH_SCREEN, fn.SEARCH_SCREEN):
+        ctx.edge_time_batch(tree, ld, n, cand, idx, grid, sh.samples, obs, mode=mode)
+    ms = ctx.kernel_times()
+    assert len(ms) == 3 and all(t > 0 for t in ms)
+    assert ms[0] > ms[1]  # the plain search evaluates far more points
+    assert ctx.kernel_times() == []  # cleared
+    ctx.kernel_timing(False)
+    ctx.edge_time_batch(tree, ld, n, cand, idx, grid, sh.samples, obs, mode=fn.SEARCH_SCREEN)
+    assert ctx.kernel_times() == []
+
+
+def test_tuning_and_problem_set_are_validated(iteration):
+    sh, wl, ctx, tree, ld, n, cand = iteration
+    with pytest.raises(fn.FnError, match="multiple of 64"):
+        ctx.set_tuning(4096, 100)
+    with pytest.raises(fn.FnError, match="target waves"):
+        ctx.set_tuning(1 << 20, 512)
+    with pytest.raises(fn.FnError, match="max_problems = 0"):
+        fn.Batch(ctx, fn.dev(wl["grid"]), sh.samples, sh.k).prepare()
+    arm, probs = W.make_problem_set(2, 5, nodes=(300, 600), batch=(40, 60))
+    sumB = sum(p["shape"].batch for p in probs)
+    c2 = fn.Context(arm, 4096, sumB, 8, max_edges=sumB * 8, max_problems=2)
+    bt = fn.Batch(c2, fn.dev(probs[0]["grid"]), 32, 8)
+    with pytest.raises(fn.FnError, match="no prepared problem set"):
+        bt.launch()
+    with pytest.raises(fn.FnError, match="nothing captured"):
+        bt.replay()
+    for wl2 in probs + probs:  # four problems, cap two
+        bt.add_problem(wl2["tree_x"], wl2["tree_t"], wl2["cand"], wl2["obs"],
+                       capacity=wl2["shape"].n_nodes + 64)
+    with pytest.raises(fn.FnError, match="problems"):
+        bt.prepare()
+    c2.close()
