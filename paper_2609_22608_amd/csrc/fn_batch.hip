@@ -99,7 +99,7 @@ __global__ __launch_bounds__(64) void batch_knn_merge(const KnnProb* __restrict_
 
 // EDGE_WAVES edges per workgroup (see edge_time_kernel).
 template <int PAT, int MODE>
-__global__ __launch_bounds__(64 * EDGE_WAVES) __attribute__((amdgpu_waves_per_eu(3))) void
+__global__ __launch_bounds__(64 * EDGE_WAVES) __attribute__((amdgpu_waves_per_eu(4))) void
 batch_edge_kernel(ProbTable pt, const float* __restrict__ grid, int n_t,
                   const ArmConst<float>* __restrict__ Ap) {
   __shared__ float s_end_all[EDGE_WAVES][FN_MAX_NT];
