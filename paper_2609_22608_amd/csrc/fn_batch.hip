@@ -110,7 +110,10 @@ batch_edge_kernel(ProbTable pt, const float* __restrict__ grid, int n_t,
   for (int t = threadIdx.x; t < n_t; t += blockDim.x) s_T[t] = grid[t];
   __syncthreads();
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t eg = (int64_t)blockIdx.x * EDGE_WAVES + wave;
+  // global candidate order: problem p's candidates follow problem p - 1's and
+  // every problem has the same k, so global edge = global candidate k + i
+  const int64_t eg = xcd_edge(blockIdx.x, pt.args[0].k, pt.edge_off[pt.n] / pt.args[0].k);
+  if (eg < 0) return;
   if (eg >= pt.edge_off[pt.n]) return;
   const int p = problem_of(pt, eg);
   search_edge<PAT, MODE, true>(pt.args[p], eg - pt.edge_off[p], eg, *Ap, s_end_all[wave], s_T,
@@ -383,7 +386,7 @@ static void launch_batch_search(fn_ctx* c, fn_batch* bt, hipStream_t s) {
   if (MODE != FN_SEARCH_PLAIN)
     hipLaunchKernelGGL(batch_model_kernel<PAT>, dim3((unsigned)(((bt->edges + bt->queries) * 8 + 255) / 256)),
                        dim3(256), 0, s, pt, bt->query_off, c->arm32);
-  hipLaunchKernelGGL((batch_edge_kernel<PAT, MODE>), dim3((unsigned)((bt->edges + EDGE_WAVES - 1) / EDGE_WAVES)),
+  hipLaunchKernelGGL((batch_edge_kernel<PAT, MODE>), dim3((unsigned)xcd_grid(bt->queries, bt->k)),
                      dim3(64 * EDGE_WAVES), 0, s, pt, bt->grid, bt->n_t, c->arm32);
   const unsigned rw = (unsigned)(bt->edges < 4096 ? bt->edges : 4096);
   hipLaunchKernelGGL(edge_recheck_kernel<PAT>, dim3(rw), dim3(64), 0, s, bt->a0, pt, c->arm32, c->arm64);

@@ -283,6 +283,24 @@ __device__ __forceinline__ void stage_of(int mode, int st, int jmax, int lo, int
 // Edges (wavefronts) per workgroup of the search kernels.
 constexpr int EDGE_WAVES = 1;
 
+// XCD-aware order of the search grid.  Workgroups are dealt to the 8 XCDs
+// in turn (workgroup w runs on XCD w mod 8), so consecutive edges land on
+// different L2s.  Workgroup w takes edge i of candidate b with
+// b = 8 ((w div 8) div k) + w mod 8 and i = (w div 8) mod k: all k edges of a
+// candidate run on one XCD, which then fetches the candidate's state and
+// endpoint model once.  The grid has ceil(B / 8) 8 k workgroups; the ones
+// past the last candidate return.  Returns -1 for those.
+constexpr int N_XCD = 8;
+__device__ __forceinline__ int64_t xcd_edge(int64_t w, int k, int64_t B) {
+  static_assert(EDGE_WAVES == 1, "one edge per workgroup");
+  const int64_t s = w / N_XCD;
+  const int64_t b = (s / k) * N_XCD + (w % N_XCD);
+  return b < B ? b * k + s % k : -1;
+}
+__host__ __forceinline__ int64_t xcd_grid(int64_t B, int k) {
+  return (B + N_XCD - 1) / N_XCD * N_XCD * k;
+}
+
 // Slots still to be evaluated in full: bit j of word j / 64.
 struct SlotMask {
   uint64_t w0, w1, w2, w3;

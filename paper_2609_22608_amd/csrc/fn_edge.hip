@@ -41,8 +41,8 @@ edge_time_kernel(EdgeArgs a, const ArmConst<float>* __restrict__ Ap) {
   for (int t = threadIdx.x; t < a.n_t; t += blockDim.x) s_T[t] = a.grid[t];
   __syncthreads();
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t e = (int64_t)blockIdx.x * EDGE_WAVES + wave;
-  if (e >= a.E) return;
+  const int64_t e = xcd_edge(blockIdx.x, a.k, a.E / a.k);
+  if (e < 0) return;
   search_edge<PAT, MODE, false>(a, e, e, *Ap, s_end_all[wave], s_T, &s_fix[wave], s_mod[wave],
                                 &s_geo[wave]);
 }
@@ -132,7 +132,7 @@ static void launch_search(fn_ctx* c, const EdgeArgs& a, int ti, hipStream_t s) {
     hipLaunchKernelGGL(edge_model_kernel<PAT>, dim3((unsigned)(((E + B) * 8 + 255) / 256)),
                        dim3(256), 0, s, a, c->arm32);
   if (ti >= 0) (void)hipEventRecord(c->tev[2 * ti], s);
-  hipLaunchKernelGGL((edge_time_kernel<PAT, MODE>), dim3((unsigned)((E + EDGE_WAVES - 1) / EDGE_WAVES)),
+  hipLaunchKernelGGL((edge_time_kernel<PAT, MODE>), dim3((unsigned)xcd_grid(B, a.k)),
                      dim3(64 * EDGE_WAVES), 0, s, a, c->arm32);
   if (ti >= 0) (void)hipEventRecord(c->tev[2 * ti + 1], s);
   hipLaunchKernelGGL(edge_recheck_kernel<PAT>, dim3(recheck_waves(E)), dim3(64), 0, s, a,
