@@ -104,7 +104,7 @@ batch_edge_kernel(ProbTable pt, const float* __restrict__ grid, int n_t,
                   const ArmConst<float>* __restrict__ Ap) {
   __shared__ float s_end_all[EDGE_WAVES][FN_MAX_NT];
   __shared__ float s_T[FN_MAX_NT];
-  __shared__ float s_fix[EDGE_WAVES];
+  __shared__ float s_fix[EDGE_WAVES][4];
   __shared__ float s_mod[EDGE_WAVES][2 * MODEL_FLOATS];
   __shared__ GeoLDS<float> s_geo[EDGE_WAVES];
   for (int t = threadIdx.x; t < n_t; t += blockDim.x) s_T[t] = grid[t];
@@ -117,7 +117,7 @@ batch_edge_kernel(ProbTable pt, const float* __restrict__ grid, int n_t,
   if (eg >= pt.edge_off[pt.n]) return;
   const int p = problem_of(pt, eg);
   search_edge<PAT, MODE, true>(pt.args[p], eg - pt.edge_off[p], eg, *Ap, s_end_all[wave], s_T,
-                               &s_fix[wave], s_mod[wave], &s_geo[wave]);
+                               s_fix[wave], s_mod[wave], &s_geo[wave]);
 }
 
 // Endpoint models of every problem's states: 8 lanes per state, first the
@@ -389,7 +389,7 @@ static void launch_batch_search(fn_ctx* c, fn_batch* bt, hipStream_t s) {
   hipLaunchKernelGGL((batch_edge_kernel<PAT, MODE>), dim3((unsigned)xcd_grid(bt->queries, bt->k)),
                      dim3(64 * EDGE_WAVES), 0, s, pt, bt->grid, bt->n_t, c->arm32);
   const unsigned rw = (unsigned)(bt->edges < 4096 ? bt->edges : 4096);
-  hipLaunchKernelGGL(edge_recheck_kernel<PAT>, dim3(rw), dim3(64), 0, s, bt->a0, pt, c->arm32, c->arm64);
+  hipLaunchKernelGGL(edge_recheck_kernel<PAT>, dim3(rw), dim3(64), 0, s, bt->a0, pt, c->arm64);
 }
 
 extern "C" int fn_batch_launch(fn_ctx* c, void* stream) {

@@ -15,15 +15,29 @@ struct Digits {
   int v[NJ];
 };
 
-// An edge whose decision hit a ratio within BAND of 1: the FP64 stage
-// resumes it at slot j (phase 0) or redoes its post-checks (phase 1).
+// An edge whose decision rests on a ratio within BAND of 1, handed to the
+// FP64 stage.  Phase 0: slot j is the first slot whose FP32 ratio is within
+// the band; the FP32 search went on to j2, the first slot above j that is
+// feasible in FP32 or again within the band (PH_J2_NEAR), or -1 when there is
+// none.  Phase 1 (PH_POST): j is the result and a post-check ratio at j is
+// within the band.  FP32 post-check ratios (rho_v, rho_q, rho_c) come along
+// for j (post[0..2]) and j2 (post[3..5]).
 struct QEntry {
   int32_t edge;
   int16_t j;
   int16_t phase;
-  float margin;
-  int32_t work;
+  int16_t j2;
+  int16_t pad;
+  int32_t work;      // evaluated sample lanes of the FP32 search
+  float margin;      // smallest |rho - 1| of the slots below j
+  float margin2;     // the same over the slots in (j, j2], FP32
+  float rho;         // FP32 ratio of slot j
+  float rho2;        // FP32 ratio of slot j2 (of the last slot when j2 = -1)
+  float post[6];
+  uint32_t pad2[2];
+  uint64_t todo[4];  // slots not certified infeasible (bit t: slot t)
 };
+static_assert(sizeof(QEntry) == 96, "queue entry layout");
 
 int fail(int code, const char* fmt, ...);
 int hip_fail(hipError_t e, const char* where);

@@ -73,6 +73,7 @@ __device__ __forceinline__ int nodes_of(const EdgeArgs& a) {
 // queue phase bits
 constexpr int PH_POST = 1;        // only the post-checks are left
 constexpr int PH_BELOW_FULL = 2;  // window mode: a slot below the window was evaluated in full
+constexpr int PH_J2_NEAR = 4;     // slot j2 is within the band too
 
 template <typename R>
 __device__ __forceinline__ bool load_edge(const EdgeArgs& a, int64_t e, EdgeState<R>& S,
@@ -228,16 +229,57 @@ __device__ __forceinline__ void write_out(const EdgeArgs& a, int64_t e, int j, i
   }
 }
 
-__device__ __forceinline__ void push_queue(const EdgeArgs& a, int64_t e, int j, int phase,
-                                           float m, int work) {
+// Slots still to be evaluated in full: bit j of word j / 64.
+struct SlotMask {
+  uint64_t w0, w1, w2, w3;
+  __device__ __forceinline__ uint64_t get(int i) const {
+    return i == 0 ? w0 : i == 1 ? w1 : i == 2 ? w2 : w3;
+  }
+  __device__ __forceinline__ void clear(int i, uint64_t m) {
+    if (i == 0) w0 &= ~m;
+    else if (i == 1) w1 &= ~m;
+    else if (i == 2) w2 &= ~m;
+    else w3 &= ~m;
+  }
+  // lowest set slot in [j, hi], or -1
+  __device__ __forceinline__ int next(int j, int hi) const {
+    while (j <= hi) {
+      const int w = j >> 6;
+      const uint64_t bits = get(w) & (~0ull << (j & 63));
+      if (bits) {
+        const int t = (w << 6) + __ffsll((long long)bits) - 1;
+        return t <= hi ? t : -1;
+      }
+      j = (w + 1) << 6;
+    }
+    return -1;
+  }
+};
+
+// Hands edge e over to the FP64 stage (see QEntry).
+__device__ __forceinline__ void push_queue(const EdgeArgs& a, int64_t e, int j, int phase, int j2,
+                                           float m, float m2, int work, float rho, float rho2,
+                                           const float* post, const SlotMask& todo) {
   if (lane_id() == 0) {
     const int slot = atomicAdd(a.q_count, 1);
     QEntry q;
     q.edge = (int32_t)e;
     q.j = (int16_t)j;
     q.phase = (int16_t)phase;
-    q.margin = m;
+    q.j2 = (int16_t)j2;
+    q.pad = 0;
     q.work = work;
+    q.margin = m;
+    q.margin2 = m2;
+    q.rho = rho;
+    q.rho2 = rho2;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) q.post[i] = post[i];
+    q.pad2[0] = q.pad2[1] = 0;
+    q.todo[0] = todo.w0;
+    q.todo[1] = todo.w1;
+    q.todo[2] = todo.w2;
+    q.todo[3] = todo.w3;
     a.queue[slot] = q;
   }
 }
@@ -301,33 +343,6 @@ __host__ __forceinline__ int64_t xcd_grid(int64_t B, int k) {
   return (B + N_XCD - 1) / N_XCD * N_XCD * k;
 }
 
-// Slots still to be evaluated in full: bit j of word j / 64.
-struct SlotMask {
-  uint64_t w0, w1, w2, w3;
-  __device__ __forceinline__ uint64_t get(int i) const {
-    return i == 0 ? w0 : i == 1 ? w1 : i == 2 ? w2 : w3;
-  }
-  __device__ __forceinline__ void clear(int i, uint64_t m) {
-    if (i == 0) w0 &= ~m;
-    else if (i == 1) w1 &= ~m;
-    else if (i == 2) w2 &= ~m;
-    else w3 &= ~m;
-  }
-  // lowest set slot in [j, hi], or -1
-  __device__ __forceinline__ int next(int j, int hi) const {
-    while (j <= hi) {
-      const int w = j >> 6;
-      const uint64_t bits = get(w) & (~0ull << (j & 63));
-      if (bits) {
-        const int t = (w << 6) + __ffsll((long long)bits) - 1;
-        return t <= hi ? t : -1;
-      }
-      j = (w + 1) << 6;
-    }
-    return -1;
-  }
-};
-
 // Fixed duration of a goal edge (Algorithm 1 goal branch): t_req of the
 // candidate minus the parent's time-to-come.  Returns false for a free edge.
 __device__ __forceinline__ bool fixed_T(const EdgeArgs& a, int64_t e, float& T) {
@@ -377,7 +392,7 @@ __device__ __forceinline__ void model_state(const EdgeArgs& a, int64_t st, int r
 
 // The search of one edge by one wavefront (see the stage list above).
 // eq: the edge's id in the FP64-stage queue; s_end: this wavefront's
-// FN_MAX_NT floats of LDS; s_T: the grid in LDS; s_fix: one float of LDS;
+// FN_MAX_NT floats of LDS; s_T: the grid in LDS; s_fix: four floats of LDS;
 // s_mod: 2 * MODEL_FLOATS floats of LDS; geo: the clearance tables (LDS).
 // MODE is the search mode (a
 // compile-time constant, so each mode is its own kernel); GOALS: edges of
@@ -445,7 +460,11 @@ __device__ void search_edge(const EdgeArgs& a, int64_t e, int64_t eq, const ArmC
   int jstar = -1;
   float rho_star = 0.f;
   bool below_full = false;
-  bool queued = false;
+  // the first slot whose FP32 ratio is within the band is decided in FP64 by
+  // the next stage, and the search goes on above it in case it is
+  // infeasible; that slot, its ratio and the margin below it wait in LDS
+  // (s_fix[1..3]; rarely used, so they hold no registers in the loop)
+  if (lane == 0) s_fix[1] = __int_as_float(-1);
 
   int stage = 0, type, sa, sb;
   bool below;
@@ -511,14 +530,26 @@ __device__ void search_edge(const EdgeArgs& a, int64_t e, int64_t eq, const ArmC
       const float rho = __shfl(r, q * Sw);
       const int jq = __shfl(my, q * Sw);
       if (near_one(rho)) {
-        // decided in FP64: hand the edge over at slot jq
+        __builtin_amdgcn_wave_barrier();
+        if (__builtin_amdgcn_readfirstlane(__float_as_int(s_fix[1])) >= 0) {
+          // a second slot within the band ends the FP32 search
+          jstar = jq;
+          rho_star = rho;
+          done = true;
+          break;
+        }
         float m = INFINITY;
         for (int t = lane; t < jq; t += WAVE)
           if (s_end[t] > 1.f + BAND) m = fminf(m, s_end[t] - 1.f);
         m = fminf(marg, wave_min(m));
-        push_queue(a, eq, jq, below_full ? PH_BELOW_FULL : 0, m, work);
-        queued = done = true;
-        break;
+        if (lane == 0) {
+          s_fix[1] = __int_as_float(jq);
+          s_fix[2] = rho;
+          s_fix[3] = m;
+        }
+        __builtin_amdgcn_wave_barrier();
+        marg = INFINITY;  // from here: the slots above it
+        continue;
       }
       marg = fminf(marg, fabsf(rho - 1.f));
       last = rho;
@@ -532,12 +563,13 @@ __device__ void search_edge(const EdgeArgs& a, int64_t e, int64_t eq, const ArmC
     if (done) break;
   }
   if (a.out_scr && lane == 0) a.out_scr[e] = (int16_t)scr;
-  if (queued) return;
   __builtin_amdgcn_wave_barrier();
+  const int jn = __builtin_amdgcn_readfirstlane(__float_as_int(s_fix[1]));
   // certified-infeasible margin of the screened slots below the result
+  // (above jn when a slot within the band was met)
   const int lim = jstar >= 0 ? jstar : jmax + 1;
   float mc = INFINITY;
-  for (int t = lane; t < lim; t += WAVE)
+  for (int t = jn + 1 + lane; t < lim; t += WAVE)
     if (s_end[t] > 1.f + BAND) mc = fminf(mc, s_end[t] - 1.f);
   float m = fminf(marg, wave_min(mc));
   int winbits = 0;
@@ -547,33 +579,68 @@ __device__ void search_edge(const EdgeArgs& a, int64_t e, int64_t eq, const ArmC
     const bool hit = (jstar >= 0 && jstar >= wlo && jstar <= whi) || (jstar < 0 && wlo > jmax);
     winbits = (hit ? FN_S_WIN_HIT : FN_S_WIN_MISS) | (below_full ? FN_S_WIN_BELOW : 0);
   }
-  if (jstar < 0) {
-    // ratio of the last slot: its full value, else its screened endpoint value
-    const float lastv = s_end[jmax] > 1.f + BAND ? s_end[jmax] : last;
+  // ratio of the last slot: its full value, else its screened endpoint value
+  const float lastv = jstar < 0 && s_end[jmax] > 1.f + BAND ? s_end[jmax] : last;
+  if (jstar < 0 && jn < 0) {
     write_out(a, e, -1, FN_S_NONE | winbits, m, lastv, 0, 0, 0, work);
     return;
   }
-  float rv, rq, rc;
-  const float T = Tg[jstar];
-  post_checks<float, PAT>(A, ES, T, S, a.obs, a.n_obs, a.margin_c, geo, rv, rq, rc);
+  // FP32 post-checks at jn (the result if FP64 finds it feasible) and at
+  // jstar (one call site)
+  float pst[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+  for (int pass = jn >= 0 ? 0 : 1; pass < 2; ++pass) {
+    const int js = pass == 0 ? jn : jstar;
+    if (js < 0) break;
+    float rv, rq, rc;
+    post_checks<float, PAT>(A, ES, Tg[js], S, a.obs, a.n_obs, a.margin_c, geo, rv, rq, rc);
+    if (pass == 0) {
+      pst[0] = rv; pst[1] = rq; pst[2] = rc;
+    } else {
+      pst[3] = rv; pst[4] = rq; pst[5] = rc;
+    }
+  }
+  const int ph_b = below_full ? PH_BELOW_FULL : 0;
+  if (jn >= 0) {
+    const bool j2near = jstar >= 0 && near_one(rho_star);
+    push_queue(a, eq, jn, ph_b | (j2near ? PH_J2_NEAR : 0), jstar, s_fix[3], m, work, s_fix[2],
+               jstar >= 0 ? rho_star : lastv, pst, todo);
+    return;
+  }
+  const float rv = pst[3], rq = pst[4], rc = pst[5];
   if (near_one(rv) || near_one(rq) || (a.n_obs > 0 && near_one(rc))) {
-    push_queue(a, eq, jstar, PH_POST | (below_full ? PH_BELOW_FULL : 0), m, work);
+    const float pp[6] = {rv, rq, rc, 0.f, 0.f, 0.f};
+    push_queue(a, eq, jstar, PH_POST | ph_b, -1, m, INFINITY, work, rho_star, 0.f, pp, todo);
     return;
   }
   m = fminf(m, fminf(fabsf(rv - 1.f), fminf(fabsf(rq - 1.f), fabsf(rc - 1.f))));
-  write_out(a, e, jstar, post_status(rv, rq, rc) | winbits, m, rho_star, rv, rq, rc, work, T);
+  write_out(a, e, jstar, post_status(rv, rq, rc) | winbits, m, rho_star, rv, rq, rc, work,
+            Tg[jstar]);
 }
 
-// FP64 stage of one queued edge (one wavefront).
+// Slot ratio of Eq. (7) in FP64 at the S samples (lanes < S), in every lane.
+template <int PAT>
+__device__ __forceinline__ double rho64(const ArmConst<double>& D, const EdgeState<double>& ED,
+                                        float Tf, int S) {
+  const int lane = lane_id();
+  const double T = (double)Tf;
+  double r = 0.0;
+  if (lane < S) r = eval_rho<double, PAT>(D, ED, T, 1.0 / T, double(lane) / double(S - 1));
+  return wave_max(r);
+}
+
+// FP64 stage of one queued edge (one wavefront; FP64 arithmetic only, see
+// QEntry).  Phase 0: slot j is decided in FP64; if it is infeasible the
+// result is j2 (decided in FP64 too when it is within the band), and in the
+// rare case that j2 fails as well the search goes on over the uncertified
+// slots above it in FP64.  Post-check ratios within the band of 1 are
+// recomputed in FP64 (all of them after the FP64 walk).
 template <int PAT>
 __device__ void recheck_edge(const EdgeArgs& a, int64_t e, const QEntry& q,
-                             const ArmConst<float>& A, const ArmConst<double>& D, float* s_fix,
-                             GeoLDS<float>* geo32, GeoLDS<double>* geo) {
+                             const ArmConst<double>& D, float* s_fix, GeoLDS<double>* geo) {
   const int lane = lane_id();
-  EdgeState<float> ES;
   EdgeState<double> ED;
   int st0;
-  load_edge(a, e, ES, st0);
   load_edge(a, e, ED, st0);
   float Tfix;
   const bool fixed = fixed_T(a, e, Tfix);
@@ -584,39 +651,60 @@ __device__ void recheck_edge(const EdgeArgs& a, int64_t e, const QEntry& q,
   if (a.j_max && !fixed) jmax = min(jmax, (int)a.j_max[e]);
   const int S = a.S;
   int work = q.work;
-  float marg = q.margin;
+  float m = q.margin;
   int jstar = -1;
-  double rho_star = 0;
-  float last = 0;
+  float rho_star = 0.f, last = 0.f;
+  // post-check ratios at the result: the search's FP32 values, or FP64
+  // values after the FP64 walk (exact)
+  double rv = 0.0, rq = 0.0, rc = 0.0;
+  bool exact = false;
+  int pick = -1;  // which FP32 post-check triple applies: 0 (slot j), 3 (slot j2)
   if (q.phase & PH_POST) {
     jstar = q.j;
-    // the slot ratio itself is reported from FP32 (it was outside the band)
-    const float Tf = Tg[jstar];
-    float r = 0.f;
-    if (lane < S)
-      r = eval_rho<float, PAT>(A, ES, Tf, __builtin_amdgcn_rcpf(Tf), float(lane) / float(S - 1));
-    rho_star = wave_max(r);
+    rho_star = q.rho;  // outside the band: the FP32 value stands
+    pick = 0;
   } else {
-    for (int j = q.j; j <= jmax; ++j) {
-      const float Tf = Tg[j];
-      float r = 0.f;
-      if (lane < S)
-        r = eval_rho<float, PAT>(A, ES, Tf, __builtin_amdgcn_rcpf(Tf), float(lane) / float(S - 1));
-      float rho = wave_max(r);
-      work += S;
-      double rho_d = rho;
-      if (near_one(rho)) {
-        const double T = (double)Tf;
-        double rd = 0.0;
-        if (lane < S) rd = eval_rho<double, PAT>(D, ED, T, 1.0 / T, double(lane) / double(S - 1));
-        rho_d = wave_max(rd);
-      }
-      marg = fminf(marg, (float)fabs(rho_d - 1.0));
-      last = (float)rho_d;
-      if (rho_d <= 1.0) {
-        jstar = j;
-        rho_star = rho_d;
-        break;
+    const double r0 = rho64<PAT>(D, ED, Tg[q.j], S);
+    m = fminf(m, (float)fabs(r0 - 1.0));
+    if (r0 <= 1.0) {
+      jstar = q.j;
+      rho_star = (float)r0;
+      pick = 0;
+    } else {
+      m = fminf(m, q.margin2);
+      if (q.j2 < 0) {
+        last = q.j == jmax ? (float)r0 : q.rho2;
+      } else if (!(q.phase & PH_J2_NEAR)) {
+        jstar = q.j2;
+        rho_star = q.rho2;
+        pick = 3;
+      } else {
+        const double r2 = rho64<PAT>(D, ED, Tg[q.j2], S);
+        m = fminf(m, (float)fabs(r2 - 1.0));
+        last = (float)r2;
+        if (r2 <= 1.0) {
+          jstar = q.j2;
+          rho_star = (float)r2;
+          pick = 3;
+        } else {
+          const SlotMask todo{q.todo[0], q.todo[1], q.todo[2], q.todo[3]};
+          int lastj = q.j2;
+          for (int t = todo.next(q.j2 + 1, jmax); t >= 0; t = todo.next(t + 1, jmax)) {
+            const double rd = rho64<PAT>(D, ED, Tg[t], S);
+            work += S;
+            m = fminf(m, (float)fabs(rd - 1.0));
+            last = (float)rd;
+            lastj = t;
+            if (rd <= 1.0) {
+              jstar = t;
+              rho_star = (float)rd;
+              exact = true;
+              break;
+            }
+          }
+          // the last slot was certified: report its ratio
+          if (jstar < 0 && lastj != jmax) last = (float)rho64<PAT>(D, ED, Tg[jmax], S);
+        }
       }
     }
   }
@@ -629,23 +717,27 @@ __device__ void recheck_edge(const EdgeArgs& a, int64_t e, const QEntry& q,
     winbits = (hit ? FN_S_WIN_HIT : FN_S_WIN_MISS) | (below ? FN_S_WIN_BELOW : 0);
   }
   if (jstar < 0) {
-    write_out(a, e, -1, FN_S_NONE | FN_S_RECHECK64 | winbits, marg, last, 0, 0, 0, work);
+    write_out(a, e, -1, FN_S_NONE | FN_S_RECHECK64 | winbits, m, last, 0, 0, 0, work);
     return;
   }
-  // post-checks in FP32; a ratio within the band of 1 is recomputed in FP64
-  float fv, fq, fc;
-  post_checks<float, PAT>(A, ES, Tg[jstar], S, a.obs, a.n_obs, a.margin_c, geo32, fv, fq, fc);
-  double rv = fv, rq = fq, rc = fc;
-  if (near_one(fv) || near_one(fq)) {
-    double dv, dq;
-    joint_checks<double>(D, ED, (double)Tg[jstar], dv, dq);
-    if (near_one(fv)) rv = dv;
-    if (near_one(fq)) rq = dq;
+  if (pick >= 0) {
+    rv = q.post[pick];
+    rq = q.post[pick + 1];
+    rc = q.post[pick + 2];
   }
-  if (a.n_obs > 0 && near_one(fc))
-    clearance<double, PAT>(D, ED, (double)Tg[jstar], S, a.obs, a.n_obs, a.margin_c, geo, rc);
-  const float m = fminf(marg, (float)fmin(fabs(rv - 1.0), fmin(fabs(rq - 1.0), fabs(rc - 1.0))));
-  write_out(a, e, jstar, post_status(rv, rq, rc) | FN_S_RECHECK64 | winbits, m, (float)rho_star,
+  // post-check ratios within the band of 1 (all, after the FP64 walk) in FP64
+  const bool nv = exact || near_one((float)rv), nq = exact || near_one((float)rq);
+  const bool nc = a.n_obs > 0 && (exact || near_one((float)rc));
+  const double T = (double)Tg[jstar];
+  if (nv || nq) {
+    double dv, dq;
+    joint_checks<double>(D, ED, T, dv, dq);
+    if (nv) rv = dv;
+    if (nq) rq = dq;
+  }
+  if (nc) clearance<double, PAT>(D, ED, T, S, a.obs, a.n_obs, a.margin_c, geo, rc);
+  m = fminf(m, (float)fmin(fabs(rv - 1.0), fmin(fabs(rq - 1.0), fabs(rc - 1.0))));
+  write_out(a, e, jstar, post_status(rv, rq, rc) | FN_S_RECHECK64 | winbits, m, rho_star,
             (float)rv, (float)rq, (float)rc, work, Tg[jstar]);
 }
 
@@ -671,10 +763,8 @@ __device__ __forceinline__ int problem_of(const ProbTable& pt, int64_t eg) {
 // FP64 stage over the queue; pt.n == 0: one problem (a).
 template <int PAT>
 __global__ __launch_bounds__(64) void edge_recheck_kernel(EdgeArgs a, ProbTable pt,
-                                                          const ArmConst<float>* __restrict__ Ap,
                                                           const ArmConst<double>* __restrict__ Dp) {
   __shared__ float s_fix[1];
-  __shared__ GeoLDS<float> s_geo32;
   __shared__ GeoLDS<double> s_geo;
   const int n = *a.q_count;
   for (int qi = blockIdx.x; qi < n; qi += gridDim.x) {
@@ -686,7 +776,7 @@ __global__ __launch_bounds__(64) void edge_recheck_kernel(EdgeArgs a, ProbTable 
       ap = pt.args + p;
       e -= pt.edge_off[p];
     }
-    recheck_edge<PAT>(*ap, e, q, *Ap, *Dp, s_fix, &s_geo32, &s_geo);
+    recheck_edge<PAT>(*ap, e, q, *Dp, s_fix, &s_geo);
   }
 }
 

@@ -35,7 +35,7 @@ __global__ __launch_bounds__(64 * EDGE_WAVES) __attribute__((amdgpu_waves_per_eu
 edge_time_kernel(EdgeArgs a, const ArmConst<float>* __restrict__ Ap) {
   __shared__ float s_end_all[EDGE_WAVES][FN_MAX_NT];
   __shared__ float s_T[FN_MAX_NT];
-  __shared__ float s_fix[EDGE_WAVES];
+  __shared__ float s_fix[EDGE_WAVES][4];
   __shared__ float s_mod[EDGE_WAVES][2 * MODEL_FLOATS];
   __shared__ GeoLDS<float> s_geo[EDGE_WAVES];
   for (int t = threadIdx.x; t < a.n_t; t += blockDim.x) s_T[t] = a.grid[t];
@@ -43,7 +43,7 @@ edge_time_kernel(EdgeArgs a, const ArmConst<float>* __restrict__ Ap) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t e = xcd_edge(blockIdx.x, a.k, a.E / a.k);
   if (e < 0) return;
-  search_edge<PAT, MODE, false>(a, e, e, *Ap, s_end_all[wave], s_T, &s_fix[wave], s_mod[wave],
+  search_edge<PAT, MODE, false>(a, e, e, *Ap, s_end_all[wave], s_T, s_fix[wave], s_mod[wave],
                                 &s_geo[wave]);
 }
 
@@ -136,7 +136,7 @@ static void launch_search(fn_ctx* c, const EdgeArgs& a, int ti, hipStream_t s) {
                      dim3(64 * EDGE_WAVES), 0, s, a, c->arm32);
   if (ti >= 0) (void)hipEventRecord(c->tev[2 * ti + 1], s);
   hipLaunchKernelGGL(edge_recheck_kernel<PAT>, dim3(recheck_waves(E)), dim3(64), 0, s, a,
-                     ProbTable{0, nullptr, nullptr}, c->arm32, c->arm64);
+                     ProbTable{0, nullptr, nullptr}, c->arm64);
 }
 
 template <int PAT>
