@@ -130,28 +130,33 @@ def main():
     for name in wanted:
         mode = modes[name]
 
-        def step():
+        def step(ev=None):
+            # ev: events after the kNN, before the search and at the end (the
+            # breakdown pass only; the timed steps carry no events of their own)
             ctx.plan_knn(tree, ld, n, cand, sh.k, out_idx=idx, want_d2=False)
-            ev[0].record(stream)
+            if ev:
+                ev[0].record(stream)
             if mode == fn.SEARCH_WINDOW:
                 fn.edge_features(ctx, tree, ld, n, cand, idx, out=feats)
                 net.infer(feats, grid, half=args.half, want_out=False, win_lo=win)
-                ev[2].record(stream)
+                if ev:
+                    ev[2].record(stream)
                 ctx.edge_time_batch(tree, ld, n, cand, idx, grid, sh.samples, obs, mode=mode,
                                     win_lo=win, win_half=args.half, out=out)
             else:
-                ev[2].record(stream)
+                if ev:
+                    ev[2].record(stream)
                 ctx.edge_time_batch(tree, ld, n, cand, idx, grid, sh.samples, obs, mode=mode,
                                     out=out)
-            ev[1].record(stream)
+            if ev:
+                ev[1].record(stream)
 
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
         for _ in range(args.warmup):
             step()
         torch.cuda.synchronize()
+        # timed steps; the library's own event pair brackets the search kernel
         ctx.kernel_timing(True)
         ctx.kernel_times()
-        edge_ms = []
         t0 = torch.cuda.Event(enable_timing=True)
         t1 = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
@@ -159,14 +164,19 @@ def main():
         t0.record(stream)
         for _ in range(args.steps):
             step()
-            edge_ms.append(ev)
-            ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
         t1.record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - w0
         k_ms = ctx.kernel_times()
         ctx.kernel_timing(False)
         ms = t0.elapsed_time(t1) / args.steps
+        # breakdown (untimed): a few more steps with events inside
+        edge_ms = []
+        for _ in range(min(args.steps, 5)):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            step(ev)
+            edge_ms.append(ev)
+        torch.cuda.synchronize()
         e_ms = float(np.mean([a[2].elapsed_time(a[1]) for a in edge_ms]))
         kern_ms = float(np.mean(k_ms))
         work = int(out["work"].sum().item())

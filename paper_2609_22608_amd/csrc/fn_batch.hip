@@ -93,20 +93,25 @@ __global__ __launch_bounds__(64) void batch_knn_merge(const KnnProb* __restrict_
   if (qg >= query_off[n]) return;
   const int p = bsearch_off(query_off, n, qg);
   const KnnProb& q = P[p];
-  knn_merge_query<K1>(q.tree, q.ld, *q.n_nodes, q.qs, (int)(qg - query_off[p]), k, q.n_split,
-                      part_d + q.part_off, part_i + q.part_off, part_y + q.y_off, q.nbr, nullptr);
+  if (q.n_split * K1 <= WAVE)
+    knn_merge_small<K1>(q.tree, q.ld, *q.n_nodes, q.qs, (int)(qg - query_off[p]), k, q.n_split,
+                        part_d + q.part_off, part_i + q.part_off, part_y + q.y_off, q.nbr, nullptr);
+  else
+    knn_merge_query<K1>(q.tree, q.ld, *q.n_nodes, q.qs, (int)(qg - query_off[p]), k, q.n_split,
+                        part_d + q.part_off, part_i + q.part_off, part_y + q.y_off, q.nbr, nullptr);
 }
 
 // EDGE_WAVES edges per workgroup (see edge_time_kernel).
 template <int PAT, int MODE>
 __global__ __launch_bounds__(64 * EDGE_WAVES) __attribute__((amdgpu_waves_per_eu(4))) void
 batch_edge_kernel(ProbTable pt, const float* __restrict__ grid, int n_t,
-                  const ArmConst<float>* __restrict__ Ap) {
+                  const ArmConst<float>* __restrict__ Ap, int max_obs) {
   __shared__ float s_end_all[EDGE_WAVES][FN_MAX_NT];
   __shared__ float s_T[FN_MAX_NT];
   __shared__ float s_fix[EDGE_WAVES][4];
   __shared__ float s_mod[EDGE_WAVES][2 * MODEL_FLOATS];
   __shared__ GeoLDS<float> s_geo[EDGE_WAVES];
+  extern __shared__ float s_tab[];  // EDGE_WAVES * nsph * max_obs floats
   for (int t = threadIdx.x; t < n_t; t += blockDim.x) s_T[t] = grid[t];
   __syncthreads();
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -117,7 +122,8 @@ batch_edge_kernel(ProbTable pt, const float* __restrict__ grid, int n_t,
   if (eg >= pt.edge_off[pt.n]) return;
   const int p = problem_of(pt, eg);
   search_edge<PAT, MODE, true>(pt.args[p], eg - pt.edge_off[p], eg, *Ap, s_end_all[wave], s_T,
-                               s_fix[wave], s_mod[wave], &s_geo[wave]);
+                               s_fix[wave], s_mod[wave], &s_geo[wave],
+                               s_tab + wave * Ap->nsph * max_obs);
 }
 
 // Endpoint models of every problem's states: 8 lanes per state, first the
@@ -245,6 +251,7 @@ struct fn_batch {
   const float* grid = nullptr;
   fn_risk risk{};
   int64_t pairs = 0, queries = 0, edges = 0;
+  int max_obs = 0;  // most obstacles of a problem (clearance table LDS)
   // device tables
   KnnProb* knn = nullptr;
   InsProb* ins = nullptr;
@@ -301,6 +308,7 @@ extern "C" int fn_batch_prepare(fn_ctx* c, const fn_problem_set* ps) {
   std::vector<EdgeArgs> ea(n);
   std::vector<int64_t> po(n + 1), qo(n + 1), eo(n + 1);
   int64_t part = 0, ys = 0, sumB = 0;
+  int max_obs = 0;
   po[0] = qo[0] = eo[0] = 0;
   int Sw = 1;
   while (Sw < ps->samples) Sw <<= 1;
@@ -337,6 +345,7 @@ extern "C" int fn_batch_prepare(fn_ctx* c, const fn_problem_set* ps) {
     a.grid = ps->grid; a.n_t = ps->n_t; a.S = ps->samples; a.Sw = Sw; a.mode = ps->mode;
     a.win_half = 0; a.j_max = nullptr; a.win_lo = nullptr;
     a.obs = q.obs; a.n_obs = q.n_obs; a.margin_c = ps->margin;
+    max_obs = max_obs > q.n_obs ? max_obs : q.n_obs;
     a.out_j = q.out_j; a.out_st = q.out_status; a.out_m = q.out_margin; a.out_rho = q.out_rho4;
     a.out_work = nullptr; a.out_scr = nullptr; a.q_count = c->q_count; a.queue = c->queue;
     a.model_e = c->model_e + eo[p] * MODEL_FLOATS;
@@ -367,6 +376,7 @@ extern "C" int fn_batch_prepare(fn_ctx* c, const fn_problem_set* ps) {
   bt->pairs = po[n];
   bt->queries = qo[n];
   bt->edges = eo[n];
+  bt->max_obs = max_obs;
   bt->a0 = ea[0];
   return FN_OK;
 }
@@ -386,8 +396,9 @@ static void launch_batch_search(fn_ctx* c, fn_batch* bt, hipStream_t s) {
   if (MODE != FN_SEARCH_PLAIN)
     hipLaunchKernelGGL(batch_model_kernel<PAT>, dim3((unsigned)(((bt->edges + bt->queries) * 8 + 255) / 256)),
                        dim3(256), 0, s, pt, bt->query_off, c->arm32);
+  const size_t tab = (size_t)EDGE_WAVES * c->desc.n_spheres * bt->max_obs * sizeof(float);
   hipLaunchKernelGGL((batch_edge_kernel<PAT, MODE>), dim3((unsigned)xcd_grid(bt->queries, bt->k)),
-                     dim3(64 * EDGE_WAVES), 0, s, pt, bt->grid, bt->n_t, c->arm32);
+                     dim3(64 * EDGE_WAVES), tab, s, pt, bt->grid, bt->n_t, c->arm32, bt->max_obs);
   const unsigned rw = (unsigned)(bt->edges < 4096 ? bt->edges : 4096);
   hipLaunchKernelGGL(edge_recheck_kernel<PAT>, dim3(rw), dim3(64), 0, s, bt->a0, pt, c->arm64);
 }

@@ -146,10 +146,16 @@ __device__ void joint_checks(const ArmConst<R>& A, const EdgeState<R>& E, R T, R
 // (sphere, obstacle) loop reads broadcast LDS instead of waiting on a
 // memory load per pair.  Lane = (sample, sphere part): the parts split each
 // link's spheres so that all 64 lanes work when S < 64.
+// FP32: tab (LDS, nsph * n_obs floats) receives 1 / (r_a + margin + r_o)^2
+// of every pair, and the loop keeps the smallest d^2 / (r_a + margin + r_o)^2
+// (a product and a minimum per pair instead of a reciprocal); rho_c is its
+// inverse square root.  FP64 (tab unused): the ratio of every pair by IEEE
+// division.
 template <typename R, int PAT>
 __device__ void clearance(const ArmConst<R>& A, const EdgeState<R>& E, R T, int S,
                           const float* __restrict__ obs, int n_obs, float margin_c,
-                          GeoLDS<R>* geo, R& rc) {
+                          GeoLDS<R>* geo, float* tab, R& rc) {
+  constexpr bool F32 = sizeof(R) == 4;
   const int lane = lane_id();
   for (int t = lane; t < A.nsph; t += WAVE) {
     geo->sph[4 * t] = A.sphx[t];
@@ -158,8 +164,16 @@ __device__ void clearance(const ArmConst<R>& A, const EdgeState<R>& E, R T, int 
     geo->sph[4 * t + 3] = A.sphr[t] + R(margin_c);
   }
   for (int t = lane; t < 4 * n_obs; t += WAVE) geo->obs[t] = R(obs[t]);
+  if constexpr (F32) {
+    for (int t = lane; t < A.nsph * n_obs; t += WAVE) {
+      const int k = t / n_obs, o = t - k * n_obs;
+      const float need = (A.sphr[k] + margin_c) + obs[4 * o + 3];
+      tab[t] = 1.f / (need * need);
+    }
+  }
   __builtin_amdgcn_wave_barrier();
-  R best = 0;
+  // FP32: smallest d^2 / need^2; FP64: largest need^2 / d^2
+  R best = F32 ? R(INFINITY) : R(0);
   int Sw = 1;
   while (Sw < S) Sw <<= 1;
   const int nparts = Sw >= WAVE ? 1 : WAVE / Sw;
@@ -172,31 +186,46 @@ __device__ void clearance(const ArmConst<R>& A, const EdgeState<R>& E, R T, int 
     for (int i = 0; i < NJ; ++i) sincos_r(sg[i], sn[i], cs[i]);
     const R* so = geo->obs;
     sphere_centres<R, PAT>(A, sn, cs, part, nparts, geo->sph, [&](int k, R x, R y, R z) {
-      const R ra = geo->sph[4 * k + 3];
+      if constexpr (F32) {
+        const float* tk = tab + k * n_obs;
 #pragma unroll 4
-      for (int o = 0; o < n_obs; ++o) {
-        const R dx = x - so[4 * o], dy = y - so[4 * o + 1], dz = z - so[4 * o + 2];
-        const R need = ra + so[4 * o + 3];
-        const R d2 = dx * dx + dy * dy + dz * dz;
-        // d2 = 0 gives +inf (reciprocal of zero; IEEE division in FP64)
-        best = rmax(best, fdiv(need * need, d2));
+        for (int o = 0; o < n_obs; ++o) {
+          const float dx = x - so[4 * o], dy = y - so[4 * o + 1], dz = z - so[4 * o + 2];
+          const float d2 = dx * dx + dy * dy + dz * dz;
+          best = fminf(best, d2 * tk[o]);
+        }
+      } else {
+        const R ra = geo->sph[4 * k + 3];
+#pragma unroll 4
+        for (int o = 0; o < n_obs; ++o) {
+          const R dx = x - so[4 * o], dy = y - so[4 * o + 1], dz = z - so[4 * o + 2];
+          const R need = ra + so[4 * o + 3];
+          const R d2 = dx * dx + dy * dy + dz * dz;
+          // d2 = 0 gives +inf (IEEE division)
+          best = rmax(best, need * need / d2);
+        }
       }
     });
   }
-  if constexpr (sizeof(R) == 4) rc = sqrtf(wave_max(float(best)));
-  else rc = sqrt(wave_max(double(best)));
+  if constexpr (F32) {
+    // d2 = 0 gives rho_c = +inf; no pair (no spheres) gives 0
+    const float mn = wave_min(float(best));
+    rc = mn < INFINITY ? 1.f / sqrtf(mn) : 0.f;
+  } else {
+    rc = sqrt(wave_max(double(best)));
+  }
   __builtin_amdgcn_wave_barrier();
 }
 
 // Post-checks at duration T: (rho_v, rho_q, rho_c) in every lane (rho_c = 0
-// without obstacles).
+// without obstacles).  tab: LDS for the FP32 clearance (nsph * n_obs floats).
 template <typename R, int PAT>
 __device__ void post_checks(const ArmConst<R>& A, const EdgeState<R>& E, R T, int S,
                             const float* __restrict__ obs, int n_obs, float margin_c,
-                            GeoLDS<R>* geo, R& rv, R& rq, R& rc) {
+                            GeoLDS<R>* geo, float* tab, R& rv, R& rq, R& rc) {
   joint_checks<R>(A, E, T, rv, rq);
   rc = R(0);
-  if (n_obs > 0) clearance<R, PAT>(A, E, T, S, obs, n_obs, margin_c, geo, rc);
+  if (n_obs > 0) clearance<R, PAT>(A, E, T, S, obs, n_obs, margin_c, geo, tab, rc);
 }
 
 __device__ __forceinline__ bool near_one(float r) { return fabsf(r - 1.f) <= BAND; }
@@ -393,14 +422,15 @@ __device__ __forceinline__ void model_state(const EdgeArgs& a, int64_t st, int r
 // The search of one edge by one wavefront (see the stage list above).
 // eq: the edge's id in the FP64-stage queue; s_end: this wavefront's
 // FN_MAX_NT floats of LDS; s_T: the grid in LDS; s_fix: four floats of LDS;
-// s_mod: 2 * MODEL_FLOATS floats of LDS; geo: the clearance tables (LDS).
+// s_mod: 2 * MODEL_FLOATS floats of LDS; geo, tab: the clearance tables (LDS;
+// tab: nsph * n_obs floats).
 // MODE is the search mode (a
 // compile-time constant, so each mode is its own kernel); GOALS: edges of
 // goal candidates (kind 1) are checked at their fixed duration.
 template <int PAT, int MODE, bool GOALS>
 __device__ void search_edge(const EdgeArgs& a, int64_t e, int64_t eq, const ArmConst<float>& A,
                             float* s_end, const float* s_T, float* s_fix, float* s_mod,
-                            GeoLDS<float>* geo) {
+                            GeoLDS<float>* geo, float* tab) {
   const int lane = lane_id();
   if (a.out_scr && lane == 0) a.out_scr[e] = 0;
   EdgeState<float> ES;
@@ -593,7 +623,7 @@ __device__ void search_edge(const EdgeArgs& a, int64_t e, int64_t eq, const ArmC
     const int js = pass == 0 ? jn : jstar;
     if (js < 0) break;
     float rv, rq, rc;
-    post_checks<float, PAT>(A, ES, Tg[js], S, a.obs, a.n_obs, a.margin_c, geo, rv, rq, rc);
+    post_checks<float, PAT>(A, ES, Tg[js], S, a.obs, a.n_obs, a.margin_c, geo, tab, rv, rq, rc);
     if (pass == 0) {
       pst[0] = rv; pst[1] = rq; pst[2] = rc;
     } else {
@@ -735,7 +765,7 @@ __device__ void recheck_edge(const EdgeArgs& a, int64_t e, const QEntry& q,
     if (nv) rv = dv;
     if (nq) rq = dq;
   }
-  if (nc) clearance<double, PAT>(D, ED, T, S, a.obs, a.n_obs, a.margin_c, geo, rc);
+  if (nc) clearance<double, PAT>(D, ED, T, S, a.obs, a.n_obs, a.margin_c, geo, nullptr, rc);
   m = fminf(m, (float)fmin(fabs(rv - 1.0), fmin(fabs(rq - 1.0), fabs(rc - 1.0))));
   write_out(a, e, jstar, post_status(rv, rq, rc) | FN_S_RECHECK64 | winbits, m, rho_star,
             (float)rv, (float)rq, (float)rc, work, Tg[jstar]);

@@ -19,6 +19,7 @@ template <int PAT>
 __global__ __launch_bounds__(256) void edge_model_kernel(EdgeArgs a,
                                                          const ArmConst<float>* __restrict__ Ap) {
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t == 0) *a.q_count = 0;  // the FP64-stage queue of the search that follows
   const int64_t st = t >> 3;
   if (st >= a.E + a.E / a.k) return;
   model_state<PAT>(a, st, (int)(t & 7), *Ap);
@@ -38,13 +39,14 @@ edge_time_kernel(EdgeArgs a, const ArmConst<float>* __restrict__ Ap) {
   __shared__ float s_fix[EDGE_WAVES][4];
   __shared__ float s_mod[EDGE_WAVES][2 * MODEL_FLOATS];
   __shared__ GeoLDS<float> s_geo[EDGE_WAVES];
+  extern __shared__ float s_tab[];  // EDGE_WAVES * nsph * n_obs floats
   for (int t = threadIdx.x; t < a.n_t; t += blockDim.x) s_T[t] = a.grid[t];
   __syncthreads();
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t e = xcd_edge(blockIdx.x, a.k, a.E / a.k);
   if (e < 0) return;
   search_edge<PAT, MODE, false>(a, e, e, *Ap, s_end_all[wave], s_T, s_fix[wave], s_mod[wave],
-                                &s_geo[wave]);
+                                &s_geo[wave], s_tab + wave * Ap->nsph * a.n_obs);
 }
 
 // ---------------------------------------------------------------------------
@@ -60,6 +62,7 @@ __global__ __launch_bounds__(256) void edge_check_kernel(const float* __restrict
                                                          uint16_t* out_st, float* out_rho,
                                                          float* out_tau) {
   __shared__ GeoLDS<float> s_geo[4];
+  extern __shared__ float s_tab[];  // 4 * nsph * n_obs floats
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t e = (int64_t)blockIdx.x * 4 + wave;
   if (e >= E) return;
@@ -106,7 +109,8 @@ __global__ __launch_bounds__(256) void edge_check_kernel(const float* __restrict
   }
   const float rt = wave_max(rt_all), rp = wave_max(rp_all);
   float rv, rq, rc;
-  post_checks<float, PAT>(A, ES, T, S, obs, n_obs, margin_c, &s_geo[wave], rv, rq, rc);
+  post_checks<float, PAT>(A, ES, T, S, obs, n_obs, margin_c, &s_geo[wave],
+                          s_tab + wave * A.nsph * n_obs, rv, rq, rc);
   if (lane == 0) {
     int s2 = post_status(rv, rq, rc);
     if (rt > 1.f || rp > 1.f) s2 |= FN_S_NONE;
@@ -128,12 +132,16 @@ static unsigned recheck_waves(int64_t E) { return (unsigned)(E < 4096 ? (E > 0 ?
 template <int PAT, int MODE>
 static void launch_search(fn_ctx* c, const EdgeArgs& a, int ti, hipStream_t s) {
   const int64_t E = a.E, B = a.E / a.k;
+  // the model kernel also clears the queue length
   if (MODE != FN_SEARCH_PLAIN)
     hipLaunchKernelGGL(edge_model_kernel<PAT>, dim3((unsigned)(((E + B) * 8 + 255) / 256)),
                        dim3(256), 0, s, a, c->arm32);
+  else
+    hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, s, c->q_count, 1);
   if (ti >= 0) (void)hipEventRecord(c->tev[2 * ti], s);
+  const size_t tab = (size_t)EDGE_WAVES * c->desc.n_spheres * a.n_obs * sizeof(float);
   hipLaunchKernelGGL((edge_time_kernel<PAT, MODE>), dim3((unsigned)xcd_grid(B, a.k)),
-                     dim3(64 * EDGE_WAVES), 0, s, a, c->arm32);
+                     dim3(64 * EDGE_WAVES), tab, s, a, c->arm32);
   if (ti >= 0) (void)hipEventRecord(c->tev[2 * ti + 1], s);
   hipLaunchKernelGGL(edge_recheck_kernel<PAT>, dim3(recheck_waves(E)), dim3(64), 0, s, a,
                      ProbTable{0, nullptr, nullptr}, c->arm64);
@@ -194,7 +202,6 @@ extern "C" int edge_time_batch(fn_ctx* c, const float* tree, int64_t ld, int32_t
   a.out_work = out->work; a.out_scr = out->screened; a.q_count = c->q_count; a.queue = c->queue;
   a.model_e = c->model_e; a.model_c = c->model_c;
   hipStream_t s = (hipStream_t)stream;
-  hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, s, c->q_count, 1);
   const int ti = c->timing && c->n_timed < FN_MAX_TIMED ? c->n_timed++ : -1;
   if (c->pattern == PAT_FR3) launch_search_mode<PAT_FR3>(c, a, ti, s);
   else launch_search_mode<PAT_GENERIC>(c, a, ti, s);
@@ -219,10 +226,11 @@ extern "C" int edge_check(fn_ctx* c, const float* x0, const float* x1, const flo
   const float* ob = obs ? obs->spheres : nullptr;
   const int no = obs ? obs->n : 0;
   const float mg = obs ? obs->margin : 0.f;
+  const size_t tab = (size_t)4 * c->desc.n_spheres * no * sizeof(float);
   if (c->pattern == PAT_FR3)
-    hipLaunchKernelGGL(edge_check_kernel<PAT_FR3>, grid, dim3(256), 0, s, x0, x1, T, E, S, ob, no, mg, c->arm32, out_status, out_rho5, out_tau);
+    hipLaunchKernelGGL(edge_check_kernel<PAT_FR3>, grid, dim3(256), tab, s, x0, x1, T, E, S, ob, no, mg, c->arm32, out_status, out_rho5, out_tau);
   else
-    hipLaunchKernelGGL(edge_check_kernel<PAT_GENERIC>, grid, dim3(256), 0, s, x0, x1, T, E, S, ob, no, mg, c->arm32, out_status, out_rho5, out_tau);
+    hipLaunchKernelGGL(edge_check_kernel<PAT_GENERIC>, grid, dim3(256), tab, s, x0, x1, T, E, S, ob, no, mg, c->arm32, out_status, out_rho5, out_tau);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? FN_OK : hip_fail(e, "edge_check launch");
 }

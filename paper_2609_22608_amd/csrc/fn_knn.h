@@ -265,6 +265,138 @@ __device__ __forceinline__ void wave_argmin(double d, int idx, double& wd, int& 
   wi = (int)mi;
 }
 
+// Sorts the 64 lanes' (key, index) pairs ascending, key first, then the
+// index as unsigned (bitonic network; equal pairs stay put).
+template <int K, int J>
+__device__ __forceinline__ void bitonic_stage2(uint64_t& key, int& idx) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t ok = ((uint64_t)(uint32_t)lane_xor<J>((int)(key >> 32)) << 32) |
+                      (uint32_t)lane_xor<J>((int)(uint32_t)key);
+  const int oi = lane_xor<J>(idx);
+  const bool o_less = ok < key || (ok == key && (unsigned)oi < (unsigned)idx);
+  const bool o_more = key < ok || (ok == key && (unsigned)idx < (unsigned)oi);
+  const bool want_min = ((lane & J) == 0) == ((lane & K) == 0);
+  if (want_min ? o_less : o_more) {
+    key = ok;
+    idx = oi;
+  }
+}
+template <int K, int J>
+__device__ __forceinline__ void bitonic_merge2(uint64_t& key, int& idx) {
+  bitonic_stage2<K, J>(key, idx);
+  if constexpr (J > 1) bitonic_merge2<K, J / 2>(key, idx);
+}
+__device__ __forceinline__ void wave_sort64_2(uint64_t& key, int& idx) {
+  bitonic_merge2<2, 1>(key, idx);
+  bitonic_merge2<4, 2>(key, idx);
+  bitonic_merge2<8, 4>(key, idx);
+  bitonic_merge2<16, 8>(key, idx);
+  bitonic_merge2<32, 16>(key, idx);
+  bitonic_merge2<64, 32>(key, idx);
+}
+
+// Exact FP64 rescan of the whole tree for query b (x: its state in FP64):
+// each lane keeps a sorted list of its k best, then k rounds of wave argmin
+// over the list heads.
+__device__ void knn_rescan_query(const float* __restrict__ tree, int64_t ld, int n_nodes,
+                                 const double* x, int b, int k, int32_t* __restrict__ out_idx,
+                                 float* __restrict__ out_d2) {
+  const int lane = threadIdx.x & 63;
+  double ld_d[FN_MAX_K];
+  int ld_i[FN_MAX_K];
+  for (int r = 0; r < k; ++r) {
+    ld_d[r] = INFINITY;
+    ld_i[r] = 0x7fffffff;
+  }
+  for (int n = lane; n < n_nodes; n += 64) {
+    const double d = exact_d2(tree, ld, n, x);
+    if (d < ld_d[k - 1]) {  // a lane's nodes come in increasing index
+      int r = k - 1;
+      while (r > 0 && d < ld_d[r - 1]) {
+        ld_d[r] = ld_d[r - 1];
+        ld_i[r] = ld_i[r - 1];
+        --r;
+      }
+      ld_d[r] = d;
+      ld_i[r] = n;
+    }
+  }
+  int head = 0;
+  for (int r = 0; r < k; ++r) {
+    const double hd = head < k ? ld_d[head] : INFINITY;
+    const int hi = head < k ? ld_i[head] : 0x7fffffff;
+    double wd;
+    int wi;
+    wave_argmin(hd, hi, wd, wi);
+    if (wi != 0x7fffffff && wi == hi) ++head;
+    if (wi == 0x7fffffff) {
+      wd = INFINITY;
+      wi = -1;
+    }
+    if (lane == 0) {
+      out_idx[(size_t)b * k + r] = wi;
+      if (out_d2) out_d2[(size_t)b * k + r] = (float)wd;
+    }
+  }
+}
+
+// Merge of one query whose chunk lists hold at most 64 entries in all
+// (n_split * K1 <= 64): one entry per lane, the FP32 k-th key from one sort
+// of the 64-bit keys, the FP64 ranking of the band from one sort of
+// (d64, index) -- the same result as the k rounds of argmin of the general
+// merge.  No LDS.
+template <int K1>
+__device__ void knn_merge_small(const float* __restrict__ tree, int64_t ld, int n_nodes,
+                                const float* __restrict__ qs, int b, int k, int n_split,
+                                const float* __restrict__ in_d, const int32_t* __restrict__ in_i,
+                                const float* __restrict__ in_y2, int32_t* __restrict__ out_idx,
+                                float* __restrict__ out_d2) {
+  const int lane = threadIdx.x & 63;
+  double x[FN_STATE];
+#pragma unroll
+  for (int c = 0; c < FN_STATE; ++c) x[c] = (double)qs[(size_t)b * FN_STATE + c];
+  const int total = n_split * K1;
+  const float* D = in_d + (size_t)b * total;
+  const int32_t* I = in_i + (size_t)b * total;
+  int my_i = lane < total ? I[lane] : -1;
+  float my_d = lane < total ? D[lane] : INFINITY;
+  if (my_i < 0) my_d = INFINITY;
+  // (a) FP32 k-th smallest key over all entries
+  float sd = my_d;
+  int si = my_i;
+  wave_sort64(sd, si);
+  const float th_d = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, sd), k - 1));
+  const int th_i = __builtin_amdgcn_readlane(si, k - 1);
+  // error bound of the screening distances (as in the general merge)
+  float y2 = 0.f;
+  for (int c2 = lane; c2 < n_split; c2 += 64) y2 = fmaxf(y2, in_y2[(size_t)b * n_split + c2]);
+  y2 = wave_max(y2);
+  double xn = 0.0;
+#pragma unroll
+  for (int c = 0; c < FN_STATE; ++c) xn += x[c] * x[c];
+  const float rad = (float)sqrt(xn) + sqrtf(y2);
+  const float eps = KNN_EPS * rad * rad;
+  const float band = th_i < 0 ? INFINITY : th_d + 2.f * eps + fabsf(th_d) * KNN_BAND + 1e-30f;
+  // (b) a chunk whose last entry is in the band may hold more in-band nodes
+  const bool last = lane < total && lane % K1 == K1 - 1;
+  if (__any(last && my_i >= 0 && my_d <= band)) {
+    knn_rescan_query(tree, ld, n_nodes, x, b, k, out_idx, out_d2);
+    return;
+  }
+  // (c) FP64 re-rank of the band: one sort of (d64, index); entries outside
+  // the band rank last (+inf, max index)
+  const bool in = my_i >= 0 && my_d <= band;
+  const double dd = in ? exact_d2(tree, ld, my_i, x) : INFINITY;
+  uint64_t key = (uint64_t)__double_as_longlong(dd);  // d >= 0: bit order = value order
+  int idx = in ? my_i : 0x7fffffff;
+  wave_sort64_2(key, idx);
+  if (lane < k) {
+    const bool ok = idx != 0x7fffffff;
+    out_idx[(size_t)b * k + lane] = ok ? idx : -1;
+    if (out_d2) out_d2[(size_t)b * k + lane] = ok ? (float)__longlong_as_double((long long)key) : INFINITY;
+  }
+}
+
 template <int K1>
 __device__ void knn_merge_query(const float* __restrict__ tree, int64_t ld, int n_nodes,
                                 const float* __restrict__ qs, int b, int k, int n_split,
@@ -370,44 +502,7 @@ __device__ void knn_merge_query(const float* __restrict__ tree, int64_t ld, int 
       }
     }
   } else {
-    // (d) exact FP64 rescan of the whole tree for this query: each lane keeps
-    // a sorted list of its k best, then k rounds of wave argmin over heads
-    double ld_d[FN_MAX_K];
-    int ld_i[FN_MAX_K];
-    for (int r = 0; r < k; ++r) {
-      ld_d[r] = INFINITY;
-      ld_i[r] = 0x7fffffff;
-    }
-    for (int n = lane; n < n_nodes; n += 64) {
-      const double d = exact_d2(tree, ld, n, x);
-      if (d < ld_d[k - 1]) {  // a lane's nodes come in increasing index
-        int r = k - 1;
-        while (r > 0 && d < ld_d[r - 1]) {
-          ld_d[r] = ld_d[r - 1];
-          ld_i[r] = ld_i[r - 1];
-          --r;
-        }
-        ld_d[r] = d;
-        ld_i[r] = n;
-      }
-    }
-    int head = 0;
-    for (int r = 0; r < k; ++r) {
-      const double hd = head < k ? ld_d[head] : INFINITY;
-      const int hi = head < k ? ld_i[head] : 0x7fffffff;
-      double wd;
-      int wi;
-      wave_argmin(hd, hi, wd, wi);
-      if (wi != 0x7fffffff && wi == hi) ++head;
-      if (wi == 0x7fffffff) {
-        wd = INFINITY;
-        wi = -1;
-      }
-      if (lane == 0) {
-        out_idx[(size_t)b * k + r] = wi;
-        if (out_d2) out_d2[(size_t)b * k + r] = (float)wd;
-      }
-    }
+    knn_rescan_query(tree, ld, n_nodes, x, b, k, out_idx, out_d2);
   }
 }
 

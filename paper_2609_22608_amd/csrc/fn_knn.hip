@@ -37,6 +37,16 @@ __global__ __launch_bounds__(64) void knn_merge(const float* __restrict__ tree, 
                       out_d2);
 }
 
+// chunk lists of at most 64 entries per query: sort-based merge, no LDS
+template <int K1>
+__global__ __launch_bounds__(64) void knn_merge_small_kernel(
+    const float* __restrict__ tree, int64_t ld, int n_nodes, const float* __restrict__ qs, int k,
+    int n_split, const float* __restrict__ in_d, const int32_t* __restrict__ in_i,
+    const float* __restrict__ in_y2, int32_t* __restrict__ out_idx, float* __restrict__ out_d2) {
+  knn_merge_small<K1>(tree, ld, n_nodes, qs, blockIdx.x, k, n_split, in_d, in_i, in_y2, out_idx,
+                      out_d2);
+}
+
 template <int K1>
 static void launch_knn(fn_ctx* c, const float* tree, int64_t ld, int n_nodes, const float* qs,
                        int B, int k, int32_t* out_idx, float* out_d2, hipStream_t s) {
@@ -53,8 +63,12 @@ static void launch_knn(fn_ctx* c, const float* tree, int64_t ld, int n_nodes, co
   const int pairs = n_groups * n_split;
   hipLaunchKernelGGL((knn_scan<K1, KNN_QG>), dim3((pairs + 3) / 4), dim3(256), 0, s, tree, ld,
                      n_nodes, qs, B, n_groups, n_split, chunk, c->knn_d, c->knn_i, c->knn_y);
-  hipLaunchKernelGGL(knn_merge<K1>, dim3(B), dim3(64), 0, s, tree, ld, n_nodes, qs, k, n_split,
-                     c->knn_d, c->knn_i, c->knn_y, out_idx, out_d2);
+  if (n_split * K1 <= WAVE)
+    hipLaunchKernelGGL(knn_merge_small_kernel<K1>, dim3(B), dim3(64), 0, s, tree, ld, n_nodes, qs,
+                       k, n_split, c->knn_d, c->knn_i, c->knn_y, out_idx, out_d2);
+  else
+    hipLaunchKernelGGL(knn_merge<K1>, dim3(B), dim3(64), 0, s, tree, ld, n_nodes, qs, k, n_split,
+                       c->knn_d, c->knn_i, c->knn_y, out_idx, out_d2);
 }
 
 size_t knn_scratch_entries(int max_batch, int max_k, int max_problems) {
