@@ -93,7 +93,7 @@ __global__ __launch_bounds__(64) void batch_knn_merge(const KnnProb* __restrict_
   if (qg >= query_off[n]) return;
   const int p = bsearch_off(query_off, n, qg);
   const KnnProb& q = P[p];
-  if (q.n_split * K1 <= WAVE)
+  if (q.n_split * K1 <= 2 * WAVE)
     knn_merge_small<K1>(q.tree, q.ld, *q.n_nodes, q.qs, (int)(qg - query_off[p]), k, q.n_split,
                         part_d + q.part_off, part_i + q.part_off, part_y + q.y_off, q.nbr, nullptr);
   else

@@ -340,11 +340,28 @@ __device__ void knn_rescan_query(const float* __restrict__ tree, int64_t ld, int
   }
 }
 
-// Merge of one query whose chunk lists hold at most 64 entries in all
-// (n_split * K1 <= 64): one entry per lane, the FP32 k-th key from one sort
-// of the 64-bit keys, the FP64 ranking of the band from one sort of
-// (d64, index) -- the same result as the k rounds of argmin of the general
-// merge.  No LDS.
+// Smallest 64 of two ascending 64-lane lists (a in every lane, b in every
+// lane): a's first 32 keys in lanes 0..31 and b's first 32 in reverse in
+// lanes 32..63 form a bitonic sequence, and one merge sorts it.  Enough for
+// the k <= 32 smallest.
+__device__ __forceinline__ void wave_merge_heads(uint64_t& a, int& ai, uint64_t b, int bi) {
+  const int lane = threadIdx.x & 63;
+  const int src = (63 - lane) << 2;
+  const uint64_t rb = ((uint64_t)(uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)(b >> 32)) << 32) |
+                      (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)(uint32_t)b);
+  const int rbi = __builtin_amdgcn_ds_bpermute(src, bi);
+  if (lane >= 32) {
+    a = rb;
+    ai = rbi;
+  }
+  bitonic_merge2<64, 32>(a, ai);
+}
+
+// Merge of one query whose chunk lists hold at most 128 entries in all
+// (n_split * K1 <= 128): one or two entries per lane; the FP32 k-th key
+// comes from sorts of the 64-bit keys, the FP64 ranking of the band from
+// sorts of (d64, index) -- the same result as the k rounds of argmin of the
+// general merge.  No LDS.
 template <int K1>
 __device__ void knn_merge_small(const float* __restrict__ tree, int64_t ld, int n_nodes,
                                 const float* __restrict__ qs, int b, int k, int n_split,
@@ -356,17 +373,27 @@ __device__ void knn_merge_small(const float* __restrict__ tree, int64_t ld, int 
 #pragma unroll
   for (int c = 0; c < FN_STATE; ++c) x[c] = (double)qs[(size_t)b * FN_STATE + c];
   const int total = n_split * K1;
+  const bool two = total > WAVE;
   const float* D = in_d + (size_t)b * total;
   const int32_t* I = in_i + (size_t)b * total;
-  int my_i = lane < total ? I[lane] : -1;
-  float my_d = lane < total ? D[lane] : INFINITY;
-  if (my_i < 0) my_d = INFINITY;
+  // entry e0 = lane and (two lists) e1 = lane + 64
+  const int e1 = lane + WAVE;
+  int i0 = lane < total ? I[lane] : -1, i1 = two && e1 < total ? I[e1] : -1;
+  float d0 = i0 >= 0 ? D[lane] : INFINITY, d1 = i1 >= 0 ? D[e1] : INFINITY;
   // (a) FP32 k-th smallest key over all entries
-  float sd = my_d;
-  int si = my_i;
-  wave_sort64(sd, si);
-  const float th_d = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, sd), k - 1));
-  const int th_i = __builtin_amdgcn_readlane(si, k - 1);
+  uint64_t ka = knn_key(d0, i0);
+  int ia = 0;
+  wave_sort64_2(ka, ia);
+  if (two) {
+    uint64_t kb = knn_key(d1, i1);
+    int ib = 0;
+    wave_sort64_2(kb, ib);
+    wave_merge_heads(ka, ia, kb, ib);
+  }
+  const uint64_t th = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(ka >> 32), k - 1) << 32) |
+                      (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)ka, k - 1);
+  const float th_d = knn_key_d(th);
+  const int th_i = (int)(uint32_t)th;
   // error bound of the screening distances (as in the general merge)
   float y2 = 0.f;
   for (int c2 = lane; c2 < n_split; c2 += 64) y2 = fmaxf(y2, in_y2[(size_t)b * n_split + c2]);
@@ -378,22 +405,29 @@ __device__ void knn_merge_small(const float* __restrict__ tree, int64_t ld, int 
   const float eps = KNN_EPS * rad * rad;
   const float band = th_i < 0 ? INFINITY : th_d + 2.f * eps + fabsf(th_d) * KNN_BAND + 1e-30f;
   // (b) a chunk whose last entry is in the band may hold more in-band nodes
-  const bool last = lane < total && lane % K1 == K1 - 1;
-  if (__any(last && my_i >= 0 && my_d <= band)) {
+  const bool over0 = lane < total && lane % K1 == K1 - 1 && i0 >= 0 && d0 <= band;
+  const bool over1 = e1 < total && e1 % K1 == K1 - 1 && i1 >= 0 && d1 <= band;
+  if (__any(over0 || over1)) {
     knn_rescan_query(tree, ld, n_nodes, x, b, k, out_idx, out_d2);
     return;
   }
-  // (c) FP64 re-rank of the band: one sort of (d64, index); entries outside
-  // the band rank last (+inf, max index)
-  const bool in = my_i >= 0 && my_d <= band;
-  const double dd = in ? exact_d2(tree, ld, my_i, x) : INFINITY;
-  uint64_t key = (uint64_t)__double_as_longlong(dd);  // d >= 0: bit order = value order
-  int idx = in ? my_i : 0x7fffffff;
-  wave_sort64_2(key, idx);
+  // (c) FP64 re-rank of the band: sorts of (d64, index); entries outside
+  // the band rank last (+inf, max index).  d >= 0, so the bit order of the
+  // doubles is their value order.
+  const bool in0 = i0 >= 0 && d0 <= band, in1 = i1 >= 0 && d1 <= band;
+  uint64_t ga = (uint64_t)__double_as_longlong(in0 ? exact_d2(tree, ld, i0, x) : INFINITY);
+  int gia = in0 ? i0 : 0x7fffffff;
+  wave_sort64_2(ga, gia);
+  if (two) {
+    uint64_t gb = (uint64_t)__double_as_longlong(in1 ? exact_d2(tree, ld, i1, x) : INFINITY);
+    int gib = in1 ? i1 : 0x7fffffff;
+    wave_sort64_2(gb, gib);
+    wave_merge_heads(ga, gia, gb, gib);
+  }
   if (lane < k) {
-    const bool ok = idx != 0x7fffffff;
-    out_idx[(size_t)b * k + lane] = ok ? idx : -1;
-    if (out_d2) out_d2[(size_t)b * k + lane] = ok ? (float)__longlong_as_double((long long)key) : INFINITY;
+    const bool ok = gia != 0x7fffffff;
+    out_idx[(size_t)b * k + lane] = ok ? gia : -1;
+    if (out_d2) out_d2[(size_t)b * k + lane] = ok ? (float)__longlong_as_double((long long)ga) : INFINITY;
   }
 }
 

@@ -37,7 +37,7 @@ __global__ __launch_bounds__(64) void knn_merge(const float* __restrict__ tree, 
                       out_d2);
 }
 
-// chunk lists of at most 64 entries per query: sort-based merge, no LDS
+// chunk lists of at most 128 entries per query: sort-based merge, no LDS
 template <int K1>
 __global__ __launch_bounds__(64) void knn_merge_small_kernel(
     const float* __restrict__ tree, int64_t ld, int n_nodes, const float* __restrict__ qs, int k,
@@ -63,7 +63,7 @@ static void launch_knn(fn_ctx* c, const float* tree, int64_t ld, int n_nodes, co
   const int pairs = n_groups * n_split;
   hipLaunchKernelGGL((knn_scan<K1, KNN_QG>), dim3((pairs + 3) / 4), dim3(256), 0, s, tree, ld,
                      n_nodes, qs, B, n_groups, n_split, chunk, c->knn_d, c->knn_i, c->knn_y);
-  if (n_split * K1 <= WAVE)
+  if (n_split * K1 <= 2 * WAVE)
     hipLaunchKernelGGL(knn_merge_small_kernel<K1>, dim3(B), dim3(64), 0, s, tree, ld, n_nodes, qs,
                        k, n_split, c->knn_d, c->knn_i, c->knn_y, out_idx, out_d2);
   else

@@ -27,7 +27,9 @@ def iteration():
 def test_knn_result_is_independent_of_the_launch_mapping(iteration):
     sh, wl, ctx, tree, ld, n, cand = iteration
     ref = None
-    for tw, mc in ((0, 0), (1024, 256), (16384, 64), (2048, 4096)):
+    # chunk lists per query: 48 (default), 12, 192 (general merge), 24, 96
+    # (sort-based merge over two entries per lane)
+    for tw, mc in ((0, 0), (1024, 256), (16384, 64), (2048, 4096), (8192, 512)):
         ctx.set_tuning(tw, mc)
         idx, d2 = ctx.plan_knn(tree, ld, n, cand, sh.k)
         torch.cuda.synchronize()
