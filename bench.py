@@ -258,15 +258,20 @@ def main():
 
 
 def kernel_source_hash():
-    """Hash of the sources the search kernels are built from: a stored
-    traffic figure applies only to the kernel it was measured on."""
+    """Hash of the code the search kernels are built from (comments and
+    blank lines dropped): a stored traffic figure applies only to the kernel
+    it was measured on."""
     import hashlib
+    import re
 
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2609_22608_amd", "csrc")
     for name in ("fn_internal.h", "fn_ctx.h", "fn_edge.h", "fn_edge.hip"):
-        with open(os.path.join(d, name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(d, name)) as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        lines = (re.sub(r"//.*", "", ln).rstrip() for ln in text.splitlines())
+        h.update("\n".join(ln for ln in lines if ln).encode())
     return h.hexdigest()[:16]
 
 

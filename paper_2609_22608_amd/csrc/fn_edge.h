@@ -19,7 +19,9 @@
 //            feasible slot.  "Hit" = the result lies in the window (or the
 //            network predicted no feasible slot and there is none).
 // Every FP32 ratio within BAND of 1 that a decision rests on sends the edge
-// to the FP64 stage, which resumes it from that slot.
+// to the FP64 stage.  At the first slot in the band the search does not
+// stop: it goes on to the next candidate slot and post-checks both in FP32,
+// so that the FP64 stage only has FP64 decisions left (see QEntry).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -288,7 +290,8 @@ struct SlotMask {
 // Hands edge e over to the FP64 stage (see QEntry).
 __device__ __forceinline__ void push_queue(const EdgeArgs& a, int64_t e, int j, int phase, int j2,
                                            float m, float m2, int work, float rho, float rho2,
-                                           const float* post, const SlotMask& todo) {
+                                           float v1, float q1, float c1, float v2, float q2,
+                                           float c2, const SlotMask& todo) {
   if (lane_id() == 0) {
     const int slot = atomicAdd(a.q_count, 1);
     QEntry q;
@@ -302,8 +305,12 @@ __device__ __forceinline__ void push_queue(const EdgeArgs& a, int64_t e, int j, 
     q.margin2 = m2;
     q.rho = rho;
     q.rho2 = rho2;
-#pragma unroll
-    for (int i = 0; i < 6; ++i) q.post[i] = post[i];
+    q.post[0] = v1;
+    q.post[1] = q1;
+    q.post[2] = c1;
+    q.post[3] = v2;
+    q.post[4] = q2;
+    q.post[5] = c2;
     q.pad2[0] = q.pad2[1] = 0;
     q.todo[0] = todo.w0;
     q.todo[1] = todo.w1;
@@ -616,31 +623,31 @@ __device__ void search_edge(const EdgeArgs& a, int64_t e, int64_t eq, const ArmC
     return;
   }
   // FP32 post-checks at jn (the result if FP64 finds it feasible) and at
-  // jstar (one call site)
-  float pst[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  // jstar (one call site; plain registers, no array, so nothing goes to
+  // scratch memory)
+  float v1 = 0.f, q1 = 0.f, c1 = 0.f, rv = 0.f, rq = 0.f, rc = 0.f;
 #pragma unroll 1
   for (int pass = jn >= 0 ? 0 : 1; pass < 2; ++pass) {
     const int js = pass == 0 ? jn : jstar;
     if (js < 0) break;
-    float rv, rq, rc;
-    post_checks<float, PAT>(A, ES, Tg[js], S, a.obs, a.n_obs, a.margin_c, geo, tab, rv, rq, rc);
+    float pv, pq, pc;
+    post_checks<float, PAT>(A, ES, Tg[js], S, a.obs, a.n_obs, a.margin_c, geo, tab, pv, pq, pc);
     if (pass == 0) {
-      pst[0] = rv; pst[1] = rq; pst[2] = rc;
+      v1 = pv; q1 = pq; c1 = pc;
     } else {
-      pst[3] = rv; pst[4] = rq; pst[5] = rc;
+      rv = pv; rq = pq; rc = pc;
     }
   }
   const int ph_b = below_full ? PH_BELOW_FULL : 0;
   if (jn >= 0) {
     const bool j2near = jstar >= 0 && near_one(rho_star);
     push_queue(a, eq, jn, ph_b | (j2near ? PH_J2_NEAR : 0), jstar, s_fix[3], m, work, s_fix[2],
-               jstar >= 0 ? rho_star : lastv, pst, todo);
+               jstar >= 0 ? rho_star : lastv, v1, q1, c1, rv, rq, rc, todo);
     return;
   }
-  const float rv = pst[3], rq = pst[4], rc = pst[5];
   if (near_one(rv) || near_one(rq) || (a.n_obs > 0 && near_one(rc))) {
-    const float pp[6] = {rv, rq, rc, 0.f, 0.f, 0.f};
-    push_queue(a, eq, jstar, PH_POST | ph_b, -1, m, INFINITY, work, rho_star, 0.f, pp, todo);
+    push_queue(a, eq, jstar, PH_POST | ph_b, -1, m, INFINITY, work, rho_star, 0.f, rv, rq, rc, 0.f,
+               0.f, 0.f, todo);
     return;
   }
   m = fminf(m, fminf(fabsf(rv - 1.f), fminf(fabsf(rq - 1.f), fabsf(rc - 1.f))));
