@@ -25,8 +25,8 @@ import torch
 from . import fn
 
 # (target wavefronts, minimum chunk of nodes per wavefront)
-KNN_CANDIDATES = ((1024, 256), (2048, 256), (2048, 512), (4096, 512), (4096, 1024),
-                  (8192, 512), (8192, 1024), (16384, 1024))
+KNN_CANDIDATES = ((1024, 256), (2048, 256), (2048, 512), (3072, 1024), (4096, 512),
+                  (4096, 1024), (6144, 1024), (8192, 512), (8192, 1024), (16384, 1024))
 
 
 @dataclass
