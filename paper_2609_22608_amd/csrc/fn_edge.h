@@ -272,24 +272,6 @@ struct SlotMask {
     else if (i == 2) w2 &= ~m;
     else w3 &= ~m;
   }
-  // the 64 slots from j on: bit t = slot j + t (wave-uniform)
-  __device__ __forceinline__ uint64_t window(int j) const {
-    const int w = j >> 6, sh = j & 63;
-    const uint64_t lo = get(w) >> sh;
-    return sh > 0 && w < 3 ? lo | (get(w + 1) << (64 - sh)) : lo;
-  }
-  // number of set slots in [j, hi]
-  __device__ __forceinline__ int count(int j, int hi) const {
-    int n = 0;
-#pragma unroll
-    for (int w = 0; w < 4; ++w) {
-      const int lo = max(j - 64 * w, 0), top = min(hi - 64 * w, 63);
-      if (lo > top) continue;
-      const uint64_t m = (~0ull << lo) & (~0ull >> (63 - top));
-      n += __popcll(get(w) & m);
-    }
-    return n;
-  }
   // lowest set slot in [j, hi], or -1
   __device__ __forceinline__ int next(int j, int hi) const {
     while (j <= hi) {
@@ -521,13 +503,6 @@ __device__ void search_edge(const EdgeArgs& a, int64_t e, int64_t eq, const ArmC
   // (s_fix[1..3]; rarely used, so they hold no registers in the loop)
   if (lane == 0) s_fix[1] = __int_as_float(-1);
 
-  // witness passes (screening modes): after a full pass that rejected every
-  // slot it took, the sample where the last of them peaked is evaluated for
-  // the next 64 slots still to do, one slot per lane; a slot whose ratio there
-  // exceeds 1 + BAND is infeasible for certain and leaves the to-do mask
-  float u_w = -1.f;  // pending witness sample (u), or -1
-  int n_wit = 0;
-
   int stage = 0, type, sa, sb;
   bool below;
   stage_of(mode, stage, jmax, wlo, whi, type, sa, sb, below);
@@ -563,14 +538,6 @@ __device__ void search_edge(const EdgeArgs& a, int64_t e, int64_t eq, const ArmC
       todo.clear(w0, bits << sh);
       if (sh > 0 && w0 < 3) todo.clear(w0 + 1, bits >> (64 - sh));
       continue;
-    }
-    const bool witness = u_w >= 0.f;
-    if (witness) {
-      // lane l: slot j + l if still to do, at the witness sample
-      const int jj = j + lane;
-      my = jj <= sb && ((todo.window(j) >> lane) & 1ull) ? jj : -1;
-      u = u_w;
-      u_w = -1.f;
     } else {
       // next G slots still to be evaluated; lane group g takes the g-th
       while (cnt < G) {
@@ -594,22 +561,7 @@ __device__ void search_edge(const EdgeArgs& a, int64_t e, int64_t eq, const ArmC
       r = eval_rho<float, PAT>(A, ES, T, __builtin_amdgcn_rcpf(T), u);
     }
     work += __popcll(__ballot(act));
-    if (witness) {
-      // one sample bounds the slot's ratio from below (kept for the margin)
-      const bool cert = act && r > 1.f + BAND;
-      if (cert) s_end[my] = fmaxf(s_end[my], r);
-      const uint64_t bits = __ballot(cert);
-      const int w0 = j >> 6, sh = j & 63;
-      todo.clear(w0, bits << sh);
-      if (sh > 0 && w0 < 3) todo.clear(w0 + 1, bits >> (64 - sh));
-      __builtin_amdgcn_wave_barrier();
-      continue;
-    }
-    // the lanes' own ratios wait in the (idle) clearance table for the
-    // witness choice below
-    if (mode != FN_SEARCH_PLAIN) geo->sph[lane] = r;
     r = group_max(r, Sw);
-    int wq = -1;  // lane group of the last slot rejected outside the band
     bool done = false;
     for (int q = 0; q < cnt; ++q) {
       const float rho = __shfl(r, q * Sw);
@@ -644,17 +596,8 @@ __device__ void search_edge(const EdgeArgs& a, int64_t e, int64_t eq, const ArmC
         done = true;
         break;
       }
-      wq = q;
     }
     if (done) break;
-    if (mode != FN_SEARCH_PLAIN && wq >= 0 && n_wit < 2 && todo.count(j, sb) > 2 * G) {
-      // the witness: the sample where slot wq peaked (lowest such lane)
-      __builtin_amdgcn_wave_barrier();
-      const uint64_t pk = __ballot(g == wq && s_ok && my >= 0 && geo->sph[lane] == r);
-      const int s_star = (__ffsll((long long)pk) - 1) & (Sw - 1);
-      u_w = float(s_star) / float(S - 1);
-      ++n_wit;
-    }
   }
   if (a.out_scr && lane == 0) a.out_scr[e] = (int16_t)scr;
   __builtin_amdgcn_wave_barrier();
