@@ -149,7 +149,7 @@ __device__ void joint_checks(const ArmConst<R>& A, const EdgeState<R>& E, R T, R
 // memory load per pair.  Lane = (sample, sphere part): the parts split each
 // link's spheres so that all 64 lanes work when S < 64.
 // FP32: tab (LDS, nsph * n_obs floats) receives 1 / (r_a + margin + r_o)^2
-// of every pair, and the loop keeps the smallest d^2 / (r_a + margin + r_o)^2
+// of every pair (hardware reciprocal, within 1 ulp), and the loop keeps the smallest d^2 / (r_a + margin + r_o)^2
 // (a product and a minimum per pair instead of a reciprocal); rho_c is its
 // inverse square root.  FP64 (tab unused): the ratio of every pair by IEEE
 // division.
@@ -166,14 +166,17 @@ __device__ void clearance(const ArmConst<R>& A, const EdgeState<R>& E, R T, int 
     geo->sph[4 * t + 3] = A.sphr[t] + R(margin_c);
   }
   for (int t = lane; t < 4 * n_obs; t += WAVE) geo->obs[t] = R(obs[t]);
-  if constexpr (F32) {
-    for (int t = lane; t < A.nsph * n_obs; t += WAVE) {
-      const int k = t / n_obs, o = t - k * n_obs;
-      const float need = (A.sphr[k] + margin_c) + obs[4 * o + 3];
-      tab[t] = 1.f / (need * need);
-    }
-  }
   __builtin_amdgcn_wave_barrier();
+  if constexpr (F32) {
+    // lane = (obstacle o, sphere offset k0): WAVE / n_obs spheres per step
+    const int kstep = WAVE / n_obs, o = lane % n_obs, k0 = lane / n_obs;
+    if (k0 < kstep)
+      for (int k = k0; k < A.nsph; k += kstep) {
+        const float need = geo->sph[4 * k + 3] + geo->obs[4 * o + 3];
+        tab[k * n_obs + o] = __builtin_amdgcn_rcpf(need * need);
+      }
+    __builtin_amdgcn_wave_barrier();
+  }
   // FP32: smallest d^2 / need^2; FP64: largest need^2 / d^2
   R best = F32 ? R(INFINITY) : R(0);
   int Sw = 1;
@@ -561,7 +564,9 @@ __device__ void search_edge(const EdgeArgs& a, int64_t e, int64_t eq, const ArmC
       r = eval_rho<float, PAT>(A, ES, T, __builtin_amdgcn_rcpf(T), u);
     }
     work += __popcll(__ballot(act));
-    r = group_max(r, Sw);
+    // the plain search is bound by VALU issue: its group maxima go through
+    // the LDS; the screened searches are latency-bound: DPP
+    r = MODE == FN_SEARCH_PLAIN ? group_max_lds(r, Sw) : group_max(r, Sw);
     bool done = false;
     for (int q = 0; q < cnt; ++q) {
       const float rho = __shfl(r, q * Sw);

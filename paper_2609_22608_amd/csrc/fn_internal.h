@@ -468,24 +468,82 @@ __device__ __forceinline__ void sphere_centres(const ArmConst<R>& A, const R* sn
 // wave helpers
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
+// Value of lane (lane ^ J) for J = 1..16 without the LDS where DPP can do
+// it: quad permutations for 1 and 2; for 4 the half-row mirror (lane ^ 7)
+// then the quad reversal (^ 3); for 8 the row mirror (^ 15) then the
+// half-row mirror; 16 by LDS swizzle.  Every lane must be active.
+template <int J>
+__device__ __forceinline__ int xlane(int v) {
+  if constexpr (J == 1) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xf, 0xf, true);  // quad_perm 1,0,3,2
+  else if constexpr (J == 2) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xf, 0xf, true);  // 2,3,0,1
+  else if constexpr (J == 4)
+    return __builtin_amdgcn_mov_dpp(__builtin_amdgcn_mov_dpp(v, 0x141, 0xf, 0xf, true), 0x1B, 0xf,
+                                    0xf, true);
+  else if constexpr (J == 8)
+    return __builtin_amdgcn_mov_dpp(__builtin_amdgcn_mov_dpp(v, 0x140, 0xf, 0xf, true), 0x141, 0xf,
+                                    0xf, true);
+  else return __builtin_amdgcn_ds_swizzle(v, (16 << 10) | 0x1f);
+}
+template <int J>
+__device__ __forceinline__ float xlane(float v) {
+  return __int_as_float(xlane<J>(__float_as_int(v)));
+}
+template <int J>
+__device__ __forceinline__ double xlane(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = xlane<J>((int)(b & 0xffffffff)), hi = xlane<J>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ float readlane(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double readlane(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Reductions over the wave (the result in every lane; called with every lane
+// active): exchanges within each half, then the two halves' lane 0.
 __device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
-  return v;
+  v = fmaxf(v, xlane<1>(v));
+  v = fmaxf(v, xlane<2>(v));
+  v = fmaxf(v, xlane<4>(v));
+  v = fmaxf(v, xlane<8>(v));
+  v = fmaxf(v, xlane<16>(v));
+  return fmaxf(readlane(v, 0), readlane(v, 32));
 }
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-  return v;
+  v = fmax(v, xlane<1>(v));
+  v = fmax(v, xlane<2>(v));
+  v = fmax(v, xlane<4>(v));
+  v = fmax(v, xlane<8>(v));
+  v = fmax(v, xlane<16>(v));
+  return fmax(readlane(v, 0), readlane(v, 32));
 }
 __device__ __forceinline__ float wave_min(float v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o));
+  v = fminf(v, xlane<1>(v));
+  v = fminf(v, xlane<2>(v));
+  v = fminf(v, xlane<4>(v));
+  v = fminf(v, xlane<8>(v));
+  v = fminf(v, xlane<16>(v));
+  return fminf(readlane(v, 0), readlane(v, 32));
+}
+// The same through LDS permutes: no VALU moves, for VALU-bound loops.
+__device__ __forceinline__ float group_max_lds(float v, int width) {
+  for (int o = 1; o < width; o <<= 1) v = fmaxf(v, __shfl_xor(v, o));
   return v;
 }
-// max over aligned groups of `width` lanes (width a power of two <= 64)
+// max over aligned groups of `width` lanes (width a wave-uniform power of two
+// <= 64)
 __device__ __forceinline__ float group_max(float v, int width) {
-  for (int o = 1; o < width; o <<= 1) v = fmaxf(v, __shfl_xor(v, o));
+  if (width > 1) v = fmaxf(v, xlane<1>(v));
+  if (width > 2) v = fmaxf(v, xlane<2>(v));
+  if (width > 4) v = fmaxf(v, xlane<4>(v));
+  if (width > 8) v = fmaxf(v, xlane<8>(v));
+  if (width > 16) v = fmaxf(v, xlane<16>(v));
+  if (width > 32) v = fmaxf(readlane(v, 0), readlane(v, 32));
   return v;
 }
 
