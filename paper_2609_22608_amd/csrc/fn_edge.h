@@ -569,8 +569,9 @@ __device__ void search_edge(const EdgeArgs& a, int64_t e, int64_t eq, const ArmC
     r = MODE == FN_SEARCH_PLAIN ? group_max_lds(r, Sw) : group_max(r, Sw);
     bool done = false;
     for (int q = 0; q < cnt; ++q) {
-      const float rho = __shfl(r, q * Sw);
-      const int jq = __shfl(my, q * Sw);
+      // lane q * Sw holds group q's slot and ratio (a scalar read, no LDS)
+      const float rho = readlane(r, q * Sw);
+      const int jq = __builtin_amdgcn_readlane(my, q * Sw);
       if (near_one(rho)) {
         __builtin_amdgcn_wave_barrier();
         if (__builtin_amdgcn_readfirstlane(__float_as_int(s_fix[1])) >= 0) {
