@@ -51,7 +51,7 @@ enum {
   FN_OK = 0,
   FN_E_ARG = -1,         /* bad pointer or value */
   FN_E_SHAPE = -2,       /* size out of range or beyond the context's caps */
-  FN_E_UNSUPPORTED = -3, /* arm or option this build does not handle */
+  FN_E_UNSUPPORTED = -3, /* arm or option the library does not handle */
   FN_E_HIP = -4,         /* HIP runtime error (message has the HIP text) */
   FN_E_NOMEM = -5,       /* device allocation failed (create calls only) */
   FN_E_STATE = -6        /* wrong object state (e.g. untrained surrogate) */

@@ -706,7 +706,7 @@ extern "C" int fn_mlp_load(fn_ctx* ctx, const char* path, fn_mlp** out) {
             std::fread(&np, 4, 1, f) == 1 && np == NP_PAD && std::fread(&step, 8, 1, f) == 1 &&
             std::fread(buf.data(), 4, buf.size(), f) == buf.size();
   std::fclose(f);
-  if (!ok) return fail(FN_E_ARG, "fn_mlp_load: %s is not a surrogate file of this build", path);
+  if (!ok) return fail(FN_E_ARG, "fn_mlp_load: %s is not a surrogate file of this library version", path);
   fn_mlp* n = nullptr;
   int rc = fn_mlp_create(ctx, 0, &n);
   if (rc) return rc;
