@@ -42,8 +42,9 @@ F_MODEL = 8271
 F_JOINTS = 980
 
 
-def f_post(S, n_obs, n_sph):
-    return F_JOINTS + (S * (371 + n_sph * (19 + 13 * n_obs)) if n_obs > 0 else 0)
+def f_clear(S, n_obs, n_sph):
+    """Clearance of one edge (evaluated only when its limit checks pass)."""
+    return S * (371 + n_sph * (19 + 13 * n_obs)) if n_obs > 0 else 0
 
 
 WORKLOADS = {
@@ -183,12 +184,17 @@ def main():
         scr = int(out["screened"].sum().item())
         st = out["status"].cpu().numpy().astype(np.uint16)
         jj = out["j"].cpu().numpy()
-        n_post = int(((jj >= 0) & ((st & fn.S_RECHECK64) == 0)).sum())
+        post = (jj >= 0) & ((st & fn.S_RECHECK64) == 0)
+        n_post = int(post.sum())
+        # the clearance runs only where the limit checks passed
+        n_clear = int((post & ((st & (fn.S_VEL | fn.S_POS)) == 0)).sum())
         n_sph = len(wl["arm"]["sph"])
-        flop = work * F_EVAL + scr * F_SCREEN + n_post * f_post(sh.samples, sh.n_obs, n_sph)
+        flop = (work * F_EVAL + scr * F_SCREEN + n_post * F_JOINTS
+                + n_clear * f_clear(sh.samples, sh.n_obs, n_sph))
         f = dict(edges_per_s=E / (ms * 1e-3), ms_per_step=ms, edge_search_ms=e_ms,
                  edge_time_kernel_ms=kern_ms, evaluations=work, screened_slots=scr,
-                 post_checked=n_post, kernel_gflop=flop / 1e9, wall_s=wall,
+                 post_checked=n_post, clearance_checked=n_clear, kernel_gflop=flop / 1e9,
+                 wall_s=wall,
                  fp32_tflops=flop / (kern_ms * 1e-3) / 1e12,
                  model_states=(E + sh.batch) if mode != fn.SEARCH_PLAIN else 0,
                  recheck64=int(((st & fn.S_RECHECK64) > 0).sum()))
@@ -234,12 +240,14 @@ def main():
                      "kernel_ms": bf["edge_time_kernel_ms"],
                      "flop_per_launch": bf["kernel_gflop"] * 1e9,
                      "flop_model": {"eval": F_EVAL, "screened_slot": F_SCREEN,
-                                    "post_checked_edge": f_post(sh.samples, sh.n_obs,
-                                                                len(wl["arm"]["sph"])),
+                                    "post_checked_edge": F_JOINTS,
+                                    "clearance_edge": f_clear(sh.samples, sh.n_obs,
+                                                              len(wl["arm"]["sph"])),
                                     "model_state": F_MODEL},
                      "units": {"evaluations": bf["evaluations"],
                                "screened_slots": bf["screened_slots"],
-                               "post_checked_edges": bf["post_checked"]}},
+                               "post_checked_edges": bf["post_checked"],
+                               "clearance_checked_edges": bf["clearance_checked"]}},
     }
     if args.batch_problems > 0:
         res["batched_round"] = batched_round(args, fn, W, torch)

@@ -63,7 +63,8 @@ enum {
   FN_S_NONE = 1,        /* no grid slot with rho_tau <= 1 and rho_P <= 1 (Def. 7) */
   FN_S_VEL = 2,         /* velocity taper violated at the searched T (Def. 6 rho_v) */
   FN_S_POS = 4,         /* joint position limit crossed along the edge */
-  FN_S_COLL = 8,        /* arm sphere closer than the margin to an obstacle */
+  FN_S_COLL = 8,        /* arm sphere closer than the margin to an obstacle (checked only
+                           when every limit check passed: Alg. 1 and-s Clear in last) */
   FN_S_RECHECK64 = 16,  /* informational: a ratio within 1e-3 of 1 was decided in FP64 */
   FN_S_WIN_HIT = 32,    /* informational: the result lies in the predicted window */
   FN_S_WIN_MISS = 64,   /* informational: it does not; the exact scan found it elsewhere */
@@ -187,7 +188,8 @@ typedef struct {
 
 /* Per-edge outputs (device, length E each).  rho4 (nullable): (rho_tauP at
  * the result slot (at the last slot when none), rho_v, rho_q, rho_c) where
- * rho_c = max (r_a + r_o + margin)/distance.  margin: the smallest
+ * rho_c = max (r_a + r_o + margin)/distance, NaN when rho_v or rho_q fails
+ * (the clearance is then not evaluated), 0 without obstacles.  margin: the smallest
  * |rho - 1| over the ratios the decision rests on.  work (nullable): number
  * of (slot, sample) evaluations of Eq. (4) performed for the edge.
  * screened (nullable): number of slots whose two endpoint ratios were
@@ -228,8 +230,9 @@ int edge_time_batch(fn_ctx* ctx, const float* tree, int64_t ld, int32_t n_nodes,
 /* x0, x1: device [E][14]; T: device [E]; S samples as above.  out_status:
  * device [E] (NONE when rho_tau or rho_P > 1 or T <= 0, VEL, POS, COLL,
  * BAD_INPUT); out_rho5: device [E][5] = (rho_tau, rho_P, rho_v, rho_q,
- * rho_c); out_tau: device [E][S][7] torques of Eq. (4) at the samples, or
- * NULL.  FP32 arithmetic (no FP64 recheck here). */
+ * rho_c; NaN unless the four limit ratios pass); out_tau: device [E][S][7]
+ * torques of Eq. (4) at the samples, or NULL.  FP32 arithmetic (no FP64
+ * recheck here). */
 int edge_check(fn_ctx* ctx, const float* x0, const float* x1, const float* T, int64_t E,
                int32_t S, const fn_obstacles* obs, uint16_t* out_status, float* out_rho5,
                float* out_tau, void* stream);

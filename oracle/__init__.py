@@ -206,7 +206,9 @@ def rho_c(A, x0, x1, T, S, obs, margin=0.0):
 def edge_time(A: OArm, x0, x1, grid, S, obs=None, jmax=None, parent_ok=None, margin=0.0,
               scan=1):
     """Plain search (Def. 7 on the grid) + post-checks for every edge.
-    scan=1 stops at the first feasible slot, scan=0 evaluates every slot."""
+    scan=1 stops at the first feasible slot, scan=0 evaluates every slot.
+    rho[:, 3] (rho_c) is NaN where rho_v or rho_q already fails: Alg. 1
+    and-s the clearance in after the limit checks."""
     x0, p0 = _d(x0)
     x1, p1 = _d(x1)
     E = x0.shape[0]

@@ -23,7 +23,11 @@
  *    clearance adds rho_c = (r_a + r_o + margin) / |c_a - c_o|, both checked
  *    once at the searched T, like rho_v;
  *  - the search predicate of Def. 7 uses rho_tau and rho_P only; feasibility
- *    is inclusive (rho <= 1).
+ *    is inclusive (rho <= 1);
+ *  - Alg. 1 and-s the clearance into the edge's flag after the limit checks
+ *    (ok_p <- ok_p and Clear): clearance is evaluated only for an edge that
+ *    passed them (rho_tau, rho_P, rho_v, rho_q <= 1); otherwise rho_c is
+ *    reported as NaN (not evaluated) and never sets the collision bit.
  */
 #include <math.h>
 #include <stdint.h>
@@ -388,7 +392,8 @@ static int finite_state(int n, const double* x) {
  * stops at the first feasible slot (same result: it is the first).
  * Outputs: j* (or -1), status bits, margin = the smallest |rho - 1| over the
  * slots up to j* (all slots when none) and the post-check ratios at j*,
- * rho4 = (rho_tauP(j*), rho_v, rho_q, rho_c), nslots = slots evaluated. */
+ * rho4 = (rho_tauP(j*), rho_v, rho_q, rho_c), nslots = slots evaluated;
+ * rho_c is NaN when rho_v or rho_q already fails (not evaluated). */
 static void edge_one(const oarm* A, const double* x0, const double* x1, int NT,
                      const double* grid, int S, int jmax, const double* obs, int n_obs,
                      double margin_c, int scan, int16_t* out_j, uint16_t* out_st,
@@ -428,7 +433,10 @@ static void edge_one(const oarm* A, const double* x0, const double* x1, int NT,
     double T = grid[jstar];
     double rv = oracle_rho_v(A, x0, x1, T);
     double rq = oracle_rho_q(A, x0, x1, T);
-    double rc = oracle_rho_c(A, x0, x1, T, S, obs, n_obs, margin_c);
+    /* Clear is and-ed after the limit checks (Alg. 1): evaluated only when
+     * they pass; fmin below ignores the NaN of an unevaluated clearance */
+    double rc = (rv <= 1.0 && rq <= 1.0) ? oracle_rho_c(A, x0, x1, T, S, obs, n_obs, margin_c)
+                                         : NAN;
     rho4[1] = rv;
     rho4[2] = rq;
     rho4[3] = rc;
@@ -525,7 +533,8 @@ void oracle_edge_nary(const oarm* A, int E, const double* x0, const double* x1, 
 
 /* Fixed-duration check of one edge (goal candidates, Alg. 1 fixed-T branch;
  * also the full-resolution recheck of a sent plan, Sec. IV-E).
- * rho5 = (rho_tau, rho_P, rho_v, rho_q, rho_c); T <= 0 is infeasible. */
+ * rho5 = (rho_tau, rho_P, rho_v, rho_q, rho_c); T <= 0 is infeasible; rho_c is
+ * NaN unless rho_tau, rho_P, rho_v and rho_q all pass. */
 void oracle_edge_check(const oarm* A, int E, const double* x0, const double* x1,
                        const double* T, int S, const double* obs, int n_obs, double margin_c,
                        uint16_t* out_st, double* out_rho /*[E][5]*/, double* out_tau /*[E][S][n]*/) {
@@ -549,7 +558,9 @@ void oracle_edge_check(const oarm* A, int E, const double* x0, const double* x1,
     oracle_slot_rho(A, a, b, T[e], S, &r5[0], &r5[1], tau);
     r5[2] = oracle_rho_v(A, a, b, T[e]);
     r5[3] = oracle_rho_q(A, a, b, T[e]);
-    r5[4] = oracle_rho_c(A, a, b, T[e], S, obs, n_obs, margin_c);
+    /* clearance only for an edge that passed every limit check (Alg. 1) */
+    const int lim_ok = r5[0] <= 1.0 && r5[1] <= 1.0 && r5[2] <= 1.0 && r5[3] <= 1.0;
+    r5[4] = lim_ok ? oracle_rho_c(A, a, b, T[e], S, obs, n_obs, margin_c) : NAN;
     uint16_t st = 0;
     if (r5[0] > 1.0 || r5[1] > 1.0) st |= S_NONE;
     if (r5[2] > 1.0) st |= S_VEL;

@@ -222,15 +222,22 @@ __device__ void clearance(const ArmConst<R>& A, const EdgeState<R>& E, R T, int 
   __builtin_amdgcn_wave_barrier();
 }
 
-// Post-checks at duration T: (rho_v, rho_q, rho_c) in every lane (rho_c = 0
-// without obstacles).  tab: LDS for the FP32 clearance (nsph * n_obs floats).
+// Post-checks at duration T: (rho_v, rho_q, rho_c) in every lane.  Alg. 1
+// and-s the clearance into the edge's flag after the limit checks, so rho_c
+// is evaluated only when rho_v and rho_q are at most `pass` (1 in FP64;
+// 1 + BAND in FP32, where a ratio in the band is decided later in FP64) and
+// is NaN (not evaluated) otherwise; 0 without obstacles.  tab: LDS for the
+// FP32 clearance (nsph * n_obs floats).
 template <typename R, int PAT>
 __device__ void post_checks(const ArmConst<R>& A, const EdgeState<R>& E, R T, int S,
                             const float* __restrict__ obs, int n_obs, float margin_c,
-                            GeoLDS<R>* geo, float* tab, R& rv, R& rq, R& rc) {
+                            GeoLDS<R>* geo, float* tab, R pass, R& rv, R& rq, R& rc) {
   joint_checks<R>(A, E, T, rv, rq);
-  rc = R(0);
-  if (n_obs > 0) clearance<R, PAT>(A, E, T, S, obs, n_obs, margin_c, geo, tab, rc);
+  rc = R(NAN);
+  if (rv <= pass && rq <= pass) {
+    rc = R(0);
+    if (n_obs > 0) clearance<R, PAT>(A, E, T, S, obs, n_obs, margin_c, geo, tab, rc);
+  }
 }
 
 __device__ __forceinline__ bool near_one(float r) { return fabsf(r - 1.f) <= BAND; }
@@ -637,7 +644,8 @@ __device__ void search_edge(const EdgeArgs& a, int64_t e, int64_t eq, const ArmC
     const int js = pass == 0 ? jn : jstar;
     if (js < 0) break;
     float pv, pq, pc;
-    post_checks<float, PAT>(A, ES, Tg[js], S, a.obs, a.n_obs, a.margin_c, geo, tab, pv, pq, pc);
+    post_checks<float, PAT>(A, ES, Tg[js], S, a.obs, a.n_obs, a.margin_c, geo, tab, 1.f + BAND,
+                            pv, pq, pc);
     if (pass == 0) {
       v1 = pv; q1 = pq; c1 = pc;
     } else {
@@ -768,9 +776,8 @@ __device__ void recheck_edge(const EdgeArgs& a, int64_t e, const QEntry& q,
     rq = q.post[pick + 1];
     rc = q.post[pick + 2];
   }
-  // post-check ratios within the band of 1 (all, after the FP64 walk) in FP64
+  // limit ratios within the band of 1 (all, after the FP64 walk) in FP64
   const bool nv = exact || near_one((float)rv), nq = exact || near_one((float)rq);
-  const bool nc = a.n_obs > 0 && (exact || near_one((float)rc));
   const double T = (double)Tg[jstar];
   if (nv || nq) {
     double dv, dq;
@@ -778,7 +785,12 @@ __device__ void recheck_edge(const EdgeArgs& a, int64_t e, const QEntry& q,
     if (nv) rv = dv;
     if (nq) rq = dq;
   }
-  if (nc) clearance<double, PAT>(D, ED, T, S, a.obs, a.n_obs, a.margin_c, geo, nullptr, rc);
+  // clearance only for an edge that passes the limit checks (Alg. 1); in
+  // FP64 when its FP32 value is in the band or missing, or after the walk
+  if (rv > 1.0 || rq > 1.0) rc = NAN;
+  else if (a.n_obs == 0) rc = 0.0;
+  else if (exact || isnan(rc) || near_one((float)rc))
+    clearance<double, PAT>(D, ED, T, S, a.obs, a.n_obs, a.margin_c, geo, nullptr, rc);
   m = fminf(m, (float)fmin(fabs(rv - 1.0), fmin(fabs(rq - 1.0), fabs(rc - 1.0))));
   write_out(a, e, jstar, post_status(rv, rq, rc) | FN_S_RECHECK64 | winbits, m, rho_star,
             (float)rv, (float)rq, (float)rc, work, Tg[jstar]);

@@ -109,8 +109,10 @@ __global__ __launch_bounds__(256) void edge_check_kernel(const float* __restrict
   }
   const float rt = wave_max(rt_all), rp = wave_max(rp_all);
   float rv, rq, rc;
+  // clearance only when every limit check passes (Alg. 1)
   post_checks<float, PAT>(A, ES, T, S, obs, n_obs, margin_c, &s_geo[wave],
-                          s_tab + wave * A.nsph * n_obs, rv, rq, rc);
+                          s_tab + wave * A.nsph * n_obs, rt <= 1.f && rp <= 1.f ? 1.f : -1.f,
+                          rv, rq, rc);
   if (lane == 0) {
     int s2 = post_status(rv, rq, rc);
     if (rt > 1.f || rp > 1.f) s2 |= FN_S_NONE;

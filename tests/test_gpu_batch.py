@@ -79,8 +79,8 @@ def expected_round(arm, wl):
     gst = np.where(g_none, O.S_NONE, gst)  # an infeasible slot ends the check
     j = np.where(kind == 1, np.where(g_none, -1, 0), free["j"]).astype(np.int64)
     st = np.where(kind == 1, gst, free["status"]).astype(np.int64)
-    strict = np.where(kind == 1, np.all(np.abs(goal["rho"] - 1) > 1e-3, axis=1),
-                      free["margin"] > 1e-3)
+    g_far = (np.abs(goal["rho"] - 1) > 1e-3) | np.isnan(goal["rho"])  # NaN: not evaluated
+    strict = np.where(kind == 1, np.all(g_far, axis=1), free["margin"] > 1e-3)
     T = np.where(kind == 1, Tg, grid32[np.maximum(free["j"], 0)]).astype(np.float32)
     rv = np.where(kind == 1, goal["rho"][:, 2], free["rho"][:, 1])
     return dict(idx=idx, j=j, st=st, strict=strict, T=T, rv=rv, t_par=t_par)

@@ -126,7 +126,8 @@ def test_dense_equals_scan_tiny_workload():
     a = O.edge_time(A, x0, x1, wl["grid"], sh.samples, scan=0)
     b = O.edge_time(A, x0, x1, wl["grid"], sh.samples, scan=1)
     for key in ("j", "status", "margin", "rho"):
-        assert np.array_equal(a[key], b[key]), key
+        # rho_c is NaN where the limit checks fail (the clearance is not evaluated)
+        assert np.array_equal(a[key], b[key], equal_nan=key == "rho"), key
     assert b["nslots"].sum() <= a["nslots"].sum()
     # first-feasible definition against the dense rho table
     dense = O.edge_dense(A, x0, x1, wl["grid"], sh.samples).max(axis=2)
@@ -187,7 +188,11 @@ def test_edge_check_matches_slot_and_post_checks():
         assert r["rho"][e, 0] == rt and r["rho"][e, 1] == rp
         assert np.array_equal(r["tau"][e], tau)
         assert r["rho"][e, 2] == O.rho_v(A, x0[e], x1[e], T[e])
-        assert r["rho"][e, 4] == O.rho_c(A, x0[e], x1[e], T[e], sh.samples, wl["obs"])
+        # clearance only after every limit check passed (Alg. 1), else NaN
+        if np.all(r["rho"][e, :4] <= 1.0):
+            assert r["rho"][e, 4] == O.rho_c(A, x0[e], x1[e], T[e], sh.samples, wl["obs"])
+        else:
+            assert np.isnan(r["rho"][e, 4]) and not r["status"][e] & O.S_COLL
         # the stored torques are the samples of Eq. (4) along the cubic
         u = 7 / (sh.samples - 1)
         s, sd, sdd = O.cubic(x0[e], x1[e], T[e], u * T[e])
