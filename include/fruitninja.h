@@ -333,12 +333,19 @@ int surrogate_infer(fn_ctx* ctx, const fn_mlp* mlp, const float* X, int64_t N, c
 /* ------------------------------------------------------------------ */
 /* kNN: the scan is split into node chunks until about knn_target_waves
  * wavefronts run (chunks of at least knn_min_chunk nodes).  0 keeps the
- * default (4096 wavefronts, 512 nodes).  Applies to later plan_knn calls
+ * default (4096 wavefronts, 512 nodes).  knn_form: 1 = every wavefront
+ * loads its own node rows; 2 = the 4 wavefronts of a workgroup share
+ * 256-node tiles in LDS (one global load per node instead of four: the
+ * better form once the tree outgrows the L2); 0 = chosen by tree size
+ * (tiles above FN_KNN_TILE_NODES nodes).  Applies to later plan_knn calls
  * and fn_batch_prepare.  Errors: FN_E_ARG when knn_target_waves is outside
- * [0, 16384] or knn_min_chunk is negative or not a multiple of 64. */
+ * [0, 16384], knn_min_chunk is negative or not a multiple of 64, or
+ * knn_form is not 0, 1 or 2. */
+#define FN_KNN_TILE_NODES 65536
 typedef struct {
   int32_t knn_target_waves;
   int32_t knn_min_chunk;
+  int32_t knn_form;
 } fn_tuning;
 int fn_set_tuning(fn_ctx* ctx, const fn_tuning* t /*host*/);
 

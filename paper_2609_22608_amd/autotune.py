@@ -27,6 +27,8 @@ from . import fn
 # (target wavefronts, minimum chunk of nodes per wavefront)
 KNN_CANDIDATES = ((1024, 256), (2048, 256), (2048, 512), (3072, 1024), (4096, 512),
                   (4096, 1024), (6144, 1024), (8192, 512), (8192, 1024), (16384, 1024))
+# kNN scan forms: 1 = per-wavefront node loads, 2 = workgroup node tiles in LDS
+KNN_FORMS = (1, 2)
 
 
 @dataclass
@@ -35,10 +37,11 @@ class Choice:
     knn_min_chunk: int
     mode: int
     ms: float
+    knn_form: int = 0
 
     def as_dict(self):
         return dict(knn_target_waves=self.knn_target_waves, knn_min_chunk=self.knn_min_chunk,
-                    mode=self.mode, ms=self.ms)
+                    knn_form=self.knn_form, mode=self.mode, ms=self.ms)
 
 
 class Cache:
@@ -97,20 +100,21 @@ def tune_knn(ctx: fn.Context, tree, ld, n_nodes, cand, k, reps=5, cache: Cache |
     key = f"knn|n{n_nodes}|B{B}|k{k}|{_device_tag()}"
     hit = cache.get(key) if cache else None
     if hit is not None:
-        ctx.set_tuning(hit.knn_target_waves, hit.knn_min_chunk)
+        ctx.set_tuning(hit.knn_target_waves, hit.knn_min_chunk, hit.knn_form)
         return hit, {}
     idx = torch.empty((B, k), dtype=torch.int32, device=cand.device)
     times = {}
-    for tw, mc in candidates:
-        ctx.set_tuning(tw, mc)
-        times[(tw, mc)] = _time(lambda: ctx.plan_knn(tree, ld, n_nodes, cand, k, out_idx=idx,
-                                                     want_d2=False), reps)
-    (tw, mc), ms = min(times.items(), key=lambda kv: kv[1])
-    ch = Choice(tw, mc, -1, ms)
-    ctx.set_tuning(tw, mc)
+    for form in KNN_FORMS:
+        for tw, mc in candidates:
+            ctx.set_tuning(tw, mc, form)
+            times[(tw, mc, form)] = _time(lambda: ctx.plan_knn(tree, ld, n_nodes, cand, k,
+                                                               out_idx=idx, want_d2=False), reps)
+    (tw, mc, form), ms = min(times.items(), key=lambda kv: kv[1])
+    ch = Choice(tw, mc, -1, ms, form)
+    ctx.set_tuning(tw, mc, form)
     if cache:
         cache.put(key, ch)
-    return ch, {f"{a}/{b}": v for (a, b), v in times.items()}
+    return ch, {f"{a}/{b}/{f}": v for (a, b, f), v in times.items()}
 
 
 def tune_batch(bt: fn.Batch, reps=3, cache: Cache | None = None, candidates=KNN_CANDIDATES,
@@ -123,24 +127,25 @@ def tune_batch(bt: fn.Batch, reps=3, cache: Cache | None = None, candidates=KNN_
     key = f"batch|{sig}|k{bt.k}|nt{bt.grid.shape[0]}|S{bt.samples}|{_device_tag()}"
     hit = cache.get(key) if cache else None
     if hit is not None:
-        bt.ctx.set_tuning(hit.knn_target_waves, hit.knn_min_chunk)
+        bt.ctx.set_tuning(hit.knn_target_waves, hit.knn_min_chunk, hit.knn_form)
         bt.mode = hit.mode
         bt.prepare()
         return hit, {}
     times = {}
     for mode in modes:
-        for tw, mc in candidates:
-            bt.ctx.set_tuning(tw, mc)
-            bt.mode = mode
-            bt.prepare()
-            times[(tw, mc, mode)] = _time(bt.launch, reps, setup=bt.reset_trees)
-    (tw, mc, mode), ms = min(times.items(), key=lambda kv: kv[1])
-    ch = Choice(tw, mc, mode, ms)
-    bt.ctx.set_tuning(tw, mc)
+        for form in KNN_FORMS:
+            for tw, mc in candidates:
+                bt.ctx.set_tuning(tw, mc, form)
+                bt.mode = mode
+                bt.prepare()
+                times[(tw, mc, mode, form)] = _time(bt.launch, reps, setup=bt.reset_trees)
+    (tw, mc, mode, form), ms = min(times.items(), key=lambda kv: kv[1])
+    ch = Choice(tw, mc, mode, ms, form)
+    bt.ctx.set_tuning(tw, mc, form)
     bt.mode = mode
     bt.prepare()
     bt.reset_trees()
     if cache:
         cache.put(key, ch)
-    return ch, {f"{a}/{b}/{'plain' if m == fn.SEARCH_PLAIN else 'screen'}": v
-                for (a, b, m), v in times.items()}
+    return ch, {f"{a}/{b}/{'plain' if m == fn.SEARCH_PLAIN else 'screen'}/{f}": v
+                for (a, b, m, f), v in times.items()}

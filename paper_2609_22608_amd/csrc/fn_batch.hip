@@ -64,6 +64,8 @@ __device__ __forceinline__ int bsearch_off(const int64_t* __restrict__ off, int 
   return lo;
 }
 
+// Per-wavefront form: one wavefront per (problem, query group, node chunk)
+// (pair offsets per problem in pair_off).
 template <int K1>
 __global__ __launch_bounds__(256) void batch_knn_scan(const KnnProb* __restrict__ P, int n,
                                                       const int64_t* __restrict__ pair_off,
@@ -81,6 +83,30 @@ __global__ __launch_bounds__(256) void batch_knn_scan(const KnnProb* __restrict_
   knn_scan_item<K1, KNN_QG>(q.tree, q.ld, *q.n_nodes, q.qs, q.B, grp, ch, q.n_split, q.chunk,
                             part_d + q.part_off, part_i + q.part_off, part_y + q.y_off,
                             &s_buf[wave]);
+}
+
+// Tiled form: one workgroup per (problem, node chunk, 4 query groups), its
+// 4 wavefronts sharing the chunk's node tiles in LDS (workgroup offsets per
+// problem in blk_off).
+template <int K1>
+__global__ __launch_bounds__(256) void batch_knn_scan_tiled(const KnnProb* __restrict__ P, int n,
+                                                      const int64_t* __restrict__ blk_off,
+                                                      float* __restrict__ part_d,
+                                                      int32_t* __restrict__ part_i,
+                                                      float* __restrict__ part_y) {
+  __shared__ KnnBuf<KNN_QG> s_buf[4];
+  __shared__ float s_tile[KNN_TILE * KNN_TILE_LD];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t blk = blockIdx.x;
+  if (blk >= blk_off[n]) return;
+  const int p = bsearch_off(blk_off, n, blk);
+  const KnnProb& q = P[p];
+  const int local = (int)(blk - blk_off[p]);
+  const int n_gq = (q.n_groups + 3) / 4;
+  const int ch = local / n_gq, grp = (local - ch * n_gq) * 4 + wave;
+  knn_scan_item<K1, KNN_QG, true>(q.tree, q.ld, *q.n_nodes, q.qs, q.B, grp, ch, q.n_split,
+                                  q.chunk, part_d + q.part_off, part_i + q.part_off,
+                                  part_y + q.y_off, &s_buf[wave], grp < q.n_groups, s_tile);
 }
 
 template <int K1>
@@ -250,13 +276,14 @@ struct fn_batch {
   int K1 = 0, k = 0, n_t = 0, pattern = 0, mode = 0;
   const float* grid = nullptr;
   fn_risk risk{};
-  int64_t pairs = 0, queries = 0, edges = 0;
+  int64_t pairs = 0, queries = 0, edges = 0;  // pairs: kNN scan work items
+  bool tiled = false;                          // kNN scan form (fn_tuning)
   int max_obs = 0;  // most obstacles of a problem (clearance table LDS)
   // device tables
   KnnProb* knn = nullptr;
   InsProb* ins = nullptr;
   EdgeArgs* args = nullptr;
-  int64_t *pair_off = nullptr, *query_off = nullptr, *edge_off = nullptr;
+  int64_t *pair_off = nullptr, *query_off = nullptr, *edge_off = nullptr;  // pair_off: scan work items
   EdgeArgs a0{};  // queue pointers for the FP64 stage
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -314,6 +341,11 @@ extern "C" int fn_batch_prepare(fn_ctx* c, const fn_problem_set* ps) {
   while (Sw < ps->samples) Sw <<= 1;
   const int target = std::min(KNN_TARGET_MAX, c->tune.knn_target_waves > 0 ? c->tune.knn_target_waves : 4096);
   const int minchunk = c->tune.knn_min_chunk > 0 ? c->tune.knn_min_chunk : 512;
+  // scan form: tuned, else node tiles once the largest tree capacity
+  // outgrows the L2
+  int64_t max_ld = 0;
+  for (int p = 0; p < n; ++p) max_ld = std::max(max_ld, ps->problems[p].ld);
+  const bool tiled = c->tune.knn_form > 0 ? c->tune.knn_form == 2 : max_ld > FN_KNN_TILE_NODES;
   for (int p = 0; p < n; ++p) {
     const fn_problem& q = ps->problems[p];
     if (!q.tree || !q.n_nodes || !q.t_node || !q.parent || !q.nu || !q.cand || !q.kind || !q.t_req ||
@@ -334,7 +366,8 @@ extern "C" int fn_batch_prepare(fn_ctx* c, const fn_problem_set* ps) {
     kp[p] = KnnProb{q.tree, q.ld, q.n_nodes, q.cand, q.B, groups, split, chunk, part, ys, q.nbr};
     part += (int64_t)q.B * split * K1;
     ys += (int64_t)q.B * split;
-    po[p + 1] = po[p] + (int64_t)groups * split;
+    // scan work items: wavefronts (per-wavefront form) or workgroups (tiled)
+    po[p + 1] = po[p] + (tiled ? (int64_t)(groups + 3) / 4 : (int64_t)groups) * split;
     qo[p + 1] = qo[p] + q.B;
     eo[p + 1] = eo[p] + (int64_t)q.B * ps->k;
     sumB += q.B;
@@ -374,6 +407,7 @@ extern "C" int fn_batch_prepare(fn_ctx* c, const fn_problem_set* ps) {
   bt->pattern = c->pattern;
   bt->mode = ps->mode;
   bt->pairs = po[n];
+  bt->tiled = tiled;
   bt->queries = qo[n];
   bt->edges = eo[n];
   bt->max_obs = max_obs;
@@ -383,8 +417,12 @@ extern "C" int fn_batch_prepare(fn_ctx* c, const fn_problem_set* ps) {
 
 template <int K1>
 static void launch_batch_knn(fn_ctx* c, fn_batch* bt, hipStream_t s) {
-  hipLaunchKernelGGL(batch_knn_scan<K1>, dim3((unsigned)((bt->pairs + 3) / 4)), dim3(256), 0, s,
-                     bt->knn, bt->n, bt->pair_off, c->knn_d, c->knn_i, c->knn_y);
+  if (bt->tiled)
+    hipLaunchKernelGGL(batch_knn_scan_tiled<K1>, dim3((unsigned)bt->pairs), dim3(256), 0, s,
+                       bt->knn, bt->n, bt->pair_off, c->knn_d, c->knn_i, c->knn_y);
+  else
+    hipLaunchKernelGGL(batch_knn_scan<K1>, dim3((unsigned)((bt->pairs + 3) / 4)), dim3(256), 0, s,
+                       bt->knn, bt->n, bt->pair_off, c->knn_d, c->knn_i, c->knn_y);
   hipLaunchKernelGGL(batch_knn_merge<K1>, dim3((unsigned)bt->queries), dim3(64), 0, s, bt->knn,
                      bt->n, bt->query_off, c->knn_d, c->knn_i, c->knn_y, bt->k);
 }
@@ -469,8 +507,8 @@ extern "C" int fn_graph_launch(fn_ctx* c, void* stream) {
 extern "C" int fn_set_tuning(fn_ctx* c, const fn_tuning* t) {
   if (!c || !t) return fail(FN_E_ARG, "fn_set_tuning: NULL argument");
   if (t->knn_target_waves < 0 || t->knn_target_waves > KNN_TARGET_MAX || t->knn_min_chunk < 0 ||
-      (t->knn_min_chunk & 63) != 0)
-    return fail(FN_E_ARG, "fn_set_tuning: target waves in [0, %d], min chunk >= 0 and a multiple of 64", KNN_TARGET_MAX);
+      (t->knn_min_chunk & 63) != 0 || t->knn_form < 0 || t->knn_form > 2)
+    return fail(FN_E_ARG, "fn_set_tuning: target waves in [0, %d], min chunk >= 0 and a multiple of 64, form 0..2", KNN_TARGET_MAX);
   c->tune = *t;
   return FN_OK;
 }

@@ -118,11 +118,24 @@ struct KnnBuf {
 // equals the threshold never beats it, and every node left out has a key
 // above the chunk's final K1-th key: the list is the chunk's exact FP32
 // top K1 by (d^2, index).
-template <int K1, int QG>
+// Node tiles shared by the 4 wavefronts of a workgroup (tiled form): 256
+// nodes x (14 coordinates, |y|^2), row stride 17 so that the 64 lanes of a
+// wavefront reading 64 consecutive rows hit distinct banks.
+constexpr int KNN_TILE = 256;
+constexpr int KNN_TILE_LD = FN_STATE + 3;
+
+// TILED = false: the wavefront loads its own node rows (several query groups
+// of one workgroup may scan different chunks).  TILED = true: the workgroup's
+// wavefronts all scan chunk ch, and each tile of 256 nodes is loaded once
+// into LDS with |y|^2 (the same FMA chain as the untiled form, so the keys
+// are bit-identical) for the 4 x QG queries; `active` = false for a
+// wavefront past the last query group (it still loads and synchronises).
+template <int K1, int QG, bool TILED = false>
 __device__ void knn_scan_item(const float* __restrict__ tree, int64_t ld, int n_nodes,
                               const float* __restrict__ qs, int B, int grp, int ch, int n_split,
                               int chunk, float* __restrict__ out_d, int32_t* __restrict__ out_i,
-                              float* __restrict__ out_y2, KnnBuf<QG>* buf) {
+                              float* __restrict__ out_y2, KnnBuf<QG>* buf, bool active = true,
+                              float* tile = nullptr) {
   constexpr int CAP = WAVE - K1;  // buffer entries that fit beside the list
   const int lane = threadIdx.x & 63;
   float xm2[QG][FN_STATE], xx[QG];
@@ -171,18 +184,11 @@ __device__ void knn_scan_item(const float* __restrict__ tree, int64_t ld, int n_
   float y2max = 0.f;
   const int n0 = ch * chunk;
   const int n1 = min(n0 + chunk, n_nodes);
-  for (int nb0 = n0; nb0 < n1; nb0 += WAVE) {
+  // 64 nodes from nb0 on: coordinates and |y|^2 of this lane's node
+  auto block = [&](int nb0, const float* y, float yy) {
     const int node = nb0 + lane;
     const bool valid = node < n1;
-    const int nc = valid ? node : n1 - 1;
-    float y[FN_STATE];
-    float yy = 0.f;
-#pragma unroll
-    for (int c = 0; c < FN_STATE; ++c) {
-      y[c] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, nc * 4, c * row_bytes, 0));
-      yy = fmaf(y[c], y[c], yy);
-    }
-    y2max = fmaxf(y2max, yy);
+    y2max = valid ? fmaxf(y2max, yy) : y2max;
 #pragma unroll
     for (int q = 0; q < QG; ++q) {
       float d = yy + xx[q];
@@ -209,6 +215,49 @@ __device__ void knn_scan_item(const float* __restrict__ tree, int64_t ld, int n_
         }
       }
     }
+  };
+  if constexpr (!TILED) {
+    for (int nb0 = n0; nb0 < n1; nb0 += WAVE) {
+      const int node = nb0 + lane;
+      const int nc = node < n1 ? node : n1 - 1;
+      float y[FN_STATE];
+      float yy = 0.f;
+#pragma unroll
+      for (int c = 0; c < FN_STATE; ++c) {
+        y[c] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, nc * 4, c * row_bytes, 0));
+        yy = fmaf(y[c], y[c], yy);
+      }
+      block(nb0, y, yy);
+    }
+  } else {
+    const int tid = threadIdx.x;  // 0 .. 255
+    for (int t0 = n0; t0 < n1; t0 += KNN_TILE) {
+      {
+        const int node = t0 + tid;
+        const int nc = node < n1 ? node : n1 - 1;
+        float yy = 0.f;
+#pragma unroll
+        for (int c = 0; c < FN_STATE; ++c) {
+          const float v = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, nc * 4, c * row_bytes, 0));
+          tile[tid * KNN_TILE_LD + c] = v;
+          yy = fmaf(v, v, yy);
+        }
+        tile[tid * KNN_TILE_LD + FN_STATE] = yy;
+      }
+      __syncthreads();
+      if (active) {
+        const int nt = min(KNN_TILE, n1 - t0);
+        for (int sb = 0; sb < nt; sb += WAVE) {
+          const float* row = tile + (sb + lane) * KNN_TILE_LD;
+          float y[FN_STATE];
+#pragma unroll
+          for (int c = 0; c < FN_STATE; ++c) y[c] = row[c];
+          block(t0 + sb, y, row[FN_STATE]);
+        }
+      }
+      __syncthreads();
+    }
+    if (!active) return;
   }
 #pragma unroll
   for (int q = 0; q < QG; ++q)

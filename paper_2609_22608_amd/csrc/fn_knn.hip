@@ -24,6 +24,26 @@ __global__ __launch_bounds__(256) void knn_scan(const float* __restrict__ tree, 
                         &s_buf[wave]);
 }
 
+// Tiled form: workgroup = (chunk, 4 query groups); the 4 wavefronts share
+// each 256-node tile of the chunk through LDS (one global load per node
+// instead of four, |y|^2 once per node).
+template <int K1, int QG>
+__global__ __launch_bounds__(256) void knn_scan_tiled(const float* __restrict__ tree, int64_t ld,
+                                                      int n_nodes, const float* __restrict__ qs,
+                                                      int B, int n_groups, int n_split, int chunk,
+                                                      float* __restrict__ out_d,
+                                                      int32_t* __restrict__ out_i,
+                                                      float* __restrict__ out_y2) {
+  __shared__ KnnBuf<QG> s_buf[4];
+  __shared__ float s_tile[KNN_TILE * KNN_TILE_LD];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int n_gq = (n_groups + 3) / 4;
+  const int ch = blockIdx.x / n_gq, gq = blockIdx.x - ch * n_gq;
+  const int grp = gq * 4 + wave;
+  knn_scan_item<K1, QG, true>(tree, ld, n_nodes, qs, B, grp, ch, n_split, chunk, out_d, out_i,
+                              out_y2, &s_buf[wave], grp < n_groups, s_tile);
+}
+
 template <int K1>
 __global__ __launch_bounds__(64) void knn_merge(const float* __restrict__ tree, int64_t ld,
                                                 int n_nodes, const float* __restrict__ qs,
@@ -60,9 +80,16 @@ static void launch_knn(fn_ctx* c, const float* tree, int64_t ld, int n_nodes, co
   int chunk = (n_nodes + n_split - 1) / n_split;
   chunk = max(WAVE, (chunk + WAVE - 1) / WAVE * WAVE);
   n_split = max(1, (n_nodes + chunk - 1) / chunk);
-  const int pairs = n_groups * n_split;
-  hipLaunchKernelGGL((knn_scan<K1, KNN_QG>), dim3((pairs + 3) / 4), dim3(256), 0, s, tree, ld,
-                     n_nodes, qs, B, n_groups, n_split, chunk, c->knn_d, c->knn_i, c->knn_y);
+  const int form = c->tune.knn_form > 0 ? c->tune.knn_form : (n_nodes > FN_KNN_TILE_NODES ? 2 : 1);
+  if (form == 2) {
+    const int n_gq = (n_groups + 3) / 4;
+    hipLaunchKernelGGL((knn_scan_tiled<K1, KNN_QG>), dim3(n_gq * n_split), dim3(256), 0, s, tree,
+                       ld, n_nodes, qs, B, n_groups, n_split, chunk, c->knn_d, c->knn_i, c->knn_y);
+  } else {
+    const int pairs = n_groups * n_split;
+    hipLaunchKernelGGL((knn_scan<K1, KNN_QG>), dim3((pairs + 3) / 4), dim3(256), 0, s, tree, ld,
+                       n_nodes, qs, B, n_groups, n_split, chunk, c->knn_d, c->knn_i, c->knn_y);
+  }
   if (n_split * K1 <= 2 * WAVE)
     hipLaunchKernelGGL(knn_merge_small_kernel<K1>, dim3(B), dim3(64), 0, s, tree, ld, n_nodes, qs,
                        k, n_split, c->knn_d, c->knn_i, c->knn_y, out_idx, out_d2);

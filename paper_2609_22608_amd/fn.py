@@ -51,7 +51,8 @@ class Caps(C.Structure):
 
 
 class Tuning(C.Structure):
-    _fields_ = [("knn_target_waves", C.c_int32), ("knn_min_chunk", C.c_int32)]
+    _fields_ = [("knn_target_waves", C.c_int32), ("knn_min_chunk", C.c_int32),
+                ("knn_form", C.c_int32)]
 
 
 class Search(C.Structure):
@@ -245,8 +246,8 @@ class Context:
         _check(lib().fn_kernel_times(self.h, buf, max_n, C.byref(n)), "fn_kernel_times")
         return [buf[i] for i in range(n.value)]
 
-    def set_tuning(self, knn_target_waves=0, knn_min_chunk=0):
-        t = Tuning(int(knn_target_waves), int(knn_min_chunk))
+    def set_tuning(self, knn_target_waves=0, knn_min_chunk=0, knn_form=0):
+        t = Tuning(int(knn_target_waves), int(knn_min_chunk), int(knn_form))
         _check(lib().fn_set_tuning(self.h, C.byref(t)), "fn_set_tuning")
 
     # -- plan_knn -----------------------------------------------------------

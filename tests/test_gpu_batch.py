@@ -44,10 +44,11 @@ def small_set(n_problems=5, seed=3):
     return arm, [with_goal_parents(wl) for wl in probs]
 
 
-def build(arm, probs, capacity_extra=1024, mode=fn.SEARCH_SCREEN):
+def build(arm, probs, capacity_extra=1024, mode=fn.SEARCH_SCREEN, knn_form=0):
     sh = probs[0]["shape"]
     sumB = sum(p["shape"].batch for p in probs)
     ctx = fn.Context(arm, 70000, sumB, sh.k, max_edges=sumB * sh.k, max_problems=len(probs))
+    ctx.set_tuning(0, 0, knn_form)
     grid = fn.dev(probs[0]["grid"])
     bt = fn.Batch(ctx, grid, sh.samples, sh.k, mode=mode)
     for wl in probs:
@@ -196,4 +197,17 @@ def test_batch_plain_equals_screen():
     torch.cuda.synchronize()
     for P, Q in zip(b1.problems, b2.problems):
         for k in ("out_j", "out_node", "n_nodes"):
+            assert torch.equal(P[k], Q[k]), k
+
+
+def test_batch_knn_forms_agree():
+    """Per-wavefront node loads and workgroup node tiles give the same round."""
+    arm, probs = small_set(4, seed=13)
+    _, b1 = build(arm, probs, knn_form=1)
+    b1.launch()
+    _, b2 = build(arm, probs, knn_form=2)
+    b2.launch()
+    torch.cuda.synchronize()
+    for P, Q in zip(b1.problems, b2.problems):
+        for k in ("nbr", "out_j", "out_status", "out_node", "n_nodes"):
             assert torch.equal(P[k], Q[k]), k

@@ -28,16 +28,18 @@ def test_knn_result_is_independent_of_the_launch_mapping(iteration):
     sh, wl, ctx, tree, ld, n, cand = iteration
     ref = None
     # chunk lists per query: 48 (default), 12, 192 (general merge), 24, 96
-    # (sort-based merge over two entries per lane)
-    for tw, mc in ((0, 0), (1024, 256), (16384, 64), (2048, 4096), (8192, 512)):
-        ctx.set_tuning(tw, mc)
+    # (sort-based merge over two entries per lane); both scan forms
+    for tw, mc, form in ((0, 0, 0), (1024, 256, 1), (16384, 64, 1), (2048, 4096, 1),
+                         (8192, 512, 1), (4096, 512, 2), (1024, 256, 2), (16384, 64, 2),
+                         (8192, 512, 2)):
+        ctx.set_tuning(tw, mc, form)
         idx, d2 = ctx.plan_knn(tree, ld, n, cand, sh.k)
         torch.cuda.synchronize()
         got = (idx.cpu().numpy(), d2.cpu().numpy())
         if ref is None:
             ref = got
         else:
-            assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (tw, mc)
+            assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (tw, mc, form)
     ctx.set_tuning(0, 0)
 
 
@@ -46,7 +48,9 @@ def test_autotuner_picks_a_candidate_and_caches_it(iteration, tmp_path):
     cache = autotune.Cache(str(tmp_path / "t.json"))
     ch, times = autotune.tune_knn(ctx, tree, ld, n, cand, sh.k, reps=1, cache=cache)
     assert (ch.knn_target_waves, ch.knn_min_chunk) in autotune.KNN_CANDIDATES
-    assert len(times) == len(autotune.KNN_CANDIDATES) and ch.ms == min(times.values())
+    assert ch.knn_form in autotune.KNN_FORMS
+    assert len(times) == len(autotune.KNN_CANDIDATES) * len(autotune.KNN_FORMS)
+    assert ch.ms == min(times.values())
     ch2, times2 = autotune.tune_knn(ctx, tree, ld, n, cand, sh.k, cache=cache)
     assert ch2 == ch and times2 == {}  # from the cache
     ctx.set_tuning(0, 0)
@@ -75,6 +79,8 @@ def test_tuning_and_problem_set_are_validated(iteration):
         ctx.set_tuning(4096, 100)
     with pytest.raises(fn.FnError, match="target waves"):
         ctx.set_tuning(1 << 20, 512)
+    with pytest.raises(fn.FnError, match="form"):
+        ctx.set_tuning(4096, 512, 3)
     with pytest.raises(fn.FnError, match="max_problems = 0"):
         fn.Batch(ctx, fn.dev(wl["grid"]), sh.samples, sh.k).prepare()
     arm, probs = W.make_problem_set(2, 5, nodes=(300, 600), batch=(40, 60))
