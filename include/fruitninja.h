@@ -334,13 +334,17 @@ int surrogate_infer(fn_ctx* ctx, const fn_mlp* mlp, const float* X, int64_t N, c
 /* kNN: the scan is split into node chunks until about knn_target_waves
  * wavefronts run (chunks of at least knn_min_chunk nodes).  0 keeps the
  * default (4096 wavefronts, 512 nodes).  knn_form: 1 = every wavefront
- * loads its own node rows; 2 = the 4 wavefronts of a workgroup share
- * 256-node tiles in LDS (one global load per node instead of four: the
- * better form once the tree outgrows the L2); 0 = chosen by tree size
- * (tiles above FN_KNN_TILE_NODES nodes).  Applies to later plan_knn calls
- * and fn_batch_prepare.  Errors: FN_E_ARG when knn_target_waves is outside
+ * loads its own node rows (4 queries per wavefront, keys by FP32 FMAs);
+ * 2 = the 4 wavefronts of a workgroup share 256-node tiles in LDS (one
+ * global load per node instead of four); 3 = matrix cores: 16 queries per
+ * wavefront, each 16 x 16 block of keys by four v_mfma_f32_16x16x4_f32 over
+ * the augmented vectors (-2x, |x|^2, 1) . (y, 1, |y|^2) (at most 4096
+ * wavefronts, whatever knn_target_waves says); 0 = chosen by tree size
+ * (tiles above FN_KNN_TILE_NODES nodes).  Every form returns the same
+ * neighbours and distances.  Applies to later plan_knn calls and
+ * fn_batch_prepare.  Errors: FN_E_ARG when knn_target_waves is outside
  * [0, 16384], knn_min_chunk is negative or not a multiple of 64, or
- * knn_form is not 0, 1 or 2. */
+ * knn_form is not 0, 1, 2 or 3. */
 #define FN_KNN_TILE_NODES 65536
 typedef struct {
   int32_t knn_target_waves;

@@ -27,8 +27,22 @@ from . import fn
 # (target wavefronts, minimum chunk of nodes per wavefront)
 KNN_CANDIDATES = ((1024, 256), (2048, 256), (2048, 512), (3072, 1024), (4096, 512),
                   (4096, 1024), (6144, 1024), (8192, 512), (8192, 1024), (16384, 1024))
-# kNN scan forms: 1 = per-wavefront node loads, 2 = workgroup node tiles in LDS
-KNN_FORMS = (1, 2)
+# the matrix-core form runs 16 queries per wavefront (and at most 4096
+# wavefronts): fewer wavefronts for the same split
+KNN_CANDIDATES_MFMA = ((512, 512), (1024, 512), (2048, 512), (2048, 1024), (4096, 512),
+                       (4096, 1024))
+# kNN scan forms: 1 = VALU keys, per-wavefront node loads; 2 = VALU keys,
+# workgroup node tiles in LDS; 3 = matrix-core keys
+KNN_FORMS = (1, 2, 3)
+
+
+def knn_grid(candidates=None):
+    """(target wavefronts, minimum chunk, form) triples the tuner times."""
+    for form in KNN_FORMS:
+        cl = candidates if candidates is not None else (
+            KNN_CANDIDATES_MFMA if form == 3 else KNN_CANDIDATES)
+        for tw, mc in cl:
+            yield tw, mc, form
 
 
 @dataclass
@@ -94,7 +108,7 @@ def _time(run, reps, setup=None):
 
 
 def tune_knn(ctx: fn.Context, tree, ld, n_nodes, cand, k, reps=5, cache: Cache | None = None,
-             candidates=KNN_CANDIDATES):
+             candidates=None):
     """Fastest kNN mapping for one (tree, batch, k); leaves it set on ctx."""
     B = cand.shape[0]
     key = f"knn|n{n_nodes}|B{B}|k{k}|{_device_tag()}"
@@ -104,11 +118,10 @@ def tune_knn(ctx: fn.Context, tree, ld, n_nodes, cand, k, reps=5, cache: Cache |
         return hit, {}
     idx = torch.empty((B, k), dtype=torch.int32, device=cand.device)
     times = {}
-    for form in KNN_FORMS:
-        for tw, mc in candidates:
-            ctx.set_tuning(tw, mc, form)
-            times[(tw, mc, form)] = _time(lambda: ctx.plan_knn(tree, ld, n_nodes, cand, k,
-                                                               out_idx=idx, want_d2=False), reps)
+    for tw, mc, form in knn_grid(candidates):
+        ctx.set_tuning(tw, mc, form)
+        times[(tw, mc, form)] = _time(lambda: ctx.plan_knn(tree, ld, n_nodes, cand, k,
+                                                           out_idx=idx, want_d2=False), reps)
     (tw, mc, form), ms = min(times.items(), key=lambda kv: kv[1])
     ch = Choice(tw, mc, -1, ms, form)
     ctx.set_tuning(tw, mc, form)
@@ -117,7 +130,7 @@ def tune_knn(ctx: fn.Context, tree, ld, n_nodes, cand, k, reps=5, cache: Cache |
     return ch, {f"{a}/{b}/{f}": v for (a, b, f), v in times.items()}
 
 
-def tune_batch(bt: fn.Batch, reps=3, cache: Cache | None = None, candidates=KNN_CANDIDATES,
+def tune_batch(bt: fn.Batch, reps=3, cache: Cache | None = None, candidates=None,
                modes=(fn.SEARCH_PLAIN, fn.SEARCH_SCREEN)):
     """Fastest (kNN mapping, search form) for a prepared batched round.
 
@@ -133,12 +146,11 @@ def tune_batch(bt: fn.Batch, reps=3, cache: Cache | None = None, candidates=KNN_
         return hit, {}
     times = {}
     for mode in modes:
-        for form in KNN_FORMS:
-            for tw, mc in candidates:
-                bt.ctx.set_tuning(tw, mc, form)
-                bt.mode = mode
-                bt.prepare()
-                times[(tw, mc, mode, form)] = _time(bt.launch, reps, setup=bt.reset_trees)
+        for tw, mc, form in knn_grid(candidates):
+            bt.ctx.set_tuning(tw, mc, form)
+            bt.mode = mode
+            bt.prepare()
+            times[(tw, mc, mode, form)] = _time(bt.launch, reps, setup=bt.reset_trees)
     (tw, mc, mode, form), ms = min(times.items(), key=lambda kv: kv[1])
     ch = Choice(tw, mc, mode, ms, form)
     bt.ctx.set_tuning(tw, mc, form)

@@ -109,6 +109,25 @@ __global__ __launch_bounds__(256) void batch_knn_scan_tiled(const KnnProb* __res
                                   part_y + q.y_off, &s_buf[wave], grp < q.n_groups, s_tile);
 }
 
+// Matrix-core form: one wavefront per (problem, 16-query group, node chunk).
+template <int K1>
+__global__ __launch_bounds__(256) void batch_knn_scan_mfma(const KnnProb* __restrict__ P, int n,
+                                                           const int64_t* __restrict__ pair_off,
+                                                           float* __restrict__ part_d,
+                                                           int32_t* __restrict__ part_i,
+                                                           float* __restrict__ part_y) {
+  __shared__ KnnBuf<KNN_QB> s_buf[4];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t pair = (int64_t)blockIdx.x * 4 + wave;
+  if (pair >= pair_off[n]) return;
+  const int p = bsearch_off(pair_off, n, pair);
+  const KnnProb& q = P[p];
+  const int local = (int)(pair - pair_off[p]);
+  const int ch = local / q.n_groups, grp = local - ch * q.n_groups;
+  knn_scan_mfma_item<K1>(q.tree, q.ld, *q.n_nodes, q.qs, q.B, grp, ch, q.n_split, q.chunk,
+                         part_d + q.part_off, part_i + q.part_off, part_y + q.y_off, &s_buf[wave]);
+}
+
 template <int K1>
 __global__ __launch_bounds__(64) void batch_knn_merge(const KnnProb* __restrict__ P, int n,
                                                       const int64_t* __restrict__ query_off,
@@ -277,7 +296,7 @@ struct fn_batch {
   const float* grid = nullptr;
   fn_risk risk{};
   int64_t pairs = 0, queries = 0, edges = 0;  // pairs: kNN scan work items
-  bool tiled = false;                          // kNN scan form (fn_tuning)
+  int form = 1;                                // kNN scan form (fn_tuning)
   int max_obs = 0;  // most obstacles of a problem (clearance table LDS)
   // device tables
   KnnProb* knn = nullptr;
@@ -339,13 +358,15 @@ extern "C" int fn_batch_prepare(fn_ctx* c, const fn_problem_set* ps) {
   po[0] = qo[0] = eo[0] = 0;
   int Sw = 1;
   while (Sw < ps->samples) Sw <<= 1;
-  const int target = std::min(KNN_TARGET_MAX, c->tune.knn_target_waves > 0 ? c->tune.knn_target_waves : 4096);
+  int target = std::min(KNN_TARGET_MAX, c->tune.knn_target_waves > 0 ? c->tune.knn_target_waves : 4096);
   const int minchunk = c->tune.knn_min_chunk > 0 ? c->tune.knn_min_chunk : 512;
   // scan form: tuned, else node tiles once the largest tree capacity
   // outgrows the L2
   int64_t max_ld = 0;
   for (int p = 0; p < n; ++p) max_ld = std::max(max_ld, ps->problems[p].ld);
-  const bool tiled = c->tune.knn_form > 0 ? c->tune.knn_form == 2 : max_ld > FN_KNN_TILE_NODES;
+  const int form = c->tune.knn_form > 0 ? c->tune.knn_form : (max_ld > FN_KNN_TILE_NODES ? 2 : 1);
+  const int qpw = form == 3 ? KNN_QB : KNN_QG;  // queries per scan wavefront
+  if (form == 3) target = std::min(target, KNN_TARGET_MAX * KNN_QG / KNN_QB);
   for (int p = 0; p < n; ++p) {
     const fn_problem& q = ps->problems[p];
     if (!q.tree || !q.n_nodes || !q.t_node || !q.parent || !q.nu || !q.cand || !q.kind || !q.t_req ||
@@ -357,7 +378,7 @@ extern "C" int fn_batch_prepare(fn_ctx* c, const fn_problem_set* ps) {
     if (q.n_obs < 0 || q.n_obs > FN_MAX_OBS || (q.n_obs > 0 && !q.obs))
       return fail(FN_E_SHAPE, "fn_batch_prepare: problem %d: %d obstacles", p, q.n_obs);
     // kNN geometry from the node capacity (node counts change on the device)
-    const int groups = (q.B + KNN_QG - 1) / KNN_QG;
+    const int groups = (q.B + qpw - 1) / qpw;
     int split = (int)((target / n + groups - 1) / groups);
     split = std::max(1, std::min(split, std::min(KNN_MAX_SPLIT, (int)(q.ld / minchunk))));
     int chunk = (int)((q.ld + split - 1) / split);
@@ -366,8 +387,9 @@ extern "C" int fn_batch_prepare(fn_ctx* c, const fn_problem_set* ps) {
     kp[p] = KnnProb{q.tree, q.ld, q.n_nodes, q.cand, q.B, groups, split, chunk, part, ys, q.nbr};
     part += (int64_t)q.B * split * K1;
     ys += (int64_t)q.B * split;
-    // scan work items: wavefronts (per-wavefront form) or workgroups (tiled)
-    po[p + 1] = po[p] + (tiled ? (int64_t)(groups + 3) / 4 : (int64_t)groups) * split;
+    // scan work items: wavefronts (per-wavefront and matrix-core forms) or
+    // workgroups (tiled)
+    po[p + 1] = po[p] + (form == 2 ? (int64_t)(groups + 3) / 4 : (int64_t)groups) * split;
     qo[p + 1] = qo[p] + q.B;
     eo[p + 1] = eo[p] + (int64_t)q.B * ps->k;
     sumB += q.B;
@@ -407,7 +429,7 @@ extern "C" int fn_batch_prepare(fn_ctx* c, const fn_problem_set* ps) {
   bt->pattern = c->pattern;
   bt->mode = ps->mode;
   bt->pairs = po[n];
-  bt->tiled = tiled;
+  bt->form = form;
   bt->queries = qo[n];
   bt->edges = eo[n];
   bt->max_obs = max_obs;
@@ -417,9 +439,12 @@ extern "C" int fn_batch_prepare(fn_ctx* c, const fn_problem_set* ps) {
 
 template <int K1>
 static void launch_batch_knn(fn_ctx* c, fn_batch* bt, hipStream_t s) {
-  if (bt->tiled)
+  if (bt->form == 2)
     hipLaunchKernelGGL(batch_knn_scan_tiled<K1>, dim3((unsigned)bt->pairs), dim3(256), 0, s,
                        bt->knn, bt->n, bt->pair_off, c->knn_d, c->knn_i, c->knn_y);
+  else if (bt->form == 3)
+    hipLaunchKernelGGL(batch_knn_scan_mfma<K1>, dim3((unsigned)((bt->pairs + 3) / 4)), dim3(256), 0,
+                       s, bt->knn, bt->n, bt->pair_off, c->knn_d, c->knn_i, c->knn_y);
   else
     hipLaunchKernelGGL(batch_knn_scan<K1>, dim3((unsigned)((bt->pairs + 3) / 4)), dim3(256), 0, s,
                        bt->knn, bt->n, bt->pair_off, c->knn_d, c->knn_i, c->knn_y);
@@ -507,8 +532,8 @@ extern "C" int fn_graph_launch(fn_ctx* c, void* stream) {
 extern "C" int fn_set_tuning(fn_ctx* c, const fn_tuning* t) {
   if (!c || !t) return fail(FN_E_ARG, "fn_set_tuning: NULL argument");
   if (t->knn_target_waves < 0 || t->knn_target_waves > KNN_TARGET_MAX || t->knn_min_chunk < 0 ||
-      (t->knn_min_chunk & 63) != 0 || t->knn_form < 0 || t->knn_form > 2)
-    return fail(FN_E_ARG, "fn_set_tuning: target waves in [0, %d], min chunk >= 0 and a multiple of 64, form 0..2", KNN_TARGET_MAX);
+      (t->knn_min_chunk & 63) != 0 || t->knn_form < 0 || t->knn_form > 3)
+    return fail(FN_E_ARG, "fn_set_tuning: target waves in [0, %d], min chunk >= 0 and a multiple of 64, form 0..3", KNN_TARGET_MAX);
   c->tune = *t;
   return FN_OK;
 }

@@ -277,6 +277,198 @@ __device__ void knn_scan_item(const float* __restrict__ tree, int64_t ld, int n_
   }
 }
 
+// Matrix-core form: one wavefront per (16 queries, node chunk).  With
+// augmented vectors a = (-2 x, |x|^2, 1) and b = (y, 1, |y|^2) (16
+// components) the screening key |x|^2 + |y|^2 - 2 x.y is the dot product
+// a.b, so a 16 x 16 block of keys (16 queries x 16 nodes) is four
+// v_mfma_f32_16x16x4_f32 steps over K = 16.  Operand layout: lane l = 16 r +
+// c holds A[c][4 s + r] and B[4 s + r][c] in step s and receives D[4 r + i][c],
+// i = 0..3: the keys of queries 4 r + i against node c.  |y|^2 is summed from
+// the four lanes that hold a node's coordinates (lane exchanges).  Any order of the 16 products and sums stays within the key error
+// bound the merge assumes (16 roundings of terms bounded by (|x| + |y|)^2).
+// Selection as in the VALU form, per query: a node below the query's
+// threshold is appended to its LDS buffer (lanes of a row rank their
+// candidates within the row); a query whose buffer would overflow is merged
+// first (the 64 entries sorted over the wavefront, K1 kept, threshold
+// renewed).  Nodes arrive in increasing index, so the strict test keeps the
+// exact FP32 top K1 by (d^2, index), and the chunk lists match the VALU form's
+// key for key whenever the FP32 keys agree; the band the merge re-ranks in
+// FP64 covers any difference.
+constexpr int KNN_QB = 16;
+typedef float knn_v4f __attribute__((ext_vector_type(4)));
+
+// Sorts the first n entries of an LDS buffer of 64 (d^2, index) pairs over
+// the wavefront, writes the K1 smallest back in order and returns the K1-th
+// key (+inf when fewer than K1 entries).
+template <int K1>
+__device__ __noinline__ float knn_sort_buffer(float* bd, int32_t* bi, int n) {
+  const int lane = threadIdx.x & 63;
+  __builtin_amdgcn_wave_barrier();
+  float d = lane < n ? bd[lane] : INFINITY;
+  int idx = lane < n ? bi[lane] : -1;
+  wave_sort64(d, idx);
+  if (lane < K1) {
+    bd[lane] = d;
+    bi[lane] = idx;
+  }
+  __builtin_amdgcn_wave_barrier();
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, d), K1 - 1));
+}
+
+
+template <int K1>
+__device__ __forceinline__ void knn_scan_mfma_item(const float* __restrict__ tree, int64_t ld, int n_nodes,
+                                   const float* __restrict__ qs, int B, int grp, int ch,
+                                   int n_split, int chunk, float* __restrict__ out_d,
+                                   int32_t* __restrict__ out_i, float* __restrict__ out_y2,
+                                   KnnBuf<KNN_QB>* buf) {
+  static_assert(K1 + 16 <= WAVE, "a merge must leave room for one 16-node block");
+  const int lane = threadIdx.x & 63;
+  const int col = lane & 15, row = lane >> 4;
+  // A operand: query grp * 16 + col (padding queries repeat the last one)
+  float a[4];
+  {
+    const float* x = qs + (size_t)min(grp * KNN_QB + col, B - 1) * FN_STATE;
+    float xx = 0.f;
+#pragma unroll
+    for (int c = 0; c < FN_STATE; ++c) xx = fmaf(x[c], x[c], xx);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int k = 4 * s + row;
+      a[s] = k < FN_STATE ? -2.f * x[k] : (k == FN_STATE ? xx : 1.f);
+    }
+  }
+  // per lane, for its queries 4 row + i: threshold, buffer count, and
+  // whether the buffer holds entries not yet merged
+  float thv[4];
+  int nbv[4];
+  bool dirty[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    thv[i] = INFINITY;
+    nbv[i] = 0;
+    dirty[i] = true;  // never merged: the final merge sorts (or pads) the list
+  }
+  // query 4 g + i: buffer sorted over the wavefront (one out-of-line copy
+  // of the sort for all call sites), K1 kept, threshold and counts renewed
+  // in row g
+  auto merge = [&](int g, int i) {
+    const int q = 4 * g + i;
+    const int nbq = __builtin_amdgcn_readlane(nbv[i], 16 * g);
+    const float th = knn_sort_buffer<K1>(buf->d[q], buf->i[q], nbq);
+    if (row == g) {
+      thv[i] = th;
+      nbv[i] = K1;
+      dirty[i] = false;
+    }
+  };
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)tree, (short)0, (int)(FN_STATE * ld * 4), 0x00020000);
+  const int row_bytes = (int)ld * 4;
+  // step s reads coordinate 4 s + row; step 3 of rows 2 and 3 (the |x|^2 and
+  // 1 components) reads row 13 and replaces it
+  const int voff_r = row * row_bytes, voff_r3 = min(row, 1) * row_bytes;
+  const int n0 = ch * chunk;
+  const int n1 = min(n0 + chunk, n_nodes);
+  float y2max = 0.f;
+  for (int nb0 = n0; nb0 < n1; nb0 += WAVE) {
+    float bv[4][4];
+    int node[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      node[j] = nb0 + 16 * j + col;
+      const int nc = node[j] < n1 ? node[j] : n1 - 1;
+#pragma unroll
+      for (int s = 0; s < 3; ++s)
+        bv[j][s] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                                 rs, nc * 4 + voff_r, 4 * s * row_bytes, 0));
+      bv[j][3] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                               rs, nc * 4 + voff_r3, 12 * row_bytes, 0));
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float p = bv[j][0] * bv[j][0];
+      p = fmaf(bv[j][1], bv[j][1], p);
+      p = fmaf(bv[j][2], bv[j][2], p);
+      p = row < 2 ? fmaf(bv[j][3], bv[j][3], p) : p;
+      // sum over the four rows; a lane and its partner add the same two
+      // values, so the four lanes of a node hold the same |y|^2
+      const float t = p + __builtin_bit_cast(float, lane_xor<16>(__builtin_bit_cast(int, p)));
+      const float yy = t + __builtin_bit_cast(float, lane_xor<32>(__builtin_bit_cast(int, t)));
+      const bool valid = node[j] < n1;
+      y2max = valid ? fmaxf(y2max, yy) : y2max;
+      // a node past the chunk gets |y|^2 = +inf: every key of it is +inf
+      const float y15 = valid ? yy : INFINITY;
+      bv[j][3] = row < 2 ? bv[j][3] : (row == 2 ? 1.f : y15);
+    }
+    knn_v4f acc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = knn_v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], bv[j][s], acc[j], 0, 0, 0);
+    bool any = false;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) any |= acc[j][i] < thv[i];
+    if (__ballot(any) == 0) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float d = acc[j][i];
+        uint64_t m = __ballot(d < thv[i]);
+        if (m == 0) continue;
+        uint32_t gm = (uint32_t)(m >> (16 * row)) & 0xffffu;
+        // rows whose query would overflow its buffer: merge those first
+        uint64_t over = __ballot(nbv[i] + (int)__popc(gm) > WAVE) & 0x0001000100010001ull;
+        if (over) {
+          while (over) {
+            const int g = (int)__builtin_ctzll(over) >> 4;
+            over &= over - 1;
+            merge(g, i);
+          }
+          m = __ballot(d < thv[i]);
+          gm = (uint32_t)(m >> (16 * row)) & 0xffffu;
+        }
+        if (d < thv[i]) {
+          const int slot = nbv[i] + (int)__popc(gm & ((1u << col) - 1u));
+          buf->d[4 * row + i][slot] = d;
+          buf->i[4 * row + i][slot] = node[j];
+        }
+        nbv[i] += (int)__popc(gm);
+        dirty[i] = dirty[i] || gm != 0;
+      }
+    }
+  }
+  // final merges: every query with unmerged entries (or never merged)
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    uint64_t pend = __ballot(dirty[i]) & 0x0001000100010001ull;
+    while (pend) {
+      const int g = (int)__builtin_ctzll(pend) >> 4;
+      pend &= pend - 1;
+      merge(g, i);
+    }
+  }
+  y2max = wave_max(y2max);
+  __builtin_amdgcn_wave_barrier();
+  for (int e = lane; e < KNN_QB * K1; e += WAVE) {
+    const int q = e / K1, t = e - q * K1;
+    const int b = grp * KNN_QB + q;
+    if (b < B) {
+      const size_t base = ((size_t)b * n_split + ch) * K1;
+      out_d[base + t] = buf->d[q][t];
+      out_i[base + t] = buf->i[q][t];
+    }
+  }
+  if (lane < KNN_QB && grp * KNN_QB + lane < B)
+    out_y2[(size_t)(grp * KNN_QB + lane) * n_split + ch] = y2max;
+}
+
 // FP64 squared distance, summed in the reference order with separately
 // rounded operations.
 __device__ __forceinline__ double exact_d2(const float* __restrict__ tree, int64_t ld, int node,

@@ -44,6 +44,24 @@ __global__ __launch_bounds__(256) void knn_scan_tiled(const float* __restrict__ 
                               out_y2, &s_buf[wave], grp < n_groups, s_tile);
 }
 
+// Matrix-core form: one wavefront per (16 queries, node chunk), keys by
+// v_mfma_f32_16x16x4_f32; the wavefronts of a block share a node chunk.
+template <int K1>
+__global__ __launch_bounds__(256) void knn_scan_mfma(const float* __restrict__ tree, int64_t ld,
+                                                     int n_nodes, const float* __restrict__ qs,
+                                                     int B, int n_groups, int n_split, int chunk,
+                                                     float* __restrict__ out_d,
+                                                     int32_t* __restrict__ out_i,
+                                                     float* __restrict__ out_y2) {
+  __shared__ KnnBuf<KNN_QB> s_buf[4];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int pair = blockIdx.x * 4 + wave;
+  if (pair >= n_groups * n_split) return;
+  const int ch = pair / n_groups, grp = pair - ch * n_groups;
+  knn_scan_mfma_item<K1>(tree, ld, n_nodes, qs, B, grp, ch, n_split, chunk, out_d, out_i, out_y2,
+                         &s_buf[wave]);
+}
+
 template <int K1>
 __global__ __launch_bounds__(64) void knn_merge(const float* __restrict__ tree, int64_t ld,
                                                 int n_nodes, const float* __restrict__ qs,
@@ -70,9 +88,14 @@ __global__ __launch_bounds__(64) void knn_merge_small_kernel(
 template <int K1>
 static void launch_knn(fn_ctx* c, const float* tree, int64_t ld, int n_nodes, const float* qs,
                        int B, int k, int32_t* out_idx, float* out_d2, hipStream_t s) {
-  const int n_groups = (B + KNN_QG - 1) / KNN_QG;
-  // enough wavefronts to fill the chip, chunks of at least 512 nodes
-  const int target = min(KNN_TARGET_MAX, c->tune.knn_target_waves > 0 ? c->tune.knn_target_waves : KNN_TARGET_WAVES);
+  const int form = c->tune.knn_form > 0 ? c->tune.knn_form : (n_nodes > FN_KNN_TILE_NODES ? 2 : 1);
+  const int qpw = form == 3 ? KNN_QB : KNN_QG;  // queries per scan wavefront
+  const int n_groups = (B + qpw - 1) / qpw;
+  // enough wavefronts to fill the chip, chunks of at least 512 nodes; the
+  // matrix-core form (4x the queries per wavefront) takes a quarter of the
+  // wavefront target at most, so its chunk lists fit the same scratch
+  int target = min(KNN_TARGET_MAX, c->tune.knn_target_waves > 0 ? c->tune.knn_target_waves : KNN_TARGET_WAVES);
+  if (form == 3) target = min(target, KNN_TARGET_MAX * KNN_QG / KNN_QB);
   const int minchunk = c->tune.knn_min_chunk > 0 ? c->tune.knn_min_chunk : 512;
   int n_split = (target + n_groups - 1) / n_groups;
   n_split = min(n_split, KNN_MAX_SPLIT);
@@ -80,11 +103,14 @@ static void launch_knn(fn_ctx* c, const float* tree, int64_t ld, int n_nodes, co
   int chunk = (n_nodes + n_split - 1) / n_split;
   chunk = max(WAVE, (chunk + WAVE - 1) / WAVE * WAVE);
   n_split = max(1, (n_nodes + chunk - 1) / chunk);
-  const int form = c->tune.knn_form > 0 ? c->tune.knn_form : (n_nodes > FN_KNN_TILE_NODES ? 2 : 1);
   if (form == 2) {
     const int n_gq = (n_groups + 3) / 4;
     hipLaunchKernelGGL((knn_scan_tiled<K1, KNN_QG>), dim3(n_gq * n_split), dim3(256), 0, s, tree,
                        ld, n_nodes, qs, B, n_groups, n_split, chunk, c->knn_d, c->knn_i, c->knn_y);
+  } else if (form == 3) {
+    const int pairs = n_groups * n_split;
+    hipLaunchKernelGGL((knn_scan_mfma<K1>), dim3((pairs + 3) / 4), dim3(256), 0, s, tree, ld,
+                       n_nodes, qs, B, n_groups, n_split, chunk, c->knn_d, c->knn_i, c->knn_y);
   } else {
     const int pairs = n_groups * n_split;
     hipLaunchKernelGGL((knn_scan<K1, KNN_QG>), dim3((pairs + 3) / 4), dim3(256), 0, s, tree, ld,
@@ -102,10 +128,15 @@ size_t knn_scratch_entries(int max_batch, int max_k, int max_problems) {
   // one problem: B * n_split <= QG * n_groups * ceil(TARGET / n_groups)
   // <= QG * (TARGET + n_groups); P problems of a batch, each with a share of
   // the target and its own rounding: <= QG * (TARGET + sum n_groups) and
-  // sum n_groups <= n_groups(sum B) + P
-  const size_t groups = (size_t)(max_batch + KNN_QG - 1) / KNN_QG;
+  // sum n_groups <= n_groups(sum B) + P.  The matrix-core form (16 queries
+  // per wavefront, a quarter of the target): 16 * (TARGET / 4 + n_groups16
+  // + P).
   const size_t np = max_problems > 0 ? (size_t)max_problems : 0;
-  return (size_t)KNN_QG * (KNN_TARGET_MAX + groups + np) * (max_k > 0 ? knn_k1(max_k) : 1);
+  const size_t g4 = (size_t)(max_batch + KNN_QG - 1) / KNN_QG;
+  const size_t g16 = (size_t)(max_batch + KNN_QB - 1) / KNN_QB;
+  const size_t e4 = (size_t)KNN_QG * (KNN_TARGET_MAX + g4 + np);
+  const size_t e16 = (size_t)KNN_QB * (KNN_TARGET_MAX * KNN_QG / KNN_QB + g16 + np);
+  return (e4 > e16 ? e4 : e16) * (max_k > 0 ? knn_k1(max_k) : 1);
 }
 
 }  // namespace fn

@@ -29,8 +29,12 @@ def test_cache_round_trip(tmp_path):
 
 
 def test_candidates_are_valid_tunings():
-    for tw, mc in autotune.KNN_CANDIDATES:
-        assert 0 < tw <= 16384 and mc > 0 and mc % 64 == 0
+    grid = list(autotune.knn_grid())
+    assert {f for _, _, f in grid} == {1, 2, 3}
+    for tw, mc, form in grid:
+        assert 0 < tw <= 16384 and mc > 0 and mc % 64 == 0 and form in (1, 2, 3)
+        if form == 3:
+            assert tw <= 4096  # the matrix-core form caps its wavefront target
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")

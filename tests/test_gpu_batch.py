@@ -200,12 +200,14 @@ def test_batch_plain_equals_screen():
             assert torch.equal(P[k], Q[k]), k
 
 
-def test_batch_knn_forms_agree():
-    """Per-wavefront node loads and workgroup node tiles give the same round."""
+@pytest.mark.parametrize("form", [2, 3])
+def test_batch_knn_forms_agree(form):
+    """Per-wavefront node loads, workgroup node tiles and matrix-core keys
+    give the same round."""
     arm, probs = small_set(4, seed=13)
     _, b1 = build(arm, probs, knn_form=1)
     b1.launch()
-    _, b2 = build(arm, probs, knn_form=2)
+    _, b2 = build(arm, probs, knn_form=form)
     b2.launch()
     torch.cuda.synchronize()
     for P, Q in zip(b1.problems, b2.problems):

@@ -58,9 +58,16 @@ def iteration():
 
 # ------------------------------------------------------------------ kNN
 
-def test_knn_tiny_exact(tiny):
+# kNN scan forms: 1 = VALU keys, per-wavefront node loads; 2 = VALU keys,
+# workgroup node tiles in LDS; 3 = matrix-core keys (16 queries per wavefront)
+KNN_FORMS = (1, 2, 3)
+
+
+@pytest.mark.parametrize("form", KNN_FORMS)
+def test_knn_tiny_exact(tiny, form):
     sh = tiny["shape"]
     ctx = _ctx(tiny)
+    ctx.set_tuning(0, 0, form)
     tree, ld, n = fn.tree_soa(tiny["tree_x"])
     q = fn.dev(tiny["cand"]["x"])
     idx, d2 = ctx.plan_knn(tree, ld, n, q, sh.k)
@@ -69,11 +76,13 @@ def test_knn_tiny_exact(tiny):
     assert np.array_equal(d2.cpu().numpy(), rd2.astype(np.float32))
 
 
+@pytest.mark.parametrize("form", KNN_FORMS)
 @pytest.mark.parametrize("k", [1, 4, 8, 16, 20])
-def test_knn_iteration_exact_sampled(iteration, k):
+def test_knn_iteration_exact_sampled(iteration, k, form):
     """Full tree of 16,384 nodes, 4,096 queries; 256 sampled queries checked."""
     sh = iteration["shape"]
     ctx = _ctx(iteration, k=max(k, sh.k))
+    ctx.set_tuning(0, 0, form)
     tree, ld, n = fn.tree_soa(iteration["tree_x"])
     q = fn.dev(iteration["cand"]["x"])
     idx, d2 = ctx.plan_knn(tree, ld, n, q, k)
@@ -83,7 +92,8 @@ def test_knn_iteration_exact_sampled(iteration, k):
     assert np.array_equal(d2.cpu().numpy()[rows], rd2.astype(np.float32))
 
 
-def test_knn_ties_duplicates_and_padding():
+@pytest.mark.parametrize("form", KNN_FORMS)
+def test_knn_ties_duplicates_and_padding(form):
     rng = np.random.default_rng(3)
     arm = W.make_arm(0)
     nodes = W.uniform_states(arm, 301, rng)
@@ -96,6 +106,7 @@ def test_knn_ties_duplicates_and_padding():
     qs[6] = nodes[40]
     qs[7] = nodes[100]
     ctx = fn.Context(arm, 400, 128, 16)
+    ctx.set_tuning(0, 0, form)
     tree, ld, n = fn.tree_soa(nodes)
     for k in (3, 8, 16):
         idx, d2 = ctx.plan_knn(tree, ld, n, fn.dev(qs), k)
@@ -112,6 +123,30 @@ def test_knn_ties_duplicates_and_padding():
     tree, ld, n = fn.tree_soa(np.zeros((0, 14), np.float32))
     idx, _ = ctx.plan_knn(tree, ld, 0, fn.dev(qs[:2]), 4)
     assert (idx.cpu().numpy() == -1).all()
+
+
+def test_knn_stress_forms_sampled():
+    """Stress tree (262,144 nodes, 65,536 queries, k = 16) in every scan form:
+    identical results, 32 sampled queries bit-exact against the oracle."""
+    sh = W.CONFIGS["stress"]
+    wl = W.make_workload(sh, seed=9)
+    ctx = _ctx(wl)
+    tree, ld, n = fn.tree_soa(wl["tree_x"])
+    cand = fn.dev(wl["cand"]["x"])
+    rows = np.sort(np.random.default_rng(6).choice(sh.batch, 32, replace=False))
+    ridx, rd2 = O.plan_knn(wl["tree_x"], wl["cand"]["x"][rows], sh.k)
+    first = None
+    for form in KNN_FORMS:
+        ctx.set_tuning(0, 0, form)
+        idx, d2 = ctx.plan_knn(tree, ld, n, cand, sh.k)
+        got = (idx.cpu().numpy(), d2.cpu().numpy())
+        assert np.array_equal(got[0][rows], ridx), form
+        assert np.array_equal(got[1][rows], rd2.astype(np.float32)), form
+        if first is None:
+            first = got
+        else:
+            assert np.array_equal(got[0], first[0]) and np.array_equal(got[1], first[1]), form
+    ctx.close()
 
 
 # ------------------------------------------------------------------ edge timing

@@ -28,10 +28,13 @@ def test_knn_result_is_independent_of_the_launch_mapping(iteration):
     sh, wl, ctx, tree, ld, n, cand = iteration
     ref = None
     # chunk lists per query: 48 (default), 12, 192 (general merge), 24, 96
-    # (sort-based merge over two entries per lane); both scan forms
+    # (sort-based merge over two entries per lane); all three scan forms (the
+    # matrix-core form: 16 queries per wavefront, at most 4096 wavefronts:
+    # 12, 192 and 48 entries)
     for tw, mc, form in ((0, 0, 0), (1024, 256, 1), (16384, 64, 1), (2048, 4096, 1),
                          (8192, 512, 1), (4096, 512, 2), (1024, 256, 2), (16384, 64, 2),
-                         (8192, 512, 2)):
+                         (8192, 512, 2), (1024, 256, 3), (16384, 64, 3), (2048, 4096, 3),
+                         (1024, 512, 3)):
         ctx.set_tuning(tw, mc, form)
         idx, d2 = ctx.plan_knn(tree, ld, n, cand, sh.k)
         torch.cuda.synchronize()
@@ -47,9 +50,9 @@ def test_autotuner_picks_a_candidate_and_caches_it(iteration, tmp_path):
     sh, wl, ctx, tree, ld, n, cand = iteration
     cache = autotune.Cache(str(tmp_path / "t.json"))
     ch, times = autotune.tune_knn(ctx, tree, ld, n, cand, sh.k, reps=1, cache=cache)
-    assert (ch.knn_target_waves, ch.knn_min_chunk) in autotune.KNN_CANDIDATES
-    assert ch.knn_form in autotune.KNN_FORMS
-    assert len(times) == len(autotune.KNN_CANDIDATES) * len(autotune.KNN_FORMS)
+    grid = list(autotune.knn_grid())
+    assert (ch.knn_target_waves, ch.knn_min_chunk, ch.knn_form) in grid
+    assert len(times) == len(grid) and {f for _, _, f in grid} == set(autotune.KNN_FORMS)
     assert ch.ms == min(times.values())
     ch2, times2 = autotune.tune_knn(ctx, tree, ld, n, cand, sh.k, cache=cache)
     assert ch2 == ch and times2 == {}  # from the cache
@@ -80,7 +83,7 @@ def test_tuning_and_problem_set_are_validated(iteration):
     with pytest.raises(fn.FnError, match="target waves"):
         ctx.set_tuning(1 << 20, 512)
     with pytest.raises(fn.FnError, match="form"):
-        ctx.set_tuning(4096, 512, 3)
+        ctx.set_tuning(4096, 512, 4)
     with pytest.raises(fn.FnError, match="max_problems = 0"):
         fn.Batch(ctx, fn.dev(wl["grid"]), sh.samples, sh.k).prepare()
     arm, probs = W.make_problem_set(2, 5, nodes=(300, 600), batch=(40, 60))
