@@ -340,12 +340,12 @@ int surrogate_infer(fn_ctx* ctx, const fn_mlp* mlp, const float* X, int64_t N, c
  * wavefront, each 16 x 16 block of keys by four v_mfma_f32_16x16x4_f32 over
  * the augmented vectors (-2x, |x|^2, 1) . (y, 1, |y|^2) (at most 4096
  * wavefronts, whatever knn_target_waves says); 0 = chosen by tree size
- * (tiles above FN_KNN_TILE_NODES nodes).  Every form returns the same
+ * (matrix cores above FN_KNN_LARGE_TREE nodes).  Every form returns the same
  * neighbours and distances.  Applies to later plan_knn calls and
  * fn_batch_prepare.  Errors: FN_E_ARG when knn_target_waves is outside
  * [0, 16384], knn_min_chunk is negative or not a multiple of 64, or
  * knn_form is not 0, 1, 2 or 3. */
-#define FN_KNN_TILE_NODES 65536
+#define FN_KNN_LARGE_TREE 65536
 typedef struct {
   int32_t knn_target_waves;
   int32_t knn_min_chunk;

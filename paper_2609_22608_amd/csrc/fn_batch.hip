@@ -360,11 +360,11 @@ extern "C" int fn_batch_prepare(fn_ctx* c, const fn_problem_set* ps) {
   while (Sw < ps->samples) Sw <<= 1;
   int target = std::min(KNN_TARGET_MAX, c->tune.knn_target_waves > 0 ? c->tune.knn_target_waves : 4096);
   const int minchunk = c->tune.knn_min_chunk > 0 ? c->tune.knn_min_chunk : 512;
-  // scan form: tuned, else node tiles once the largest tree capacity
-  // outgrows the L2
+  // scan form: tuned, else the matrix-core form once the largest tree
+  // capacity outgrows the L2
   int64_t max_ld = 0;
   for (int p = 0; p < n; ++p) max_ld = std::max(max_ld, ps->problems[p].ld);
-  const int form = c->tune.knn_form > 0 ? c->tune.knn_form : (max_ld > FN_KNN_TILE_NODES ? 2 : 1);
+  const int form = c->tune.knn_form > 0 ? c->tune.knn_form : (max_ld > FN_KNN_LARGE_TREE ? 3 : 1);
   const int qpw = form == 3 ? KNN_QB : KNN_QG;  // queries per scan wavefront
   if (form == 3) target = std::min(target, KNN_TARGET_MAX * KNN_QG / KNN_QB);
   for (int p = 0; p < n; ++p) {
@@ -474,7 +474,7 @@ extern "C" int fn_batch_launch(fn_ctx* c, void* stream) {
   switch (bt->K1) {
 #define FN_K(KK) case KK: launch_batch_knn<KK>(c, bt, s); break;
     FN_K(5) FN_K(6) FN_K(7) FN_K(8) FN_K(9) FN_K(10) FN_K(11) FN_K(12) FN_K(13) FN_K(14) FN_K(15)
-    FN_K(16) FN_K(33)
+    FN_K(16) FN_K(20) FN_K(24) FN_K(33)
 #undef FN_K
     default: return fail(FN_E_SHAPE, "fn_batch_launch: k");
   }

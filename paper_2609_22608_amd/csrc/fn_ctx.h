@@ -52,9 +52,10 @@ __global__ void zero_i32_kernel(int32_t* p, int n);
 constexpr int KNN_TARGET_MAX = 16384;
 size_t knn_scratch_entries(int max_batch, int max_k, int max_problems);
 // list length a kNN launch uses for k
-// (k + 4 spare entries per node chunk, so that near ties at the k-th
-// distance almost never force the exact rescan; 33 for k > 12)
-inline int knn_k1(int k) { return k <= 12 ? k + 4 : 33; }
+// (at least k + 4 spare entries per node chunk, so that near ties at the
+// k-th distance almost never force the exact rescan: k + 4 up to k = 12,
+// then 20, 24 and 33 for k up to 16, 20 and 32)
+inline int knn_k1(int k) { return k <= 12 ? k + 4 : (k <= 16 ? 20 : (k <= 20 ? 24 : 33)); }
 
 }  // namespace fn
 

@@ -4,7 +4,7 @@
 // Stage 1 (knn_scan): one wavefront per (4 queries, node chunk); lanes run
 // over the chunk's nodes with coalesced loads of the SoA tree rows, every
 // screening distance costs 14 FMAs, and each query keeps its chunk's K1
-// smallest FP32 keys (d^2, index), K1 = k + 4 (33 for k > 12), sorted over
+// smallest FP32 keys (d^2, index), K1 >= k + 4 (knn_k1), sorted over
 // lanes 0..K1-1.
 // Stage 2 (knn_merge): one wavefront per query merges the chunk lists.  The
 // FP32 k-th key bounds a band that provably holds the exact top-k; every

@@ -88,7 +88,7 @@ __global__ __launch_bounds__(64) void knn_merge_small_kernel(
 template <int K1>
 static void launch_knn(fn_ctx* c, const float* tree, int64_t ld, int n_nodes, const float* qs,
                        int B, int k, int32_t* out_idx, float* out_d2, hipStream_t s) {
-  const int form = c->tune.knn_form > 0 ? c->tune.knn_form : (n_nodes > FN_KNN_TILE_NODES ? 2 : 1);
+  const int form = c->tune.knn_form > 0 ? c->tune.knn_form : (n_nodes > FN_KNN_LARGE_TREE ? 3 : 1);
   const int qpw = form == 3 ? KNN_QB : KNN_QG;  // queries per scan wavefront
   const int n_groups = (B + qpw - 1) / qpw;
   // enough wavefronts to fill the chip, chunks of at least 512 nodes; the
@@ -161,7 +161,7 @@ extern "C" int plan_knn(fn_ctx* c, const float* tree, int64_t ld, int32_t n_node
   switch (knn_k1(k)) {
 #define FN_K(KK) case KK: launch_knn<KK>(c, tree, ld, n_nodes, queries, B, k, out_idx, out_d2, s); break;
     FN_K(5) FN_K(6) FN_K(7) FN_K(8) FN_K(9) FN_K(10) FN_K(11) FN_K(12) FN_K(13) FN_K(14) FN_K(15)
-    FN_K(16) FN_K(33)
+    FN_K(16) FN_K(20) FN_K(24) FN_K(33)
 #undef FN_K
     default: return fail(FN_E_SHAPE, "plan_knn: k = %d", k);
   }
