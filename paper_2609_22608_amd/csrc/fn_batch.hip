@@ -462,8 +462,10 @@ static void launch_batch_search(fn_ctx* c, fn_batch* bt, hipStream_t s) {
   const size_t tab = (size_t)EDGE_WAVES * c->desc.n_spheres * bt->max_obs * sizeof(float);
   hipLaunchKernelGGL((batch_edge_kernel<PAT, MODE>), dim3((unsigned)xcd_grid(bt->queries, bt->k)),
                      dim3(64 * EDGE_WAVES), tab, s, pt, bt->grid, bt->n_t, c->arm32, bt->max_obs);
-  const unsigned rw = (unsigned)(bt->edges < 4096 ? bt->edges : 4096);
-  hipLaunchKernelGGL(edge_recheck_kernel<PAT>, dim3(rw), dim3(64), 0, s, bt->a0, pt, c->arm64);
+  const unsigned rw = (unsigned)(bt->edges < RECHECK_WAVES ? bt->edges : RECHECK_WAVES);
+  hipLaunchKernelGGL(edge_recheck_kernel<PAT>, dim3(rw), dim3(64),
+                     (size_t)c->desc.n_spheres * bt->max_obs * sizeof(double), s, bt->a0, pt,
+                     c->arm64);
 }
 
 extern "C" int fn_batch_launch(fn_ctx* c, void* stream) {

@@ -148,15 +148,15 @@ __device__ void joint_checks(const ArmConst<R>& A, const EdgeState<R>& E, R T, R
 // (sphere, obstacle) loop reads broadcast LDS instead of waiting on a
 // memory load per pair.  Lane = (sample, sphere part): the parts split each
 // link's spheres so that all 64 lanes work when S < 64.
-// FP32: tab (LDS, nsph * n_obs floats) receives 1 / (r_a + margin + r_o)^2
-// of every pair (hardware reciprocal, within 1 ulp), and the loop keeps the smallest d^2 / (r_a + margin + r_o)^2
-// (a product and a minimum per pair instead of a reciprocal); rho_c is its
-// inverse square root.  FP64 (tab unused): the ratio of every pair by IEEE
-// division.
+// tab (LDS, nsph * n_obs values) receives 1 / (r_a + margin + r_o)^2 of every
+// (sphere, obstacle) pair (FP32: hardware reciprocal, within 1 ulp; FP64:
+// IEEE division), and the loop keeps the smallest d^2 / (r_a + margin +
+// r_o)^2 (a product and a minimum per pair instead of a division); rho_c is
+// its inverse square root.
 template <typename R, int PAT>
 __device__ void clearance(const ArmConst<R>& A, const EdgeState<R>& E, R T, int S,
                           const float* __restrict__ obs, int n_obs, float margin_c,
-                          GeoLDS<R>* geo, float* tab, R& rc) {
+                          GeoLDS<R>* geo, R* tab, R& rc) {
   constexpr bool F32 = sizeof(R) == 4;
   const int lane = lane_id();
   for (int t = lane; t < A.nsph; t += WAVE) {
@@ -167,18 +167,21 @@ __device__ void clearance(const ArmConst<R>& A, const EdgeState<R>& E, R T, int 
   }
   for (int t = lane; t < 4 * n_obs; t += WAVE) geo->obs[t] = R(obs[t]);
   __builtin_amdgcn_wave_barrier();
-  if constexpr (F32) {
-    // lane = (obstacle o, sphere offset k0): WAVE / n_obs spheres per step
+  {
+    // 1 / need^2 per (sphere, obstacle) pair: the hardware reciprocal in
+    // FP32, an IEEE division in FP64; lane = (obstacle o, sphere offset k0),
+    // WAVE / n_obs spheres per step
     const int kstep = WAVE / n_obs, o = lane % n_obs, k0 = lane / n_obs;
     if (k0 < kstep)
       for (int k = k0; k < A.nsph; k += kstep) {
-        const float need = geo->sph[4 * k + 3] + geo->obs[4 * o + 3];
-        tab[k * n_obs + o] = __builtin_amdgcn_rcpf(need * need);
+        const R need = geo->sph[4 * k + 3] + geo->obs[4 * o + 3];
+        if constexpr (F32) tab[k * n_obs + o] = __builtin_amdgcn_rcpf(need * need);
+        else tab[k * n_obs + o] = R(1) / (need * need);
       }
     __builtin_amdgcn_wave_barrier();
   }
-  // FP32: smallest d^2 / need^2; FP64: largest need^2 / d^2
-  R best = F32 ? R(INFINITY) : R(0);
+  // smallest d^2 / need^2 over the (sample, sphere, obstacle) triples
+  R best = R(INFINITY);
   int Sw = 1;
   while (Sw < S) Sw <<= 1;
   const int nparts = Sw >= WAVE ? 1 : WAVE / Sw;
@@ -191,34 +194,19 @@ __device__ void clearance(const ArmConst<R>& A, const EdgeState<R>& E, R T, int 
     for (int i = 0; i < NJ; ++i) sincos_r(sg[i], sn[i], cs[i]);
     const R* so = geo->obs;
     sphere_centres<R, PAT>(A, sn, cs, part, nparts, geo->sph, [&](int k, R x, R y, R z) {
-      if constexpr (F32) {
-        const float* tk = tab + k * n_obs;
+      const R* tk = tab + k * n_obs;
 #pragma unroll 4
-        for (int o = 0; o < n_obs; ++o) {
-          const float dx = x - so[4 * o], dy = y - so[4 * o + 1], dz = z - so[4 * o + 2];
-          const float d2 = dx * dx + dy * dy + dz * dz;
-          best = fminf(best, d2 * tk[o]);
-        }
-      } else {
-        const R ra = geo->sph[4 * k + 3];
-#pragma unroll 4
-        for (int o = 0; o < n_obs; ++o) {
-          const R dx = x - so[4 * o], dy = y - so[4 * o + 1], dz = z - so[4 * o + 2];
-          const R need = ra + so[4 * o + 3];
-          const R d2 = dx * dx + dy * dy + dz * dz;
-          // d2 = 0 gives +inf (IEEE division)
-          best = rmax(best, need * need / d2);
-        }
+      for (int o = 0; o < n_obs; ++o) {
+        const R dx = x - so[4 * o], dy = y - so[4 * o + 1], dz = z - so[4 * o + 2];
+        const R d2 = dx * dx + dy * dy + dz * dz;
+        if constexpr (F32) best = fminf(best, d2 * tk[o]);
+        else best = fmin(best, d2 * tk[o]);
       }
     });
   }
-  if constexpr (F32) {
-    // d2 = 0 gives rho_c = +inf; no pair (no spheres) gives 0
-    const float mn = wave_min(float(best));
-    rc = mn < INFINITY ? 1.f / sqrtf(mn) : 0.f;
-  } else {
-    rc = sqrt(wave_max(double(best)));
-  }
+  // d2 = 0 gives rho_c = +inf; no pair (no spheres) gives 0
+  const R mn = wave_min(best);
+  rc = mn < R(INFINITY) ? R(1) / sqrt(mn) : R(0);
   __builtin_amdgcn_wave_barrier();
 }
 
@@ -370,6 +358,8 @@ __device__ __forceinline__ void stage_of(int mode, int st, int jmax, int lo, int
 
 // Edges (wavefronts) per workgroup of the search kernels.
 constexpr int EDGE_WAVES = 1;
+// Largest grid of the FP64 stage (one wavefront per SIMD of the chip).
+constexpr int RECHECK_WAVES = 1024;
 
 // XCD-aware order of the search grid.  Workgroups are dealt to the 8 XCDs
 // in turn (workgroup w runs on XCD w mod 8), so consecutive edges land on
@@ -688,7 +678,8 @@ __device__ __forceinline__ double rho64(const ArmConst<double>& D, const EdgeSta
 // recomputed in FP64 (all of them after the FP64 walk).
 template <int PAT>
 __device__ void recheck_edge(const EdgeArgs& a, int64_t e, const QEntry& q,
-                             const ArmConst<double>& D, float* s_fix, GeoLDS<double>* geo) {
+                             const ArmConst<double>& D, float* s_fix, GeoLDS<double>* geo,
+                             double* tab) {
   const int lane = lane_id();
   EdgeState<double> ED;
   int st0;
@@ -790,7 +781,7 @@ __device__ void recheck_edge(const EdgeArgs& a, int64_t e, const QEntry& q,
   if (rv > 1.0 || rq > 1.0) rc = NAN;
   else if (a.n_obs == 0) rc = 0.0;
   else if (exact || isnan(rc) || near_one((float)rc))
-    clearance<double, PAT>(D, ED, T, S, a.obs, a.n_obs, a.margin_c, geo, nullptr, rc);
+    clearance<double, PAT>(D, ED, T, S, a.obs, a.n_obs, a.margin_c, geo, tab, rc);
   m = fminf(m, (float)fmin(fabs(rv - 1.0), fmin(fabs(rq - 1.0), fabs(rc - 1.0))));
   write_out(a, e, jstar, post_status(rv, rq, rc) | FN_S_RECHECK64 | winbits, m, rho_star,
             (float)rv, (float)rq, (float)rc, work, Tg[jstar]);
@@ -815,12 +806,14 @@ __device__ __forceinline__ int problem_of(const ProbTable& pt, int64_t eg) {
   return lo;
 }
 
-// FP64 stage over the queue; pt.n == 0: one problem (a).
+// FP64 stage over the queue; pt.n == 0: one problem (a).  Dynamic LDS: the
+// clearance table, nsph * (largest obstacle count) doubles.
 template <int PAT>
 __global__ __launch_bounds__(64) void edge_recheck_kernel(EdgeArgs a, ProbTable pt,
                                                           const ArmConst<double>* __restrict__ Dp) {
   __shared__ float s_fix[1];
   __shared__ GeoLDS<double> s_geo;
+  extern __shared__ double s_tab64[];
   const int n = *a.q_count;
   for (int qi = blockIdx.x; qi < n; qi += gridDim.x) {
     const QEntry q = a.queue[qi];
@@ -831,7 +824,7 @@ __global__ __launch_bounds__(64) void edge_recheck_kernel(EdgeArgs a, ProbTable 
       ap = pt.args + p;
       e -= pt.edge_off[p];
     }
-    recheck_edge<PAT>(*ap, e, q, *Dp, s_fix, &s_geo);
+    recheck_edge<PAT>(*ap, e, q, *Dp, s_fix, &s_geo, s_tab64);
   }
 }
 

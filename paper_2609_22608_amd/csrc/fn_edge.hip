@@ -127,7 +127,10 @@ __global__ __launch_bounds__(256) void edge_check_kernel(const float* __restrict
 
 // waves of the FP64 stage: one per queued edge up to 4096 (the queue
 // length is known only on the device)
-static unsigned recheck_waves(int64_t E) { return (unsigned)(E < 4096 ? (E > 0 ? E : 1) : 4096); }
+// FP64 stage grid: one wavefront per SIMD at most (its FP64 recursion holds
+// 512 registers per lane), each looping over queue entries; more workgroups
+// than SIMDs would only queue up empty waves behind the working ones
+static unsigned recheck_waves(int64_t E) { return (unsigned)(E < RECHECK_WAVES ? (E > 0 ? E : 1) : RECHECK_WAVES); }
 
 // model kernel (screening modes), search kernel between the timing events,
 // FP64 stage
@@ -145,7 +148,8 @@ static void launch_search(fn_ctx* c, const EdgeArgs& a, int ti, hipStream_t s) {
   hipLaunchKernelGGL((edge_time_kernel<PAT, MODE>), dim3((unsigned)xcd_grid(B, a.k)),
                      dim3(64 * EDGE_WAVES), tab, s, a, c->arm32);
   if (ti >= 0) (void)hipEventRecord(c->tev[2 * ti + 1], s);
-  hipLaunchKernelGGL(edge_recheck_kernel<PAT>, dim3(recheck_waves(E)), dim3(64), 0, s, a,
+  hipLaunchKernelGGL(edge_recheck_kernel<PAT>, dim3(recheck_waves(E)), dim3(64),
+                     (size_t)c->desc.n_spheres * a.n_obs * sizeof(double), s, a,
                      ProbTable{0, nullptr, nullptr}, c->arm64);
 }
 

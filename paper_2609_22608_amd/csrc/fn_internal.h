@@ -66,8 +66,7 @@ __device__ __forceinline__ void sincos_r(float x, float& s, float& c) {
   c = __builtin_amdgcn_cosf(r);
 }
 __device__ __forceinline__ void sincos_r(double x, double& s, double& c) {
-  s = sin(x);
-  c = cos(x);
+  sincos(x, &s, &c);  // one argument reduction for both
 }
 __device__ __forceinline__ float logistic_neg(float k2x) {
   // 1 / (1 + 2^(k2x)) with k2x = -psi2 (qd + psi3) log2(e)
@@ -529,6 +528,14 @@ __device__ __forceinline__ float wave_min(float v) {
   v = fminf(v, xlane<8>(v));
   v = fminf(v, xlane<16>(v));
   return fminf(readlane(v, 0), readlane(v, 32));
+}
+__device__ __forceinline__ double wave_min(double v) {
+  v = fmin(v, xlane<1>(v));
+  v = fmin(v, xlane<2>(v));
+  v = fmin(v, xlane<4>(v));
+  v = fmin(v, xlane<8>(v));
+  v = fmin(v, xlane<16>(v));
+  return fmin(readlane(v, 0), readlane(v, 32));
 }
 // The same through LDS permutes: no VALU moves, for VALU-bound loops.
 __device__ __forceinline__ float group_max_lds(float v, int width) {
