@@ -121,23 +121,25 @@ struct GeoLDS {
   R obs[4 * FN_MAX_OBS];
 };
 
-// Velocity taper (Def. 6 rho_v) and position limits at duration T, lane
-// i < 7 checking joint i; (rho_v, rho_q) in every lane.
+// Velocity taper (Def. 6 rho_v) and position limits at duration T: lane
+// 8 i + p evaluates candidate extremum p of joint i (joint_point), and the
+// wave maxima give (rho_v, rho_q) in every lane.
 template <typename R>
 __device__ void joint_checks(const ArmConst<R>& A, const EdgeState<R>& E, R T, R& rv, R& rq) {
   const int lane = lane_id();
+  const int ji = lane >> 3, p = lane & 7;
   R v = 0, q = 0;
   // register selects keep the edge state in VGPRs
   R q0 = 0, qd0 = 0, dq = 0, d2v = 0;
 #pragma unroll
   for (int i = 0; i < NJ; ++i)
-    if (lane == i) {
+    if (ji == i) {
       q0 = E.q0[i];
       qd0 = E.qd0[i];
       dq = E.dq[i];
       d2v = E.d2[i];
     }
-  if (lane < NJ) joint_post(A, lane, q0, qd0, dq, d2v, T, v, q);
+  if (ji < NJ) joint_point(A, ji, p, q0, qd0, dq, d2v, T, v, q);
   rv = wave_max(v);
   rq = wave_max(q);
 }

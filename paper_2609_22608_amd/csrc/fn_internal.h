@@ -367,46 +367,59 @@ __device__ __forceinline__ R vel_ratio(const ArmConst<R>& A, int i, R q, R v) {
   return rabs(v) / lim;
 }
 
-// rho_v and rho_q of one joint at duration T (exact extrema of the cubic):
-// boundary state (q0, qd0), dq = q1 - q0, d2 = qd1 - qd0; i indexes the
-// joint's limits.
+// One candidate extremum of joint i's cubic at duration T (boundary state
+// (q0, qd0), dq = q1 - q0, d2 = qd1 - qd0): point p = 0, 1, 2 are the
+// velocity peaks (t = 0, t = T, vertex of the quadratic velocity), p = 3, 4,
+// 5, 6 the position extrema (t = 0, t = T, real roots of the velocity in
+// [0, T]).  v receives the velocity-taper ratio of a velocity point, q the
+// position ratio of a position point, 0 for the other kind or a point that
+// does not exist; rho_v and rho_q are the maxima over the 7 points of every
+// joint.  Every lane runs the same instructions (the point is selected, not
+// branched on), so a wavefront evaluates all 49 (joint, point) pairs at the
+// latency of one.
 template <typename R>
-__device__ __forceinline__ void joint_post(const ArmConst<R>& A, int i, R q0, R qd0, R dq, R d2v,
-                                           R T, R& rv, R& rq) {
+__device__ __forceinline__ void joint_point(const ArmConst<R>& A, int i, int p, R q0, R qd0, R dq,
+                                            R d2v, R T, R& v, R& q) {
   const R invT = R(1) / T;
   const R c0 = q0, c1 = qd0;
   const R d1 = dq - c1 * T;
   const R c2 = (R(3) * d1 * invT - d2v) * invT;
   const R c3 = (d2v - R(2) * d1 * invT) * invT * invT;
-  auto pos = [&](R t) { return c0 + t * (c1 + t * (c2 + t * c3)); };
-  auto vel = [&](R t) { return c1 + t * (R(2) * c2 + R(3) * c3 * t); };
-  // velocity peaks: t = 0, t = T, vertex of the quadratic velocity
-  rv = rmax(vel_ratio(A, i, pos(R(0)), vel(R(0))), vel_ratio(A, i, pos(T), vel(T)));
-  if (c3 != R(0)) {
-    const R tv = -c2 / (R(3) * c3);
-    if (tv > R(0) && tv < T) rv = rmax(rv, vel_ratio(A, i, pos(tv), vel(tv)));
-  }
-  // position extrema: endpoints and real roots of the velocity in (0, T)
-  auto pr = [&](R t) { return rabs(pos(t) - A.qcen[i]) * A.inv_qhalf[i]; };
-  rq = rmax(pr(R(0)), pr(T));
+  // velocity vertex
+  const R tv = -c2 / (R(3) * c3);
+  const bool tv_ok = c3 != R(0) && tv > R(0) && tv < T;
+  // roots of the velocity 3 c3 t^2 + 2 c2 t + c1
   const R qa = R(3) * c3, qb = R(2) * c2, qc = c1;
-  if (qa == R(0)) {
-    if (qb != R(0)) {
-      const R t = -qc / qb;
-      if (t >= R(0) && t <= T) rq = rmax(rq, pr(t));
-    }
-  } else {
-    const R disc = qb * qb - R(4) * qa * qc;
-    if (disc >= R(0)) {
-      const R sq = sqrt(disc);
-      const R qq = R(-0.5) * (qb + (qb >= R(0) ? sq : -sq));
-      if (qq != R(0)) {
-        const R t1 = qq / qa, t2 = qc / qq;
-        if (t1 >= R(0) && t1 <= T) rq = rmax(rq, pr(t1));
-        if (t2 >= R(0) && t2 <= T) rq = rmax(rq, pr(t2));
-      }
-    }
+  const R tl = -qc / qb;  // qa = 0: the linear root
+  const bool tl_ok = qb != R(0) && tl >= R(0) && tl <= T;
+  const R disc = qb * qb - R(4) * qa * qc;
+  const R sq = sqrt(disc >= R(0) ? disc : R(0));
+  const R qq = R(-0.5) * (qb + (qb >= R(0) ? sq : -sq));
+  const R t1 = qq / qa, t2 = qc / qq;
+  const bool quad = qa != R(0) && disc >= R(0) && qq != R(0);
+  const bool t1_ok = quad && t1 >= R(0) && t1 <= T;
+  const bool t2_ok = quad && t2 >= R(0) && t2 <= T;
+  R t = R(0);
+  bool ok = p <= 6;
+  if (p == 1 || p == 4) t = T;
+  if (p == 2) {
+    t = tv;
+    ok = tv_ok;
   }
+  if (p == 5) {
+    t = qa == R(0) ? tl : t1;
+    ok = qa == R(0) ? tl_ok : t1_ok;
+  }
+  if (p == 6) {
+    t = t2;
+    ok = qa != R(0) && t2_ok;
+  }
+  const R pt = c0 + t * (c1 + t * (c2 + t * c3));
+  const R vt = c1 + t * (R(2) * c2 + R(3) * c3 * t);
+  const R rvel = vel_ratio(A, i, pt, vt);
+  const R rpos = rabs(pt - A.qcen[i]) * A.inv_qhalf[i];
+  v = ok && p <= 2 ? rvel : R(0);
+  q = ok && p >= 3 ? rpos : R(0);
 }
 
 // World-frame centres of the collision spheres at configuration (sn, cs),
