@@ -151,9 +151,11 @@ def test_batch_matches_oracle_and_attachment_rule():
               f"{int((~ex['strict']).sum())} edges in the band")
 
 
-def test_graph_replay_equals_eager_and_is_deterministic():
+@pytest.mark.parametrize("form", [0, 3])
+def test_graph_replay_equals_eager_and_is_deterministic(form):
+    """Default kNN form and the matrix-core form."""
     arm, probs = small_set(6, seed=9)
-    ctx, bt = build(arm, probs)
+    ctx, bt = build(arm, probs, knn_form=form)
     keys = ("nbr", "out_j", "out_status", "out_T", "out_node", "out_J", "n_nodes", "t_node",
             "parent", "tree")
 
