@@ -158,7 +158,9 @@ int fn_kernel_times(fn_ctx* ctx, float* out_ms /*host*/, int32_t max, int32_t* n
  * an FP32 scan selects candidates and every candidate near the k-th
  * distance is re-ranked with d^2 = sum_{c=0..13} (x_c - y_c)^2 in FP64,
  * summed in order c = 0..13 with separately rounded products and sums;
- * out_d2 is that FP64 value rounded to float.  With fewer than k nodes the
+ * out_d2 is that FP64 value rounded to float.  The FP32 screening keys come
+ * from FMAs or from the matrix cores, as fn_set_tuning selects; the result
+ * is the same.  With fewer than k nodes the
  * tail is padded with -1 (d^2 = +inf).  Returns FN_E_SHAPE if B > max_batch,
  * k > max_k, k < 1, n_nodes > max_nodes or ld > 38,347,920 (the scan's
  * 32-bit row offsets); FN_E_ARG if ld is not a multiple of 4 or too small. */
