@@ -371,20 +371,23 @@ __device__ __forceinline__ void knn_scan_mfma_item(const float* __restrict__ tre
   const int n0 = ch * chunk;
   const int n1 = min(n0 + chunk, n_nodes);
   float y2max = 0.f;
+  // node nb0 + 16 j + col at byte offset 4 (nb0 + col) + 64 j of its row.
+  // Lanes past the chunk read whatever lies there (the next chunk, the row
+  // padding, or 0 beyond the buffer's end: the resource bounds every read)
+  // and get |y|^2 = +inf below.
   for (int nb0 = n0; nb0 < n1; nb0 += WAVE) {
     float bv[4][4];
-    int node[4];
+    const int vn = (nb0 + col) * 4;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      node[j] = nb0 + 16 * j + col;
-      const int nc = node[j] < n1 ? node[j] : n1 - 1;
 #pragma unroll
       for (int s = 0; s < 3; ++s)
         bv[j][s] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
-                                                 rs, nc * 4 + voff_r, 4 * s * row_bytes, 0));
+                                                 rs, vn + voff_r + 64 * j, 4 * s * row_bytes, 0));
       bv[j][3] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
-                                               rs, nc * 4 + voff_r3, 12 * row_bytes, 0));
+                                               rs, vn + voff_r3 + 64 * j, 12 * row_bytes, 0));
     }
+    const bool tail = nb0 + WAVE > n1;  // wave-uniform: the last block of the chunk
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       float p = bv[j][0] * bv[j][0];
@@ -395,7 +398,7 @@ __device__ __forceinline__ void knn_scan_mfma_item(const float* __restrict__ tre
       // values, so the four lanes of a node hold the same |y|^2
       const float t = p + __builtin_bit_cast(float, lane_xor<16>(__builtin_bit_cast(int, p)));
       const float yy = t + __builtin_bit_cast(float, lane_xor<32>(__builtin_bit_cast(int, t)));
-      const bool valid = node[j] < n1;
+      const bool valid = !tail || nb0 + 16 * j + col < n1;
       y2max = valid ? fmaxf(y2max, yy) : y2max;
       // a node past the chunk gets |y|^2 = +inf: every key of it is +inf
       const float y15 = valid ? yy : INFINITY;
@@ -437,7 +440,7 @@ __device__ __forceinline__ void knn_scan_mfma_item(const float* __restrict__ tre
         if (d < thv[i]) {
           const int slot = nbv[i] + (int)__popc(gm & ((1u << col) - 1u));
           buf->d[4 * row + i][slot] = d;
-          buf->i[4 * row + i][slot] = node[j];
+          buf->i[4 * row + i][slot] = nb0 + 16 * j + col;
         }
         nbv[i] += (int)__popc(gm);
         dirty[i] = dirty[i] || gm != 0;
