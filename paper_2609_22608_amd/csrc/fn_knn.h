@@ -371,23 +371,35 @@ __device__ __forceinline__ void knn_scan_mfma_item(const float* __restrict__ tre
   const int n0 = ch * chunk;
   const int n1 = min(n0 + chunk, n_nodes);
   float y2max = 0.f;
-  // node nb0 + 16 j + col at byte offset 4 (nb0 + col) + 64 j of its row.
-  // Lanes past the chunk read whatever lies there (the next chunk, the row
-  // padding, or 0 beyond the buffer's end: the resource bounds every read)
-  // and get |y|^2 = +inf below.
+  // node nb0 + 16 j + col at byte offset 4 (nb0 + col) + 64 j of its row;
+  // in the chunk's last block (wave-uniform test) the nodes past the chunk
+  // read its last node and get |y|^2 = +inf below
   for (int nb0 = n0; nb0 < n1; nb0 += WAVE) {
     float bv[4][4];
-    const int vn = (nb0 + col) * 4;
+    const bool tail = nb0 + WAVE > n1;
+    if (!tail) {
+      const int vn = (nb0 + col) * 4;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < 4; ++j) {
 #pragma unroll
-      for (int s = 0; s < 3; ++s)
-        bv[j][s] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
-                                                 rs, vn + voff_r + 64 * j, 4 * s * row_bytes, 0));
-      bv[j][3] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
-                                               rs, vn + voff_r3 + 64 * j, 12 * row_bytes, 0));
+        for (int s = 0; s < 3; ++s)
+          bv[j][s] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                                   rs, vn + voff_r + 64 * j, 4 * s * row_bytes, 0));
+        bv[j][3] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                                 rs, vn + voff_r3 + 64 * j, 12 * row_bytes, 0));
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int vn = min(nb0 + 16 * j + col, n1 - 1) * 4;
+#pragma unroll
+        for (int s = 0; s < 3; ++s)
+          bv[j][s] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                                   rs, vn + voff_r, 4 * s * row_bytes, 0));
+        bv[j][3] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                                 rs, vn + voff_r3, 12 * row_bytes, 0));
+      }
     }
-    const bool tail = nb0 + WAVE > n1;  // wave-uniform: the last block of the chunk
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       float p = bv[j][0] * bv[j][0];
