@@ -284,8 +284,9 @@ __device__ void knn_scan_item(const float* __restrict__ tree, int64_t ld, int n_
 // v_mfma_f32_16x16x4_f32 steps over K = 16.  Operand layout: lane l = 16 r +
 // c holds A[c][4 s + r] and B[4 s + r][c] in step s and receives D[4 r + i][c],
 // i = 0..3: the keys of queries 4 r + i against node c.  |y|^2 is summed from
-// the four lanes that hold a node's coordinates (lane exchanges).  Any order of the 16 products and sums stays within the key error
-// bound the merge assumes (16 roundings of terms bounded by (|x| + |y|)^2).
+// the four lanes that hold a node's coordinates (lane exchanges).  Any order
+// of the 16 products and sums stays within the key error bound the merge
+// assumes (16 roundings of terms bounded by (|x| + |y|)^2).
 // Selection as in the VALU form, per query: a node below the query's
 // threshold is appended to its LDS buffer (lanes of a row rank their
 // candidates within the row); a query whose buffer would overflow is merged
