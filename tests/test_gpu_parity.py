@@ -77,7 +77,7 @@ def test_knn_tiny_exact(tiny, form):
 
 
 @pytest.mark.parametrize("form", KNN_FORMS)
-@pytest.mark.parametrize("k", [1, 4, 8, 16, 20])
+@pytest.mark.parametrize("k", [1, 4, 8, 16, 20, 32])
 def test_knn_iteration_exact_sampled(iteration, k, form):
     """Full tree of 16,384 nodes, 4,096 queries; 256 sampled queries checked."""
     sh = iteration["shape"]
