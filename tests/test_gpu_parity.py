@@ -125,6 +125,29 @@ def test_knn_ties_duplicates_and_padding(form):
     assert (idx.cpu().numpy() == -1).all()
 
 
+@pytest.mark.parametrize("form", KNN_FORMS)
+def test_knn_far_from_the_origin(form):
+    """Tree and queries offset by 30 in every coordinate: the FP32 keys
+    |x|^2 + |y|^2 - 2 x.y cancel ~10^4 against distances of order 1, the band
+    (4e-6 (|x| + |y|)^2 wide) holds many entries and chunks can strike the
+    exact rescan; the result must still equal the oracle's in every form."""
+    rng = np.random.default_rng(11)
+    arm = W.make_arm(0)
+    nodes = W.uniform_states(arm, 2000, rng) + 30.0
+    qs = W.uniform_states(arm, 100, rng) + 30.0
+    nodes = nodes.astype(np.float32)
+    qs = qs.astype(np.float32)
+    ctx = fn.Context(arm, 2048, 128, 16)
+    ctx.set_tuning(1024, 256, form)
+    tree, ld, n = fn.tree_soa(nodes)
+    for k in (1, 8, 16):
+        idx, d2 = ctx.plan_knn(tree, ld, n, fn.dev(qs), k)
+        ridx, rd2 = O.plan_knn(nodes, qs, k)
+        assert np.array_equal(idx.cpu().numpy(), ridx), (form, k)
+        assert np.array_equal(d2.cpu().numpy(), rd2.astype(np.float32)), (form, k)
+    ctx.close()
+
+
 def test_knn_stress_forms_sampled():
     """Stress tree (262,144 nodes, 65,536 queries, k = 16) in every scan form:
     identical results, 32 sampled queries bit-exact against the oracle."""
