@@ -2,8 +2,8 @@
 
 Argument marshalling only: every step of the path runs in the library's HIP
 kernels.  PyTorch provides device memory and the current stream.  The
-library must have been built (``python -m paper_2609_22608_amd.build`` or
-``__graft_entry__.build()``); loading fails loudly otherwise.
+library must have been built (``python -m paper_2609_22608_amd.build``);
+loading fails loudly otherwise.
 """
 from __future__ import annotations
 
