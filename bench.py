@@ -42,6 +42,14 @@ F_MODEL = 8271
 F_JOINTS = 980
 
 
+# One row of surrogate inference: 2 x (28 x 256 + 2 x 256 x 256 + 256 x 2).
+F_MLP_ROW = 277504
+# One (query, node) pair of the kNN scan: 14 differences and 14 squares
+# summed (FMA = 2).
+F_KNN_PAIR = 42
+PEAK_BF16 = 2500e12  # MI355X dense BF16 matrix peak, FLOP/s
+
+
 def f_clear(S, n_obs, n_sph):
     """Clearance of one edge (evaluated only when its limit checks pass)."""
     return S * (371 + n_sph * (19 + 13 * n_obs)) if n_obs > 0 else 0
@@ -63,9 +71,11 @@ def parse():
     p.add_argument("--seed", type=int, default=101)
     p.add_argument("--modes", default="plain,screen,window")
     p.add_argument("--surrogate", default=None, help="checkpoint to load instead of training")
-    p.add_argument("--train-batches", type=int, default=32,
-                   help="one-iteration batches labelled for the surrogate (32 x 32,768 edges)")
-    p.add_argument("--train-epochs", type=int, default=8)
+    p.add_argument("--save-surrogate", default=None, help="write the trained network here")
+    p.add_argument("--train-batches", type=int, default=306,
+                   help="one-iteration batches labelled for the surrogate (306 x 32,768 = "
+                        "10.0 M edges)")
+    p.add_argument("--train-epochs", type=int, default=20)
     p.add_argument("--half", type=int, default=4)
     p.add_argument("--workload", default="iteration", choices=sorted(WORKLOADS))
     p.add_argument("--cpu-sample", type=int, default=None,
@@ -125,6 +135,8 @@ def main():
         # trained on one-iteration-shaped edges whatever the workload
         net, surrogate_info = surrogate(args, ctx, wl["arm"], W.CONFIGS["iteration"], fn, W,
                                         torch)
+        if args.save_surrogate:
+            net.save(args.save_surrogate)
     feats = torch.empty((E, 28), dtype=torch.float32, device="cuda")
     win = torch.empty(E, dtype=torch.int16, device="cuda")
     forms = {}
@@ -200,12 +212,11 @@ def main():
                  recheck64=int(((st & fn.S_RECHECK64) > 0).sum()))
         if mode == fn.SEARCH_WINDOW:
             pre = float(np.mean([a[0].elapsed_time(a[2]) for a in edge_ms]))
-            feas = jj >= 0
-            miss = (st & fn.S_WIN_MISS) > 0
-            f.update(features_infer_ms=pre,
-                     miss_rate_feasible=float(miss[feas].mean()) if feas.any() else None,
-                     miss_rate_all=float(miss.mean()),
-                     below_window_rate=float(((st & fn.S_WIN_BELOW) > 0).mean()))
+            f.update(features_infer_ms=pre)
+            f.update(window_stats(args, ctx, net, tree, ld, n, cand, idx, grid, sh, obs, feats,
+                                  out, fn, torch))
+        f["roofline"] = {"bound": "alu", "achieved": f["fp32_tflops"], "peak": PEAK_FP32 / 1e12,
+                         "unit": "TFLOP/s", "frac": f["fp32_tflops"] * 1e12 / PEAK_FP32}
         forms[name] = f
     best = min(forms, key=lambda k: forms[k]["ms_per_step"])
     speed = {}
@@ -249,6 +260,8 @@ def main():
                                "post_checked_edges": bf["post_checked"],
                                "clearance_checked_edges": bf["clearance_checked"]}},
     }
+    res["roofline_other"] = other_rooflines(args, ctx, net, tree, ld, n, cand, idx, grid, sh,
+                                            feats, win, fn, torch)
     if args.batch_problems > 0:
         res["batched_round"] = batched_round(args, fn, W, torch)
     if args.profile:
@@ -265,16 +278,102 @@ def main():
     ctx.close()
 
 
-def kernel_source_hash():
-    """Hash of the code the search kernels are built from (comments and
-    blank lines dropped): a stored traffic figure applies only to the kernel
-    it was measured on."""
+def window_stats(args, ctx, net, tree, ld, n, cand, idx, grid, sh, obs, feats, out, fn, torch):
+    """Window outcome of the timed window runs (out holds the last one) and
+    what the network gains: the same exact search with the window placed at
+    the first slot the endpoint screen leaves open (no network), and the
+    network's raw window before that lower bound is applied."""
+    jj = out["j"].cpu().numpy().astype(np.int64)
+    st = out["status"].cpu().numpy().astype(np.uint16)
+    feas = jj >= 0
+    miss = (st & fn.S_WIN_MISS) > 0
+    y, w_net = net.infer(feats, grid, half=args.half)
+    E = jj.size
+    base = ctx.edge_time_batch(tree, ld, n, cand, idx, grid, sh.samples, obs,
+                               mode=fn.SEARCH_WINDOW,
+                               win_lo=torch.zeros(E, dtype=torch.int16, device="cuda"),
+                               win_half=args.half, want_rho=False)
+    torch.cuda.synchronize()
+    jb = base["j"].cpu().numpy().astype(np.int64)
+    sb = base["status"].cpu().numpy().astype(np.uint16)
+    assert np.array_equal(jb, jj), "window placement changed a result"
+    miss_base = (sb & fn.S_WIN_MISS) > 0
+    lo = w_net.cpu().numpy().astype(np.int64)
+    raw_hit = feas & (jj >= lo) & (jj <= lo + 2 * args.half)
+    lg = np.log(grid.cpu().numpy().astype(np.float64))
+    yy = y.cpu().numpy().astype(np.float64)
+    lt_hat = 0.5 * (lg[0] + lg[-1]) + 0.5 * (lg[-1] - lg[0]) * yy[:, 0]
+    err = np.abs(lt_hat[feas] - lg[jj[feas]])
+    nf = max(1, int(feas.sum()))
+    return dict(
+        miss_rate_feasible=float(miss[feas].sum() / nf),
+        miss_rate_all=float(miss.mean()),
+        below_window_rate=float(((st & fn.S_WIN_BELOW) > 0).mean()),
+        miss_rate_feasible_raw_network_window=float(1.0 - raw_hit.sum() / nf),
+        miss_rate_feasible_without_network=float(miss_base[feas].sum() / nf),
+        logT_abs_err_median=float(np.median(err)) if err.size else None,
+        logT_abs_err_p90=float(np.quantile(err, 0.9)) if err.size else None,
+        bin_width_logT=float((lg[-1] - lg[0]) / (len(lg) - 1)),
+        predicted_infeasible_frac=float((yy[:, 1] < 0.0).mean()))
+
+
+def other_rooflines(args, ctx, net, tree, ld, n, cand, idx, grid, sh, feats, win, fn, torch):
+    """Rooflines of the kNN call (scan + merge; FP32 VALU) and of the fused
+    surrogate inference kernel (BF16 matrix cores), each timed alone with HIP
+    events on the stream the library launches on."""
+    stream = torch.cuda.current_stream()
+
+    def time_it(call, reps):
+        for _ in range(2):
+            call()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            call()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    reps = max(5, args.steps)
+    res = {}
+    ms = time_it(lambda: ctx.plan_knn(tree, ld, n, cand, sh.k, out_idx=idx, want_d2=False), reps)
+    flop = float(sh.batch) * n * F_KNN_PAIR
+    res["plan_knn"] = {"bound": "alu", "achieved": flop / (ms * 1e-3) / 1e12,
+                       "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+                       "frac": flop / (ms * 1e-3) / PEAK_FP32, "ms": ms,
+                       "pairs": sh.batch * n, "flop_per_pair": F_KNN_PAIR,
+                       "traffic": traffic_bytes("knn_scan", "knn")}
+    if net is not None:
+        E = feats.shape[0]
+        ms = time_it(lambda: net.infer(feats, grid, half=args.half, want_out=False, win_lo=win),
+                     reps)
+        flop = float(E) * F_MLP_ROW
+        res["mlp_infer_fused"] = {"bound": "mfma", "achieved": flop / (ms * 1e-3) / 1e12,
+                                  "peak": PEAK_BF16 / 1e12, "unit": "TFLOP/s",
+                                  "frac": flop / (ms * 1e-3) / PEAK_BF16, "ms": ms, "rows": E,
+                                  "flop_per_row": F_MLP_ROW}
+    return res
+
+
+# Sources each counter record depends on: a stored traffic figure applies
+# only to the kernel code it was measured on.
+KERNEL_SOURCES = {
+    "edge_time_kernel": ("fn_internal.h", "fn_ctx.h", "fn_edge.h", "fn_edge.hip"),
+    "knn_scan": ("fn_internal.h", "fn_ctx.h", "fn_knn.h", "fn_knn.hip"),
+}
+
+
+def kernel_source_hash(kernel="edge_time_kernel"):
+    """Hash of the code a kernel is built from (comments and blank lines
+    dropped)."""
     import hashlib
     import re
 
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2609_22608_amd", "csrc")
-    for name in ("fn_internal.h", "fn_ctx.h", "fn_edge.h", "fn_edge.hip"):
+    for name in KERNEL_SOURCES[kernel]:
         with open(os.path.join(d, name)) as f:
             text = f.read()
         text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
@@ -293,7 +392,7 @@ def traffic_bytes(kernel, form):
     except (OSError, ValueError):
         return None
     rec = t.get(kernel, {})
-    if rec.get("source_hash") != kernel_source_hash() or rec.get("form") != form:
+    if rec.get("source_hash") != kernel_source_hash(kernel) or rec.get("form") != form:
         return None
     return rec.get("bytes_per_launch")
 
@@ -363,31 +462,34 @@ def batched_round(args, fn, W, torch):
 
 
 def surrogate(args, ctx, arm, sh, fn, W, torch):
-    """The T-window network: loaded from a checkpoint, or trained here on
-    one-iteration batches with seeds disjoint from the benchmark's."""
+    """The T-window network: loaded from a checkpoint, or trained here to the
+    recipe (one-iteration batches with seeds disjoint from the benchmark's,
+    labelled by the exact search, 20 epochs of minibatch 4,096, Adam with a
+    cosine-decayed learning rate of 1e-3) by the library's own kernels."""
     if args.surrogate and os.path.exists(args.surrogate):
         return fn.Surrogate.load(ctx, args.surrogate), {"checkpoint": args.surrogate}
+    from paper_2609_22608_amd import train_surrogate as TS
+
     t0 = time.perf_counter()
-    grid = fn.dev(W.t_grid(sh.n_t, sh.t_min, sh.t_max))
-    Xs, ys = [], []
-    for seed in range(1000, 1000 + args.train_batches):
-        w = W.make_workload(sh, seed=seed, arm=arm)
-        tree, ld, n = fn.tree_soa(w["tree_x"])
-        cand = fn.dev(w["cand"]["x"])
-        idx, _ = ctx.plan_knn(tree, ld, n, cand, sh.k, want_d2=False)
-        o = ctx.edge_time_batch(tree, ld, n, cand, idx, grid, sh.samples, fn.dev(w["obs"]),
-                                mode=fn.SEARCH_SCREEN, want_rho=False, want_work=False)
-        Xs.append(fn.edge_features(ctx, tree, ld, n, cand, idx))
-        ys.append(o["j"].clone())
-    X, y = torch.cat(Xs), torch.cat(ys)
+    X, y, grid = TS.label_batches(ctx, arm, sh, range(1000, 1000 + args.train_batches), fn,
+                                  torch, W)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
     net = fn.Surrogate(ctx, seed=1)
+    t1 = time.perf_counter()
     losses = net.train(X, y, grid, epochs=args.train_epochs, batch=4096, lr=1e-3)
     torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
     L = losses.cpu().numpy()
-    return net, {"train_edges": int(X.shape[0]), "epochs": args.train_epochs,
-                 "seeds": f"1000..{999 + args.train_batches}",
-                 "loss_first_last": [float(L[0, 0]), float(L[-1, 0])],
-                 "setup_s": time.perf_counter() - t0}
+    rows = X.shape[0] // 4096 * 4096 * args.train_epochs
+    info = {"train_edges": int(X.shape[0]), "epochs": args.train_epochs,
+            "seeds": f"1000..{999 + args.train_batches}",
+            "feasible_frac": float((y >= 0).float().mean().item()),
+            "loss_first_last": [float(L[0, 0]), float(L[-1, 0])],
+            "label_s": t_data, "train_s": t_train,
+            "train_bf16_tflops": rows * 3 * F_MLP_ROW / t_train / 1e12}
+    del X, y
+    return net, info
 
 
 def diagnostics(o, sh, fn):

@@ -1,6 +1,11 @@
-"""Builds libfruitninja.so from the HIP sources for gfx950 (hipcc)."""
+"""Builds libfruitninja.so from the HIP sources for gfx950 (hipcc).
+
+Each translation unit is compiled to an object file in parallel, then the
+objects are linked into the shared library.
+"""
 from __future__ import annotations
 
+import concurrent.futures as cf
 import os
 import subprocess
 import sys
@@ -8,9 +13,11 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfruitninja.so")
-SOURCES = ["fn_core.hip", "fn_knn.hip", "fn_edge.hip", "fn_mlp.hip", "fn_batch.hip"]
+OBJ = os.path.join(HERE, "_build")
+SOURCES = ["fn_core.hip", "fn_knn.hip", "fn_edge.hip", "fn_mlp.hip", "fn_batch.hip",
+           "fn_static.hip"]
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # no packed FP32 instructions (v_pk_*_f32)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
@@ -18,13 +25,26 @@ FLAGS = [
 
 
 def sources():
-    return [os.path.join(CSRC, s) for s in SOURCES]
+    return [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
 
 
 def build(verbose: bool = False, extra=()) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    os.makedirs(OBJ, exist_ok=True)
+    srcs = sources()
+    objs = [os.path.join(OBJ, os.path.basename(s)[:-4] + ".o") for s in srcs]
+
+    def compile_one(pair):
+        src, obj = pair
+        cmd = [hipcc, *FLAGS, *extra, "-c", "-o", obj, src]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
+
+    with cf.ThreadPoolExecutor(max(1, min(len(srcs), os.cpu_count() or 1, 8))) as ex:
+        list(ex.map(compile_one, zip(srcs, objs)))
     tmp = LIB + ".tmp"
-    cmd = [hipcc, *FLAGS, *extra, "-o", tmp, *sources()]
+    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

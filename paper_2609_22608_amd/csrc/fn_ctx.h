@@ -27,7 +27,7 @@ struct QEntry {
   int16_t j;
   int16_t phase;
   int16_t j2;
-  int16_t pad;
+  int16_t wlo;       // window mode: lowest slot of the window
   int32_t work;      // evaluated sample lanes of the FP32 search
   float margin;      // smallest |rho - 1| of the slots below j
   float margin2;     // the same over the slots in (j, j2], FP32

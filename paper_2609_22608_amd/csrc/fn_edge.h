@@ -13,11 +13,13 @@
 //            ratio exceeds 1 + BAND is infeasible for certain and never
 //            evaluated in full.  Then full passes over the remaining slots
 //            in ascending order.
-//  WINDOW -- the surrogate's window [lo, lo + 2h]: slots below it are
-//            screened (the certificate), the window is evaluated in full, the
-//            slots above it are screened only if the window holds no
-//            feasible slot.  "Hit" = the result lies in the window (or the
-//            network predicted no feasible slot and there is none).
+//  WINDOW -- every slot is screened first, as in SCREEN; the surrogate's
+//            window [lo, lo + 2h] then starts no lower than the first slot
+//            the screen leaves open (slots below it are certified
+//            infeasible, so no window needs them), and the open slots are
+//            scanned below, inside and above the window in ascending order.
+//            The work equals SCREEN's; "hit" = the result lies in the window
+//            (or the network predicted no feasible slot and there is none).
 // Every FP32 ratio within BAND of 1 that a decision rests on sends the edge
 // to the FP64 stage.  At the first slot in the band the search does not
 // stop: it goes on to the next candidate slot and post-checks both in FP32,
@@ -291,7 +293,7 @@ struct SlotMask {
 __device__ __forceinline__ void push_queue(const EdgeArgs& a, int64_t e, int j, int phase, int j2,
                                            float m, float m2, int work, float rho, float rho2,
                                            float v1, float q1, float c1, float v2, float q2,
-                                           float c2, const SlotMask& todo) {
+                                           float c2, const SlotMask& todo, int wlo) {
   if (lane_id() == 0) {
     const int slot = atomicAdd(a.q_count, 1);
     QEntry q;
@@ -299,7 +301,7 @@ __device__ __forceinline__ void push_queue(const EdgeArgs& a, int64_t e, int j, 
     q.j = (int16_t)j;
     q.phase = (int16_t)phase;
     q.j2 = (int16_t)j2;
-    q.pad = 0;
+    q.wlo = (int16_t)wlo;
     q.work = work;
     q.margin = m;
     q.margin2 = m2;
@@ -328,8 +330,8 @@ __device__ __forceinline__ void push_queue(const EdgeArgs& a, int64_t e, int j, 
 // ascending order, certified slots skipped):
 //   PLAIN : scan [0, jmax]
 //   SCREEN: screen [0, jmax], scan [0, jmax]
-//   WINDOW: screen [0, lo-1], scan [0, lo-1], scan [lo, hi],
-//           screen [hi+1, jmax], scan [hi+1, jmax]
+//   WINDOW: screen [0, jmax], scan [0, lo-1], scan [lo, hi], scan [hi+1, jmax]
+//           (lo raised to the first open slot once the screen is done)
 // One loop walks the stages so that the evaluation of Eq. (4) has a single
 // call site.
 // ---------------------------------------------------------------------------
@@ -348,11 +350,10 @@ __device__ __forceinline__ void stage_of(int mode, int st, int jmax, int lo, int
     if (st == 1) { type = ST_SCAN; a = 0; b = jmax; }
   } else {
     switch (st) {
-      case 0: type = ST_SCREEN; a = 0; b = lo - 1; break;
+      case 0: type = ST_SCREEN; a = 0; b = jmax; break;
       case 1: type = ST_SCAN; a = 0; b = lo - 1; below = true; break;
       case 2: type = ST_SCAN; a = lo; b = hi; break;
-      case 3: type = ST_SCREEN; a = hi + 1; b = jmax; break;
-      case 4: type = ST_SCAN; a = hi + 1; b = jmax; break;
+      case 3: type = ST_SCAN; a = hi + 1; b = jmax; break;
       default: break;
     }
   }
@@ -471,7 +472,9 @@ __device__ void search_edge(const EdgeArgs& a, int64_t e, int64_t eq, const ArmC
   int jmax = n_t - 1;
   if (a.j_max && !fixed) jmax = min(jmax, (int)a.j_max[e]);
   if (jmax < 0) {
-    write_out(a, e, -1, FN_S_NONE, INFINITY, 0, 0, 0, 0, 0);
+    // no slot to search: the window is empty and so is the result (a hit)
+    write_out(a, e, -1, FN_S_NONE | (mode == FN_SEARCH_WINDOW ? FN_S_WIN_HIT : 0), INFINITY, 0,
+              0, 0, 0, 0);
     return;
   }
   const int S = a.S, Sw = a.Sw, G = WAVE / Sw;
@@ -511,6 +514,13 @@ __device__ void search_edge(const EdgeArgs& a, int64_t e, int64_t eq, const ArmC
   int j = sa;
   while (type != ST_END) {
     if (j > sb) {
+      if (mode == FN_SEARCH_WINDOW && stage == 0) {
+        // every slot is screened: the window starts no lower than the first
+        // slot the screen leaves open
+        const int f0 = todo.next(0, jmax);
+        wlo = max(wlo, f0 < 0 ? jmax + 1 : f0);
+        whi = min(wlo + 2 * a.win_half, jmax);
+      }
       ++stage;
       stage_of(mode, stage, jmax, wlo, whi, type, sa, sb, below);
       j = sa;
@@ -648,12 +658,12 @@ __device__ void search_edge(const EdgeArgs& a, int64_t e, int64_t eq, const ArmC
   if (jn >= 0) {
     const bool j2near = jstar >= 0 && near_one(rho_star);
     push_queue(a, eq, jn, ph_b | (j2near ? PH_J2_NEAR : 0), jstar, s_fix[3], m, work, s_fix[2],
-               jstar >= 0 ? rho_star : lastv, v1, q1, c1, rv, rq, rc, todo);
+               jstar >= 0 ? rho_star : lastv, v1, q1, c1, rv, rq, rc, todo, wlo);
     return;
   }
   if (near_one(rv) || near_one(rq) || (a.n_obs > 0 && near_one(rc))) {
     push_queue(a, eq, jstar, PH_POST | ph_b, -1, m, INFINITY, work, rho_star, 0.f, rv, rq, rc, 0.f,
-               0.f, 0.f, todo);
+               0.f, 0.f, todo, wlo);
     return;
   }
   m = fminf(m, fminf(fabsf(rv - 1.f), fminf(fabsf(rq - 1.f), fabsf(rc - 1.f))));
@@ -754,7 +764,7 @@ __device__ void recheck_edge(const EdgeArgs& a, int64_t e, const QEntry& q,
   }
   int winbits = 0;
   if (a.mode == FN_SEARCH_WINDOW && !fixed) {
-    const int wlo = min(max((int)a.win_lo[e], 0), jmax + 1);
+    const int wlo = q.wlo;  // raised to the first open slot by the search
     const int whi = min(wlo + 2 * a.win_half, jmax);
     const bool below = (q.phase & PH_BELOW_FULL) != 0;
     const bool hit = (jstar >= 0 && jstar >= wlo && jstar <= whi) || (jstar < 0 && wlo > jmax);

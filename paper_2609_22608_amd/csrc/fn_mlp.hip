@@ -349,6 +349,131 @@ __global__ void mlp_window(const float* __restrict__ Y, int rows, const float* _
   win[r] = (int16_t)max(0, j - half);
 }
 
+// ---------------------------------------------------------------------------
+// Fused inference: all four layers of FR rows in one workgroup.  The row
+// tile's activations stay in LDS (one BF16 buffer, row stride HLD); wave w
+// computes output columns [64 w, 64 w + 64) of a 256-wide layer for all FR
+// rows (4 x 4 tiles of 16 x 16, FP32 accumulators), with the weights read
+// from L2 straight into the MFMA B operands.  Every wave holds its whole
+// output tile in registers until the layer's reads are done, so one barrier
+// later the tile overwrites the layer's input in place.  The MFMA
+// instruction, operand layout and K order are those of gemm_bf16, so the
+// outputs equal the layer-by-layer path bit for bit.
+// ---------------------------------------------------------------------------
+constexpr int FR = 64;        // rows per workgroup
+constexpr int HLD = W + 8;    // LDS row stride of the activation tile (BF16)
+
+// One 256-wide layer, K inputs (a multiple of 32) from Hs, SiLU(z + bias)
+// rounded to BF16 back into Hs.
+template <int K>
+__device__ __forceinline__ void fused_layer(bf16 (*Hs)[HLD], const bf16* __restrict__ Wt, int ldw,
+                                            const float* __restrict__ bias, int wave, int lane) {
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int row = lane & 15, kg = (lane >> 4) * 8, n0 = wave * 64;
+#pragma unroll
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    bf16x8 b[4], a[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      b[j] = *reinterpret_cast<const bf16x8*>(Wt + (size_t)(n0 + 16 * j + row) * ldw + k0 + kg);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] = *reinterpret_cast<const bf16x8*>(&Hs[16 * i + row][k0 + kg]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+  }
+  __syncthreads();  // every wave has read the layer's input
+  // result fragment: lane l holds rows 4 (l >> 4) .. + 3 of column (l & 15)
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int n = n0 + 16 * j + row;
+    const float bn = bias[n];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const float z = acc[i][j][t] + bn;
+        Hs[16 * i + (lane >> 4) * 4 + t][n] = (bf16)(z * sigmoidf_(z));
+      }
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void mlp_infer_fused(const float* __restrict__ X, int64_t N,
+                                                       Norm nm, const bf16* __restrict__ wb,
+                                                       const float* __restrict__ p,
+                                                       const float* __restrict__ grid, int n_t,
+                                                       int half, float logit_min,
+                                                       float* __restrict__ out,
+                                                       int16_t* __restrict__ win) {
+  __shared__ bf16 Hs[FR][HLD];
+  __shared__ float s_y[FR][NOUT];
+  __shared__ float s_lg[FN_MAX_NT];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int64_t r0 = (int64_t)blockIdx.x * FR;
+  // normalised inputs, padded to 32 columns, rounded to BF16 (rows past N: 0)
+  for (int t = tid; t < FR * NIN_P; t += 256) {
+    const int r = t / NIN_P, c = t % NIN_P;
+    const int64_t row = r0 + r;
+    Hs[r][c] = (bf16)(c < NIN && row < N ? (X[row * NIN + c] - nm.shift[c]) * nm.scale[c] : 0.f);
+  }
+  if (win)
+    for (int t = tid; t < n_t; t += 256) s_lg[t] = logf(grid[t]);
+  __syncthreads();
+  fused_layer<NIN_P>(Hs, wb + OFF_W1, NIN_P, p + OFF_B1, wave, lane);
+  fused_layer<W>(Hs, wb + OFF_W2, W, p + OFF_B2, wave, lane);
+  fused_layer<W>(Hs, wb + OFF_W3, W, p + OFF_B3, wave, lane);
+  {
+    // output layer: wave w takes rows [16 w, 16 w + 16), output columns 0..15
+    // (W4 is padded with zero rows; columns 0 and 1 are the outputs)
+    f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int row = lane & 15, kg = (lane >> 4) * 8;
+    const bf16* W4 = wb + OFF_W4;
+#pragma unroll
+    for (int k0 = 0; k0 < W; k0 += BK) {
+      const bf16x8 a = *reinterpret_cast<const bf16x8*>(&Hs[16 * wave + row][k0 + kg]);
+      const bf16x8 b = *reinterpret_cast<const bf16x8*>(W4 + (size_t)row * W + k0 + kg);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+    }
+    if (row < NOUT) {
+      const float bn = p[OFF_B4 + row];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) s_y[16 * wave + (lane >> 4) * 4 + t][row] = acc[t] + bn;
+    }
+  }
+  __syncthreads();
+  if (tid >= FR) return;
+  const int64_t r = r0 + tid;
+  if (r >= N) return;
+  const float y0 = s_y[tid][0], y1 = s_y[tid][1];
+  if (out) {
+    out[2 * r] = y0;
+    out[2 * r + 1] = y1;
+  }
+  if (!win) return;
+  if (!(y1 >= logit_min)) {
+    win[r] = (int16_t)n_t;
+    return;
+  }
+  const float l0 = s_lg[0], l1 = s_lg[n_t - 1];
+  const float lt = 0.5f * (l0 + l1) + 0.5f * (l1 - l0) * y0;
+  // nearest grid slot in log T (binary search, grid increasing)
+  int lo = 0, hi = n_t - 1;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (s_lg[mid] <= lt) lo = mid;
+    else hi = mid;
+  }
+  const int j = (lt - s_lg[lo] <= s_lg[hi] - lt) ? lo : hi;
+  win[r] = (int16_t)max(0, j - half);
+}
+
 // edge features: row e = (state of tree node nbr[e], state of candidate e / k)
 __global__ void edge_features_kernel(const float* __restrict__ tree, int64_t ld, int n_nodes,
                                      const float* __restrict__ cand, const int32_t* __restrict__ nbr,
@@ -659,18 +784,10 @@ extern "C" int surrogate_infer(fn_ctx* c, const fn_mlp* nc, const float* X, int6
   if (!c || !n || !X || !grid) return fail(FN_E_ARG, "surrogate_infer: NULL argument");
   if (N < 0 || n_t < 2 || n_t > FN_MAX_NT || half < 0) return fail(FN_E_SHAPE, "surrogate_infer: N / n_t / half");
   if (N == 0) return FN_OK;
+  if ((N + FR - 1) / FR > 0x7fffffff) return fail(FN_E_SHAPE, "surrogate_infer: N = %lld", (long long)N);
   hipStream_t s = (hipStream_t)stream;
-  for (int64_t r0 = 0; r0 < N; r0 += n->rows) {
-    const int rows = (int)std::min<int64_t>(n->rows, N - r0);
-    const int rows8 = (rows + 7) & ~7;
-    hipLaunchKernelGGL(mlp_gather, dim3((rows8 + 255) / 256), dim3(256), 0, s, X + r0 * NIN,
-                       (const int16_t*)nullptr, (int64_t)rows, (int64_t)0, (uint64_t)1,
-                       (uint64_t)0, rows8, n->norm, grid, n_t, n->Xb, n->tgt, n->feas, n->nf);
-    mlp_forward(n, rows8, false, s);
-    hipLaunchKernelGGL(mlp_window, dim3((rows + 255) / 256), dim3(256), 0, s, n->Y, rows, grid, n_t,
-                       half, logit_min, out ? out + 2 * r0 : nullptr,
-                       out_win_lo ? out_win_lo + r0 : nullptr);
-  }
+  hipLaunchKernelGGL(mlp_infer_fused, dim3((unsigned)((N + FR - 1) / FR)), dim3(256), 0, s, X, N,
+                     n->norm, n->wb, n->p, grid, n_t, half, logit_min, out, out_win_lo);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? FN_OK : hip_fail(e, "surrogate_infer launch");
 }

@@ -104,7 +104,7 @@ def traffic(args):
         data = {}
         if os.path.exists(args.json):
             data = json.load(open(args.json))
-        data[base] = dict(kernel=args.kernel, form=args.form, source_hash=kernel_source_hash(),
+        data[base] = dict(kernel=args.kernel, form=args.form, source_hash=kernel_source_hash(base),
                           fetch_kib=fk, write_kib=wk, fetch_scale=f_scale, write_scale=w_scale,
                           bytes_per_launch=fb + wb, command=args.command)
         with open(args.json, "w") as f:

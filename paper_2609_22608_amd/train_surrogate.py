@@ -31,22 +31,40 @@ def log(msg):
     print(f"[train_surrogate {time.strftime('%H:%M:%S')}] {msg}", flush=True)
 
 
-def label_batches(ctx, arm, sh, seeds, fn, torch, W):
-    """Edge features and exact slot labels of the given workload seeds."""
+def label_batches(ctx, arm, sh, seeds, fn, torch, W, workers=8):
+    """Edge features and exact slot labels of the given workload seeds.  Host
+    processes (spawned; they import numpy only and never touch the GPU) draw
+    upcoming workloads, at most 2 x workers ahead, while the GPU labels the
+    current one."""
+    import collections
+    import concurrent.futures as cf
+    import multiprocessing as mp
+
     grid = fn.dev(W.t_grid(sh.n_t, sh.t_min, sh.t_max))
     Xs, ys = [], []
-    for i, seed in enumerate(seeds):
-        wl = W.make_workload(sh, seed=seed, arm=arm)
-        tree, ld, n = fn.tree_soa(wl["tree_x"])
-        cand = fn.dev(wl["cand"]["x"])
-        idx, _ = ctx.plan_knn(tree, ld, n, cand, sh.k, want_d2=False)
-        out = ctx.edge_time_batch(tree, ld, n, cand, idx, grid, sh.samples, fn.dev(wl["obs"]),
-                                  mode=fn.SEARCH_SCREEN, want_rho=False, want_work=False)
-        Xs.append(fn.edge_features(ctx, tree, ld, n, cand, idx))
-        ys.append(out["j"].clone())
-        if (i + 1) % 25 == 0:
-            log(f"labelled {i + 1}/{len(seeds)} batches")
+    seeds = list(seeds)
+    with cf.ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn")) as ex:
+        pending = collections.deque()
+        nxt = 0
+        for i in range(len(seeds)):
+            while nxt < len(seeds) and len(pending) < 2 * workers:
+                pending.append(ex.submit(W.make_workload, sh, seeds[nxt], 0, arm))
+                nxt += 1
+            _label_one(ctx, sh, pending.popleft().result(), grid, fn, Xs, ys)
+            if (i + 1) % 50 == 0:
+                log(f"labelled {i + 1}/{len(seeds)} batches")
     return torch.cat(Xs), torch.cat(ys), grid
+
+
+def _label_one(ctx, sh, wl, grid, fn, Xs, ys):
+    """Appends one workload's edge features and exact slot labels."""
+    tree, ld, n = fn.tree_soa(wl["tree_x"])
+    cand = fn.dev(wl["cand"]["x"])
+    idx, _ = ctx.plan_knn(tree, ld, n, cand, sh.k, want_d2=False)
+    out = ctx.edge_time_batch(tree, ld, n, cand, idx, grid, sh.samples, fn.dev(wl["obs"]),
+                              mode=fn.SEARCH_SCREEN, want_rho=False, want_work=False)
+    Xs.append(fn.edge_features(ctx, tree, ld, n, cand, idx))
+    ys.append(out["j"].clone())
 
 
 def evaluate(ctx, net, arm, sh, seeds, fn, torch, W, half=4, logit_min=0.0, reps=5):

@@ -58,23 +58,38 @@ def build(arm, probs, capacity_extra=1024, mode=fn.SEARCH_SCREEN, knn_form=0):
     return ctx, bt
 
 
-def expected_round(arm, wl):
-    """Oracle edge decisions for one round of one problem.  Durations and
-    path times are formed in float32 as the library stores them (t_req and
-    node times are float32 inputs), so the attachment comparison below sees
-    the same sums."""
+def _par(fn_, n, *arrays, threads=16):
+    """Runs an oracle routine over row chunks in a thread pool (the C calls
+    release the GIL) and concatenates the dict results."""
+    import concurrent.futures as cf
+
+    parts = [p for p in np.array_split(np.arange(n), threads) if len(p)]
+    with cf.ThreadPoolExecutor(len(parts)) as ex:
+        res = list(ex.map(lambda p: fn_(*[a[p] for a in arrays]), parts))
+    return {key: np.concatenate([r[key] for r in res]) for key in res[0]
+            if res[0][key] is not None}
+
+
+def expected_round(arm, wl, rows=None):
+    """Oracle edge decisions for one round of one problem (of the candidates
+    `rows` only, when given).  Durations and path times are formed in float32
+    as the library stores them (t_req and node times are float32 inputs), so
+    the attachment comparison below sees the same sums."""
     sh = wl["shape"]
     A = O.make_oarm(arm)
-    cx = wl["cand"]["x"]
+    rows = np.arange(sh.batch) if rows is None else np.asarray(rows)
+    cx = wl["cand"]["x"][rows]
     idx, _ = O.plan_knn(wl["tree_x"], cx, sh.k)
     x0, x1, ok = O.edges_of(wl["tree_x"], cx, idx)
-    kind = np.repeat(wl["cand"]["kind"], sh.k)
+    kind = np.repeat(wl["cand"]["kind"][rows], sh.k)
     t_par = np.asarray(wl["tree_t"], np.float32)[np.maximum(idx.reshape(-1), 0)]
-    t_req = np.repeat(np.asarray(wl["cand"]["t_req"], np.float32), sh.k)
+    t_req = np.repeat(np.asarray(wl["cand"]["t_req"], np.float32)[rows], sh.k)
     Tg = t_req - t_par  # float32, as the goal branch forms it
     grid32 = np.asarray(wl["grid"], np.float32)
-    free = O.edge_time(A, x0, x1, wl["grid"], sh.samples, wl["obs"], parent_ok=ok)
-    goal = O.edge_check(A, x0, x1, Tg.astype(np.float64), sh.samples, wl["obs"])
+    free = _par(lambda a, b, c: O.edge_time(A, a, b, wl["grid"], sh.samples, wl["obs"],
+                                            parent_ok=c), len(x0), x0, x1, ok)
+    goal = _par(lambda a, b, t: O.edge_check(A, a, b, t, sh.samples, wl["obs"]), len(x0), x0, x1,
+                Tg.astype(np.float64))
     gst = goal["status"].astype(np.int64)
     g_none = (gst & O.S_NONE) > 0
     gst = np.where(g_none, O.S_NONE, gst)  # an infeasible slot ends the check
@@ -149,6 +164,90 @@ def test_batch_matches_oracle_and_attachment_rule():
         print(f"problem {p}: {sh.n_nodes} nodes, {sh.batch} candidates, {sh.n_obs} obstacles, "
               f"{int(has.sum())} attached ({int(goals.sum())} goal), "
               f"{int((~ex['strict']).sum())} edges in the band")
+
+
+def test_bench_problem_set_full_size():
+    """The benchmark's own round: 32 problems (make_problem_set(32, 101)),
+    trees of 1,343-50,955 nodes, 298-7,786 candidates, 638,352 edges, in the
+    screened form with a node capacity of n + B each.  Every problem: the
+    attachment rule holds for the library's own decisions (each attached
+    candidate takes its valid parent of least t(parent) + T, nodes appended
+    in candidate order, node count, parent, time and state of every new
+    node).  The smallest tree (1,343 nodes, all 1,533 candidates) is checked
+    in full against the oracle; the largest (50,955 nodes) on 64 sampled
+    candidates (512 edges): parents bit-exact, decisions on strict edges,
+    attachment and risk from oracle decisions."""
+    arm, probs = W.make_problem_set(32, 101, nodes=(1024, 65536), batch=(256, 8192))
+    sh = probs[0]["shape"]
+    sumB = sum(p["shape"].batch for p in probs)
+    cap = max(p["shape"].n_nodes + p["shape"].batch for p in probs)
+    ctx = fn.Context(arm, cap, sumB, sh.k, max_edges=sumB * sh.k, max_problems=len(probs))
+    grid = fn.dev(probs[0]["grid"])
+    bt = fn.Batch(ctx, grid, sh.samples, sh.k, mode=fn.SEARCH_SCREEN)
+    for wl in probs:
+        bt.add_problem(wl["tree_x"], wl["tree_t"], wl["cand"], wl["obs"],
+                       capacity=wl["shape"].n_nodes + wl["shape"].batch)
+    bt.prepare()
+    bt.launch()
+    torch.cuda.synchronize()
+    assert sum(p["shape"].batch for p in probs) * sh.k == 638352
+    R = O.make_orisk(sigma_mode=1, s0=0.01, s1=0.05)
+    small = int(np.argmin([p["shape"].n_nodes for p in probs]))
+    large = int(np.argmax([p["shape"].n_nodes for p in probs]))
+    for p, (wl, P) in enumerate(zip(probs, bt.problems)):
+        k, B, n0 = sh.k, wl["shape"].batch, wl["shape"].n_nodes
+        nbr = P["nbr"].cpu().numpy()
+        gj = P["out_j"].cpu().numpy().astype(np.int64)
+        gs = P["out_status"].cpu().numpy().astype(np.uint16).astype(np.int64)
+        gT = P["out_T"].cpu().numpy()
+        node = P["out_node"].cpu().numpy()
+        t_par = np.asarray(wl["tree_t"], np.float32)[np.maximum(nbr.reshape(-1), 0)]
+        valid = ((gj >= 0) & ((gs & FAIL) == 0)).reshape(B, k)
+        cost = np.where(valid, (t_par + gT).reshape(B, k), np.float32(np.inf))
+        pick = np.argmin(cost, axis=1)
+        has = np.isfinite(cost.min(axis=1))
+        exp_node = np.where(has, n0 + np.cumsum(has) - 1, -1)
+        assert np.array_equal(node, exp_node), p
+        assert int(P["n_nodes"].item()) == n0 + int(has.sum()), p
+        att = np.nonzero(has)[0]
+        par = P["parent"].cpu().numpy()
+        assert np.array_equal(par[exp_node[att]], nbr[att, pick[att]]), p
+        assert np.array_equal(P["t_node"].cpu().numpy()[exp_node[att]], cost[att, pick[att]]), p
+        tree = P["tree"].cpu().numpy()
+        assert np.array_equal(tree[:, exp_node[att]].T, wl["cand"]["x"][att].astype(np.float32)), p
+        if p not in (small, large):
+            continue
+        rows = (np.arange(B) if p == small else
+                np.sort(np.random.default_rng(3).choice(B, 64, replace=False)))
+        print(f"problem {p}: {n0} nodes, {B} candidates, {wl['shape'].n_obs} obstacles; "
+              f"oracle on {len(rows)} candidates", flush=True)
+        ex = expected_round(arm, wl, rows)
+        assert np.array_equal(nbr[rows], ex["idx"]), p
+        e = (rows[:, None] * k + np.arange(k)[None, :]).reshape(-1)
+        bad = ex["strict"] & ((gj[e] != ex["j"]) | ((gs[e] & fn.S_DECISION) != ex["st"]))
+        assert bad.sum() == 0, (p, np.nonzero(bad)[0][:10])
+        ok = gj[e] >= 0
+        assert np.array_equal(gT[e][ok], ex["T"][ok]), p
+        valid_o = (ex["j"] >= 0) & ((ex["st"] & FAIL) == 0)
+        v = np.where(ex["strict"], valid_o, valid.reshape(-1)[e]).reshape(-1, k)
+        c2 = np.where(v, (ex["t_par"] + ex["T"]).reshape(-1, k), np.float32(np.inf))
+        h2 = np.isfinite(c2.min(axis=1))
+        assert np.array_equal(h2, has[rows]), p
+        pk = np.argmin(c2, axis=1)
+        assert np.array_equal(pk[h2], pick[rows][h2]), p
+        J = P["out_J"].cpu().numpy()
+        goals = rows[h2 & (wl["cand"]["kind"][rows] == 1)]
+        if len(goals):
+            b = goals
+            pos = np.searchsorted(rows, b)
+            nu = np.maximum(0.0, ex["rv"][pos * k + pick[b]])  # initial nodes carry nu = 0
+            fl = wl["cand"]["flight"]
+            ref = O.risk_score(R, cost[b, pick[b]].astype(np.float64), fl["v_rel"][b], nu,
+                               np.asarray(fl["v0"])[b, 2], fl["t_fall"][b])
+            assert np.allclose(J[b], ref, rtol=1e-4, atol=1e-4), p
+        print(f"problem {p}: {int(has.sum())} attached, {len(goals)} sampled goal nodes, "
+              f"{int((~ex['strict']).sum())} sampled edges in the band")
+    ctx.close()
 
 
 @pytest.mark.parametrize("form", [0, 3])

@@ -234,9 +234,11 @@ def test_edge_time_iteration_sampled(iteration, mode):
 
 def test_stress_shape_sampled(tmp_path):
     """Full stress shape (262,144 nodes, 65,536 candidates, k = 16, 128 T x 64
-    samples, 20 obstacles: 1,048,576 edges) in the screened form the bench
-    times; 32 sampled candidates (512 edges) checked against the oracle:
-    parents bit-exact, decisions on every strict edge."""
+    samples, 20 obstacles: 1,048,576 edges) in every search form the bench
+    times (plain, screened, windowed with random windows); 32 sampled
+    candidates (512 edges) checked against the oracle in each form: parents
+    bit-exact, decisions on every strict edge; the three forms agree on all
+    1,048,576 edges."""
     import concurrent.futures as cf
 
     sh = W.CONFIGS["stress"]
@@ -245,7 +247,15 @@ def test_stress_shape_sampled(tmp_path):
     tree, ld, n = fn.tree_soa(wl["tree_x"])
     cand = fn.dev(wl["cand"]["x"])
     idx, d2 = ctx.plan_knn(tree, ld, n, cand, sh.k)
-    out = _run_edges(ctx, wl, idx, fn.SEARCH_SCREEN)
+    E = idx.numel()
+    lo = np.random.default_rng(8).integers(0, sh.n_t + 1, E).astype(np.int16)
+    outs = {}
+    for name, mode, kw in (("screen", fn.SEARCH_SCREEN, {}), ("plain", fn.SEARCH_PLAIN, {}),
+                           ("window", fn.SEARCH_WINDOW,
+                            dict(win_lo=fn.dev(lo, torch.int16), win_half=4))):
+        print(f"stress form {name}", flush=True)
+        o = _run_edges(ctx, wl, idx, mode, **kw)
+        outs[name] = {key: o[key].cpu().numpy() for key in ("j", "status", "margin")}
     rows = np.sort(np.random.default_rng(5).choice(sh.batch, 32, replace=False))
     ridx, rd2 = O.plan_knn(wl["tree_x"], wl["cand"]["x"][rows], sh.k)
     assert np.array_equal(idx.cpu().numpy()[rows], ridx)
@@ -261,7 +271,14 @@ def test_stress_shape_sampled(tmp_path):
         refs = list(ex.map(job, parts))
     ref = {key: np.concatenate([r[key] for r in refs]) for key in ("j", "status", "margin")}
     sel = (rows[:, None] * sh.k + np.arange(sh.k)[None, :]).reshape(-1)
-    compare_edges(out, ref, sel, label="stress screen")
+    for name, o in outs.items():
+        g = {key: torch.as_tensor(v) for key, v in o.items()}
+        compare_edges(g, ref, sel, label=f"stress {name}")
+    for name in ("plain", "window"):
+        assert np.array_equal(outs[name]["j"], outs["screen"]["j"]), name
+        da = outs[name]["status"].astype(np.uint16) & fn.S_DECISION
+        db = outs["screen"]["status"].astype(np.uint16) & fn.S_DECISION
+        assert np.array_equal(da, db), name
     ctx.close()
 
 
@@ -284,6 +301,64 @@ def test_modes_agree_full_iteration(iteration):
     wa, wb = a["work"].cpu().numpy(), b["work"].cpu().numpy()
     print(f"work plain {wa.sum()} screen {wb.sum()} ({wa.sum() / max(1, wb.sum()):.2f}x)")
     assert wb.sum() < wa.sum()
+
+
+def check_window_flags(out, lo, half, label):
+    """Every edge with a parent carries exactly one of WIN_HIT / WIN_MISS, and
+    an edge whose result lies in the network's raw window [lo, lo + 2 half] is
+    a hit (the search only raises the window's low end to the first slot the
+    endpoint screen leaves open, which never passes the result)."""
+    st = out["status"].cpu().numpy().astype(np.uint16)
+    gj = out["j"].cpu().numpy().astype(np.int64)
+    has = (st & (fn.S_NO_PARENT | fn.S_BAD_INPUT)) == 0
+    hit = (st & fn.S_WIN_HIT) > 0
+    miss = (st & fn.S_WIN_MISS) > 0
+    assert np.all(hit[has] ^ miss[has]), label
+    raw = has & (gj >= 0) & (gj >= lo) & (gj <= lo + 2 * half)
+    assert hit[raw].all(), (label, np.nonzero(raw & ~hit)[0][:10])
+    return hit, miss
+
+
+def check_screened_margin(out, ref, label):
+    """Screened slots report their endpoint ratio, a lower bound of the full
+    ratio, so a screened search's margin lies between min(oracle margin,
+    1e-3) and the oracle margin (FP32 tolerance)."""
+    m = out["margin"].cpu().numpy().astype(np.float64)
+    r = ref["margin"]
+    fin = np.isfinite(r)
+    assert (m[fin] <= r[fin] * (1 + 1e-3) + 2e-5).all(), label
+    assert (m[fin] >= np.minimum(r[fin], 1e-3) * (1 - 1e-2) - 2e-5).all(), label
+
+
+@pytest.mark.parametrize("half,with_jmax", [(0, False), (1, False), (4, False), (4, True)])
+def test_window_tiny_all_edges_vs_oracle(tiny, half, with_jmax):
+    """Windowed search against the FP64 oracle on every tiny-shape edge, with
+    random windows (including lo = 0, lo = n_t "predicted infeasible" and lo
+    past the top of the grid) and optionally a random j_max bound."""
+    sh = tiny["shape"]
+    ctx = _ctx(tiny)
+    ridx, _ = O.plan_knn(tiny["tree_x"], tiny["cand"]["x"], sh.k)
+    E = ridx.size
+    rng = np.random.default_rng(100 + half + 10 * with_jmax)
+    lo = rng.integers(0, sh.n_t + 4, E).astype(np.int16)
+    lo[:16] = 0
+    lo[16:32] = sh.n_t
+    jm = rng.integers(-1, sh.n_t, E).astype(np.int16) if with_jmax else None
+    out = _run_edges(ctx, tiny, fn.dev(ridx, torch.int32), fn.SEARCH_WINDOW,
+                     win_lo=fn.dev(lo, torch.int16), win_half=half,
+                     j_max=None if jm is None else fn.dev(jm, torch.int16))
+    x0, x1, ok = O.edges_of(tiny["tree_x"], tiny["cand"]["x"], ridx)
+    ref = O.edge_time(O.make_oarm(tiny["arm"]), x0, x1, tiny["grid"], sh.samples, parent_ok=ok,
+                      jmax=jm)
+    label = f"window tiny half={half} jmax={with_jmax}"
+    gj, _ = compare_edges(out, ref, label=label)
+    hit, miss = check_window_flags(out, lo.astype(np.int64), half, label)
+    check_screened_margin(out, ref, label)
+    rho = out["rho"].cpu().numpy()
+    f = gj >= 0
+    assert np.allclose(rho[f, 0], ref["rho"][f, 0], rtol=1e-4)
+    assert np.allclose(rho[f, 1:3], ref["rho"][f, 1:3], rtol=1e-4)
+    print(f"{label}: hits {hit.sum()}, misses {miss.sum()}")
 
 
 def test_edge_time_bad_input_and_padding(tiny):
@@ -368,6 +443,13 @@ def test_edge_check_torques_and_ratios(iteration):
     nerr = np.max(np.abs(tau - rt) / tmax, axis=2) / np.maximum(load, 1e-2)
     print(f"normwise torque error: max {nerr.max():.2e}, p99 {np.quantile(nerr, 0.99):.2e}")
     assert nerr.max() <= 1e-4
+    # componentwise at decision loads: every sample whose peak torque ratio is
+    # at most 1 (the slots a feasibility decision can accept)
+    dec = load <= 1.0
+    assert dec.sum() >= 100
+    print(f"componentwise error at peak ratio <= 1: max {err[dec].max():.2e} "
+          f"over {dec.sum()} samples")
+    assert err[dec].max() <= 1e-4
     rho = out["rho"].cpu().numpy()
     # rho_c is NaN (not evaluated) where a limit check fails: on both sides for
     # every edge whose ratios are all clear of the band

@@ -54,6 +54,37 @@ def test_forward_matches_oracle(setup):
     assert np.median(err) <= 1e-3
 
 
+@pytest.mark.parametrize("N", [1, 63, 64, 65, 4097])
+def test_fused_inference_ragged_rows_and_windows(setup, N):
+    """The one-launch inference kernel over a ragged number of rows: outputs
+    against the BF16-emulating oracle, and the window of every row from its
+    own output (nearest grid slot of the predicted log T, minus half, or n_t
+    below the logit threshold)."""
+    arm, ctx = setup
+    params = M.init_params(21)
+    net = fn.Surrogate(ctx)
+    net.set_params(M.pack(params))
+    X, _ = _batch(arm, N, 40 + N)
+    grid = W.t_grid(64, 0.02, 1.0)
+    out, win = net.infer(fn.dev(X), fn.dev(grid), half=3, logit_min=0.1)
+    torch.cuda.synchronize()
+    Y = out.cpu().numpy().astype(np.float64)
+    ref, _ = M.forward(params, M.features(X[:, :14], X[:, 14:], arm), bf=True)
+    err = np.abs(Y - ref)
+    assert err.max() <= 2e-2 * max(1.0, np.abs(ref).max())
+    assert np.median(err) <= 1e-3
+    y = out.cpu().numpy()
+    lg = np.log(grid.astype(np.float32)).astype(np.float32)
+    lt = np.float32(0.5) * (lg[0] + lg[-1]) + np.float32(0.5) * (lg[-1] - lg[0]) * y[:, 0]
+    d = np.abs(lt[:, None] - lg[None, :])
+    j = np.argmin(d, axis=1)
+    exp = np.where(y[:, 1] >= np.float32(0.1), np.maximum(0, j - 3), 64)
+    got = win.cpu().numpy().astype(np.int64)
+    srt = np.sort(d, axis=1)
+    tie = (srt[:, 1] - srt[:, 0]) < 1e-5  # nearest slot decided by rounding
+    assert np.array_equal(got[~tie], exp[~tie])
+
+
 def test_gradient_matches_oracle(setup):
     arm, ctx = setup
     params = M.init_params(12)
@@ -159,3 +190,19 @@ def test_training_learns_and_window_is_exact(setup):
           f"all edges {miss.mean():.4f}; below-window full passes {below.mean():.4f}; "
           f"work plain {a['work'].sum().item()} window {b['work'].sum().item()}")
     assert b["work"].sum().item() < a["work"].sum().item()
+    # the windowed search never evaluates more than the screened one
+    c = ctx.edge_time_batch(tree, ld, n, cand, idx, grid, sh.samples, obs, mode=fn.SEARCH_SCREEN)
+    torch.cuda.synchronize()
+    assert b["work"].sum().item() <= c["work"].sum().item()
+    # 384 sampled held-out edges of the windowed search against the FP64 oracle
+    nbr = idx.cpu().numpy()
+    sel = np.random.default_rng(17).choice(nbr.size, 384, replace=False)
+    x0, x1, ok = O.edges_of(wl["tree_x"], wl["cand"]["x"], nbr)
+    ref = O.edge_time(O.make_oarm(arm), x0[sel], x1[sel], wl["grid"], sh.samples, wl["obs"],
+                      parent_ok=ok[sel])
+    gj = b["j"].cpu().numpy().astype(np.int64)[sel]
+    gs = db[sel].astype(np.int64)
+    strict = ref["margin"] > 1e-3
+    assert strict.sum() >= 350
+    bad = strict & ((gj != ref["j"]) | (gs != ref["status"]))
+    assert bad.sum() == 0, np.nonzero(bad)[0][:10]
