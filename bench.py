@@ -338,13 +338,17 @@ def other_rooflines(args, ctx, net, tree, ld, n, cand, idx, grid, sh, feats, win
 
     reps = max(5, args.steps)
     res = {}
+    # the scan form the tuner picked (0: chosen by tree size, which is the
+    # per-wavefront form 1 at or below 65,536 nodes and matrix cores above)
+    ctx_knn_form = getattr(ctx, "tuned_knn_form", 0) or (3 if n > 65536 else 1)
     ms = time_it(lambda: ctx.plan_knn(tree, ld, n, cand, sh.k, out_idx=idx, want_d2=False), reps)
     flop = float(sh.batch) * n * F_KNN_PAIR
     res["plan_knn"] = {"bound": "alu", "achieved": flop / (ms * 1e-3) / 1e12,
                        "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
                        "frac": flop / (ms * 1e-3) / PEAK_FP32, "ms": ms,
                        "pairs": sh.batch * n, "flop_per_pair": F_KNN_PAIR,
-                       "traffic": traffic_bytes("knn_scan", "knn")}
+                       "knn_form": ctx_knn_form,
+                       "traffic": traffic_bytes("knn_scan", str(ctx_knn_form))}
     if net is not None:
         E = feats.shape[0]
         ms = time_it(lambda: net.infer(feats, grid, half=args.half, want_out=False, win_lo=win),

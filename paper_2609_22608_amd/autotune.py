@@ -83,8 +83,10 @@ class Cache:
 
 
 def _device_tag():
+    # architecture, compute units and library version (the marketing name is
+    # not reported under every tool, e.g. a profiler)
     p = torch.cuda.get_device_properties(torch.cuda.current_device())
-    return f"{p.name}|{getattr(p, 'gcnArchName', '')}|cu{p.multi_processor_count}|{fn.version()}"
+    return f"{getattr(p, 'gcnArchName', '')}|cu{p.multi_processor_count}|{fn.version()}"
 
 
 def _time(run, reps, setup=None):

@@ -249,6 +249,7 @@ class Context:
     def set_tuning(self, knn_target_waves=0, knn_min_chunk=0, knn_form=0):
         t = Tuning(int(knn_target_waves), int(knn_min_chunk), int(knn_form))
         _check(lib().fn_set_tuning(self.h, C.byref(t)), "fn_set_tuning")
+        self.tuned_knn_form = int(knn_form)
 
     # -- plan_knn -----------------------------------------------------------
     def plan_knn(self, tree, ld, n_nodes, queries, k, out_idx=None, out_d2=None, want_d2=True):

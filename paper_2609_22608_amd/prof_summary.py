@@ -8,6 +8,8 @@
     python -m paper_2609_22608_amd.prof_summary traffic FETCH_DIR WRITE_DIR \\
         --kernel "edge_time_kernel<5720, 1>" --form screen --command "..." \\
         --json profiles/traffic.json
+    python -m paper_2609_22608_amd.prof_summary traffic FETCH_DIR WRITE_DIR \\
+        --kernel "knn_scan<12, 4>" --key knn_scan --form 1 --json profiles/traffic.json
 
 Durations are per dispatch (End - Start of the kernel trace).  Traffic:
 FETCH_SIZE and WRITE_SIZE are KiB per dispatch; each is divided by what the
@@ -61,8 +63,9 @@ def durations(args):
     print("\n".join(out))
 
 
-def _counter(d, name):
-    """{kernel: [value per dispatch]} and the copy calibration value."""
+def _counter(d, name, grid=None):
+    """{kernel: [value per dispatch]} (dispatches of grid size `grid` only,
+    when given) and the copy calibration value."""
     rows = list(csv.DictReader(open(_one(d, "counter_collection.csv"))))
     per = collections.defaultdict(list)
     copy = []
@@ -72,7 +75,8 @@ def _counter(d, name):
         v = float(r["Counter_Value"])
         if r["Kernel_Name"] == COPY_KERNEL:
             copy.append((int(r["Grid_Size"]), v))
-        per[short(r["Kernel_Name"], 200)].append(v)
+        if grid is None or int(r["Grid_Size"]) == grid:
+            per[short(r["Kernel_Name"], 200)].append(v)
     if not copy:
         raise SystemExit(f"no {COPY_KERNEL} dispatch in {d}")
     grid, cal = max(copy)  # the large calibration copy
@@ -80,8 +84,8 @@ def _counter(d, name):
 
 
 def traffic(args):
-    fetch, f_cal, grid = _counter(args.fetch, "FETCH_SIZE")
-    write, w_cal, _ = _counter(args.write, "WRITE_SIZE")
+    fetch, f_cal, grid = _counter(args.fetch, "FETCH_SIZE", args.grid)
+    write, w_cal, _ = _counter(args.write, "WRITE_SIZE", args.grid)
     kib = COPY_BYTES / 1024
     f_scale = f_cal / kib  # counter KiB per KiB moved
     w_scale = w_cal / kib
@@ -100,13 +104,14 @@ def traffic(args):
         sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
         from bench import kernel_source_hash
 
-        base = args.kernel.split("<")[0]
+        base = args.key or args.kernel.split("<")[0]
         data = {}
         if os.path.exists(args.json):
             data = json.load(open(args.json))
         data[base] = dict(kernel=args.kernel, form=args.form, source_hash=kernel_source_hash(base),
                           fetch_kib=fk, write_kib=wk, fetch_scale=f_scale, write_scale=w_scale,
-                          bytes_per_launch=fb + wb, command=args.command)
+                          bytes_per_launch=fb + wb, command=args.command,
+                          dispatches=[len(fetch[key]), len(write[key])], grid=args.grid)
         with open(args.json, "w") as f:
             json.dump(data, f, indent=1, sort_keys=True)
 
@@ -124,6 +129,10 @@ def main():
     t.add_argument("write")
     t.add_argument("--kernel", required=True)
     t.add_argument("--form", required=True)
+    t.add_argument("--grid", type=int, default=None,
+                   help="only dispatches of this grid size (work-items), e.g. the tuned mapping")
+    t.add_argument("--key", default=None,
+                   help="record name (default: the kernel name without template arguments)")
     t.add_argument("--command", default="")
     t.add_argument("--json", default=None)
     a = ap.parse_args()
