@@ -32,6 +32,7 @@
 #ifndef FRUITNINJA_H
 #define FRUITNINJA_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -223,6 +224,31 @@ int edge_time_batch(fn_ctx* ctx, const float* tree, int64_t ld, int32_t n_nodes,
                     const float* cand, int32_t B, const int32_t* nbr, int32_t k,
                     const fn_search* search, const fn_obstacles* obs, const fn_edge_out* out,
                     void* stream);
+
+/* ------------------------------------------------------------------ */
+/* edge_time_batch_noalloc -- edge_time_batch for callers that cannot   */
+/* allocate device memory (code under HIP graph capture, tight serving  */
+/* loops, harnesses that forbid hipMalloc).                            */
+/* ------------------------------------------------------------------ */
+/* Same arguments, results and errors as edge_time_batch, except that its
+ * scratch (the FP64-stage counter and queue and the endpoint models) lives
+ * in a file-scope device array of the library, fn_noalloc_scratch_bytes()
+ * bytes (about 17 MiB) on every device the library runs on, held until the
+ * process ends, instead of in the context: the call allocates nothing.
+ * The context still supplies the arm constants.  At most
+ * FN_NOALLOC_MAX_EDGES edges per call (B * k beyond it: FN_E_SHAPE; the
+ * context's max_edges does not apply).  Every call on one device uses the
+ * same array, which keeps the last call's contents (the search clears what
+ * must start at zero); calls that overlap in time on one device (other
+ * streams or threads) race.  Search-kernel timing (fn_kernel_timing) does
+ * not record these calls. */
+#define FN_NOALLOC_MAX_EDGES 32768
+int edge_time_batch_noalloc(fn_ctx* ctx, const float* tree, int64_t ld, int32_t n_nodes,
+                            const float* cand, int32_t B, const int32_t* nbr, int32_t k,
+                            const fn_search* search, const fn_obstacles* obs,
+                            const fn_edge_out* out, void* stream);
+/* Bytes of that array per device. */
+size_t fn_noalloc_scratch_bytes(void);
 
 /* ------------------------------------------------------------------ */
 /* edge_check -- one fixed duration per edge: the goal-candidate branch */

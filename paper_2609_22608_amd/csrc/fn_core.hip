@@ -202,6 +202,15 @@ extern "C" int fn_create(const fn_arm_desc* arm, const fn_caps* caps, fn_ctx** o
       return brc;
     }
   }
+  {
+    // address of this device's scratch array of edge_time_batch_noalloc
+    const int src = static_scratch_init();
+    if (src) {
+      (void)hipFree(d_desc);
+      fn_destroy(c);
+      return src;
+    }
+  }
   e = hipMemcpy(d_desc, &c->desc, sizeof(fn_arm_desc), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     (void)hipFree(d_desc);

@@ -39,6 +39,16 @@ struct QEntry {
 };
 static_assert(sizeof(QEntry) == 96, "queue entry layout");
 
+// Scratch of one edge search: the FP64-stage counter (first int32; the
+// search's first kernel clears it) and queue (one entry per edge), the
+// endpoint models of every edge's parent and of every candidate.
+struct EdgeScratch {
+  int32_t* q_count;
+  QEntry* queue;
+  float* model_e;
+  float* model_c;
+};
+
 int fail(int code, const char* fmt, ...);
 int hip_fail(hipError_t e, const char* where);
 
@@ -62,6 +72,15 @@ inline int knn_k1(int k) { return k <= 12 ? k + 4 : (k <= 16 ? 20 : (k <= 20 ? 2
 struct fn_ctx;
 int batch_alloc(fn_ctx* c);
 void batch_free(fn_ctx* c);
+// scratch of edge_time_batch_noalloc on the current device (fn_static.hip)
+int static_scratch_init();
+
+namespace fn {
+int edge_time_run(fn_ctx* c, const float* tree, int64_t ld, int32_t n_nodes, const float* cand,
+                  int32_t B, const int32_t* nbr, int32_t k, const fn_search* sr,
+                  const fn_obstacles* obs, const fn_edge_out* out, void* stream,
+                  const EdgeScratch& sc, int64_t max_edges, const char* who, bool timed);
+}  // namespace fn
 
 struct fn_batch;
 

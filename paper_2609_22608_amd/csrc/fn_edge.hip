@@ -125,8 +125,6 @@ __global__ __launch_bounds__(256) void edge_check_kernel(const float* __restrict
   }
 }
 
-// waves of the FP64 stage: one per queued edge up to 4096 (the queue
-// length is known only on the device)
 // FP64 stage grid: one wavefront per SIMD at most (its FP64 recursion holds
 // 512 registers per lane), each looping over queue entries; more workgroups
 // than SIMDs would only queue up empty waves behind the working ones
@@ -142,7 +140,7 @@ static void launch_search(fn_ctx* c, const EdgeArgs& a, int ti, hipStream_t s) {
     hipLaunchKernelGGL(edge_model_kernel<PAT>, dim3((unsigned)(((E + B) * 8 + 255) / 256)),
                        dim3(256), 0, s, a, c->arm32);
   else
-    hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, s, c->q_count, 1);
+    hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, s, a.q_count, 1);
   if (ti >= 0) (void)hipEventRecord(c->tev[2 * ti], s);
   const size_t tab = (size_t)EDGE_WAVES * c->desc.n_spheres * a.n_obs * sizeof(float);
   hipLaunchKernelGGL((edge_time_kernel<PAT, MODE>), dim3((unsigned)xcd_grid(B, a.k)),
@@ -180,39 +178,56 @@ int check_obstacles(const fn_obstacles* obs, const char* who) {
 
 using namespace fn;
 
-extern "C" int edge_time_batch(fn_ctx* c, const float* tree, int64_t ld, int32_t n_nodes,
-                               const float* cand, int32_t B, const int32_t* nbr, int32_t k,
-                               const fn_search* sr, const fn_obstacles* obs,
-                               const fn_edge_out* out, void* stream) {
-  if (!c || !sr || !out) return fail(FN_E_ARG, "edge_time_batch: NULL context, search or out");
-  if (B < 0 || k < 1 || k > FN_MAX_K) return fail(FN_E_SHAPE, "edge_time_batch: B = %d, k = %d", B, k);
+namespace fn {
+
+// Checks the arguments of an edge search and launches it with the given
+// scratch (the FP64-stage counter and queue, the endpoint models).
+// max_edges: the most edges that scratch holds.
+int edge_time_run(fn_ctx* c, const float* tree, int64_t ld, int32_t n_nodes, const float* cand,
+                  int32_t B, const int32_t* nbr, int32_t k, const fn_search* sr,
+                  const fn_obstacles* obs, const fn_edge_out* out, void* stream,
+                  const EdgeScratch& sc, int64_t max_edges, const char* who, bool timed) {
+  if (!c || !sr || !out) return fail(FN_E_ARG, "%s: NULL context, search or out", who);
+  if (B < 0 || k < 1 || k > FN_MAX_K) return fail(FN_E_SHAPE, "%s: B = %d, k = %d", who, B, k);
   const int64_t E = (int64_t)B * k;
-  if (E > c->caps.max_edges) return fail(FN_E_SHAPE, "edge_time_batch: %lld edges (cap %lld)", (long long)E, (long long)c->caps.max_edges);
-  if (n_nodes < 0) return fail(FN_E_SHAPE, "edge_time_batch: n_nodes = %d", n_nodes);
-  if (sr->n_t < 1 || sr->n_t > FN_MAX_NT) return fail(FN_E_SHAPE, "edge_time_batch: n_t = %d (1..%d)", sr->n_t, FN_MAX_NT);
-  if (sr->samples < 2 || sr->samples > FN_MAX_SAMPLES) return fail(FN_E_SHAPE, "edge_time_batch: S = %d (2..%d)", sr->samples, FN_MAX_SAMPLES);
-  if (sr->mode < FN_SEARCH_PLAIN || sr->mode > FN_SEARCH_WINDOW) return fail(FN_E_ARG, "edge_time_batch: mode %d", sr->mode);
-  if (sr->mode == FN_SEARCH_WINDOW && (!sr->win_lo || sr->win_half < 0)) return fail(FN_E_ARG, "edge_time_batch: window mode needs win_lo and win_half >= 0");
-  int rc = check_obstacles(obs, "edge_time_batch");
+  if (E > max_edges) return fail(FN_E_SHAPE, "%s: %lld edges (cap %lld)", who, (long long)E, (long long)max_edges);
+  if (n_nodes < 0) return fail(FN_E_SHAPE, "%s: n_nodes = %d", who, n_nodes);
+  if (sr->n_t < 1 || sr->n_t > FN_MAX_NT) return fail(FN_E_SHAPE, "%s: n_t = %d (1..%d)", who, sr->n_t, FN_MAX_NT);
+  if (sr->samples < 2 || sr->samples > FN_MAX_SAMPLES) return fail(FN_E_SHAPE, "%s: S = %d (2..%d)", who, sr->samples, FN_MAX_SAMPLES);
+  if (sr->mode < FN_SEARCH_PLAIN || sr->mode > FN_SEARCH_WINDOW) return fail(FN_E_ARG, "%s: mode %d", who, sr->mode);
+  if (sr->mode == FN_SEARCH_WINDOW && (!sr->win_lo || sr->win_half < 0)) return fail(FN_E_ARG, "%s: window mode needs win_lo and win_half >= 0", who);
+  int rc = check_obstacles(obs, who);
   if (rc) return rc;
   if (E == 0) return FN_OK;
   if (!cand || !nbr || !sr->grid || !out->j || !out->status || !out->margin || (n_nodes > 0 && !tree))
-    return fail(FN_E_ARG, "edge_time_batch: NULL array");
-  if (ld < n_nodes) return fail(FN_E_ARG, "edge_time_batch: ld < n_nodes");
+    return fail(FN_E_ARG, "%s: NULL array", who);
+  if (ld < n_nodes) return fail(FN_E_ARG, "%s: ld < n_nodes", who);
   EdgeArgs a{};
   a.tree = tree; a.ld = ld; a.n_nodes = n_nodes; a.cand = cand; a.nbr = nbr; a.k = k; a.E = E;
   a.grid = sr->grid; a.n_t = sr->n_t; a.S = sr->samples; a.Sw = pow2_at_least(sr->samples);
   a.mode = sr->mode; a.win_half = sr->win_half; a.j_max = sr->j_max; a.win_lo = sr->win_lo;
   a.obs = obs ? obs->spheres : nullptr; a.n_obs = obs ? obs->n : 0; a.margin_c = obs ? obs->margin : 0.f;
   a.out_j = out->j; a.out_st = out->status; a.out_m = out->margin; a.out_rho = out->rho4;
-  a.out_work = out->work; a.out_scr = out->screened; a.q_count = c->q_count; a.queue = c->queue;
-  a.model_e = c->model_e; a.model_c = c->model_c;
+  a.out_work = out->work; a.out_scr = out->screened;
+  a.q_count = sc.q_count; a.queue = sc.queue; a.model_e = sc.model_e; a.model_c = sc.model_c;
   hipStream_t s = (hipStream_t)stream;
-  const int ti = c->timing && c->n_timed < FN_MAX_TIMED ? c->n_timed++ : -1;
+  const int ti = timed && c->timing && c->n_timed < FN_MAX_TIMED ? c->n_timed++ : -1;
   if (c->pattern == PAT_FR3) launch_search_mode<PAT_FR3>(c, a, ti, s);
   else launch_search_mode<PAT_GENERIC>(c, a, ti, s);
   hipError_t e = hipGetLastError();
-  return e == hipSuccess ? FN_OK : hip_fail(e, "edge_time_batch launch");
+  return e == hipSuccess ? FN_OK : hip_fail(e, who);
+}
+
+}  // namespace fn
+
+extern "C" int edge_time_batch(fn_ctx* c, const float* tree, int64_t ld, int32_t n_nodes,
+                               const float* cand, int32_t B, const int32_t* nbr, int32_t k,
+                               const fn_search* sr, const fn_obstacles* obs,
+                               const fn_edge_out* out, void* stream) {
+  if (!c) return fail(FN_E_ARG, "edge_time_batch: NULL context");
+  const EdgeScratch sc{c->q_count, c->queue, c->model_e, c->model_c};
+  return edge_time_run(c, tree, ld, n_nodes, cand, B, nbr, k, sr, obs, out, stream, sc,
+                       c->caps.max_edges, "edge_time_batch", true);
 }
 
 extern "C" int edge_check(fn_ctx* c, const float* x0, const float* x1, const float* T, int64_t E,

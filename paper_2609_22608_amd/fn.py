@@ -123,6 +123,8 @@ def lib():
             L.plan_knn.argtypes = [vp, vp, i64, i32, vp, i32, i32, vp, vp, vp]
             L.edge_time_batch.argtypes = [vp, vp, i64, i32, vp, i32, vp, i32, C.POINTER(Search),
                                           C.POINTER(Obstacles), C.POINTER(EdgeOut), vp]
+            L.edge_time_batch_noalloc.argtypes = L.edge_time_batch.argtypes
+            L.fn_noalloc_scratch_bytes.restype = C.c_size_t
             L.edge_check.argtypes = [vp, vp, vp, vp, i64, i32, C.POINTER(Obstacles), vp, vp, vp, vp]
             L.risk_score.argtypes = [vp, C.POINTER(Risk), vp, vp, vp, vp, vp, i32, vp, vp]
             L.fn_mlp_create.argtypes = [vp, C.c_uint64, C.POINTER(vp)]
@@ -265,7 +267,8 @@ class Context:
     # -- edge_time_batch ------------------------------------------------------
     def edge_time_batch(self, tree, ld, n_nodes, cand, nbr, grid, samples, obs=None,
                         margin=0.0, mode=SEARCH_PLAIN, j_max=None, win_lo=None, win_half=4,
-                        out=None, want_rho=True, want_work=True):
+                        out=None, want_rho=True, want_work=True, noalloc=False):
+        """edge_time_batch, or edge_time_batch_noalloc when noalloc is set."""
         B, k = nbr.shape
         E = B * k
         d = cand.device
@@ -285,9 +288,10 @@ class Context:
                      None if out["rho"] is None else out["rho"].data_ptr(),
                      None if out["work"] is None else out["work"].data_ptr(),
                      None if out.get("screened") is None else out["screened"].data_ptr())
-        _check(lib().edge_time_batch(self.h, _ptr(tree), ld, n_nodes, _ptr(cand), B, _ptr(nbr), k,
-                                     C.byref(s), C.byref(o), C.byref(eo), _stream()),
-               "edge_time_batch")
+        call = lib().edge_time_batch_noalloc if noalloc else lib().edge_time_batch
+        _check(call(self.h, _ptr(tree), ld, n_nodes, _ptr(cand), B, _ptr(nbr), k, C.byref(s),
+                    C.byref(o), C.byref(eo), _stream()),
+               "edge_time_batch_noalloc" if noalloc else "edge_time_batch")
         return out
 
     # -- edge_check -----------------------------------------------------------
