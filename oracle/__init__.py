@@ -93,6 +93,9 @@ def lib():
             L.oracle_edge_nary.argtypes = [ap, C.c_int, dp, dp, C.c_int, dp, C.c_int, C.c_int, sp]
             L.oracle_edge_check.argtypes = [ap, C.c_int, dp, dp, dp, C.c_int, dp, C.c_int,
                                             C.c_double, up, dp, dp]
+            L.oracle_edge_refine.argtypes = [ap, C.c_int, dp, dp, sp, C.c_int, dp, C.c_int,
+                                             C.c_int, C.c_double, dp, C.c_int, C.c_double, dp,
+                                             dp, up, dp, ip]
             L.oracle_plan_knn.argtypes = [C.c_int, dp, C.c_int, dp, C.c_int, C.c_int, ip, dp]
             L.oracle_log_phi.argtypes = [C.c_double]
             L.oracle_log_phi.restype = C.c_double
@@ -267,6 +270,29 @@ def edge_check(A, x0, x1, T, S, obs=None, margin=0.0, want_tau=False):
                             _p(st, C.c_uint16), _p(rho, C.c_double),
                             _p(tau, C.c_double) if want_tau else None)
     return dict(status=st, rho=rho, tau=tau)
+
+
+def edge_refine(A, x0, x1, j, grid, S, N, eps, obs=None, margin=0.0):
+    """N-ary refinement below the grid result j of every edge (Sec. IV-D):
+    returns T, the final lower end lo, status, rho4 = (rho_tauP(T), rho_v,
+    rho_q, rho_c) and the rounds run."""
+    x0, p0 = _d(x0)
+    x1, p1 = _d(x1)
+    grid, pg = _d(grid)
+    E = x0.shape[0]
+    jj = np.ascontiguousarray(j, np.int16)
+    obs = np.zeros((0, 4)) if obs is None else np.asarray(obs, np.float64).reshape(-1, 4)
+    n_obs = len(obs)
+    obs, po = _d(obs if n_obs else np.zeros((1, 4)))
+    T, lo = np.zeros(E), np.zeros(E)
+    st = np.zeros(E, np.uint16)
+    rho = np.zeros((E, 4))
+    rounds = np.zeros(E, np.int32)
+    lib().oracle_edge_refine(C.byref(A), E, p0, p1, _p(jj, C.c_int16), len(grid), pg, int(S),
+                             int(N), float(eps), po, n_obs, float(margin), _p(T, C.c_double),
+                             _p(lo, C.c_double), _p(st, C.c_uint16), _p(rho, C.c_double),
+                             _p(rounds, C.c_int32))
+    return dict(T=T, lo=lo, status=st, rho=rho, rounds=rounds)
 
 
 def plan_knn(nodes, queries, k):

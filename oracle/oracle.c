@@ -531,6 +531,79 @@ void oracle_edge_nary(const oarm* A, int E, const double* x0, const double* x1, 
   }
 }
 
+/* Multi-round N-ary refinement of the minimum feasible time below the grid
+ * (Sec. IV-D after Def. 7: the interval [T_lo, T_hi] is cut into N equal
+ * slots, their ends are evaluated, and the slot whose end is the first
+ * feasible one is cut again, until it is no wider than eps).  It starts from
+ * the grid search's result j (the first feasible slot): T_hi = grid[j] is
+ * feasible, T_lo = grid[j-1] is not (T_lo = 0 for j = 0).  A round
+ * evaluates t_i = T_lo + i (T_hi - T_lo)/N for i = 1 .. N-1 in ascending
+ * order; the first feasible t_i becomes T_hi and t_{i-1} becomes T_lo; when
+ * none is feasible, T_lo = t_{N-1}.  The result is T_hi, a feasible duration
+ * within eps of the boundary below it.  Velocity taper, position limits and
+ * clearance are then checked at that duration as in the grid search
+ * (clearance only when the limits pass).  Edges with j < 0 are not refined
+ * (T = NaN, status S_NONE).  out_lo: the final T_lo; out_rounds: rounds run;
+ * rho4 = (rho_tauP(T), rho_v, rho_q, rho_c). */
+void oracle_edge_refine(const oarm* A, int E, const double* x0, const double* x1,
+                        const int16_t* j_in, int NT, const double* grid, int S, int N,
+                        double eps, const double* obs, int n_obs, double margin_c,
+                        double* out_T, double* out_lo, uint16_t* out_st, double* out_rho,
+                        int32_t* out_rounds) {
+  int w = 2 * A->n;
+  for (int e = 0; e < E; ++e) {
+    const double* a = x0 + (size_t)e * w;
+    const double* b = x1 + (size_t)e * w;
+    double* r4 = out_rho + (size_t)e * 4;
+    int j = j_in[e];
+    r4[0] = r4[1] = r4[2] = r4[3] = 0.0;
+    out_rounds[e] = 0;
+    if (j < 0 || j >= NT || !finite_state(A->n, a) || !finite_state(A->n, b)) {
+      out_T[e] = NAN;
+      out_lo[e] = NAN;
+      out_st[e] = (j < 0 || j >= NT) ? S_NONE : S_BAD;
+      continue;
+    }
+    double hi = grid[j];
+    double lo = j > 0 ? grid[j - 1] : 0.0;
+    int rounds = 0;
+    while (hi - lo > eps) {
+      double wd = (hi - lo) / (double)N;
+      int first = N;
+      for (int i = 1; i < N; ++i) {
+        double rt, rp;
+        oracle_slot_rho(A, a, b, lo + (double)i * wd, S, &rt, &rp, NULL);
+        if (dmax(rt, rp) <= 1.0) {
+          first = i;
+          break;
+        }
+      }
+      double nlo = lo + (double)(first - 1) * wd;
+      double nhi = first < N ? lo + (double)first * wd : hi;
+      lo = nlo;
+      hi = nhi;
+      rounds++;
+    }
+    double rt, rp;
+    oracle_slot_rho(A, a, b, hi, S, &rt, &rp, NULL);
+    double rv = oracle_rho_v(A, a, b, hi);
+    double rq = oracle_rho_q(A, a, b, hi);
+    double rc = (rv <= 1.0 && rq <= 1.0) ? oracle_rho_c(A, a, b, hi, S, obs, n_obs, margin_c) : NAN;
+    uint16_t st = 0;
+    if (rv > 1.0) st |= S_VEL;
+    if (rq > 1.0) st |= S_POS;
+    if (rc > 1.0) st |= S_COLL;
+    r4[0] = dmax(rt, rp);
+    r4[1] = rv;
+    r4[2] = rq;
+    r4[3] = rc;
+    out_T[e] = hi;
+    out_lo[e] = lo;
+    out_st[e] = st;
+    out_rounds[e] = rounds;
+  }
+}
+
 /* Fixed-duration check of one edge (goal candidates, Alg. 1 fixed-T branch;
  * also the full-resolution recheck of a sent plan, Sec. IV-E).
  * rho5 = (rho_tau, rho_P, rho_v, rho_q, rho_c); T <= 0 is infeasible; rho_c is
