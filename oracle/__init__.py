@@ -96,6 +96,8 @@ def lib():
             L.oracle_edge_refine.argtypes = [ap, C.c_int, dp, dp, sp, C.c_int, dp, C.c_int,
                                              C.c_int, C.c_double, dp, C.c_int, C.c_double, dp,
                                              dp, up, dp, ip]
+            L.oracle_control.argtypes = [ap, C.c_int, dp, dp, dp, dp, dp, dp, C.c_double, dp,
+                                         dp, dp, up]
             L.oracle_plan_knn.argtypes = [C.c_int, dp, C.c_int, dp, C.c_int, C.c_int, ip, dp]
             L.oracle_log_phi.argtypes = [C.c_double]
             L.oracle_log_phi.restype = C.c_double
@@ -293,6 +295,24 @@ def edge_refine(A, x0, x1, j, grid, S, N, eps, obs=None, margin=0.0):
                              _p(lo, C.c_double), _p(st, C.c_uint16), _p(rho, C.c_double),
                              _p(rounds, C.c_int32))
     return dict(T=T, lo=lo, status=st, rho=rho, rounds=rounds)
+
+
+C_ACC, C_SLEW, C_TORQUE, C_POWER, C_BAD = 1, 2, 4, 8, 128
+
+
+def control(A, q, qd, tau_prev, qg, qdg, T, dt, slew):
+    """One step of the tracking controller of Eq. (9) per instance: returns
+    (tau [n][dof], clipped qdd [n][dof], status [n])."""
+    arrs = [_d(np.atleast_2d(x)) for x in (q, qd, tau_prev, qg, qdg)]
+    n = arrs[0][0].shape[0]
+    T, pT = _d(np.broadcast_to(np.asarray(T, np.float64), (n,)))
+    slew, ps = _d(slew)
+    tau = np.zeros((n, A.n))
+    qdd = np.zeros((n, A.n))
+    st = np.zeros(n, np.uint16)
+    lib().oracle_control(C.byref(A), n, *[p for _, p in arrs], pT, float(dt), ps,
+                         _p(tau, C.c_double), _p(qdd, C.c_double), _p(st, C.c_uint16))
+    return tau, qdd, st
 
 
 def plan_knn(nodes, queries, k):

@@ -604,6 +604,97 @@ void oracle_edge_refine(const oarm* A, int E, const double* x0, const double* x1
   }
 }
 
+/* ------------------------------------------------------------------ */
+/* The 1 kHz tracking controller (Sec. IV-F, Eq. (9))                  */
+/* ------------------------------------------------------------------ */
+/* Control status bits */
+#define C_ACC 1      /* the desired acceleration was clipped to [l, u] */
+#define C_SLEW 2     /* the torque was clipped to the slew limit */
+#define C_TORQUE 4   /* the torque was clipped to the torque limit */
+#define C_POWER 8    /* the torque was scaled to the power limit */
+#define C_BAD 128    /* non-finite input or horizon T <= 0: zero torque */
+
+/* One control step per instance.  The controller refits the cubic of
+ * Eq. (6) from the measured state (q, qd) to the rendezvous (qg, qdg) over
+ * the horizon T and takes its initial acceleration, Eq. (9):
+ *   qdd_des = 6 (qg - q) / T^2 - (4 qd + 2 qdg) / T.
+ * Readings: [l, u] keeps the velocity after one period dt inside the taper
+ * of Def. 1 (braking law), l = (-qdbar(q, -) - qd) / dt,
+ * u = (qdbar(q, +) - qd) / dt, where qdbar(q, +) = min(qdmax, sqrt(2 acc
+ * (qmax - q)_+)) and qdbar(q, -) = min(qdmax, sqrt(2 acc (q - qmin)_+));
+ * the torque of Eq. (4) at (q, qd, qdd) is then clipped in the order slew
+ * (|tau - tau_prev| <= slew dt), torque (|tau| <= taumax), power (when
+ * |sum tau qd| > W_max the torque is scaled by W_max / |sum tau qd|).
+ * Outputs: tau [n][dof], the clipped acceleration qdd [n][dof], status. */
+void oracle_control(const oarm* A, int n_inst, const double* q, const double* qd,
+                    const double* tau_prev, const double* qg, const double* qdg, const double* T,
+                    double dt, const double* slew, double* out_tau, double* out_qdd,
+                    uint16_t* out_st) {
+  int n = A->n;
+  for (int e = 0; e < n_inst; ++e) {
+    const double* qe = q + (size_t)e * n;
+    const double* ve = qd + (size_t)e * n;
+    const double* pe = tau_prev + (size_t)e * n;
+    const double* ge = qg + (size_t)e * n;
+    const double* we = qdg + (size_t)e * n;
+    double* te = out_tau + (size_t)e * n;
+    double* ae = out_qdd + (size_t)e * n;
+    int ok = isfinite(T[e]) && T[e] > 0.0;
+    for (int i = 0; i < n; ++i)
+      ok = ok && isfinite(qe[i]) && isfinite(ve[i]) && isfinite(pe[i]) && isfinite(ge[i]) &&
+           isfinite(we[i]);
+    if (!ok) {
+      for (int i = 0; i < n; ++i) te[i] = ae[i] = 0.0;
+      out_st[e] = C_BAD;
+      continue;
+    }
+    uint16_t st = 0;
+    double Te = T[e];
+    for (int i = 0; i < n; ++i) {
+      double a = 6.0 * (ge[i] - qe[i]) / (Te * Te) - (4.0 * ve[i] + 2.0 * we[i]) / Te;
+      double vp = sqrt(2.0 * A->acc[i] * dmax(0.0, A->qmax[i] - qe[i]));
+      double vm = sqrt(2.0 * A->acc[i] * dmax(0.0, qe[i] - A->qmin[i]));
+      if (vp > A->qdmax[i]) vp = A->qdmax[i];
+      if (vm > A->qdmax[i]) vm = A->qdmax[i];
+      double lo = (-vm - ve[i]) / dt, hi = (vp - ve[i]) / dt;
+      if (a < lo) {
+        a = lo;
+        st |= C_ACC;
+      } else if (a > hi) {
+        a = hi;
+        st |= C_ACC;
+      }
+      ae[i] = a;
+    }
+    oracle_rnea(A, qe, ve, ae, te);
+    for (int i = 0; i < n; ++i) {
+      double d = slew[i] * dt;
+      if (te[i] > pe[i] + d) {
+        te[i] = pe[i] + d;
+        st |= C_SLEW;
+      } else if (te[i] < pe[i] - d) {
+        te[i] = pe[i] - d;
+        st |= C_SLEW;
+      }
+      if (te[i] > A->taumax[i]) {
+        te[i] = A->taumax[i];
+        st |= C_TORQUE;
+      } else if (te[i] < -A->taumax[i]) {
+        te[i] = -A->taumax[i];
+        st |= C_TORQUE;
+      }
+    }
+    double p = 0.0;
+    for (int i = 0; i < n; ++i) p += te[i] * ve[i];
+    if (fabs(p) > A->wmax) {
+      double s = A->wmax / fabs(p);
+      for (int i = 0; i < n; ++i) te[i] *= s;
+      st |= C_POWER;
+    }
+    out_st[e] = st;
+  }
+}
+
 /* Fixed-duration check of one edge (goal candidates, Alg. 1 fixed-T branch;
  * also the full-resolution recheck of a sent plan, Sec. IV-E).
  * rho5 = (rho_tau, rho_P, rho_v, rho_q, rho_c); T <= 0 is infeasible; rho_c is
