@@ -26,7 +26,7 @@ OSPH = 64
 T_RIGID, T_ARMATURE, T_FRICTION, T_GRAVITY = 1, 2, 4, 8
 T_ALL = T_RIGID | T_ARMATURE | T_FRICTION | T_GRAVITY
 
-S_NONE, S_VEL, S_POS, S_COLL, S_BAD, S_NOPARENT = 1, 2, 4, 8, 128, 512
+S_NONE, S_VEL, S_POS, S_COLL, S_BAD, S_NOPARENT, S_SELF = 1, 2, 4, 8, 128, 512, 1024
 DECISION_BITS = S_NONE | S_VEL | S_POS | S_COLL | S_BAD | S_NOPARENT
 
 
@@ -52,6 +52,40 @@ class OArm(C.Structure):
         ("wmax", C.c_double), ("g", C.c_double * 3), ("tool", C.c_double * 3),
         ("nsph", C.c_int32), ("sph_link", C.c_int32 * OSPH), ("sph", (C.c_double * 4) * OSPH),
     ]
+
+
+class OWorld(C.Structure):
+    _fields_ = [
+        ("sph", C.POINTER(C.c_double)), ("n_sph", C.c_int32),
+        ("cap", C.POINTER(C.c_double)), ("n_cap", C.c_int32),
+        ("margin", C.c_double),
+        ("pairs", C.POINTER(C.c_int32)), ("n_pairs", C.c_int32),
+        ("margin_self", C.c_double),
+    ]
+
+
+def make_world(obs=None, caps=None, pairs=None, margin=0.0, margin_self=0.0):
+    """The oracle's world: obstacle spheres [n][4], obstacle capsules [m][7]
+    = (p0, p1, radius), the clearance margin, and the arm's self-collision
+    sphere pairs [p][2] with their margin (fixed-duration check only).
+    Returns (struct, arrays to keep alive while it is used)."""
+    W = OWorld()
+    keep = []
+    o = np.zeros((0, 4)) if obs is None else np.ascontiguousarray(obs, np.float64).reshape(-1, 4)
+    c = np.zeros((0, 7)) if caps is None else np.ascontiguousarray(caps, np.float64).reshape(-1, 7)
+    p = np.zeros((0, 2), np.int32) if pairs is None else \
+        np.ascontiguousarray(pairs, np.int32).reshape(-1, 2)
+    o, c, p = (np.ascontiguousarray(a) for a in (o, c, p))
+    keep += [o, c, p]
+    W.sph = o.ctypes.data_as(C.POINTER(C.c_double))
+    W.n_sph = len(o)
+    W.cap = c.ctypes.data_as(C.POINTER(C.c_double))
+    W.n_cap = len(c)
+    W.margin = float(margin)
+    W.pairs = p.ctypes.data_as(C.POINTER(C.c_int32))
+    W.n_pairs = len(p)
+    W.margin_self = float(margin_self)
+    return W, keep
 
 
 class ORisk(C.Structure):
@@ -85,17 +119,20 @@ def lib():
             L.oracle_rho_v.restype = C.c_double
             L.oracle_rho_q.argtypes = [ap, dp, dp, C.c_double]
             L.oracle_rho_q.restype = C.c_double
-            L.oracle_rho_c.argtypes = [ap, dp, dp, C.c_double, C.c_int, dp, C.c_int, C.c_double]
+            wp = C.POINTER(OWorld)
+            L.oracle_rho_c.argtypes = [ap, dp, dp, C.c_double, C.c_int, wp]
             L.oracle_rho_c.restype = C.c_double
-            L.oracle_edge_time.argtypes = [ap, C.c_int, dp, dp, ip, C.c_int, dp, C.c_int, sp, dp,
-                                           C.c_int, C.c_double, C.c_int, sp, up, dp, dp, ip]
+            L.oracle_rho_self.argtypes = [ap, dp, dp, C.c_double, C.c_int, wp]
+            L.oracle_rho_self.restype = C.c_double
+            L.oracle_point_segment.argtypes = [dp, dp, dp]
+            L.oracle_point_segment.restype = C.c_double
+            L.oracle_edge_time.argtypes = [ap, C.c_int, dp, dp, ip, C.c_int, dp, C.c_int, sp, wp,
+                                           C.c_int, sp, up, dp, dp, ip]
             L.oracle_edge_dense.argtypes = [ap, C.c_int, dp, dp, C.c_int, dp, C.c_int, dp]
             L.oracle_edge_nary.argtypes = [ap, C.c_int, dp, dp, C.c_int, dp, C.c_int, C.c_int, sp]
-            L.oracle_edge_check.argtypes = [ap, C.c_int, dp, dp, dp, C.c_int, dp, C.c_int,
-                                            C.c_double, up, dp, dp]
+            L.oracle_edge_check.argtypes = [ap, C.c_int, dp, dp, dp, C.c_int, wp, up, dp, dp]
             L.oracle_edge_refine.argtypes = [ap, C.c_int, dp, dp, sp, C.c_int, dp, C.c_int,
-                                             C.c_int, C.c_double, dp, C.c_int, C.c_double, dp,
-                                             dp, up, dp, ip]
+                                             C.c_int, C.c_double, wp, dp, dp, up, dp, ip]
             L.oracle_control.argtypes = [ap, C.c_int, dp, dp, dp, dp, dp, dp, C.c_double, dp,
                                          dp, dp, up]
             L.oracle_plan_knn.argtypes = [C.c_int, dp, C.c_int, dp, C.c_int, C.c_int, ip, dp]
@@ -201,15 +238,31 @@ def rho_q(A, x0, x1, T):
     return lib().oracle_rho_q(C.byref(A), p0, p1, float(T))
 
 
-def rho_c(A, x0, x1, T, S, obs, margin=0.0):
+def rho_c(A, x0, x1, T, S, obs=None, margin=0.0, caps=None):
+    """Clearance ratio against obstacle spheres and capsules (Sec. IV-E)."""
     x0, p0 = _d(x0)
     x1, p1 = _d(x1)
-    obs, po = _d(np.asarray(obs).reshape(-1, 4))
-    return lib().oracle_rho_c(C.byref(A), p0, p1, float(T), int(S), po, len(obs), float(margin))
+    W, keep = make_world(obs, caps, None, margin)
+    return lib().oracle_rho_c(C.byref(A), p0, p1, float(T), int(S), C.byref(W))
+
+
+def rho_self(A, x0, x1, T, S, pairs, margin_self=0.0):
+    """Clearance ratio of the arm's self-collision sphere pairs."""
+    x0, p0 = _d(x0)
+    x1, p1 = _d(x1)
+    W, keep = make_world(None, None, pairs, 0.0, margin_self)
+    return lib().oracle_rho_self(C.byref(A), p0, p1, float(T), int(S), C.byref(W))
+
+
+def point_segment(c, p0, p1):
+    c, pc = _d(c)
+    p0, pa = _d(p0)
+    p1, pb = _d(p1)
+    return lib().oracle_point_segment(pc, pa, pb)
 
 
 def edge_time(A: OArm, x0, x1, grid, S, obs=None, jmax=None, parent_ok=None, margin=0.0,
-              scan=1):
+              scan=1, caps=None):
     """Plain search (Def. 7 on the grid) + post-checks for every edge.
     scan=1 stops at the first feasible slot, scan=0 evaluates every slot.
     rho[:, 3] (rho_c) is NaN where rho_v or rho_q already fails: Alg. 1
@@ -218,9 +271,7 @@ def edge_time(A: OArm, x0, x1, grid, S, obs=None, jmax=None, parent_ok=None, mar
     x1, p1 = _d(x1)
     E = x0.shape[0]
     grid, pg = _d(grid)
-    obs = np.zeros((0, 4)) if obs is None else np.asarray(obs, np.float64).reshape(-1, 4)
-    n_obs = len(obs)
-    obs, po = _d(obs if n_obs else np.zeros((1, 4)))
+    W, keep = make_world(obs, caps, None, margin)
     out_j = np.zeros(E, np.int16)
     out_st = np.zeros(E, np.uint16)
     out_m = np.zeros(E)
@@ -230,7 +281,7 @@ def edge_time(A: OArm, x0, x1, grid, S, obs=None, jmax=None, parent_ok=None, mar
     pok = None if parent_ok is None else np.ascontiguousarray(parent_ok, np.int32)
     lib().oracle_edge_time(C.byref(A), E, p0, p1, None if pok is None else _p(pok, C.c_int32),
                            len(grid), pg, int(S), None if jm is None else _p(jm, C.c_int16),
-                           po, n_obs, float(margin), int(scan), _p(out_j, C.c_int16),
+                           C.byref(W), int(scan), _p(out_j, C.c_int16),
                            _p(out_st, C.c_uint16), _p(out_m, C.c_double), _p(out_rho, C.c_double),
                            _p(out_ns, C.c_int32))
     return dict(j=out_j, status=out_st, margin=out_m, rho=out_rho, nslots=out_ns)
@@ -257,24 +308,25 @@ def edge_nary(A, x0, x1, grid, S, N):
     return out
 
 
-def edge_check(A, x0, x1, T, S, obs=None, margin=0.0, want_tau=False):
+def edge_check(A, x0, x1, T, S, obs=None, margin=0.0, want_tau=False, caps=None, pairs=None,
+               margin_self=0.0):
+    """Fixed-duration check; rho[:, 4] is the larger of the obstacle and
+    self-collision clearance ratios (S_SELF marks the self part > 1)."""
     x0, p0 = _d(x0)
     x1, p1 = _d(x1)
     T, pT = _d(T)
     E = x0.shape[0]
-    obs = np.zeros((0, 4)) if obs is None else np.asarray(obs, np.float64).reshape(-1, 4)
-    n_obs = len(obs)
-    obs, po = _d(obs if n_obs else np.zeros((1, 4)))
+    W, keep = make_world(obs, caps, pairs, margin, margin_self)
     st = np.zeros(E, np.uint16)
     rho = np.zeros((E, 5))
     tau = np.zeros((E, S, A.n)) if want_tau else None
-    lib().oracle_edge_check(C.byref(A), E, p0, p1, pT, int(S), po, n_obs, float(margin),
+    lib().oracle_edge_check(C.byref(A), E, p0, p1, pT, int(S), C.byref(W),
                             _p(st, C.c_uint16), _p(rho, C.c_double),
                             _p(tau, C.c_double) if want_tau else None)
     return dict(status=st, rho=rho, tau=tau)
 
 
-def edge_refine(A, x0, x1, j, grid, S, N, eps, obs=None, margin=0.0):
+def edge_refine(A, x0, x1, j, grid, S, N, eps, obs=None, margin=0.0, caps=None):
     """N-ary refinement below the grid result j of every edge (Sec. IV-D):
     returns T, the final lower end lo, status, rho4 = (rho_tauP(T), rho_v,
     rho_q, rho_c) and the rounds run."""
@@ -283,15 +335,13 @@ def edge_refine(A, x0, x1, j, grid, S, N, eps, obs=None, margin=0.0):
     grid, pg = _d(grid)
     E = x0.shape[0]
     jj = np.ascontiguousarray(j, np.int16)
-    obs = np.zeros((0, 4)) if obs is None else np.asarray(obs, np.float64).reshape(-1, 4)
-    n_obs = len(obs)
-    obs, po = _d(obs if n_obs else np.zeros((1, 4)))
+    W, keep = make_world(obs, caps, None, margin)
     T, lo = np.zeros(E), np.zeros(E)
     st = np.zeros(E, np.uint16)
     rho = np.zeros((E, 4))
     rounds = np.zeros(E, np.int32)
     lib().oracle_edge_refine(C.byref(A), E, p0, p1, _p(jj, C.c_int16), len(grid), pg, int(S),
-                             int(N), float(eps), po, n_obs, float(margin), _p(T, C.c_double),
+                             int(N), float(eps), C.byref(W), _p(T, C.c_double),
                              _p(lo, C.c_double), _p(st, C.c_uint16), _p(rho, C.c_double),
                              _p(rounds, C.c_int32))
     return dict(T=T, lo=lo, status=st, rho=rho, rounds=rounds)

@@ -50,6 +50,7 @@
 #define S_COLL 8     /* rho_c > 1 at the searched T */
 #define S_BAD 128    /* non-finite input */
 #define S_NOPARENT 512 /* padded parent (index -1) */
+#define S_SELF 1024    /* two of the arm's own spheres closer than the margin (full recheck) */
 
 typedef struct {
   int32_t n;       /* joints */
@@ -351,13 +352,49 @@ double oracle_rho_q(const oarm* A, const double* x0, const double* x1, double T)
   }
   return r;
 }
-/* rho_c: clearance of every arm sphere against every obstacle sphere at the
- * S evaluation times, as (r_a + r_o + margin) / distance. */
+/* The world an edge is checked against (Sec. IV-E, collision checking):
+ * obstacle spheres [n_sph][4] = (centre, radius) and obstacle capsules
+ * [n_cap][7] = (segment end p0, segment end p1, radius), both with the
+ * clearance margin `margin`; and the arm's self-collision sphere pairs
+ * [n_pairs][2] (indices into the arm's spheres, the pairs that survive the
+ * offline pruning) with margin `margin_self`, checked by the fixed-duration
+ * check (the full-resolution recheck of the plan sent to the controller). */
+typedef struct {
+  const double* sph;
+  int32_t n_sph;
+  const double* cap;
+  int32_t n_cap;
+  double margin;
+  const int32_t* pairs;
+  int32_t n_pairs;
+  double margin_self;
+} oworld;
+
+/* Distance from point c to the segment p0 p1: the closest point is
+ * p0 + t (p1 - p0) with t the projection clamped to [0, 1]. */
+double oracle_point_segment(const double* c, const double* p0, const double* p1) {
+  double d[3], w[3];
+  for (int r = 0; r < 3; ++r) {
+    d[r] = p1[r] - p0[r];
+    w[r] = c[r] - p0[r];
+  }
+  double dd = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+  double t = dd > 0.0 ? (w[0] * d[0] + w[1] * d[1] + w[2] * d[2]) / dd : 0.0;
+  if (t < 0.0) t = 0.0;
+  if (t > 1.0) t = 1.0;
+  double e[3];
+  for (int r = 0; r < 3; ++r) e[r] = w[r] - t * d[r];
+  return sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+}
+
+/* rho_c: clearance of every arm sphere against every obstacle sphere and
+ * capsule at the S evaluation times, as (r_a + r_o + margin) / distance
+ * (distance to the capsule's segment). */
 double oracle_rho_c(const oarm* A, const double* x0, const double* x1, double T, int S,
-                    const double* obs, int n_obs, double margin) {
+                    const oworld* W) {
   int n = A->n;
   double r = 0.0;
-  if (n_obs <= 0) return 0.0;
+  if (W->n_sph + W->n_cap <= 0) return 0.0;
   double cen[OSPH * 3];
   for (int s = 0; s < S; ++s) {
     double u = (S > 1) ? (double)s / (double)(S - 1) : 0.0;
@@ -365,14 +402,47 @@ double oracle_rho_c(const oarm* A, const double* x0, const double* x1, double T,
     double sg[OJ], sd[OJ], sdd[OJ];
     oracle_cubic(n, x0, x1, T, t, sg, sd, sdd);
     oracle_fk_spheres(A, sg, cen);
-    for (int k = 0; k < A->nsph; ++k)
-      for (int o = 0; o < n_obs; ++o) {
-        double dx = cen[3 * k] - obs[4 * o], dy = cen[3 * k + 1] - obs[4 * o + 1],
-               dz = cen[3 * k + 2] - obs[4 * o + 2];
+    for (int k = 0; k < A->nsph; ++k) {
+      for (int o = 0; o < W->n_sph; ++o) {
+        const double* ob = W->sph + 4 * o;
+        double dx = cen[3 * k] - ob[0], dy = cen[3 * k + 1] - ob[1], dz = cen[3 * k + 2] - ob[2];
         double dist = sqrt(dx * dx + dy * dy + dz * dz);
-        double need = A->sph[k][3] + obs[4 * o + 3] + margin;
+        double need = A->sph[k][3] + ob[3] + W->margin;
         r = dmax(r, dist > 0.0 ? need / dist : INFINITY);
       }
+      for (int o = 0; o < W->n_cap; ++o) {
+        const double* cp = W->cap + 7 * o;
+        double dist = oracle_point_segment(cen + 3 * k, cp, cp + 3);
+        double need = A->sph[k][3] + cp[6] + W->margin;
+        r = dmax(r, dist > 0.0 ? need / dist : INFINITY);
+      }
+    }
+  }
+  return r;
+}
+
+/* rho_self: clearance of the arm's self-collision pairs at the S
+ * evaluation times, (r_a + r_b + margin_self) / |c_a - c_b|. */
+double oracle_rho_self(const oarm* A, const double* x0, const double* x1, double T, int S,
+                       const oworld* W) {
+  int n = A->n;
+  double r = 0.0;
+  if (W->n_pairs <= 0) return 0.0;
+  double cen[OSPH * 3];
+  for (int s = 0; s < S; ++s) {
+    double u = (S > 1) ? (double)s / (double)(S - 1) : 0.0;
+    double t = u * T;
+    double sg[OJ], sd[OJ], sdd[OJ];
+    oracle_cubic(n, x0, x1, T, t, sg, sd, sdd);
+    oracle_fk_spheres(A, sg, cen);
+    for (int p = 0; p < W->n_pairs; ++p) {
+      int a = W->pairs[2 * p], b = W->pairs[2 * p + 1];
+      double dx = cen[3 * a] - cen[3 * b], dy = cen[3 * a + 1] - cen[3 * b + 1],
+             dz = cen[3 * a + 2] - cen[3 * b + 2];
+      double dist = sqrt(dx * dx + dy * dy + dz * dz);
+      double need = A->sph[a][3] + A->sph[b][3] + W->margin_self;
+      r = dmax(r, dist > 0.0 ? need / dist : INFINITY);
+    }
   }
   return r;
 }
@@ -395,8 +465,7 @@ static int finite_state(int n, const double* x) {
  * rho4 = (rho_tauP(j*), rho_v, rho_q, rho_c), nslots = slots evaluated;
  * rho_c is NaN when rho_v or rho_q already fails (not evaluated). */
 static void edge_one(const oarm* A, const double* x0, const double* x1, int NT,
-                     const double* grid, int S, int jmax, const double* obs, int n_obs,
-                     double margin_c, int scan, int16_t* out_j, uint16_t* out_st,
+                     const double* grid, int S, int jmax, const oworld* W, int scan, int16_t* out_j, uint16_t* out_st,
                      double* out_m, double* rho4, int* nslots) {
   int n = A->n;
   rho4[0] = rho4[1] = rho4[2] = rho4[3] = 0.0;
@@ -435,8 +504,7 @@ static void edge_one(const oarm* A, const double* x0, const double* x1, int NT,
     double rq = oracle_rho_q(A, x0, x1, T);
     /* Clear is and-ed after the limit checks (Alg. 1): evaluated only when
      * they pass; fmin below ignores the NaN of an unevaluated clearance */
-    double rc = (rv <= 1.0 && rq <= 1.0) ? oracle_rho_c(A, x0, x1, T, S, obs, n_obs, margin_c)
-                                         : NAN;
+    double rc = (rv <= 1.0 && rq <= 1.0) ? oracle_rho_c(A, x0, x1, T, S, W) : NAN;
     rho4[1] = rv;
     rho4[2] = rq;
     rho4[3] = rc;
@@ -456,8 +524,7 @@ static void edge_one(const oarm* A, const double* x0, const double* x1, int NT,
  * parent_ok[e] == 0 marks a padded parent (no edge).  jmax may be NULL. */
 void oracle_edge_time(const oarm* A, int E, const double* x0, const double* x1,
                       const int32_t* parent_ok, int NT, const double* grid, int S,
-                      const int16_t* jmax, const double* obs, int n_obs, double margin_c,
-                      int scan, int16_t* out_j, uint16_t* out_st, double* out_m,
+                      const int16_t* jmax, const oworld* W, int scan, int16_t* out_j, uint16_t* out_st, double* out_m,
                       double* out_rho, int32_t* out_nslots) {
   int w = 2 * A->n;
   for (int e = 0; e < E; ++e) {
@@ -470,8 +537,8 @@ void oracle_edge_time(const oarm* A, int E, const double* x0, const double* x1,
       rho4[0] = rho4[1] = rho4[2] = rho4[3] = 0.0;
     } else {
       int jm = jmax ? jmax[e] : NT - 1;
-      edge_one(A, x0 + (size_t)e * w, x1 + (size_t)e * w, NT, grid, S, jm, obs, n_obs,
-               margin_c, scan, &out_j[e], &out_st[e], &out_m[e], rho4, &ns);
+      edge_one(A, x0 + (size_t)e * w, x1 + (size_t)e * w, NT, grid, S, jm, W, scan, &out_j[e],
+               &out_st[e], &out_m[e], rho4, &ns);
     }
     if (out_rho)
       for (int r = 0; r < 4; ++r) out_rho[(size_t)e * 4 + r] = rho4[r];
@@ -547,7 +614,7 @@ void oracle_edge_nary(const oarm* A, int E, const double* x0, const double* x1, 
  * rho4 = (rho_tauP(T), rho_v, rho_q, rho_c). */
 void oracle_edge_refine(const oarm* A, int E, const double* x0, const double* x1,
                         const int16_t* j_in, int NT, const double* grid, int S, int N,
-                        double eps, const double* obs, int n_obs, double margin_c,
+                        double eps, const oworld* W,
                         double* out_T, double* out_lo, uint16_t* out_st, double* out_rho,
                         int32_t* out_rounds) {
   int w = 2 * A->n;
@@ -588,7 +655,7 @@ void oracle_edge_refine(const oarm* A, int E, const double* x0, const double* x1
     oracle_slot_rho(A, a, b, hi, S, &rt, &rp, NULL);
     double rv = oracle_rho_v(A, a, b, hi);
     double rq = oracle_rho_q(A, a, b, hi);
-    double rc = (rv <= 1.0 && rq <= 1.0) ? oracle_rho_c(A, a, b, hi, S, obs, n_obs, margin_c) : NAN;
+    double rc = (rv <= 1.0 && rq <= 1.0) ? oracle_rho_c(A, a, b, hi, S, W) : NAN;
     uint16_t st = 0;
     if (rv > 1.0) st |= S_VEL;
     if (rq > 1.0) st |= S_POS;
@@ -700,7 +767,7 @@ void oracle_control(const oarm* A, int n_inst, const double* q, const double* qd
  * rho5 = (rho_tau, rho_P, rho_v, rho_q, rho_c); T <= 0 is infeasible; rho_c is
  * NaN unless rho_tau, rho_P, rho_v and rho_q all pass. */
 void oracle_edge_check(const oarm* A, int E, const double* x0, const double* x1,
-                       const double* T, int S, const double* obs, int n_obs, double margin_c,
+                       const double* T, int S, const oworld* W,
                        uint16_t* out_st, double* out_rho /*[E][5]*/, double* out_tau /*[E][S][n]*/) {
   int n = A->n, w = 2 * n;
   for (int e = 0; e < E; ++e) {
@@ -724,12 +791,15 @@ void oracle_edge_check(const oarm* A, int E, const double* x0, const double* x1,
     r5[3] = oracle_rho_q(A, a, b, T[e]);
     /* clearance only for an edge that passed every limit check (Alg. 1) */
     const int lim_ok = r5[0] <= 1.0 && r5[1] <= 1.0 && r5[2] <= 1.0 && r5[3] <= 1.0;
-    r5[4] = lim_ok ? oracle_rho_c(A, a, b, T[e], S, obs, n_obs, margin_c) : NAN;
+    /* the full recheck adds the arm's self-collision pairs to the obstacles */
+    double rs = lim_ok ? oracle_rho_self(A, a, b, T[e], S, W) : NAN;
+    r5[4] = lim_ok ? dmax(oracle_rho_c(A, a, b, T[e], S, W), rs) : NAN;
     uint16_t st = 0;
     if (r5[0] > 1.0 || r5[1] > 1.0) st |= S_NONE;
     if (r5[2] > 1.0) st |= S_VEL;
     if (r5[3] > 1.0) st |= S_POS;
     if (r5[4] > 1.0) st |= S_COLL;
+    if (rs > 1.0) st |= S_SELF;
     out_st[e] = st;
   }
 }
