@@ -1,5 +1,5 @@
 // fn_risk.h -- the risk objective of Eq. (2) with the terms of Eq. (3)
-// (Sec. IV-B), evaluated in FP64.
+// (Sec. IV-B), evaluated in FP32.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -8,36 +8,41 @@
 
 namespace fn {
 
-// log Phi(z) = log(erfc(-z / sqrt 2) / 2); below -30 erfc underflows, so the
+// log Phi(z) = log(erfc(-z / sqrt 2) / 2).  For z < -4 erfc(x), x = -z / sqrt 2,
+// loses relative accuracy in FP32 and underflows below x ~ 10; there the
 // scaled complementary error function carries the tail:
-// erfc(x) = erfcx(x) exp(-x^2)
-__device__ __forceinline__ double log_phi_dev(double z) {
-  if (z > -30.0) return log(0.5 * erfc(-z * 0.70710678118654752));
-  const double x = -z * 0.70710678118654752;
-  return log(0.5 * erfcx(x)) - x * x;
+// log erfc(x) = log erfcx(x) - x^2.
+__device__ __forceinline__ float log_phi_dev(float z) {
+  const float x = -z * 0.70710678118654752f;
+  if (z > -4.f) return logf(0.5f * erfcf(x));
+  return logf(0.5f * erfcxf(x)) - x * x;
 }
 
 // J = w_v min(v_rel, v_target) + w_p log P_object + w_r log P_inrange
 //   + w_x log P_arm, with P_object = erf(r / (sigma sqrt 2)),
 // P_inrange = Phi((t_fall - T) / sigma_t), sigma_t = sigma / |xdot_z(t_fall)|,
 // log P_arm = -lambda (nu - nu0)_+ T (1 - nu0 / nu).
-__device__ __forceinline__ double risk_eval(const fn_risk& w, double t, double v_rel, double nu,
-                                            double vz0, double tf) {
-  double sg;
+__device__ __forceinline__ float risk_eval(const fn_risk& w, float t, float v_rel, float nu,
+                                           float vz0, float tf) {
+  float sg;
   if (w.sigma_mode == 1) {
-    sg = w.s0 + w.s1 * t;
+    sg = (float)w.s0 + (float)w.s1 * t;
   } else {
-    const double a = w.sp, b = w.sv * t, c = 0.5 * w.sa * t * t;
-    sg = sqrt(a * a + b * b + c * c);
+    const float a = (float)w.sp, b = (float)w.sv * t, c = 0.5f * (float)w.sa * t * t;
+    sg = sqrtf(a * a + b * b + c * c);
   }
-  const double x = w.r / (sg * 1.4142135623730951);
-  const double lpo = x < 0.5 ? log(erf(x)) : log1p(-erfc(x));
-  const double xdz = vz0 + w.gz * tf;
-  const double st = sg / fabs(xdz);
-  const double lpr = log_phi_dev((tf - t) / st);
-  const double lpa = nu > w.nu0 ? -w.lam * (nu - w.nu0) * t * (1.0 - w.nu0 / nu) : 0.0;
-  const double vr = fmin(v_rel, w.vtarget);
-  return w.wv * vr + w.wp * lpo + w.wr * lpr + w.wx * lpa;
+  const float x = (float)w.r / (sg * 1.41421356237309515f);
+  // log erf(x): directly for small x, through erfc where erf is close to 1
+  const float lpo = x < 0.5f ? logf(erff(x)) : log1pf(-erfcf(x));
+  // The vertical speed at t_fall vanishes near the apex of the flight, where
+  // vz0 + gz t_fall cancels; one FP64 FMA keeps it to a single FP32 rounding.
+  const float xdz = (float)fma(w.gz, (double)tf, (double)vz0);
+  const float st = sg / fabsf(xdz);
+  const float lpr = log_phi_dev((tf - t) / st);
+  const float nu0 = (float)w.nu0;
+  const float lpa = nu > nu0 ? -(float)w.lam * (nu - nu0) * t * (1.f - nu0 / nu) : 0.f;
+  const float vr = fminf(v_rel, (float)w.vtarget);
+  return (float)w.wv * vr + (float)w.wp * lpo + (float)w.wr * lpr + (float)w.wx * lpa;
 }
 
 }  // namespace fn

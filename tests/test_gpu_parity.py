@@ -480,7 +480,12 @@ def test_risk_score():
         torch.cuda.synchronize()
         R = O.make_orisk(sigma_mode=mode, sp=0.0054, sv=0.0406, sa=0.2)
         ref = O.risk_score(R, T, vr, nu, vz, tf)
-        assert np.allclose(J.cpu().numpy(), ref, rtol=1e-6, atol=1e-5)
+        # FP32 against the FP64 oracle: each term carries a few ulps of its own
+        # magnitude (the log-probability terms reach a few hundred)
+        err = np.abs(J.cpu().numpy() - ref)
+        print(f"risk sigma mode {mode}: max |dJ| {err.max():.2e}, max |dJ| / max(1, |J|) "
+              f"{(err / np.maximum(1.0, np.abs(ref))).max():.2e}, |J| up to {np.abs(ref).max():.1f}")
+        assert (err <= 1e-5 * np.maximum(1.0, np.abs(ref))).all()
 
 
 def test_errors_are_returned_not_thrown(tiny):
