@@ -48,6 +48,9 @@ F_MLP_ROW = 277504
 # summed (FMA = 2).
 F_KNN_PAIR = 42
 PEAK_BF16 = 2500e12  # MI355X dense BF16 matrix peak, FLOP/s
+# One controller step: Eq. (9) and the taper bounds 7 x 20, sin/cos 21,
+# rigid-body recursion 1,005, armature 14, friction 56, clips and power 7 x 8.
+F_CONTROL = 1252
 
 
 def f_clear(S, n_obs, n_sph):
@@ -262,6 +265,9 @@ def main():
     }
     res["roofline_other"] = other_rooflines(args, ctx, net, tree, ld, n, cand, idx, grid, sh,
                                             feats, win, fn, torch)
+    res["refine"] = refine_stats(args, ctx, wl, tree, ld, n, cand, idx, grid, sh, obs, out, fn,
+                                 torch)
+    res["controller"] = controller_stats(args, ctx, wl, fn, W, torch)
     if args.batch_problems > 0:
         res["batched_round"] = batched_round(args, fn, W, torch)
     if args.profile:
@@ -367,6 +373,88 @@ KERNEL_SOURCES = {
     "edge_time_kernel": ("fn_internal.h", "fn_ctx.h", "fn_edge.h", "fn_edge.hip"),
     "knn_scan": ("fn_internal.h", "fn_ctx.h", "fn_knn.h", "fn_knn.hip"),
 }
+
+
+def refine_stats(args, ctx, wl, tree, ld, n, cand, idx, grid, sh, obs, out, fn, torch):
+    """Multi-round N-ary refinement below the grid result of every edge of
+    the step (N = 3, eps = 1e-4 s), timed alone with HIP events: refined
+    edges/s, its FP32 rate, and how far below the grid slot the refined
+    minimum feasible time lies."""
+    stream = torch.cuda.current_stream()
+    j = out["j"].clone()
+    n_ary, eps = 3, 1e-4
+
+    def call():
+        return ctx.edge_refine(tree, ld, n, cand, idx, j, grid, sh.samples, n_ary=n_ary, eps=eps,
+                               obs=obs)
+
+    for _ in range(2):
+        r = call()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    reps = max(5, args.steps)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        r = call()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    jj = j.cpu().numpy().astype(np.int64)
+    f = jj >= 0
+    T = r["T"].cpu().numpy().astype(np.float64)
+    g = wl["grid"].astype(np.float64)
+    gain = (g[jj[f]] - T[f]) / g[jj[f]]
+    st = r["status"].cpu().numpy().astype(np.uint16)
+    n_post = int(f.sum())
+    n_clear = int((f & ((st & (fn.S_VEL | fn.S_POS)) == 0)).sum())
+    work = int(r["work"].sum().item())
+    flop = (work * F_EVAL + n_post * F_JOINTS
+            + n_clear * f_clear(sh.samples, sh.n_obs, len(wl["arm"]["sph"])))
+    return {"n_ary": n_ary, "eps_s": eps, "ms": ms, "edges": int(jj.size),
+            "refined_edges": n_post, "refined_edges_per_s": n_post / (ms * 1e-3),
+            "rounds_mean": float(r["rounds"].float()[torch.as_tensor(f).cuda()].mean().item()),
+            "evaluations": work, "fp32_tflops": flop / (ms * 1e-3) / 1e12,
+            "frac": flop / (ms * 1e-3) / PEAK_FP32,
+            "T_below_grid_rel_median": float(np.median(gain)) if gain.size else None,
+            "T_below_grid_rel_max": float(np.max(gain)) if gain.size else None,
+            "final_ok_frac_refined": float((f & ((st & (fn.S_VEL | fn.S_POS | fn.S_COLL)) == 0)).sum()
+                                           / max(1, n_post))}
+
+
+def controller_stats(args, ctx, wl, fn, W, torch, n=1 << 20):
+    """One step of the tracking controller of Eq. (9) for 1,048,576 seeded
+    instances (states in the limits, rendezvous states, horizons U[0.02,
+    0.8] s, previous torques within 80% of the limits), timed alone."""
+    arm = wl["arm"]
+    rng = np.random.default_rng(7)
+    x = W.uniform_states(arm, n, rng, qd_scale=1.0)
+    g = W.uniform_states(arm, n, rng, qd_scale=0.5)
+    dev = lambda a: fn.dev(np.asarray(a, np.float32))  # noqa: E731
+    q, qd, qg, qdg = dev(x[:, :7]), dev(x[:, 7:]), dev(g[:, :7]), dev(g[:, 7:])
+    tp = dev(rng.uniform(-0.8, 0.8, (n, 7)) * arm["taumax"])
+    T = dev(rng.uniform(0.02, 0.8, n))
+    slew = np.full(7, 1000.0)
+    stream = torch.cuda.current_stream()
+    for _ in range(2):
+        tau, qdd, st = fn.control(ctx, q, qd, tp, qg, qdg, T, 1e-3, slew)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    reps = max(5, args.steps)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        fn.control(ctx, q, qd, tp, qg, qdg, T, 1e-3, slew)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    stn = st.cpu().numpy().astype(np.uint16)
+    return {"instances": n, "ms": ms, "instances_per_s": n / (ms * 1e-3),
+            "fp32_tflops": n * F_CONTROL / (ms * 1e-3) / 1e12,
+            "frac": n * F_CONTROL / (ms * 1e-3) / PEAK_FP32, "flop_per_instance": F_CONTROL,
+            "clipped": {name: float(((stn & b) > 0).mean()) for name, b in
+                        (("acc", fn.C_ACC), ("slew", fn.C_SLEW), ("torque", fn.C_TORQUE),
+                         ("power", fn.C_POWER))}}
 
 
 def kernel_source_hash(kernel="edge_time_kernel"):

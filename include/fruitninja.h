@@ -72,7 +72,9 @@ enum {
   FN_S_BAD_INPUT = 128, /* a non-finite state or duration */
   FN_S_WIN_BELOW = 256, /* informational: a slot below the window passed the endpoint screen
                            and was evaluated in full */
-  FN_S_NO_PARENT = 512  /* padded parent index (-1): no edge */
+  FN_S_NO_PARENT = 512, /* padded parent index (-1): no edge */
+  FN_S_SELF = 1024      /* edge_check: two of the arm's own spheres closer than the margin
+                           (set together with FN_S_COLL) */
 };
 #define FN_S_DECISION (FN_S_NONE | FN_S_VEL | FN_S_POS | FN_S_COLL | FN_S_BAD_INPUT | FN_S_NO_PARENT)
 
@@ -182,11 +184,17 @@ typedef struct {
                             n_t = "predicted infeasible" */
 } fn_search;
 
-/* Obstacle spheres (world frame): device [n][4] = (x, y, z, radius). */
+/* Obstacles (world frame, Sec. IV-E): spheres, device [n][4] = (x, y, z,
+ * radius), and capsules, device [n_caps][7] = (segment end p0, segment end
+ * p1, radius); an arm sphere clears a capsule when its distance to the
+ * segment is at least r_a + r + margin.  n + n_caps <= FN_MAX_OBS. */
+#define FN_MAX_CAPS 16
 typedef struct {
-  const float* spheres; /* device, may be NULL when n == 0 */
-  int32_t n;            /* 0 .. FN_MAX_OBS */
-  float margin;         /* clearance margin, metres (>= 0) */
+  const float* spheres;  /* device, may be NULL when n == 0 */
+  int32_t n;             /* 0 .. FN_MAX_OBS */
+  float margin;          /* clearance margin, metres (>= 0) */
+  const float* capsules; /* device, may be NULL when n_caps == 0 */
+  int32_t n_caps;        /* 0 .. FN_MAX_CAPS */
 } fn_obstacles;
 
 /* Per-edge outputs (device, length E each).  rho4 (nullable): (rho_tauP at
@@ -225,6 +233,79 @@ int edge_time_batch(fn_ctx* ctx, const float* tree, int64_t ld, int32_t n_nodes,
                     const fn_search* search, const fn_obstacles* obs, const fn_edge_out* out,
                     void* stream);
 
+/* Self-collision pairs of the arm checked by edge_check (Sec. IV-E: the
+ * pairs that the joint limits make unreachable are removed offline, by the
+ * caller): pairs host [n][2] of sphere indices (the arm description's
+ * order, distinct, < n_spheres), margin >= 0 metres.  Copies them to the
+ * context (synchronous); n = 0 removes them.  Errors: FN_E_ARG, FN_E_SHAPE
+ * (n > FN_MAX_SELF_PAIRS). */
+#define FN_MAX_SELF_PAIRS 1024
+int fn_set_self_pairs(fn_ctx* ctx, const int32_t* pairs /*host*/, int32_t n, float margin);
+
+/* ------------------------------------------------------------------ */
+/* edge_refine -- multi-round N-ary refinement of the minimum feasible  */
+/* time below the grid result (Sec. IV-D after Def. 7: the interval is  */
+/* cut into N equal slots, their ends evaluated, and the slot whose end */
+/* is the first feasible one cut again until it is no wider than eps). */
+/* ------------------------------------------------------------------ */
+typedef struct {
+  const float* grid; /* device [n_t], the grid j_in indexes */
+  int32_t n_t;
+  int32_t samples;   /* S, 2..FN_MAX_SAMPLES */
+  int32_t n_ary;     /* N, 2..1024; each round evaluates N - 1 interior points */
+  float eps;         /* stop once hi - lo <= eps (seconds), > 0 */
+} fn_refine;
+
+/* Edges as edge_time_batch (edge e = b * k + i from tree node nbr[b][i] to
+ * candidate b); j_in: device [E], the grid search's result slot of every
+ * edge (-1: none).  For j_in[e] >= 0 the search starts from hi = grid[j],
+ * which is feasible, and lo = grid[j - 1] (0 for j = 0), which is not;
+ * every round evaluates t_i = lo + i (hi - lo) / N, i = 1 .. N-1, in
+ * ascending order in FP32, the first t_i with rho_tau, rho_P <= 1 becomes hi
+ * and t_{i-1} lo (lo = t_{N-1} when none is), at most 64 rounds.  Outputs
+ * (device, length E): out_T = hi (NaN when not refined), out_status
+ * (FN_S_VEL / POS / COLL of the post-checks at out_T, clearance only when
+ * the limit checks pass; FN_S_NONE when j_in < 0; BAD_INPUT, NO_PARENT),
+ * out_rho4 [E][4] = (rho_tauP(out_T), rho_v, rho_q, rho_c), out_rounds and
+ * out_work (sample evaluations) or NULL.  FP32 throughout, no FP64 stage:
+ * the result is within eps of the FP32 boundary.  Errors: FN_E_ARG (NULL
+ * arrays, N or eps out of range), FN_E_SHAPE (n_t, S, k, obstacles). */
+int edge_refine(fn_ctx* ctx, const float* tree, int64_t ld, int32_t n_nodes, const float* cand,
+                int32_t B, const int32_t* nbr, int32_t k, const int16_t* j_in,
+                const fn_refine* refine, const fn_obstacles* obs, float* out_T,
+                uint16_t* out_status, float* out_rho4, int32_t* out_rounds, int32_t* out_work,
+                void* stream);
+
+/* ------------------------------------------------------------------ */
+/* fn_control -- the 1 kHz tracking controller (Sec. IV-F, Eq. (9)),    */
+/* one step for each of n instances.                                   */
+/* ------------------------------------------------------------------ */
+/* status bits of a control step */
+enum {
+  FN_C_ACC = 1,     /* the desired acceleration was clipped to the velocity taper */
+  FN_C_SLEW = 2,    /* the torque was clipped to the slew limit */
+  FN_C_TORQUE = 4,  /* the torque was clipped to the torque limit */
+  FN_C_POWER = 8,   /* the torque was scaled to the power limit */
+  FN_C_BAD = 128    /* non-finite input or horizon T <= 0: zero torque and acceleration */
+};
+/* Per instance (device [n][7] floats each): measured q, qd, the previous
+ * torque command tau_prev, the rendezvous qg, qdg, and the horizon T
+ * (device [n], seconds to the rendezvous).  The controller refits the cubic
+ * of Eq. (6) from (q, qd) to (qg, qdg) over T and takes its initial
+ * acceleration, Eq. (9): qdd = 6 (qg - q) / T^2 - (4 qd + 2 qdg) / T, clipped
+ * to [l, u] with l = (-taper(q, -) - qd) / dt, u = (taper(q, +) - qd) / dt
+ * (the velocity after one period dt stays inside the context's velocity
+ * taper, braking law of the arm description); the torque of Eq. (4) at
+ * (q, qd, qdd) is then clipped to |tau - tau_prev| <= slew dt (slew: host
+ * [7], N m / s), to |tau| <= taumax, and scaled by W_max / |sum tau qd| when
+ * the power exceeds W_max.  Outputs (device): out_tau [n][7], out_qdd [n][7]
+ * (the clipped acceleration), out_status [n] (FN_C_* bits).  FP32.  Errors:
+ * FN_E_ARG (NULL arrays, dt <= 0, a negative slew limit), FN_E_SHAPE. */
+int fn_control(fn_ctx* ctx, int64_t n, const float* q, const float* qd, const float* tau_prev,
+               const float* qg, const float* qdg, const float* T, float dt,
+               const double* slew /*host [7]*/, float* out_tau, float* out_qdd,
+               uint16_t* out_status, void* stream);
+
 /* ------------------------------------------------------------------ */
 /* edge_time_batch_noalloc -- edge_time_batch for callers that cannot   */
 /* allocate device memory (code under HIP graph capture, tight serving  */
@@ -255,19 +336,23 @@ size_t fn_noalloc_scratch_bytes(void);
 /* of Alg. 1 (T = T_req - t_p) and the full-resolution recheck of a    */
 /* sent plan (Sec. IV-E).                                              */
 /* ------------------------------------------------------------------ */
-/* x0, x1: device [E][14]; T: device [E]; S samples as above.  out_status:
+/* x0, x1: device [E][14]; T: device [E]; S samples, 2..4096 (the full
+ * resolution of a sent plan may exceed the search's 64).  out_status:
  * device [E] (NONE when rho_tau or rho_P > 1 or T <= 0, VEL, POS, COLL,
- * BAD_INPUT); out_rho5: device [E][5] = (rho_tau, rho_P, rho_v, rho_q,
- * rho_c; NaN unless the four limit ratios pass); out_tau: device [E][S][7]
- * torques of Eq. (4) at the samples, or NULL.  FP32 arithmetic (no FP64
- * recheck here). */
+ * SELF, BAD_INPUT); out_rho5: device [E][5] = (rho_tau, rho_P, rho_v,
+ * rho_q, rho_c; NaN unless the four limit ratios pass); rho_c is the larger
+ * of the obstacle clearance and, when the context has self-collision pairs
+ * (fn_set_self_pairs), the pairs' (r_a + r_b + margin) / distance; out_tau:
+ * device [E][S][7] torques of Eq. (4) at the samples, or NULL.  FP32
+ * arithmetic (no FP64 recheck here). */
 int edge_check(fn_ctx* ctx, const float* x0, const float* x1, const float* T, int64_t E,
                int32_t S, const fn_obstacles* obs, uint16_t* out_status, float* out_rho5,
                float* out_tau, void* stream);
 
 /* ------------------------------------------------------------------ */
 /* risk_score -- the objective J of Eq. (2) with the terms of Eq. (3)   */
-/* (Sec. IV-B) for n rendezvous nodes; evaluated in FP64.              */
+/* (Sec. IV-B) for n rendezvous nodes; evaluated in FP32 (log Phi's     */
+/* tail through the scaled complementary error function).              */
 /* ------------------------------------------------------------------ */
 typedef struct {
   double gz;          /* vertical gravity of Eq. (1) (negative) */
@@ -417,6 +502,8 @@ typedef struct {
   int32_t* out_node;     /* device out [B] index of the attached node, -1 if none */
   float* out_J;          /* device out [B] J of an attached goal node, -inf otherwise */
   float* out_best;       /* device out [2]: best J among this round's goal nodes, its node (as float) */
+  const float* caps;     /* device [n_caps][7] obstacle capsules, or NULL (n_obs + n_caps <= FN_MAX_OBS) */
+  int32_t n_caps;
 } fn_problem;
 
 typedef struct {

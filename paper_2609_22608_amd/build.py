@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfruitninja.so")
 OBJ = os.path.join(HERE, "_build")
 SOURCES = ["fn_core.hip", "fn_knn.hip", "fn_edge.hip", "fn_mlp.hip", "fn_batch.hip",
-           "fn_static.hip"]
+           "fn_static.hip", "fn_control.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # no packed FP32 instructions (v_pk_*_f32)

@@ -297,7 +297,7 @@ struct fn_batch {
   fn_risk risk{};
   int64_t pairs = 0, queries = 0, edges = 0;  // pairs: kNN scan work items
   int form = 1;                                // kNN scan form (fn_tuning)
-  int max_obs = 0;  // most obstacles of a problem (clearance table LDS)
+  int max_obs = 0;  // most obstacles (spheres + capsules) of a problem (clearance table LDS)
   // device tables
   KnnProb* knn = nullptr;
   InsProb* ins = nullptr;
@@ -375,8 +375,10 @@ extern "C" int fn_batch_prepare(fn_ctx* c, const fn_problem_set* ps) {
       return fail(FN_E_ARG, "fn_batch_prepare: problem %d has a NULL array", p);
     if (q.B < 1 || q.ld < 4 || (q.ld & 3) != 0 || q.ld > KNN_MAX_LD)
       return fail(FN_E_SHAPE, "fn_batch_prepare: problem %d: B = %d, ld = %lld", p, q.B, (long long)q.ld);
-    if (q.n_obs < 0 || q.n_obs > FN_MAX_OBS || (q.n_obs > 0 && !q.obs))
-      return fail(FN_E_SHAPE, "fn_batch_prepare: problem %d: %d obstacles", p, q.n_obs);
+    if (q.n_obs < 0 || q.n_obs > FN_MAX_OBS || (q.n_obs > 0 && !q.obs) || q.n_caps < 0 ||
+        q.n_caps > FN_MAX_CAPS || q.n_obs + q.n_caps > FN_MAX_OBS || (q.n_caps > 0 && !q.caps))
+      return fail(FN_E_SHAPE, "fn_batch_prepare: problem %d: %d obstacle spheres, %d capsules", p,
+                  q.n_obs, q.n_caps);
     // kNN geometry from the node capacity (node counts change on the device)
     const int groups = (q.B + qpw - 1) / qpw;
     int split = (int)((target / n + groups - 1) / groups);
@@ -400,7 +402,8 @@ extern "C" int fn_batch_prepare(fn_ctx* c, const fn_problem_set* ps) {
     a.grid = ps->grid; a.n_t = ps->n_t; a.S = ps->samples; a.Sw = Sw; a.mode = ps->mode;
     a.win_half = 0; a.j_max = nullptr; a.win_lo = nullptr;
     a.obs = q.obs; a.n_obs = q.n_obs; a.margin_c = ps->margin;
-    max_obs = max_obs > q.n_obs ? max_obs : q.n_obs;
+    a.caps = q.caps; a.n_caps = q.n_caps;
+    max_obs = max_obs > q.n_obs + q.n_caps ? max_obs : q.n_obs + q.n_caps;
     a.out_j = q.out_j; a.out_st = q.out_status; a.out_m = q.out_margin; a.out_rho = q.out_rho4;
     a.out_work = nullptr; a.out_scr = nullptr; a.q_count = c->q_count; a.queue = c->queue;
     a.model_e = c->model_e + eo[p] * MODEL_FLOATS;

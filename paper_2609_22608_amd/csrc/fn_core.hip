@@ -80,6 +80,7 @@ __device__ void fill_arm(const fn_arm_desc* d, const int* digits, int pattern, A
     A->L[i].fk2 = R(-d->psi2[i] * 1.4426950408889634);
     A->L[i].f0 = R(d->psi1[i] / (1.0 + exp(-d->psi2[i] * d->psi3[i])));
     A->L[i].inv_taumax = R(1.0 / d->taumax[i]);
+    A->taumax[i] = R(d->taumax[i]);
     A->qmin[i] = R(d->qmin[i]);
     A->qmax[i] = R(d->qmax[i]);
     A->qcen[i] = R(0.5 * (d->qmax[i] + d->qmin[i]));
@@ -88,6 +89,7 @@ __device__ void fill_arm(const fn_arm_desc* d, const int* digits, int pattern, A
     A->two_acc[i] = R(2.0 * d->acc[i]);
   }
   A->inv_wmax = R(1.0 / d->wmax);
+  A->wmax = R(d->wmax);
   const bool grav = (d->terms & FN_T_GRAVITY) != 0;
   for (int r = 0; r < 3; ++r) A->vd0[r] = grav ? R(-d->g[r]) : R(0);
   A->nsph = d->n_spheres;
@@ -161,6 +163,7 @@ extern "C" int fn_create(const fn_arm_desc* arm, const fn_caps* caps, fn_ctx** o
     for (int l = 1; l <= NJ; ++l)
       for (int k = 0; k < arm->n_spheres; ++k)
         if (arm->sphere_link[k] == l) {
+          c->sphere_order[k] = w;
           c->desc.sphere_link[w] = l;
           for (int r = 0; r < 4; ++r) c->desc.sphere[w][r] = arm->sphere[k][r];
           ++w;
@@ -193,6 +196,7 @@ extern "C" int fn_create(const fn_arm_desc* arm, const fn_caps* caps, fn_ctx** o
   FN_ALLOC(c->queue, (size_t)(caps->max_edges > 0 ? caps->max_edges : 1) * sizeof(QEntry));
   FN_ALLOC(c->model_e, (size_t)caps->max_edges * MODEL_FLOATS * sizeof(float));
   FN_ALLOC(c->model_c, (size_t)caps->max_batch * MODEL_FLOATS * sizeof(float));
+  FN_ALLOC(c->self_pairs, (size_t)2 * FN_MAX_SELF_PAIRS * sizeof(int16_t));
 #undef FN_ALLOC
   {
     const int brc = batch_alloc(c);
@@ -280,6 +284,7 @@ extern "C" void fn_destroy(fn_ctx* c) {
   (void)hipFree(c->queue);
   (void)hipFree(c->model_e);
   (void)hipFree(c->model_c);
+  (void)hipFree(c->self_pairs);
   delete c;
 }
 

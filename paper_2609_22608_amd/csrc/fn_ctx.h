@@ -102,6 +102,13 @@ struct fn_ctx {
   // candidate [max_batch][56]
   float* model_e;
   float* model_c;
+  // self-collision pairs of the fixed-duration check (link-sorted sphere
+  // indices, device [FN_MAX_SELF_PAIRS][2]) and the caller's sphere index ->
+  // link-sorted index
+  int16_t* self_pairs;
+  int n_self;
+  float margin_self;
+  int sphere_order[FN_MAX_SPHERES];
   // kernel timing: event pairs around the search kernel of timed calls
   bool timing;
   int n_timed;

@@ -47,6 +47,8 @@ struct EdgeArgs {
   const float* __restrict__ obs;
   int n_obs;
   float margin_c;
+  const float* __restrict__ caps;  // obstacle capsules [n_caps][7] = (p0, p1, radius)
+  int n_caps;
   int16_t* out_j;
   uint16_t* out_st;
   float* out_m;
@@ -115,12 +117,26 @@ __device__ __forceinline__ float lane_u(int lane, int Sw, int S) {
   return s < S ? float(s) / float(S - 1) : 0.f;
 }
 
+// The obstacles an edge is checked against (Sec. IV-E): spheres [n_obs][4]
+// = (centre, radius) and capsules [n_caps][7] = (segment ends p0, p1,
+// radius), with the clearance margin.
+struct World {
+  const float* __restrict__ obs;
+  int n_obs;
+  const float* __restrict__ caps;
+  int n_caps;
+  float margin;
+};
+__host__ __device__ __forceinline__ int world_size(const World& w) { return w.n_obs + w.n_caps; }
+
 // LDS of one wavefront for the clearance check: every sphere as (x, y, z
-// in its link frame, radius + margin), every obstacle as (x, y, z, radius).
+// in its link frame, radius + margin), every obstacle sphere as (x, y, z,
+// radius), every capsule as (p0, p1 - p0, 1 / |p1 - p0|^2, radius).
 template <typename R>
 struct GeoLDS {
   R sph[4 * FN_MAX_SPHERES];
   R obs[4 * FN_MAX_OBS];
+  R caps[8 * FN_MAX_CAPS];
 };
 
 // Velocity taper (Def. 6 rho_v) and position limits at duration T: lane
@@ -146,41 +162,58 @@ __device__ void joint_checks(const ArmConst<R>& A, const EdgeState<R>& E, R T, R
   rq = wave_max(q);
 }
 
-// Clearance (Sec. IV-E spheres) at duration T: rho_c = max over samples,
-// arm spheres and obstacles of (r_a + margin + r_o) / distance, in every
-// lane.  The sphere and obstacle tables are staged in LDS first, so the
-// (sphere, obstacle) loop reads broadcast LDS instead of waiting on a
-// memory load per pair.  Lane = (sample, sphere part): the parts split each
-// link's spheres so that all 64 lanes work when S < 64.
-// tab (LDS, nsph * n_obs values) receives 1 / (r_a + margin + r_o)^2 of every
-// (sphere, obstacle) pair (FP32: hardware reciprocal, within 1 ulp; FP64:
-// IEEE division), and the loop keeps the smallest d^2 / (r_a + margin +
-// r_o)^2 (a product and a minimum per pair instead of a division); rho_c is
-// its inverse square root.
+// Clearance (Sec. IV-E) at duration T: rho_c = max over samples, arm spheres
+// and obstacles of (r_a + margin + r_o) / distance, in every lane; the
+// distance to a capsule is the distance to its segment.  The sphere and
+// obstacle tables are staged in LDS first, so the (sphere, obstacle) loops
+// read broadcast LDS instead of waiting on a memory load per pair.  Lane =
+// (sample, sphere part): the parts split each link's spheres so that all 64
+// lanes work when S < 64; above 64 samples the lanes take them in chunks.
+// tab (LDS, nsph * (n_obs + n_caps) values) receives 1 / (r_a + margin +
+// r_o)^2 of every (sphere, obstacle) pair (FP32: hardware reciprocal, within
+// 1 ulp; FP64: IEEE division), and the loops keep the smallest d^2 / (r_a +
+// margin + r_o)^2 (a product and a minimum per pair instead of a division);
+// rho_c is its inverse square root.
 template <typename R, int PAT>
-__device__ void clearance(const ArmConst<R>& A, const EdgeState<R>& E, R T, int S,
-                          const float* __restrict__ obs, int n_obs, float margin_c,
+__device__ void clearance(const ArmConst<R>& A, const EdgeState<R>& E, R T, int S, const World& w,
                           GeoLDS<R>* geo, R* tab, R& rc) {
   constexpr bool F32 = sizeof(R) == 4;
   const int lane = lane_id();
+  const int n_obs = w.n_obs, n_caps = w.n_caps, nt = n_obs + n_caps;
   for (int t = lane; t < A.nsph; t += WAVE) {
     geo->sph[4 * t] = A.sphx[t];
     geo->sph[4 * t + 1] = A.sphy[t];
     geo->sph[4 * t + 2] = A.sphz[t];
-    geo->sph[4 * t + 3] = A.sphr[t] + R(margin_c);
+    geo->sph[4 * t + 3] = A.sphr[t] + R(w.margin);
   }
-  for (int t = lane; t < 4 * n_obs; t += WAVE) geo->obs[t] = R(obs[t]);
+  for (int t = lane; t < 4 * n_obs; t += WAVE) geo->obs[t] = R(w.obs[t]);
+  for (int t = lane; t < n_caps; t += WAVE) {
+    const float* c = w.caps + 7 * t;
+    const R dx = R(c[3]) - R(c[0]), dy = R(c[4]) - R(c[1]), dz = R(c[5]) - R(c[2]);
+    const R dd = dx * dx + dy * dy + dz * dz;
+    R* g = geo->caps + 8 * t;
+    g[0] = R(c[0]);
+    g[1] = R(c[1]);
+    g[2] = R(c[2]);
+    g[3] = dx;
+    g[4] = dy;
+    g[5] = dz;
+    if constexpr (F32) g[6] = dd > 0.f ? __builtin_amdgcn_rcpf(dd) : 0.f;
+    else g[6] = dd > 0.0 ? 1.0 / dd : 0.0;
+    g[7] = R(c[6]);
+  }
   __builtin_amdgcn_wave_barrier();
   {
     // 1 / need^2 per (sphere, obstacle) pair: the hardware reciprocal in
     // FP32, an IEEE division in FP64; lane = (obstacle o, sphere offset k0),
-    // WAVE / n_obs spheres per step
-    const int kstep = WAVE / n_obs, o = lane % n_obs, k0 = lane / n_obs;
+    // WAVE / nt spheres per step
+    const int kstep = WAVE / nt, o = lane % nt, k0 = lane / nt;
     if (k0 < kstep)
       for (int k = k0; k < A.nsph; k += kstep) {
-        const R need = geo->sph[4 * k + 3] + geo->obs[4 * o + 3];
-        if constexpr (F32) tab[k * n_obs + o] = __builtin_amdgcn_rcpf(need * need);
-        else tab[k * n_obs + o] = R(1) / (need * need);
+        const R need = geo->sph[4 * k + 3] + (o < n_obs ? geo->obs[4 * o + 3]
+                                                          : geo->caps[8 * (o - n_obs) + 7]);
+        if constexpr (F32) tab[k * nt + o] = __builtin_amdgcn_rcpf(need * need);
+        else tab[k * nt + o] = R(1) / (need * need);
       }
     __builtin_amdgcn_wave_barrier();
   }
@@ -189,24 +222,39 @@ __device__ void clearance(const ArmConst<R>& A, const EdgeState<R>& E, R T, int 
   int Sw = 1;
   while (Sw < S) Sw <<= 1;
   const int nparts = Sw >= WAVE ? 1 : WAVE / Sw;
-  const int s = lane & (Sw - 1), part = lane / Sw;
-  if (s < S && part < nparts) {
-    const R u = R(s) / R(S - 1);
-    R sg[NJ], sd[NJ], sdd[NJ], sn[NJ], cs[NJ];
-    cubic_point(E, T, R(1) / T, u, sg, sd, sdd);
+  const int part = Sw >= WAVE ? 0 : lane / Sw;
+  for (int s0 = 0; s0 < S; s0 += (Sw >= WAVE ? WAVE : S)) {
+    const int s = Sw >= WAVE ? s0 + lane : (lane & (Sw - 1));
+    if (s < S && part < nparts) {
+      const R u = R(s) / R(S - 1);
+      R sg[NJ], sd[NJ], sdd[NJ], sn[NJ], cs[NJ];
+      cubic_point(E, T, R(1) / T, u, sg, sd, sdd);
 #pragma unroll
-    for (int i = 0; i < NJ; ++i) sincos_r(sg[i], sn[i], cs[i]);
-    const R* so = geo->obs;
-    sphere_centres<R, PAT>(A, sn, cs, part, nparts, geo->sph, [&](int k, R x, R y, R z) {
-      const R* tk = tab + k * n_obs;
+      for (int i = 0; i < NJ; ++i) sincos_r(sg[i], sn[i], cs[i]);
+      const R* so = geo->obs;
+      const R* sc = geo->caps;
+      sphere_centres<R, PAT>(A, sn, cs, part, nparts, geo->sph, [&](int k, R x, R y, R z) {
+        const R* tk = tab + k * nt;
 #pragma unroll 4
-      for (int o = 0; o < n_obs; ++o) {
-        const R dx = x - so[4 * o], dy = y - so[4 * o + 1], dz = z - so[4 * o + 2];
-        const R d2 = dx * dx + dy * dy + dz * dz;
-        if constexpr (F32) best = fminf(best, d2 * tk[o]);
-        else best = fmin(best, d2 * tk[o]);
-      }
-    });
+        for (int o = 0; o < n_obs; ++o) {
+          const R dx = x - so[4 * o], dy = y - so[4 * o + 1], dz = z - so[4 * o + 2];
+          const R d2 = dx * dx + dy * dy + dz * dz;
+          if constexpr (F32) best = fminf(best, d2 * tk[o]);
+          else best = fmin(best, d2 * tk[o]);
+        }
+        for (int o = 0; o < n_caps; ++o) {
+          // closest point of the segment: the projection clamped to [0, 1]
+          const R* g = sc + 8 * o;
+          const R wx = x - g[0], wy = y - g[1], wz = z - g[2];
+          R t = (wx * g[3] + wy * g[4] + wz * g[5]) * g[6];
+          t = t < R(0) ? R(0) : (t > R(1) ? R(1) : t);
+          const R ex = wx - t * g[3], ey = wy - t * g[4], ez = wz - t * g[5];
+          const R d2 = ex * ex + ey * ey + ez * ez;
+          if constexpr (F32) best = fminf(best, d2 * tk[n_obs + o]);
+          else best = fmin(best, d2 * tk[n_obs + o]);
+        }
+      });
+    }
   }
   // d2 = 0 gives rho_c = +inf; no pair (no spheres) gives 0
   const R mn = wave_min(best);
@@ -219,17 +267,22 @@ __device__ void clearance(const ArmConst<R>& A, const EdgeState<R>& E, R T, int 
 // is evaluated only when rho_v and rho_q are at most `pass` (1 in FP64;
 // 1 + BAND in FP32, where a ratio in the band is decided later in FP64) and
 // is NaN (not evaluated) otherwise; 0 without obstacles.  tab: LDS for the
-// FP32 clearance (nsph * n_obs floats).
+// FP32 clearance (nsph * (n_obs + n_caps) floats).
 template <typename R, int PAT>
 __device__ void post_checks(const ArmConst<R>& A, const EdgeState<R>& E, R T, int S,
-                            const float* __restrict__ obs, int n_obs, float margin_c,
-                            GeoLDS<R>* geo, float* tab, R pass, R& rv, R& rq, R& rc) {
+                            const World& w, GeoLDS<R>* geo, float* tab, R pass, R& rv, R& rq,
+                            R& rc) {
   joint_checks<R>(A, E, T, rv, rq);
   rc = R(NAN);
   if (rv <= pass && rq <= pass) {
     rc = R(0);
-    if (n_obs > 0) clearance<R, PAT>(A, E, T, S, obs, n_obs, margin_c, geo, tab, rc);
+    if (world_size(w) > 0) clearance<R, PAT>(A, E, T, S, w, geo, tab, rc);
   }
+}
+
+// The obstacles of an edge launch.
+__device__ __forceinline__ World world_of(const EdgeArgs& a) {
+  return World{a.obs, a.n_obs, a.caps, a.n_caps, a.margin_c};
 }
 
 __device__ __forceinline__ bool near_one(float r) { return fabsf(r - 1.f) <= BAND; }
@@ -646,8 +699,7 @@ __device__ void search_edge(const EdgeArgs& a, int64_t e, int64_t eq, const ArmC
     const int js = pass == 0 ? jn : jstar;
     if (js < 0) break;
     float pv, pq, pc;
-    post_checks<float, PAT>(A, ES, Tg[js], S, a.obs, a.n_obs, a.margin_c, geo, tab, 1.f + BAND,
-                            pv, pq, pc);
+    post_checks<float, PAT>(A, ES, Tg[js], S, world_of(a), geo, tab, 1.f + BAND, pv, pq, pc);
     if (pass == 0) {
       v1 = pv; q1 = pq; c1 = pc;
     } else {
@@ -661,7 +713,7 @@ __device__ void search_edge(const EdgeArgs& a, int64_t e, int64_t eq, const ArmC
                jstar >= 0 ? rho_star : lastv, v1, q1, c1, rv, rq, rc, todo, wlo);
     return;
   }
-  if (near_one(rv) || near_one(rq) || (a.n_obs > 0 && near_one(rc))) {
+  if (near_one(rv) || near_one(rq) || (a.n_obs + a.n_caps > 0 && near_one(rc))) {
     push_queue(a, eq, jstar, PH_POST | ph_b, -1, m, INFINITY, work, rho_star, 0.f, rv, rq, rc, 0.f,
                0.f, 0.f, todo, wlo);
     return;
@@ -791,9 +843,9 @@ __device__ void recheck_edge(const EdgeArgs& a, int64_t e, const QEntry& q,
   // clearance only for an edge that passes the limit checks (Alg. 1); in
   // FP64 when its FP32 value is in the band or missing, or after the walk
   if (rv > 1.0 || rq > 1.0) rc = NAN;
-  else if (a.n_obs == 0) rc = 0.0;
+  else if (a.n_obs + a.n_caps == 0) rc = 0.0;
   else if (exact || isnan(rc) || near_one((float)rc))
-    clearance<double, PAT>(D, ED, T, S, a.obs, a.n_obs, a.margin_c, geo, tab, rc);
+    clearance<double, PAT>(D, ED, T, S, world_of(a), geo, tab, rc);
   m = fminf(m, (float)fmin(fabs(rv - 1.0), fmin(fabs(rq - 1.0), fabs(rc - 1.0))));
   write_out(a, e, jstar, post_status(rv, rq, rc) | FN_S_RECHECK64 | winbits, m, rho_star,
             (float)rv, (float)rq, (float)rc, work, Tg[jstar]);

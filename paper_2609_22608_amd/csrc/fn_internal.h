@@ -54,6 +54,8 @@ struct ArmConst {
   int32_t sph_first[NJ + 1];  // spheres of link i+1: [sph_first[i], sph_first[i+1])
   int32_t sph_link[FN_MAX_SPHERES];
   R sphx[FN_MAX_SPHERES], sphy[FN_MAX_SPHERES], sphz[FN_MAX_SPHERES], sphr[FN_MAX_SPHERES];
+  R taumax[NJ];           // torque limits and power limit (the controller's clips)
+  R wmax;
 };
 
 // ---------------------------------------------------------------------------

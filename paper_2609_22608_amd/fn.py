@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libfruitninja.so")
 
 FN_OK, FN_E_ARG, FN_E_SHAPE, FN_E_UNSUPPORTED, FN_E_HIP, FN_E_NOMEM, FN_E_STATE = 0, -1, -2, -3, -4, -5, -6
 S_NONE, S_VEL, S_POS, S_COLL, S_RECHECK64, S_WIN_HIT, S_WIN_MISS, S_BAD_INPUT, S_WIN_BELOW, \
-    S_NO_PARENT = 1, 2, 4, 8, 16, 32, 64, 128, 256, 512
+    S_NO_PARENT, S_SELF = 1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024
 S_DECISION = S_NONE | S_VEL | S_POS | S_COLL | S_BAD_INPUT | S_NO_PARENT
 T_RIGID, T_ARMATURE, T_FRICTION, T_GRAVITY, T_ALL = 1, 2, 4, 8, 15
 SEARCH_PLAIN, SEARCH_SCREEN, SEARCH_WINDOW = 0, 1, 2
@@ -62,12 +62,26 @@ class Search(C.Structure):
 
 
 class Obstacles(C.Structure):
-    _fields_ = [("spheres", C.c_void_p), ("n", C.c_int32), ("margin", C.c_float)]
+    _fields_ = [("spheres", C.c_void_p), ("n", C.c_int32), ("margin", C.c_float),
+                ("capsules", C.c_void_p), ("n_caps", C.c_int32)]
+
+
+def obstacles(obs=None, margin=0.0, caps=None):
+    """fn_obstacles of device tensors: spheres [n][4], capsules [m][7]."""
+    return Obstacles(None if obs is None or obs.shape[0] == 0 else C.c_void_p(obs.data_ptr()),
+                     0 if obs is None else obs.shape[0], float(margin),
+                     None if caps is None or caps.shape[0] == 0 else C.c_void_p(caps.data_ptr()),
+                     0 if caps is None else caps.shape[0])
 
 
 class EdgeOut(C.Structure):
     _fields_ = [("j", C.c_void_p), ("status", C.c_void_p), ("margin", C.c_void_p),
                 ("rho4", C.c_void_p), ("work", C.c_void_p), ("screened", C.c_void_p)]
+
+
+class Refine(C.Structure):
+    _fields_ = [("grid", C.c_void_p), ("n_t", C.c_int32), ("samples", C.c_int32),
+                ("n_ary", C.c_int32), ("eps", C.c_float)]
 
 
 class TrainCfg(C.Structure):
@@ -93,7 +107,8 @@ class Problem(C.Structure):
                 ("B", C.c_int32), ("obs", C.c_void_p), ("n_obs", C.c_int32), ("nbr", C.c_void_p),
                 ("out_j", C.c_void_p), ("out_status", C.c_void_p), ("out_margin", C.c_void_p),
                 ("out_rho4", C.c_void_p), ("out_T", C.c_void_p), ("out_node", C.c_void_p),
-                ("out_J", C.c_void_p), ("out_best", C.c_void_p)]
+                ("out_J", C.c_void_p), ("out_best", C.c_void_p), ("caps", C.c_void_p),
+                ("n_caps", C.c_int32)]
 
 
 class ProblemSet(C.Structure):
@@ -126,6 +141,11 @@ def lib():
             L.edge_time_batch_noalloc.argtypes = L.edge_time_batch.argtypes
             L.fn_noalloc_scratch_bytes.restype = C.c_size_t
             L.edge_check.argtypes = [vp, vp, vp, vp, i64, i32, C.POINTER(Obstacles), vp, vp, vp, vp]
+            L.fn_set_self_pairs.argtypes = [vp, vp, i32, C.c_float]
+            L.fn_control.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, C.c_float,
+                                     C.POINTER(C.c_double), vp, vp, vp, vp]
+            L.edge_refine.argtypes = [vp, vp, i64, i32, vp, i32, vp, i32, vp, C.POINTER(Refine),
+                                      C.POINTER(Obstacles), vp, vp, vp, vp, vp, vp]
             L.risk_score.argtypes = [vp, C.POINTER(Risk), vp, vp, vp, vp, vp, i32, vp, vp]
             L.fn_mlp_create.argtypes = [vp, C.c_uint64, C.POINTER(vp)]
             L.fn_mlp_destroy.argtypes = [vp]
@@ -267,7 +287,7 @@ class Context:
     # -- edge_time_batch ------------------------------------------------------
     def edge_time_batch(self, tree, ld, n_nodes, cand, nbr, grid, samples, obs=None,
                         margin=0.0, mode=SEARCH_PLAIN, j_max=None, win_lo=None, win_half=4,
-                        out=None, want_rho=True, want_work=True, noalloc=False):
+                        out=None, want_rho=True, want_work=True, noalloc=False, caps=None):
         """edge_time_batch, or edge_time_batch_noalloc when noalloc is set."""
         B, k = nbr.shape
         E = B * k
@@ -282,8 +302,7 @@ class Context:
         s = Search(C.c_void_p(grid.data_ptr()), grid.shape[0], int(samples), int(mode),
                    int(win_half), None if j_max is None else C.c_void_p(j_max.data_ptr()),
                    None if win_lo is None else C.c_void_p(win_lo.data_ptr()))
-        o = Obstacles(None if obs is None or obs.shape[0] == 0 else C.c_void_p(obs.data_ptr()),
-                      0 if obs is None else obs.shape[0], float(margin))
+        o = obstacles(obs, margin, caps)
         eo = EdgeOut(out["j"].data_ptr(), out["status"].data_ptr(), out["margin"].data_ptr(),
                      None if out["rho"] is None else out["rho"].data_ptr(),
                      None if out["work"] is None else out["work"].data_ptr(),
@@ -294,15 +313,40 @@ class Context:
                "edge_time_batch_noalloc" if noalloc else "edge_time_batch")
         return out
 
+    def set_self_pairs(self, pairs, margin=0.0):
+        """Self-collision sphere pairs [n][2] of the arm for edge_check."""
+        a = np.ascontiguousarray(np.asarray(pairs, np.int32).reshape(-1, 2))
+        _check(lib().fn_set_self_pairs(self.h, a.ctypes.data_as(C.c_void_p), len(a),
+                                       C.c_float(margin)), "fn_set_self_pairs")
+
+    # -- edge_refine ----------------------------------------------------------
+    def edge_refine(self, tree, ld, n_nodes, cand, nbr, j_in, grid, samples, n_ary=3, eps=1e-4,
+                    obs=None, margin=0.0, caps=None):
+        B, k = nbr.shape
+        E = B * k
+        d = cand.device
+        out = dict(T=torch.empty(E, dtype=torch.float32, device=d),
+                   status=torch.empty(E, dtype=torch.int16, device=d),
+                   rho=torch.empty((E, 4), dtype=torch.float32, device=d),
+                   rounds=torch.empty(E, dtype=torch.int32, device=d),
+                   work=torch.empty(E, dtype=torch.int32, device=d))
+        r = Refine(C.c_void_p(grid.data_ptr()), grid.shape[0], int(samples), int(n_ary),
+                   float(eps))
+        o = obstacles(obs, margin, caps)
+        _check(lib().edge_refine(self.h, _ptr(tree), ld, n_nodes, _ptr(cand), B, _ptr(nbr), k,
+                                 _ptr(j_in), C.byref(r), C.byref(o), _ptr(out["T"]),
+                                 _ptr(out["status"]), _ptr(out["rho"]), _ptr(out["rounds"]),
+                                 _ptr(out["work"]), _stream()), "edge_refine")
+        return out
+
     # -- edge_check -----------------------------------------------------------
-    def edge_check(self, x0, x1, T, samples, obs=None, margin=0.0, want_tau=False):
+    def edge_check(self, x0, x1, T, samples, obs=None, margin=0.0, want_tau=False, caps=None):
         E = x0.shape[0]
         d = x0.device
         st = torch.empty(E, dtype=torch.int16, device=d)
         rho = torch.empty((E, 5), dtype=torch.float32, device=d)
         tau = torch.empty((E, samples, 7), dtype=torch.float32, device=d) if want_tau else None
-        o = Obstacles(None if obs is None or obs.shape[0] == 0 else C.c_void_p(obs.data_ptr()),
-                      0 if obs is None else obs.shape[0], float(margin))
+        o = obstacles(obs, margin, caps)
         _check(lib().edge_check(self.h, _ptr(x0), _ptr(x1), _ptr(T), E, int(samples), C.byref(o),
                                 _ptr(st), _ptr(rho), _ptr(tau), _stream()), "edge_check")
         return dict(status=st, rho=rho, tau=tau)
@@ -491,3 +535,22 @@ def make_risk(gz=-9.81, sigma_mode=0, sp=0.0048, sv=0.0186, sa=0.0, s0=0.01, s1=
     for key, v in ww.items():
         setattr(r, key, v)
     return r
+
+
+C_ACC, C_SLEW, C_TORQUE, C_POWER, C_BAD = 1, 2, 4, 8, 128
+
+
+def control(ctx: Context, q, qd, tau_prev, qg, qdg, T, dt, slew):
+    """One step of the tracking controller (fn_control) for n instances:
+    device [n][7] float tensors and T [n]; slew: 7 limits (N m / s).
+    Returns (tau, qdd, status) device tensors."""
+    n = q.shape[0]
+    d = q.device
+    tau = torch.empty((n, 7), dtype=torch.float32, device=d)
+    qdd = torch.empty((n, 7), dtype=torch.float32, device=d)
+    st = torch.empty(n, dtype=torch.int16, device=d)
+    sl = (C.c_double * 7)(*[float(x) for x in slew])
+    _check(lib().fn_control(ctx.h, n, _ptr(q), _ptr(qd), _ptr(tau_prev), _ptr(qg), _ptr(qdg),
+                            _ptr(T), C.c_float(dt), sl, _ptr(tau), _ptr(qdd), _ptr(st), _stream()),
+           "fn_control")
+    return tau, qdd, st

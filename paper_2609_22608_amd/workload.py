@@ -322,6 +322,42 @@ def make_obstacles(arm, n_obs: int, seed: int, r=(0.05, 0.15)) -> np.ndarray:
     return _f32(np.asarray(out).reshape(n_obs, 4))
 
 
+def make_capsules(arm, n_caps: int, seed: int, length: float = 0.75, r=(0.03, 0.08)) -> np.ndarray:
+    """Obstacle capsules [n_caps][7] = (segment end p0, segment end p1,
+    radius): 0.75 m segments (the cluttered workspace of the paper's
+    experiments) centred 0.25-0.8 of the reach from the base, z >= 0, random
+    direction, radius U[r]; redrawn when the segment comes within 0.15 m of
+    the base column."""
+    rng = np.random.default_rng([seed, 5])
+    R = reach(arm)
+    col_r = 0.15 + abs(arm["a"][1])
+    col_h = float(arm["d"][0]) + 0.1
+    out = []
+    while len(out) < n_caps:
+        rad = rng.uniform(*r)
+        dist = rng.uniform(0.25 * R, 0.8 * R)
+        v = rng.normal(size=3)
+        v[2] = abs(v[2])
+        v /= np.linalg.norm(v)
+        c = dist * v
+        d = rng.normal(size=3)
+        d *= 0.5 * length / np.linalg.norm(d)
+        p0, p1 = c - d, c + d
+        pts = np.linspace(p0, p1, 16)
+        if np.any((np.hypot(pts[:, 0], pts[:, 1]) < col_r + rad) & (pts[:, 2] < col_h + rad)):
+            continue
+        out.append([*p0, *p1, rad])
+    return _f32(np.asarray(out).reshape(n_caps, 7))
+
+
+def self_pairs_apart(arm, gap: int = 2) -> np.ndarray:
+    """Sphere pairs on links at least `gap` apart [n][2] (neighbouring links
+    always touch at their joint); a caller prunes these further offline."""
+    link = np.asarray(arm["sph_link"])
+    return np.array([(a, b) for a in range(len(link)) for b in range(a + 1, len(link))
+                     if abs(int(link[b]) - int(link[a])) >= gap], np.int32).reshape(-1, 2)
+
+
 # ---------------------------------------------------------------------------
 # Benchmark shapes
 # ---------------------------------------------------------------------------
