@@ -114,6 +114,7 @@ def lib():
             L.oracle_friction.restype = C.c_double
             L.oracle_rnea.argtypes = [ap, dp, dp, dp, dp]
             L.oracle_fk_spheres.argtypes = [ap, dp, dp]
+            L.oracle_fk_point.argtypes = [ap, C.c_int, dp, C.c_int, C.c_int, dp, dp]
             L.oracle_slot_rho.argtypes = [ap, dp, dp, C.c_double, C.c_int, dp, dp, dp]
             L.oracle_rho_v.argtypes = [ap, dp, dp, C.c_double]
             L.oracle_rho_v.restype = C.c_double
@@ -214,6 +215,17 @@ def fk_spheres(A: OArm, q):
     c = np.zeros((A.nsph, 3))
     lib().oracle_fk_spheres(C.byref(A), pq, _p(c, C.c_double))
     return c
+
+
+def fk_point(A: OArm, X, local, link=None):
+    """World position of the point `local` of link `link` (default: the last
+    link) for the configurations X[:, :n] (rows may carry velocities too)."""
+    X, pX = _d(np.atleast_2d(X))
+    local, pl = _d(local)
+    out = np.zeros((X.shape[0], 3))
+    lib().oracle_fk_point(C.byref(A), X.shape[0], pX, X.shape[1], int(A.n if link is None else link),
+                          pl, _p(out, C.c_double))
+    return out
 
 
 def slot_rho(A: OArm, x0, x1, T, S, want_tau=False):

@@ -211,8 +211,9 @@ void oracle_rnea(const oarm* A, const double* q, const double* qd, const double*
 /* Forward kinematics of the collision spheres (Sec. IV-E, collision   */
 /* checking): world centre of every arm sphere at configuration q.     */
 /* ------------------------------------------------------------------ */
-void oracle_fk_spheres(const oarm* A, const double* q, double* centres /*[nsph][3]*/) {
-  double Rw[OJ + 1][3][3], pw[OJ + 1][3];
+/* World rotation Rw[i] and origin pw[i] of every link frame i = 0..n
+ * (frame 0: the base) at configuration q, by the modified DH chain. */
+static void fk_frames(const oarm* A, const double* q, double Rw[OJ + 1][3][3], double pw[OJ + 1][3]) {
   memset(Rw[0], 0, sizeof(Rw[0]));
   Rw[0][0][0] = Rw[0][1][1] = Rw[0][2][2] = 1.0;
   pw[0][0] = pw[0][1] = pw[0][2] = 0.0;
@@ -226,11 +227,28 @@ void oracle_fk_spheres(const oarm* A, const double* q, double* centres /*[nsph][
     matvec(Rw[i], p, pr);
     for (int r = 0; r < 3; ++r) pw[i + 1][r] = pw[i][r] + pr[r];
   }
+}
+
+void oracle_fk_spheres(const oarm* A, const double* q, double* centres /*[nsph][3]*/) {
+  double Rw[OJ + 1][3][3], pw[OJ + 1][3];
+  fk_frames(A, q, Rw, pw);
   for (int k = 0; k < A->nsph; ++k) {
     int l = A->sph_link[k];
     double c[3];
     matvec(Rw[l], A->sph[k], c);
     for (int r = 0; r < 3; ++r) centres[3 * k + r] = pw[l][r] + c[r];
+  }
+}
+
+/* World position of a point given in the frame of link `link` (1..n), for
+ * n configurations q [n][stride] (the blade point p_n of Eq. (8)). */
+void oracle_fk_point(const oarm* A, int n, const double* q, int stride, int link,
+                     const double* local, double* out /*[n][3]*/) {
+  for (int i = 0; i < n; ++i) {
+    double Rw[OJ + 1][3][3], pw[OJ + 1][3], c[3];
+    fk_frames(A, q + (size_t)i * stride, Rw, pw);
+    matvec(Rw[link], local, c);
+    for (int r = 0; r < 3; ++r) out[3 * i + r] = pw[link][r] + c[r];
   }
 }
 

@@ -278,11 +278,32 @@ def goal_states(arm, n: int, rng, t_arr=(0.2, 0.8), launch=(4.0, 7.0),
     return x, t, flight
 
 
-def make_candidates(arm, b: int, goal_frac: float, seed: int, qd_scale: float = 0.5):
+def chord_states(arm, root, goals, n: int, rng, sigma: float = 0.15, p_uniform: float = 0.2,
+                 qd_frac: float = 0.3) -> np.ndarray:
+    """Free states of Algorithm 1's ChordSample: a configuration on the
+    joint-space chord from the root to a random goal (uniform position along
+    it) perturbed by N(0, sigma^2) rad per joint, or, with probability
+    p_uniform, uniform over the joint box; clipped to the box.  Velocities
+    uniform within +-qd_frac of the joint-velocity limits."""
+    q0 = np.asarray(root, np.float64)[:DOF]
+    qg = np.asarray(goals, np.float64)[rng.integers(0, len(goals), n), :DOF]
+    s = rng.uniform(0, 1, (n, 1))
+    q = q0 + s * (qg - q0) + rng.normal(0, sigma, (n, DOF))
+    uni = rng.random(n) < p_uniform
+    q[uni] = rng.uniform(arm["qmin"], arm["qmax"], (int(uni.sum()), DOF))
+    q = np.clip(q, arm["qmin"], arm["qmax"])
+    qd = rng.uniform(-qd_frac, qd_frac, (n, DOF)) * arm["qdmax"]
+    return np.concatenate([q, qd], 1)
+
+
+def make_candidates(arm, b: int, goal_frac: float, seed: int, qd_scale: float = 0.5,
+                    root=None):
     """Candidate batch: a fraction ``goal_frac`` of goal samples (inverse
-    construction, first), the rest uniform.  Returns a dict with ``x``
-    [b][14], ``kind`` [b] (0 free, 1 goal), ``t_req`` [b] (0 for free) and
-    per-goal flight data (x0, v0, t_fall, v_rel; zeros for free samples)."""
+    construction, first), the rest uniform -- or, when a root state is given
+    and there are goals, chord samples (``chord_states``).  Returns a dict
+    with ``x`` [b][14], ``kind`` [b] (0 free, 1 goal), ``t_req`` [b] (0 for
+    free) and per-goal flight data (x0, v0, t_fall, v_rel; zeros for free
+    samples)."""
     rng = np.random.default_rng([seed, 2])
     n_goal = int(round(goal_frac * b))
     xs = np.zeros((b, STATE))
@@ -296,7 +317,10 @@ def make_candidates(arm, b: int, goal_frac: float, seed: int, qd_scale: float = 
         t_req[:n_goal] = tg
         for k in flight:
             flight[k][:n_goal] = fg[k]
-    xs[n_goal:] = uniform_states(arm, b - n_goal, rng, qd_scale)
+    if root is not None and n_goal:
+        xs[n_goal:] = chord_states(arm, root, xs[:n_goal], b - n_goal, rng)
+    else:
+        xs[n_goal:] = uniform_states(arm, b - n_goal, rng, qd_scale)
     return dict(x=_f32(xs), kind=kind, t_req=_f32(t_req),
                 flight={k: _f32(v) for k, v in flight.items()})
 
@@ -389,6 +413,48 @@ CONFIGS = {
     # 128 durations over 0.01-1.2 s x 64 samples, 20 obstacles
     "stress": Shape("stress", 262144, 65536, 16, 128, 0.01, 1.2, 64, 20, 0.3, (0.03, 0.2)),
 }
+
+
+def make_flight(seed: int, t_arrive=(0.4, 0.7), window: float = 0.25,
+                launch_dist=(2.5, 3.5), g: float = 9.81):
+    """The tracked object's flight for the planner's outer loop (Eq. (1)): a
+    ballistic arc from a launch point 2.5-3.5 m from the base, 1 m high,
+    through a workspace point 0.35-0.7 m from the base and 0.2-0.8 m high,
+    reached at t* ~ U[t_arrive]; the object counts as within reach for
+    [t* - window, t* + window] (t_enter, t_fall).  Values rounded to FP32."""
+    rng = np.random.default_rng([seed, 7])
+    az = rng.uniform(0, 2 * math.pi)
+    rad = rng.uniform(0.35, 0.7)
+    target = np.array([rad * math.cos(az), rad * math.sin(az), rng.uniform(0.2, 0.8)])
+    la = az + rng.uniform(-0.6, 0.6)
+    dist = rng.uniform(*launch_dist)
+    x0 = np.array([dist * math.cos(la), dist * math.sin(la), 1.0])
+    gv = np.array([0.0, 0.0, -g])
+    ts = rng.uniform(*t_arrive)
+    v0 = (target - x0 - 0.5 * gv * ts * ts) / ts
+    return dict(x0=_f32(x0), v0=_f32(v0), g=_f32(gv), t_enter=float(np.float32(ts - window)),
+                t_fall=float(np.float32(ts + window)), target=_f32(target), t_star=float(ts))
+
+
+def goal_parents(cand, tau: float = 0.1, every: int = 2):
+    """Tree nodes that reach every `every`-th goal candidate at constant
+    velocity in tau seconds: state (q_g - qd_g tau, qd_g) with time-to-come
+    t_req - tau.  Uniform tree nodes almost never reach a goal state within
+    the limits; these let the goal branch, its attachment and its score take
+    part.  Returns (states [m][14], times [m])."""
+    g = np.nonzero(np.asarray(cand["kind"]) == KIND_GOAL)[0][::every]
+    xg = np.asarray(cand["x"], np.float64)[g]
+    x = np.concatenate([xg[:, :DOF] - xg[:, DOF:] * tau, xg[:, DOF:]], 1)
+    t = np.asarray(cand["t_req"], np.float32)[g] - np.float32(tau)
+    return _f32(x), _f32(t)
+
+
+def make_rounds(arm, n_rounds: int, batch: int, goal_frac: float, seed: int, root=None):
+    """Candidates of every round of a planning cycle, each round drawn with
+    its own seed (seed * 100 + round); free samples on the chord from `root`
+    to the round's goals when a root is given."""
+    return [make_candidates(arm, batch, goal_frac, seed * 100 + r, root=root)
+            for r in range(n_rounds)]
 
 
 def make_workload(shape: Shape, seed: int, arm_seed: int = 0, arm=None):
