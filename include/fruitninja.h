@@ -504,7 +504,25 @@ typedef struct {
   float* out_best;       /* device out [2]: best J among this round's goal nodes, its node (as float) */
   const float* caps;     /* device [n_caps][7] obstacle capsules, or NULL (n_obs + n_caps <= FN_MAX_OBS) */
   int32_t n_caps;
+  /* Anytime outer loop (Algorithm 1), optional; the same choice for every
+   * problem of a set.  With n_rounds > 1 the candidate arrays (cand, kind,
+   * t_req, v_rel, vz0, t_fall) hold n_rounds consecutive rounds of B
+   * candidates each, and round r reads the r-th; per-round outputs are
+   * overwritten by every round. */
+  int32_t n_rounds;      /* 0 or 1: one round; at most FN_MAX_ROUNDS */
+  float* incumbent;      /* device [4] or NULL: J*, node* (as float, -1: none), t_best, rounds run.
+                          * Initialise to (-inf, -1, t_fall, 0): Algorithm 1 starts with
+                          * t_best = t_fall.  When set, a free candidate searches only the
+                          * slots with t(parent) + T <= t_best (FP32 sum), every round
+                          * replaces the incumbent by its best goal node when that J is
+                          * larger, and Prune needs the flight. */
+  const float* flight;   /* device [11] or NULL: the object's flight of Eq. (1) for Prune:
+                          * x0[3], v0[3], g[3], t_enter, t_fall */
+  float* out_reach;      /* device out [ld] or NULL: T_n of Eq. (8) of every node at the last
+                          * Prune (before compaction; NaN: no T_n) */
 } fn_problem;
+
+#define FN_MAX_ROUNDS 256
 
 typedef struct {
   int32_t n_problems;
@@ -529,6 +547,48 @@ int fn_batch_launch(fn_ctx* ctx, void* stream);
  * not memset nodes. */
 int fn_graph_capture(fn_ctx* ctx, void* stream);
 int fn_graph_launch(fn_ctx* ctx, void* stream);
+
+/* Round `round` (0 .. n_rounds-1) of the prepared problems: the candidates
+ * of that round, otherwise as fn_batch_launch (which is round 0). */
+int fn_batch_round(fn_ctx* ctx, int32_t round, void* stream);
+
+/* ------------------------------------------------------------------ */
+/* Anytime outer loop: arrival-time pruning (Sec. IV-D, Eq. (8)) and   */
+/* whole planning cycles (Algorithm 1).                                */
+/* ------------------------------------------------------------------ */
+typedef struct {
+  float v_tip;     /* V_tip of Eq. (8): bound on the blade's speed, m/s (finite, > 0) */
+  float blade[3];  /* the blade point p_n, in the frame of the arm's last link, m */
+} fn_prune;
+
+/* Earliest reach time of Eq. (8) for n tree nodes (SoA [14][ld], times
+ * t_node [n], device): T_n = min{T in [t_enter, t_fall] :
+ * t_n + |p_n - x(T)| / V_tip <= T} with x(T) the flight of Eq. (1)
+ * (flight: device [11] as in fn_problem); out_T [n] device, NaN where no such
+ * T exists.  FP32; a node whose outcome comes close to changing (|G| of the
+ * quartic G(T) = |p_n - x(T)|^2 - V_tip^2 (T - t_n)^2 small at a deciding
+ * point, a shallow root, or -- in Prune -- T_n within 1 ms of t_best) is
+ * recomputed in FP64.  FN_E_ARG for a bad V_tip or blade point. */
+int fn_reach_time(fn_ctx* ctx, const float* tree, int64_t ld, int32_t n, const float* t_node,
+                  const float* flight, const fn_prune* prune, float* out_T, void* stream);
+
+/* Prune of Algorithm 1 for every prepared problem (all need an incumbent
+ * and a flight): a node stays when its T_n exists and T_n <= t_best; node
+ * 0, the incumbent and every ancestor of a kept node stay as well.  Kept
+ * nodes are compacted in their order (tree, t_node, nu; parents
+ * renumbered, freed rows get parent -1), the node count and the
+ * incumbent's node index are updated.  Node counts are read on the device. */
+int fn_batch_prune(fn_ctx* ctx, const fn_prune* prune, void* stream);
+
+/* One planning cycle of Algorithm 1 for every prepared problem: n_iter
+ * anytime iterations of n_round rounds (round a * n_round + r reads
+ * candidate round a * n_round + r; n_iter * n_round <= n_rounds), each
+ * iteration ending with Prune.  fn_graph_capture_cycle captures the same
+ * work into the context's graph (replacing a previous one) for
+ * fn_graph_launch. */
+int fn_cycle(fn_ctx* ctx, int32_t n_iter, int32_t n_round, const fn_prune* prune, void* stream);
+int fn_graph_capture_cycle(fn_ctx* ctx, int32_t n_iter, int32_t n_round, const fn_prune* prune,
+                           void* stream);
 
 #ifdef __cplusplus
 }

@@ -10,11 +10,13 @@
 // grow.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstring>
 #include <vector>
 
 #include "fn_edge.h"
 #include "fn_knn.h"
+#include "fn_reach.h"
 #include "fn_risk.h"
 
 namespace fn {
@@ -51,6 +53,7 @@ struct InsProb {
   int32_t* out_node;
   float* out_J;
   float* out_best;
+  float* inc;  // incumbent J*, node, t_best, rounds (Algorithm 1), or NULL
 };
 
 // index p with off[p] <= x < off[p + 1] (n problems)
@@ -202,13 +205,14 @@ __global__ __launch_bounds__(INS_THREADS) void batch_insert_kernel(const InsProb
   __shared__ int s_scan[INS_THREADS];
   __shared__ float s_bj[INS_THREADS];
   __shared__ int s_bn[INS_THREADS];
+  __shared__ float s_bt[INS_THREADS];
   const InsProb& q = P[blockIdx.x];
   const int tid = threadIdx.x;
   const int n0 = *q.n_nodes;
   __syncthreads();
   const uint16_t fail = FN_S_NONE | FN_S_VEL | FN_S_POS | FN_S_COLL | FN_S_BAD_INPUT | FN_S_NO_PARENT;
   int running = 0;
-  float best_j = -INFINITY;
+  float best_j = -INFINITY, best_t = 0.f;
   int best_n = -1;
   for (int base = 0; base < q.B; base += INS_THREADS) {
     const int b = base + tid;
@@ -255,6 +259,7 @@ __global__ __launch_bounds__(INS_THREADS) void batch_insert_kernel(const InsProb
           if (J > best_j || (J == best_j && node < best_n)) {
             best_j = J;
             best_n = node;
+            best_t = cost;
           }
         }
       }
@@ -266,6 +271,7 @@ __global__ __launch_bounds__(INS_THREADS) void batch_insert_kernel(const InsProb
   // best goal node of the round (fixed-order tree reduction)
   s_bj[tid] = best_j;
   s_bn[tid] = best_n;
+  s_bt[tid] = best_t;
   __syncthreads();
   for (int o = INS_THREADS / 2; o > 0; o >>= 1) {
     if (tid < o) {
@@ -274,6 +280,7 @@ __global__ __launch_bounds__(INS_THREADS) void batch_insert_kernel(const InsProb
       if (c > a || (c == a && cn >= 0 && (an < 0 || cn < an))) {
         s_bj[tid] = c;
         s_bn[tid] = cn;
+        s_bt[tid] = s_bt[tid + o];
       }
     }
     __syncthreads();
@@ -282,6 +289,241 @@ __global__ __launch_bounds__(INS_THREADS) void batch_insert_kernel(const InsProb
     *q.n_nodes = (int)min<int64_t>(q.ld, (int64_t)n0 + running);
     q.out_best[0] = s_bj[0];
     q.out_best[1] = (float)s_bn[0];
+    // incumbent: the rendezvous node of largest J in the tree (earlier
+    // nodes win ties) and t_best = its time-to-come
+    if (q.inc) {
+      if (s_bn[0] >= 0 && s_bj[0] > q.inc[0]) {
+        q.inc[0] = s_bj[0];
+        q.inc[1] = (float)s_bn[0];
+        q.inc[2] = s_bt[0];
+      }
+      q.inc[3] += 1.f;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Prune (Algorithm 1, end of an anytime iteration) with the arrival-time rule
+// of Eq. (8): node n stays when its earliest reach time T_n exists and is at
+// most t_best; node 0 (the measured state), the incumbent and every ancestor
+// of a kept node stay too.  Kept nodes are compacted in their order and
+// parents renumbered.  Grid: (node blocks of 256, problems); node counts are
+// read on the device.
+// ---------------------------------------------------------------------------
+constexpr int PRUNE_THREADS = 256;
+constexpr int PRUNE_COLS = FN_STATE + 3;  // state, t, nu, parent (as bits)
+
+struct PruneProb {
+  float* tree;
+  int64_t ld;
+  int32_t* n_nodes;
+  float* t_node;
+  int32_t* parent;
+  float* nu;
+  float* inc;
+  const float* flight;
+  float* out_reach;  // T_n of every node, or NULL
+  int64_t off;       // node offset into keep0 / walked / map; rows at PRUNE_COLS * off
+  int64_t blk_off;   // offset into the per-block counts
+};
+
+struct PruneScratch {
+  int32_t* keep0;
+  int32_t* walked;
+  int32_t* map;
+  int32_t* blk;
+  int32_t* meta;  // [problem][2]: node count before, after
+  float* rows;
+};
+
+// The blade point of node n: forward kinematics of its configuration.
+template <typename R, int PAT>
+__device__ __forceinline__ void blade_point(const ArmConst<R>& A, const float* tree, int64_t ld,
+                                            int64_t n, const float* blade, R p[3]) {
+  R sn[NJ], cs[NJ];
+#pragma unroll
+  for (int i = 0; i < NJ; ++i) sincos_r(R(tree[(size_t)i * ld + n]), sn[i], cs[i]);
+  last_link_point<R, PAT>(A, sn, cs, R(blade[0]), R(blade[1]), R(blade[2]), p[0], p[1], p[2]);
+}
+
+// T_n of node n: FP32, and FP64 when the FP32 outcome is close to changing
+// (reach_ambiguous, with the bound t_best or NaN).  *T64 receives the value
+// that decides (the FP64 one where it was computed).
+template <int PAT>
+__device__ float node_reach(const ArmConst<float>& A, const ArmConst<double>& D,
+                            const float* tree, int64_t ld, int64_t n, float tn,
+                            const float* fl, const fn_prune& pr, float t_best, double* T64) {
+  float p[3], gmin, slope;
+  blade_point<float, PAT>(A, tree, ld, n, pr.blade, p);
+  const float T = reach_time_dev<float>(p, tn, fl, pr.v_tip, gmin, slope);
+  float scale = pr.v_tip * pr.v_tip * fl[10] * fl[10];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) scale += (p[i] - fl[i]) * (p[i] - fl[i]);
+  if (!reach_ambiguous(T, gmin, slope, t_best, scale)) {
+    *T64 = T;
+    return T;
+  }
+  double pd[3], gm, sl;
+  blade_point<double, PAT>(D, tree, ld, n, pr.blade, pd);
+  *T64 = reach_time_dev<double>(pd, (double)tn, fl, (double)pr.v_tip, gm, sl);
+  return (float)*T64;
+}
+
+template <int PAT>
+__global__ __launch_bounds__(256) void reach_kernel(const float* __restrict__ tree, int64_t ld,
+                                                    int n, const float* __restrict__ t_node,
+                                                    const float* __restrict__ flight, fn_prune pr,
+                                                    const ArmConst<float>* __restrict__ Ap,
+                                                    const ArmConst<double>* __restrict__ Dp,
+                                                    float* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  double T64;
+  out[i] = node_reach<PAT>(*Ap, *Dp, tree, ld, i, t_node[i], flight, pr, __builtin_nanf(""), &T64);
+}
+
+__global__ __launch_bounds__(PRUNE_THREADS) void prune_clear(const PruneProb* __restrict__ P,
+                                                             PruneScratch sc) {
+  const PruneProb& q = P[blockIdx.y];
+  const int64_t n = (int64_t)blockIdx.x * PRUNE_THREADS + threadIdx.x;
+  if (n < q.ld) sc.walked[q.off + n] = 0;
+}
+
+// keep0 of every node; a kept node then marks its ancestors: the first
+// walker to claim a node (atomic exchange) goes on above it, every other one
+// stops there, so each ancestor chain is walked once.
+template <int PAT>
+__global__ __launch_bounds__(PRUNE_THREADS) void prune_mark(const PruneProb* __restrict__ P,
+                                                            PruneScratch sc, fn_prune pr,
+                                                            const ArmConst<float>* __restrict__ Ap,
+                                                            const ArmConst<double>* __restrict__ Dp) {
+  const PruneProb& q = P[blockIdx.y];
+  const int64_t n = (int64_t)blockIdx.x * PRUNE_THREADS + threadIdx.x;
+  const int N = *q.n_nodes;
+  if (n >= N) return;
+  const float tb = q.inc[2];
+  double T64;
+  const float T = node_reach<PAT>(*Ap, *Dp, q.tree, q.ld, n, q.t_node[n], q.flight, pr, tb, &T64);
+  if (q.out_reach) q.out_reach[n] = T;
+  const bool k0 = n == 0 || T64 <= (double)tb || n == (int64_t)q.inc[1];
+  sc.keep0[q.off + n] = k0 ? 1 : 0;
+  if (!k0) return;
+  int64_t v = n;
+  for (;;) {
+    const int par = q.parent[v];
+    if (par < 0 || par >= N) break;
+    if (atomicExch(&sc.walked[q.off + par], 1)) break;
+    v = par;
+  }
+}
+
+__device__ __forceinline__ bool prune_kept(const PruneProb& q, const PruneScratch& sc, int64_t n,
+                                           int N) {
+  return n < N && (sc.keep0[q.off + n] | sc.walked[q.off + n]);
+}
+
+// Wave-ballot rank of a flag within its 256-thread block; total in *count.
+__device__ __forceinline__ int block_rank(bool f, int* s_w, int* count) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const unsigned long long m = __ballot(f);
+  if (lane == 0) s_w[w] = __popcll(m);
+  __syncthreads();
+  int base = 0;
+  for (int i = 0; i < w; ++i) base += s_w[i];
+  *count = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+  return base + __popcll(m & ((1ull << lane) - 1ull));
+}
+
+__global__ __launch_bounds__(PRUNE_THREADS) void prune_count(const PruneProb* __restrict__ P,
+                                                             PruneScratch sc) {
+  __shared__ int s_w[PRUNE_THREADS / 64];
+  const PruneProb& q = P[blockIdx.y];
+  if ((int64_t)blockIdx.x * PRUNE_THREADS >= q.ld) return;  // whole block: uniform exit
+  const int64_t n = (int64_t)blockIdx.x * PRUNE_THREADS + threadIdx.x;
+  int count;
+  block_rank(prune_kept(q, sc, n, *q.n_nodes), s_w, &count);
+  if (threadIdx.x == 0) sc.blk[q.blk_off + blockIdx.x] = count;
+}
+
+// Exclusive scan of one problem's block counts (one workgroup per problem).
+__global__ __launch_bounds__(PRUNE_THREADS) void prune_scan(const PruneProb* __restrict__ P,
+                                                            PruneScratch sc) {
+  __shared__ int s_v[PRUNE_THREADS];
+  const PruneProb& q = P[blockIdx.x];
+  const int nb = (int)((q.ld + PRUNE_THREADS - 1) / PRUNE_THREADS);
+  const int tid = threadIdx.x;
+  int running = 0;
+  for (int base = 0; base < nb; base += PRUNE_THREADS) {
+    const int i = base + tid;
+    const int v = i < nb ? sc.blk[q.blk_off + i] : 0;
+    s_v[tid] = v;
+    __syncthreads();
+    for (int o = 1; o < PRUNE_THREADS; o <<= 1) {
+      const int t = tid >= o ? s_v[tid - o] : 0;
+      __syncthreads();
+      s_v[tid] += t;
+      __syncthreads();
+    }
+    if (i < nb) sc.blk[q.blk_off + i] = running + s_v[tid] - v;
+    running += s_v[PRUNE_THREADS - 1];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    sc.meta[2 * blockIdx.x] = *q.n_nodes;
+    sc.meta[2 * blockIdx.x + 1] = running;
+  }
+}
+
+__global__ __launch_bounds__(PRUNE_THREADS) void prune_map(const PruneProb* __restrict__ P,
+                                                           PruneScratch sc) {
+  __shared__ int s_w[PRUNE_THREADS / 64];
+  const PruneProb& q = P[blockIdx.y];
+  if ((int64_t)blockIdx.x * PRUNE_THREADS >= q.ld) return;
+  const int64_t n = (int64_t)blockIdx.x * PRUNE_THREADS + threadIdx.x;
+  const bool k = prune_kept(q, sc, n, sc.meta[2 * blockIdx.y]);
+  int count;
+  const int r = block_rank(k, s_w, &count);
+  if (n < q.ld) sc.map[q.off + n] = k ? sc.blk[q.blk_off + blockIdx.x] + r : -1;
+}
+
+// Kept node n -> its new row in the scratch columns (parent renumbered).
+__global__ __launch_bounds__(PRUNE_THREADS) void prune_gather(const PruneProb* __restrict__ P,
+                                                              PruneScratch sc) {
+  const PruneProb& q = P[blockIdx.y];
+  const int64_t n = (int64_t)blockIdx.x * PRUNE_THREADS + threadIdx.x;
+  const int N = sc.meta[2 * blockIdx.y];
+  if (n >= N) return;
+  const int m = sc.map[q.off + n];
+  if (m < 0) return;
+  float* rows = sc.rows + (size_t)PRUNE_COLS * q.off;
+  for (int c = 0; c < FN_STATE; ++c) rows[(size_t)c * q.ld + m] = q.tree[(size_t)c * q.ld + n];
+  rows[(size_t)FN_STATE * q.ld + m] = q.t_node[n];
+  rows[(size_t)(FN_STATE + 1) * q.ld + m] = q.nu[n];
+  const int par = q.parent[n];
+  const int np = par >= 0 && par < N ? sc.map[q.off + par] : -1;
+  rows[(size_t)(FN_STATE + 2) * q.ld + m] = __int_as_float(np);
+}
+
+// Scratch rows back into the tree; parents of the freed rows cleared; node
+// count and the incumbent's index updated.
+__global__ __launch_bounds__(PRUNE_THREADS) void prune_commit(const PruneProb* __restrict__ P,
+                                                              PruneScratch sc) {
+  const PruneProb& q = P[blockIdx.y];
+  const int64_t i = (int64_t)blockIdx.x * PRUNE_THREADS + threadIdx.x;
+  const int N = sc.meta[2 * blockIdx.y], M = sc.meta[2 * blockIdx.y + 1];
+  const float* rows = sc.rows + (size_t)PRUNE_COLS * q.off;
+  if (i < M) {
+    for (int c = 0; c < FN_STATE; ++c) q.tree[(size_t)c * q.ld + i] = rows[(size_t)c * q.ld + i];
+    q.t_node[i] = rows[(size_t)FN_STATE * q.ld + i];
+    q.nu[i] = rows[(size_t)(FN_STATE + 1) * q.ld + i];
+    q.parent[i] = __float_as_int(rows[(size_t)(FN_STATE + 2) * q.ld + i]);
+  } else if (i < N) {
+    q.parent[i] = -1;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *q.n_nodes = M;
+    const int in = (int)q.inc[1];
+    q.inc[1] = (float)(in >= 0 && in < N ? sc.map[q.off + in] : -1);
   }
 }
 
@@ -298,10 +540,18 @@ struct fn_batch {
   int64_t pairs = 0, queries = 0, edges = 0;  // pairs: kNN scan work items
   int form = 1;                                // kNN scan form (fn_tuning)
   int max_obs = 0;  // most obstacles (spheres + capsules) of a problem (clearance table LDS)
-  // device tables
+  int rounds = 1;   // candidate rounds held by every problem (tables per round)
+  int64_t tab_cap = 0;  // entries of knn / ins / args
+  // device tables, round r at offset r * n
   KnnProb* knn = nullptr;
   InsProb* ins = nullptr;
   EdgeArgs* args = nullptr;
+  // anytime loop: every problem has an incumbent and a flight
+  bool loop = false;
+  PruneProb* prune = nullptr;
+  PruneScratch psc{};
+  int64_t prune_nodes = 0, prune_blocks = 0;  // scratch capacity
+  int64_t max_blocks = 0;                     // node blocks of the largest tree
   int64_t *pair_off = nullptr, *query_off = nullptr, *edge_off = nullptr;  // pair_off: scan work items
   EdgeArgs a0{};  // queue pointers for the FP64 stage
   hipGraph_t graph = nullptr;
@@ -320,6 +570,9 @@ int batch_alloc(fn_ctx* c) {
   if (e == hipSuccess) e = hipMalloc((void**)&b->pair_off, sizeof(int64_t) * (np + 1));
   if (e == hipSuccess) e = hipMalloc((void**)&b->query_off, sizeof(int64_t) * (np + 1));
   if (e == hipSuccess) e = hipMalloc((void**)&b->edge_off, sizeof(int64_t) * (np + 1));
+  if (e == hipSuccess) e = hipMalloc((void**)&b->prune, sizeof(PruneProb) * np);
+  if (e == hipSuccess) e = hipMalloc((void**)&b->psc.meta, sizeof(int32_t) * 2 * np);
+  b->tab_cap = np;
   return e == hipSuccess ? FN_OK : fail(FN_E_NOMEM, "fn_create: batch tables: %s", hipGetErrorString(e));
 }
 
@@ -328,7 +581,8 @@ void batch_free(fn_ctx* c) {
   if (!b) return;
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
-  void* ps[] = {b->knn, b->ins, b->args, b->pair_off, b->query_off, b->edge_off};
+  void* ps[] = {b->knn, b->ins, b->args, b->pair_off, b->query_off, b->edge_off, b->prune,
+                b->psc.keep0, b->psc.walked, b->psc.map, b->psc.blk, b->psc.meta, b->psc.rows};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   delete b;
@@ -364,6 +618,17 @@ extern "C" int fn_batch_prepare(fn_ctx* c, const fn_problem_set* ps) {
   // capacity outgrows the L2
   int64_t max_ld = 0;
   for (int p = 0; p < n; ++p) max_ld = std::max(max_ld, ps->problems[p].ld);
+  // candidate rounds and the anytime-loop state: the same for every problem
+  const int rounds = std::max(1, ps->problems[0].n_rounds);
+  const bool loop = ps->problems[0].incumbent != nullptr;
+  for (int p = 0; p < n; ++p) {
+    const fn_problem& q = ps->problems[p];
+    if (std::max(1, q.n_rounds) != rounds || q.n_rounds < 0 || rounds > FN_MAX_ROUNDS)
+      return fail(FN_E_SHAPE, "fn_batch_prepare: problem %d: %d rounds (problem 0: %d, at most %d)",
+                  p, q.n_rounds, rounds, FN_MAX_ROUNDS);
+    if ((q.incumbent != nullptr) != loop || (loop && !q.flight))
+      return fail(FN_E_ARG, "fn_batch_prepare: problem %d: incumbent and flight must be given for every problem or for none", p);
+  }
   const int form = c->tune.knn_form > 0 ? c->tune.knn_form : (max_ld > FN_KNN_LARGE_TREE ? 3 : 1);
   const int qpw = form == 3 ? KNN_QB : KNN_QG;  // queries per scan wavefront
   if (form == 3) target = std::min(target, KNN_TARGET_MAX * KNN_QG / KNN_QB);
@@ -409,16 +674,81 @@ extern "C" int fn_batch_prepare(fn_ctx* c, const fn_problem_set* ps) {
     a.model_e = c->model_e + eo[p] * MODEL_FLOATS;
     a.model_c = c->model_c + qo[p] * MODEL_FLOATS;
     a.kind = q.kind; a.t_req = q.t_req; a.t_node = q.t_node; a.out_T = q.out_T;
+    a.t_best = loop ? q.incumbent + 2 : nullptr;
     ip[p] = InsProb{q.tree, q.ld, q.n_nodes, q.t_node, q.parent, q.nu, q.cand, q.kind, q.v_rel,
                     q.vz0, q.t_fall, q.B, q.nbr, q.out_j, q.out_status, q.out_rho4, q.out_T,
-                    q.out_node, q.out_J, q.out_best};
+                    q.out_node, q.out_J, q.out_best, q.incumbent};
   }
   if (eo[n] > c->caps.max_edges) return fail(FN_E_SHAPE, "fn_batch_prepare: %lld edges (cap %lld)", (long long)eo[n], (long long)c->caps.max_edges);
   if (sumB > c->caps.max_batch || part > cap_part || ys > cap_y)
     return fail(FN_E_SHAPE, "fn_batch_prepare: %lld candidates in total (cap %d)", (long long)sumB, c->caps.max_batch);
-  hipError_t e = hipMemcpy(bt->knn, kp.data(), sizeof(KnnProb) * n, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(bt->ins, ip.data(), sizeof(InsProb) * n, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(bt->args, ea.data(), sizeof(EdgeArgs) * n, hipMemcpyHostToDevice);
+  // round r's tables: the same problems with candidate arrays advanced by r
+  // rounds of B
+  std::vector<KnnProb> kr(kp.begin(), kp.end());
+  std::vector<InsProb> ir(ip.begin(), ip.end());
+  std::vector<EdgeArgs> er(ea.begin(), ea.end());
+  kr.resize((size_t)n * rounds);
+  ir.resize((size_t)n * rounds);
+  er.resize((size_t)n * rounds);
+  for (int r = 1; r < rounds; ++r)
+    for (int p = 0; p < n; ++p) {
+      const int64_t B = ps->problems[p].B, o = (int64_t)r * B;
+      KnnProb& kq = kr[(size_t)r * n + p];
+      InsProb& iq = ir[(size_t)r * n + p];
+      EdgeArgs& eq = er[(size_t)r * n + p];
+      kq = kp[p];
+      iq = ip[p];
+      eq = ea[p];
+      kq.qs += o * FN_STATE;
+      iq.cand += o * FN_STATE; iq.kind += o; iq.v_rel += o; iq.vz0 += o; iq.t_fall += o;
+      eq.cand += o * FN_STATE; eq.kind += o; eq.t_req += o;
+    }
+  hipError_t e = hipSuccess;
+  if ((int64_t)n * rounds > bt->tab_cap) {
+    // larger tables: a captured graph refers to the old ones
+    if (bt->exec) { (void)hipGraphExecDestroy(bt->exec); bt->exec = nullptr; }
+    if (bt->graph) { (void)hipGraphDestroy(bt->graph); bt->graph = nullptr; }
+    (void)hipFree(bt->knn); (void)hipFree(bt->ins); (void)hipFree(bt->args);
+    bt->knn = nullptr; bt->ins = nullptr; bt->args = nullptr; bt->tab_cap = 0;
+    const size_t m = (size_t)n * rounds;
+    e = hipMalloc((void**)&bt->knn, sizeof(KnnProb) * m);
+    if (e == hipSuccess) e = hipMalloc((void**)&bt->ins, sizeof(InsProb) * m);
+    if (e == hipSuccess) e = hipMalloc((void**)&bt->args, sizeof(EdgeArgs) * m);
+    if (e != hipSuccess) return fail(FN_E_NOMEM, "fn_batch_prepare: round tables: %s", hipGetErrorString(e));
+    bt->tab_cap = (int64_t)m;
+  }
+  // prune tables and scratch (anytime loop only)
+  std::vector<PruneProb> pp(n);
+  int64_t nodes = 0, blocks = 0;
+  for (int p = 0; p < n; ++p) {
+    const fn_problem& q = ps->problems[p];
+    pp[p] = PruneProb{q.tree, q.ld, q.n_nodes, q.t_node, q.parent, q.nu, q.incumbent, q.flight,
+                      q.out_reach, nodes, blocks};
+    nodes += q.ld;
+    blocks += (q.ld + PRUNE_THREADS - 1) / PRUNE_THREADS;
+  }
+  if (loop && (nodes > bt->prune_nodes || blocks > bt->prune_blocks)) {
+    if (bt->exec) { (void)hipGraphExecDestroy(bt->exec); bt->exec = nullptr; }
+    if (bt->graph) { (void)hipGraphDestroy(bt->graph); bt->graph = nullptr; }
+    PruneScratch& sc = bt->psc;
+    void* old[] = {sc.keep0, sc.walked, sc.map, sc.blk, sc.rows};
+    for (void* o : old) (void)hipFree(o);
+    sc.keep0 = sc.walked = sc.map = sc.blk = nullptr;
+    sc.rows = nullptr;
+    bt->prune_nodes = bt->prune_blocks = 0;
+    e = hipMalloc((void**)&sc.keep0, sizeof(int32_t) * nodes);
+    if (e == hipSuccess) e = hipMalloc((void**)&sc.walked, sizeof(int32_t) * nodes);
+    if (e == hipSuccess) e = hipMalloc((void**)&sc.map, sizeof(int32_t) * nodes);
+    if (e == hipSuccess) e = hipMalloc((void**)&sc.blk, sizeof(int32_t) * blocks);
+    if (e == hipSuccess) e = hipMalloc((void**)&sc.rows, sizeof(float) * PRUNE_COLS * nodes);
+    if (e != hipSuccess) return fail(FN_E_NOMEM, "fn_batch_prepare: prune scratch: %s", hipGetErrorString(e));
+    bt->prune_nodes = nodes;
+    bt->prune_blocks = blocks;
+  }
+  e = hipMemcpy(bt->knn, kr.data(), sizeof(KnnProb) * kr.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(bt->ins, ir.data(), sizeof(InsProb) * ir.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(bt->args, er.data(), sizeof(EdgeArgs) * er.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(bt->prune, pp.data(), sizeof(PruneProb) * n, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(bt->pair_off, po.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(bt->query_off, qo.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(bt->edge_off, eo.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice);
@@ -437,28 +767,31 @@ extern "C" int fn_batch_prepare(fn_ctx* c, const fn_problem_set* ps) {
   bt->edges = eo[n];
   bt->max_obs = max_obs;
   bt->a0 = ea[0];
+  bt->rounds = rounds;
+  bt->loop = loop;
+  bt->max_blocks = (max_ld + PRUNE_THREADS - 1) / PRUNE_THREADS;
   return FN_OK;
 }
 
 template <int K1>
-static void launch_batch_knn(fn_ctx* c, fn_batch* bt, hipStream_t s) {
+static void launch_batch_knn(fn_ctx* c, fn_batch* bt, const KnnProb* tab, hipStream_t s) {
   if (bt->form == 2)
     hipLaunchKernelGGL(batch_knn_scan_tiled<K1>, dim3((unsigned)bt->pairs), dim3(256), 0, s,
-                       bt->knn, bt->n, bt->pair_off, c->knn_d, c->knn_i, c->knn_y);
+                       tab, bt->n, bt->pair_off, c->knn_d, c->knn_i, c->knn_y);
   else if (bt->form == 3)
     hipLaunchKernelGGL(batch_knn_scan_mfma<K1>, dim3((unsigned)((bt->pairs + 3) / 4)), dim3(256), 0,
-                       s, bt->knn, bt->n, bt->pair_off, c->knn_d, c->knn_i, c->knn_y);
+                       s, tab, bt->n, bt->pair_off, c->knn_d, c->knn_i, c->knn_y);
   else
     hipLaunchKernelGGL(batch_knn_scan<K1>, dim3((unsigned)((bt->pairs + 3) / 4)), dim3(256), 0, s,
-                       bt->knn, bt->n, bt->pair_off, c->knn_d, c->knn_i, c->knn_y);
-  hipLaunchKernelGGL(batch_knn_merge<K1>, dim3((unsigned)bt->queries), dim3(64), 0, s, bt->knn,
+                       tab, bt->n, bt->pair_off, c->knn_d, c->knn_i, c->knn_y);
+  hipLaunchKernelGGL(batch_knn_merge<K1>, dim3((unsigned)bt->queries), dim3(64), 0, s, tab,
                      bt->n, bt->query_off, c->knn_d, c->knn_i, c->knn_y, bt->k);
 }
 
 // model kernel (screening), search, FP64 stage over all problems
 template <int PAT, int MODE>
-static void launch_batch_search(fn_ctx* c, fn_batch* bt, hipStream_t s) {
-  const ProbTable pt{bt->n, bt->edge_off, bt->args};
+static void launch_batch_search(fn_ctx* c, fn_batch* bt, const EdgeArgs* et, hipStream_t s) {
+  const ProbTable pt{bt->n, bt->edge_off, et};
   if (MODE != FN_SEARCH_PLAIN)
     hipLaunchKernelGGL(batch_model_kernel<PAT>, dim3((unsigned)(((bt->edges + bt->queries) * 8 + 255) / 256)),
                        dim3(256), 0, s, pt, bt->query_off, c->arm32);
@@ -471,36 +804,126 @@ static void launch_batch_search(fn_ctx* c, fn_batch* bt, hipStream_t s) {
                      c->arm64);
 }
 
-extern "C" int fn_batch_launch(fn_ctx* c, void* stream) {
-  if (!c) return fail(FN_E_ARG, "fn_batch_launch: NULL context");
-  fn_batch* bt = c->batch;
-  if (!bt || bt->n == 0) return fail(FN_E_STATE, "fn_batch_launch: no prepared problem set");
-  hipStream_t s = (hipStream_t)stream;
+// One round (Algorithm 1's inner loop body) on candidate round r.
+static int launch_round(fn_ctx* c, fn_batch* bt, int r, hipStream_t s) {
+  const KnnProb* kt = bt->knn + (size_t)r * bt->n;
+  const EdgeArgs* et = bt->args + (size_t)r * bt->n;
+  const InsProb* it = bt->ins + (size_t)r * bt->n;
   switch (bt->K1) {
-#define FN_K(KK) case KK: launch_batch_knn<KK>(c, bt, s); break;
+#define FN_K(KK) case KK: launch_batch_knn<KK>(c, bt, kt, s); break;
     FN_K(5) FN_K(6) FN_K(7) FN_K(8) FN_K(9) FN_K(10) FN_K(11) FN_K(12) FN_K(13) FN_K(14) FN_K(15)
     FN_K(16) FN_K(20) FN_K(24) FN_K(33)
 #undef FN_K
-    default: return fail(FN_E_SHAPE, "fn_batch_launch: k");
+    default: return fail(FN_E_SHAPE, "fn_batch_round: k");
   }
   hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, s, c->q_count, 1);
   if (bt->pattern == PAT_FR3) {
-    if (bt->mode == FN_SEARCH_PLAIN) launch_batch_search<PAT_FR3, FN_SEARCH_PLAIN>(c, bt, s);
-    else launch_batch_search<PAT_FR3, FN_SEARCH_SCREEN>(c, bt, s);
+    if (bt->mode == FN_SEARCH_PLAIN) launch_batch_search<PAT_FR3, FN_SEARCH_PLAIN>(c, bt, et, s);
+    else launch_batch_search<PAT_FR3, FN_SEARCH_SCREEN>(c, bt, et, s);
   } else {
-    if (bt->mode == FN_SEARCH_PLAIN) launch_batch_search<PAT_GENERIC, FN_SEARCH_PLAIN>(c, bt, s);
-    else launch_batch_search<PAT_GENERIC, FN_SEARCH_SCREEN>(c, bt, s);
+    if (bt->mode == FN_SEARCH_PLAIN) launch_batch_search<PAT_GENERIC, FN_SEARCH_PLAIN>(c, bt, et, s);
+    else launch_batch_search<PAT_GENERIC, FN_SEARCH_SCREEN>(c, bt, et, s);
   }
-  hipLaunchKernelGGL(batch_insert_kernel, dim3(bt->n), dim3(INS_THREADS), 0, s, bt->ins, bt->k, bt->risk);
+  hipLaunchKernelGGL(batch_insert_kernel, dim3(bt->n), dim3(INS_THREADS), 0, s, it, bt->k, bt->risk);
   hipError_t e = hipGetLastError();
-  return e == hipSuccess ? FN_OK : hip_fail(e, "fn_batch_launch");
+  return e == hipSuccess ? FN_OK : hip_fail(e, "fn_batch_round");
 }
 
-extern "C" int fn_graph_capture(fn_ctx* c, void* stream) {
-  if (!c || !c->batch) return fail(FN_E_STATE, "fn_graph_capture: no batch state");
+static bool prune_args_ok(const fn_prune* pr) {
+  return pr && std::isfinite(pr->v_tip) && pr->v_tip > 0.f && std::isfinite(pr->blade[0]) &&
+         std::isfinite(pr->blade[1]) && std::isfinite(pr->blade[2]);
+}
+
+static int launch_prune(fn_ctx* c, fn_batch* bt, const fn_prune& pr, hipStream_t s) {
+  const dim3 g((unsigned)bt->max_blocks, (unsigned)bt->n);
+  hipLaunchKernelGGL(prune_clear, g, dim3(PRUNE_THREADS), 0, s, bt->prune, bt->psc);
+  if (c->pattern == PAT_FR3)
+    hipLaunchKernelGGL(prune_mark<PAT_FR3>, g, dim3(PRUNE_THREADS), 0, s, bt->prune, bt->psc, pr, c->arm32, c->arm64);
+  else
+    hipLaunchKernelGGL(prune_mark<PAT_GENERIC>, g, dim3(PRUNE_THREADS), 0, s, bt->prune, bt->psc, pr, c->arm32, c->arm64);
+  hipLaunchKernelGGL(prune_count, g, dim3(PRUNE_THREADS), 0, s, bt->prune, bt->psc);
+  hipLaunchKernelGGL(prune_scan, dim3((unsigned)bt->n), dim3(PRUNE_THREADS), 0, s, bt->prune, bt->psc);
+  hipLaunchKernelGGL(prune_map, g, dim3(PRUNE_THREADS), 0, s, bt->prune, bt->psc);
+  hipLaunchKernelGGL(prune_gather, g, dim3(PRUNE_THREADS), 0, s, bt->prune, bt->psc);
+  hipLaunchKernelGGL(prune_commit, g, dim3(PRUNE_THREADS), 0, s, bt->prune, bt->psc);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? FN_OK : hip_fail(e, "fn_batch_prune");
+}
+
+// n_iter anytime iterations of n_round rounds, Prune after each iteration.
+static int launch_cycle(fn_ctx* c, fn_batch* bt, int n_iter, int n_round, const fn_prune& pr,
+                        hipStream_t s) {
+  for (int a = 0; a < n_iter; ++a) {
+    for (int r = 0; r < n_round; ++r) {
+      const int rc = launch_round(c, bt, a * n_round + r, s);
+      if (rc != FN_OK) return rc;
+    }
+    const int rc = launch_prune(c, bt, pr, s);
+    if (rc != FN_OK) return rc;
+  }
+  return FN_OK;
+}
+
+static int cycle_args(fn_ctx* c, const char* who, int n_iter, int n_round, const fn_prune* pr) {
+  fn_batch* bt = c->batch;
+  if (!bt || bt->n == 0) return fail(FN_E_STATE, "%s: no prepared problem set", who);
+  if (!bt->loop) return fail(FN_E_STATE, "%s: the problems have no incumbent and flight", who);
+  if (!prune_args_ok(pr)) return fail(FN_E_ARG, "%s: V_tip must be finite and positive, the blade point finite", who);
+  if (n_iter < 1 || n_round < 1 || (int64_t)n_iter * n_round > bt->rounds)
+    return fail(FN_E_SHAPE, "%s: %d x %d rounds, %d prepared", who, n_iter, n_round, bt->rounds);
+  return FN_OK;
+}
+
+extern "C" int fn_batch_round(fn_ctx* c, int32_t round, void* stream) {
+  if (!c) return fail(FN_E_ARG, "fn_batch_round: NULL context");
+  fn_batch* bt = c->batch;
+  if (!bt || bt->n == 0) return fail(FN_E_STATE, "fn_batch_round: no prepared problem set");
+  if (round < 0 || round >= bt->rounds)
+    return fail(FN_E_SHAPE, "fn_batch_round: round %d of %d", round, bt->rounds);
+  return launch_round(c, bt, round, (hipStream_t)stream);
+}
+
+extern "C" int fn_batch_launch(fn_ctx* c, void* stream) { return fn_batch_round(c, 0, stream); }
+
+extern "C" int fn_batch_prune(fn_ctx* c, const fn_prune* pr, void* stream) {
+  if (!c) return fail(FN_E_ARG, "fn_batch_prune: NULL context");
+  const int rc = cycle_args(c, "fn_batch_prune", 1, 1, pr);
+  if (rc != FN_OK) return rc;
+  return launch_prune(c, c->batch, *pr, (hipStream_t)stream);
+}
+
+extern "C" int fn_cycle(fn_ctx* c, int32_t n_iter, int32_t n_round, const fn_prune* pr,
+                        void* stream) {
+  if (!c) return fail(FN_E_ARG, "fn_cycle: NULL context");
+  const int rc = cycle_args(c, "fn_cycle", n_iter, n_round, pr);
+  if (rc != FN_OK) return rc;
+  return launch_cycle(c, c->batch, n_iter, n_round, *pr, (hipStream_t)stream);
+}
+
+extern "C" int fn_reach_time(fn_ctx* c, const float* tree, int64_t ld, int32_t n,
+                             const float* t_node, const float* flight, const fn_prune* pr,
+                             float* out_T, void* stream) {
+  if (!c || !tree || !t_node || !flight || !out_T) return fail(FN_E_ARG, "fn_reach_time: NULL argument");
+  if (!prune_args_ok(pr)) return fail(FN_E_ARG, "fn_reach_time: V_tip must be finite and positive, the blade point finite");
+  if (n < 0 || ld < n || ld < 1) return fail(FN_E_SHAPE, "fn_reach_time: n = %d, ld = %lld", n, (long long)ld);
+  if (n == 0) return FN_OK;
+  hipStream_t s = (hipStream_t)stream;
+  const unsigned g = (unsigned)((n + 255) / 256);
+  if (c->pattern == PAT_FR3)
+    hipLaunchKernelGGL(reach_kernel<PAT_FR3>, dim3(g), dim3(256), 0, s, tree, ld, n, t_node, flight, *pr, c->arm32, c->arm64, out_T);
+  else
+    hipLaunchKernelGGL(reach_kernel<PAT_GENERIC>, dim3(g), dim3(256), 0, s, tree, ld, n, t_node, flight, *pr, c->arm32, c->arm64, out_T);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? FN_OK : hip_fail(e, "fn_reach_time");
+}
+
+// Captures what `body` enqueues on `stream` into the context's HIP graph
+// (replacing a previous one).
+template <typename F>
+static int capture_into(fn_ctx* c, void* stream, const char* who, F&& body) {
   fn_batch* bt = c->batch;
   hipStream_t s = (hipStream_t)stream;
-  if (!s) return fail(FN_E_ARG, "fn_graph_capture: capture needs a non-default stream");
+  if (!s) return fail(FN_E_ARG, "%s: capture needs a non-default stream", who);
   if (bt->exec) {
     (void)hipGraphExecDestroy(bt->exec);
     bt->exec = nullptr;
@@ -510,22 +933,39 @@ extern "C" int fn_graph_capture(fn_ctx* c, void* stream) {
     bt->graph = nullptr;
   }
   hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
-  if (e != hipSuccess) return hip_fail(e, "fn_graph_capture: begin");
-  const int rc = fn_batch_launch(c, stream);
+  if (e != hipSuccess) return hip_fail(e, who);
+  const int rc = body(s);
   hipGraph_t g = nullptr;
   e = hipStreamEndCapture(s, &g);
   if (rc != FN_OK) {
     if (g) (void)hipGraphDestroy(g);
     return rc;
   }
-  if (e != hipSuccess) return hip_fail(e, "fn_graph_capture: end");
+  if (e != hipSuccess) return hip_fail(e, who);
   e = hipGraphInstantiate(&bt->exec, g, nullptr, nullptr, 0);
   if (e != hipSuccess) {
     (void)hipGraphDestroy(g);
-    return hip_fail(e, "fn_graph_capture: instantiate");
+    return hip_fail(e, who);
   }
   bt->graph = g;
   return FN_OK;
+}
+
+extern "C" int fn_graph_capture(fn_ctx* c, void* stream) {
+  if (!c || !c->batch || c->batch->n == 0) return fail(FN_E_STATE, "fn_graph_capture: no prepared problem set");
+  return capture_into(c, stream, "fn_graph_capture",
+                      [&](hipStream_t s) { return launch_round(c, c->batch, 0, s); });
+}
+
+extern "C" int fn_graph_capture_cycle(fn_ctx* c, int32_t n_iter, int32_t n_round,
+                                      const fn_prune* pr, void* stream) {
+  if (!c) return fail(FN_E_ARG, "fn_graph_capture_cycle: NULL context");
+  const int rc = cycle_args(c, "fn_graph_capture_cycle", n_iter, n_round, pr);
+  if (rc != FN_OK) return rc;
+  const fn_prune p = *pr;
+  return capture_into(c, stream, "fn_graph_capture_cycle", [&](hipStream_t s) {
+    return launch_cycle(c, c->batch, n_iter, n_round, p, s);
+  });
 }
 
 extern "C" int fn_graph_launch(fn_ctx* c, void* stream) {

@@ -70,10 +70,30 @@ struct EdgeArgs {
   const float* __restrict__ t_req;
   const float* __restrict__ t_node;
   float* out_T;  // duration of the result (grid slot or fixed T), or NULL
+  // anytime loop (Algorithm 1): a free edge searches only the slots with
+  // t(parent) + T <= *t_best; NULL: no bound
+  const float* __restrict__ t_best;
 };
 
 __device__ __forceinline__ int nodes_of(const EdgeArgs& a) {
   return a.n_nodes_dev ? *a.n_nodes_dev : a.n_nodes;
+}
+
+// Largest slot j <= jmax with t(parent) + Tg[j] <= t_best in FP32 (the sums
+// grow with j), -1 when there is none; jmax unchanged without a bound.
+// Edge e's parent index must be valid.
+__device__ __forceinline__ int bound_slots(const EdgeArgs& a, int64_t e, const float* Tg,
+                                           int jmax) {
+  if (!a.t_best) return jmax;
+  const float tb = *a.t_best;
+  const float tp = a.t_node[a.nbr[e]];
+  int lo = -1, hi = jmax;  // slot lo passes (or -1); slots above hi fail
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tp + Tg[mid] <= tb) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
 }
 
 // queue phase bits
@@ -524,6 +544,7 @@ __device__ void search_edge(const EdgeArgs& a, int64_t e, int64_t eq, const ArmC
   }
   int jmax = n_t - 1;
   if (a.j_max && !fixed) jmax = min(jmax, (int)a.j_max[e]);
+  if (!fixed) jmax = bound_slots(a, e, Tg, jmax);
   if (jmax < 0) {
     // no slot to search: the window is empty and so is the result (a hit)
     write_out(a, e, -1, FN_S_NONE | (mode == FN_SEARCH_WINDOW ? FN_S_WIN_HIT : 0), INFINITY, 0,
@@ -755,6 +776,7 @@ __device__ void recheck_edge(const EdgeArgs& a, int64_t e, const QEntry& q,
   const float* Tg = fixed ? s_fix : a.grid;
   int jmax = fixed ? 0 : a.n_t - 1;
   if (a.j_max && !fixed) jmax = min(jmax, (int)a.j_max[e]);
+  if (!fixed) jmax = bound_slots(a, e, Tg, jmax);
   const int S = a.S;
   int work = q.work;
   float m = q.margin;

@@ -424,14 +424,11 @@ __device__ __forceinline__ void joint_point(const ArmConst<R>& A, int i, int p, 
   q = ok && p >= 3 ? rpos : R(0);
 }
 
-// World-frame centres of the collision spheres at configuration (sn, cs),
-// streamed link by link: fn(k, x, y, z) is called for the spheres
-// k = first + part, first + part + nparts, ... of every link, so that
-// `nparts` lane groups share the spheres of one pose.  sph: sphere k's
-// centre in its link frame at sph[4k .. 4k + 2].
+// Modified-DH frame chain at configuration (sn, cs): after frame i + 1 is
+// formed, fn(i, r, o) receives its world rotation (rows r[0..8]) and origin.
 template <typename R, int PAT, typename F>
-__device__ __forceinline__ void sphere_centres(const ArmConst<R>& A, const R* sn, const R* cs,
-                                               int part, int nparts, const R* sph, F&& fn) {
+__device__ __forceinline__ void frame_chain(const ArmConst<R>& A, const R* sn, const R* cs,
+                                            F&& fn) {
   // world rotation of frame i (rows) and its origin
   R r00 = 1, r01 = 0, r02 = 0, r10 = 0, r11 = 1, r12 = 0, r20 = 0, r21 = 0, r22 = 1;
   R ox = 0, oy = 0, oz = 0;
@@ -470,12 +467,39 @@ __device__ __forceinline__ void sphere_centres(const ArmConst<R>& A, const R* sn
     r00 = a0 * c + a1 * s; r01 = a1 * c - a0 * s; r02 = a2;
     r10 = b0 * c + b1 * s; r11 = b1 * c - b0 * s; r12 = b2;
     r20 = c0 * c + c1 * s; r21 = c1 * c - c0 * s; r22 = c2;
+    const R r[9] = {r00, r01, r02, r10, r11, r12, r20, r21, r22};
+    fn(i, r, ox, oy, oz);
+  }
+}
+
+// World-frame centres of the collision spheres at configuration (sn, cs),
+// streamed link by link: fn(k, x, y, z) is called for the spheres
+// k = first + part, first + part + nparts, ... of every link, so that
+// `nparts` lane groups share the spheres of one pose.  sph: sphere k's
+// centre in its link frame at sph[4k .. 4k + 2].
+template <typename R, int PAT, typename F>
+__device__ __forceinline__ void sphere_centres(const ArmConst<R>& A, const R* sn, const R* cs,
+                                               int part, int nparts, const R* sph, F&& fn) {
+  frame_chain<R, PAT>(A, sn, cs, [&](int i, const R* r, R ox, R oy, R oz) {
     for (int k = A.sph_first[i] + part; k < A.sph_first[i + 1]; k += nparts) {
       const R lx = sph[4 * k], ly = sph[4 * k + 1], lz = sph[4 * k + 2];
-      fn(k, ox + r00 * lx + r01 * ly + r02 * lz, oy + r10 * lx + r11 * ly + r12 * lz,
-         oz + r20 * lx + r21 * ly + r22 * lz);
+      fn(k, ox + r[0] * lx + r[1] * ly + r[2] * lz, oy + r[3] * lx + r[4] * ly + r[5] * lz,
+         oz + r[6] * lx + r[7] * ly + r[8] * lz);
     }
-  }
+  });
+}
+
+// World position of the point (lx, ly, lz) of the last link's frame.
+template <typename R, int PAT>
+__device__ __forceinline__ void last_link_point(const ArmConst<R>& A, const R* sn, const R* cs,
+                                                R lx, R ly, R lz, R& x, R& y, R& z) {
+  frame_chain<R, PAT>(A, sn, cs, [&](int i, const R* r, R ox, R oy, R oz) {
+    if (i == NJ - 1) {
+      x = ox + r[0] * lx + r[1] * ly + r[2] * lz;
+      y = oy + r[3] * lx + r[4] * ly + r[5] * lz;
+      z = oz + r[6] * lx + r[7] * ly + r[8] * lz;
+    }
+  });
 }
 
 // ---------------------------------------------------------------------------

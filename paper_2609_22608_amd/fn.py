@@ -108,7 +108,27 @@ class Problem(C.Structure):
                 ("out_j", C.c_void_p), ("out_status", C.c_void_p), ("out_margin", C.c_void_p),
                 ("out_rho4", C.c_void_p), ("out_T", C.c_void_p), ("out_node", C.c_void_p),
                 ("out_J", C.c_void_p), ("out_best", C.c_void_p), ("caps", C.c_void_p),
-                ("n_caps", C.c_int32)]
+                ("n_caps", C.c_int32), ("n_rounds", C.c_int32), ("incumbent", C.c_void_p),
+                ("flight", C.c_void_p), ("out_reach", C.c_void_p)]
+
+
+class Prune(C.Structure):
+    _fields_ = [("v_tip", C.c_float), ("blade", C.c_float * 3)]
+
+
+def make_prune(v_tip, blade):
+    pr = Prune()
+    pr.v_tip = float(v_tip)
+    pr.blade[:] = [float(x) for x in blade]
+    return pr
+
+
+def flight_array(fl):
+    """Device [11] flight of Eq. (1): x0, v0, g, t_enter, t_fall."""
+    a = np.concatenate([np.asarray(fl["x0"], np.float32), np.asarray(fl["v0"], np.float32),
+                        np.asarray(fl["g"], np.float32),
+                        np.asarray([fl["t_enter"], fl["t_fall"]], np.float32)])
+    return dev(a)
 
 
 class ProblemSet(C.Structure):
@@ -163,6 +183,11 @@ def lib():
             L.fn_batch_launch.argtypes = [vp, vp]
             L.fn_graph_capture.argtypes = [vp, vp]
             L.fn_graph_launch.argtypes = [vp, vp]
+            L.fn_batch_round.argtypes = [vp, i32, vp]
+            L.fn_batch_prune.argtypes = [vp, C.POINTER(Prune), vp]
+            L.fn_cycle.argtypes = [vp, i32, i32, C.POINTER(Prune), vp]
+            L.fn_graph_capture_cycle.argtypes = [vp, i32, i32, C.POINTER(Prune), vp]
+            L.fn_reach_time.argtypes = [vp, vp, i64, i32, vp, vp, C.POINTER(Prune), vp, vp]
             L.fn_kernel_timing.argtypes = [vp, C.c_int]
             L.fn_kernel_times.argtypes = [vp, vp, i32, C.POINTER(i32)]
             _lib = L
@@ -340,6 +365,16 @@ class Context:
         return out
 
     # -- edge_check -----------------------------------------------------------
+    def reach_time(self, tree, ld, n, t_node, flight, v_tip, blade):
+        """Eq. (8)'s earliest reach time of the first n nodes of an SoA tree;
+        flight: dict (x0, v0, g, t_enter, t_fall) or a device [11] tensor."""
+        fl = flight if isinstance(flight, torch.Tensor) else flight_array(flight)
+        out = torch.empty(max(int(n), 1), dtype=torch.float32, device="cuda")
+        pr = make_prune(v_tip, blade)
+        _check(lib().fn_reach_time(self.h, _ptr(tree), int(ld), int(n), _ptr(t_node), _ptr(fl),
+                                   C.byref(pr), _ptr(out), _stream()), "fn_reach_time")
+        return out[:n]
+
     def edge_check(self, x0, x1, T, samples, obs=None, margin=0.0, want_tau=False, caps=None):
         E = x0.shape[0]
         d = x0.device
@@ -450,22 +485,37 @@ class Batch:
         self.risk = risk if risk is not None else make_risk(sigma_mode=1, s0=0.01, s1=0.05)
         self.problems = []
 
-    def add_problem(self, tree_x, tree_t, cand, obs, capacity):
-        """tree_x [n][14], tree_t [n], cand dict (x, kind, t_req, flight), obs [m][4]."""
+    def add_problem(self, tree_x, tree_t, cand, obs, capacity, flight=None, parent=None):
+        """tree_x [n][14], tree_t [n], cand dict (x, kind, t_req, flight) or a
+        list of such dicts (one per round, equal sizes), obs [m][4].  With a
+        flight dict (x0, v0, g, t_enter, t_fall) the problem carries the
+        anytime loop's incumbent (initial t_best = t_fall) and can be pruned;
+        parent [n]: initial parents (default -1)."""
         d = "cuda"
         n = len(tree_x)
         tree, ld, _ = tree_soa(tree_x, capacity=capacity)
-        B = len(cand["x"])
+        rounds = cand if isinstance(cand, (list, tuple)) else [cand]
+        B = len(rounds[0]["x"])
+        assert all(len(c["x"]) == B for c in rounds)
         k = self.k
         t_node = torch.zeros(ld, dtype=torch.float32, device=d)
         t_node[:n] = torch.as_tensor(np.asarray(tree_t, np.float32))
-        fl = cand["flight"]
+        par0 = torch.full((ld,), -1, dtype=torch.int32, device=d)
+        if parent is not None:
+            par0[:n] = torch.as_tensor(np.asarray(parent, np.int32))
+
+        def cat(f):
+            return np.concatenate([f(c) for c in rounds])
+
         P = dict(tree=tree, ld=ld, n0=n, n_nodes=torch.tensor([n], dtype=torch.int32, device=d),
                  t_node=t_node, t_node0=t_node.clone(), tree0=tree.clone(),
-                 parent=torch.full((ld,), -1, dtype=torch.int32, device=d),
+                 parent=par0.clone(), parent0=par0,
                  nu=torch.zeros(ld, dtype=torch.float32, device=d),
-                 cand=dev(cand["x"]), kind=dev(cand["kind"], torch.int32), t_req=dev(cand["t_req"]),
-                 v_rel=dev(fl["v_rel"]), vz0=dev(np.asarray(fl["v0"])[:, 2]), t_fall=dev(fl["t_fall"]),
+                 cand=dev(cat(lambda c: c["x"])), kind=dev(cat(lambda c: c["kind"]), torch.int32),
+                 t_req=dev(cat(lambda c: c["t_req"])),
+                 v_rel=dev(cat(lambda c: c["flight"]["v_rel"])),
+                 vz0=dev(cat(lambda c: np.asarray(c["flight"]["v0"])[:, 2])),
+                 t_fall=dev(cat(lambda c: c["flight"]["t_fall"])), n_rounds=len(rounds),
                  B=B, obs=dev(obs) if len(obs) else None, n_obs=len(obs),
                  nbr=torch.empty((B, k), dtype=torch.int32, device=d),
                  out_j=torch.empty(B * k, dtype=torch.int16, device=d),
@@ -476,17 +526,26 @@ class Batch:
                  out_node=torch.empty(B, dtype=torch.int32, device=d),
                  out_J=torch.empty(B, dtype=torch.float32, device=d),
                  out_best=torch.empty(2, dtype=torch.float32, device=d))
+        if flight is not None:
+            P["flight"] = flight_array(flight)
+            P["inc0"] = torch.tensor([-np.inf, -1.0, np.float32(flight["t_fall"]), 0.0],
+                                     dtype=torch.float32, device=d)
+            P["incumbent"] = P["inc0"].clone()
+            P["out_reach"] = torch.full((ld,), np.nan, dtype=torch.float32, device=d)
         self.problems.append(P)
         return P
 
     def reset_trees(self):
-        """Back to the initial trees (node counts, times, parents, states)."""
+        """Back to the initial trees (node counts, times, parents, states,
+        incumbents)."""
         for P in self.problems:
             P["n_nodes"].fill_(P["n0"])
             P["t_node"].copy_(P["t_node0"])
             P["tree"].copy_(P["tree0"])
-            P["parent"].fill_(-1)
+            P["parent"].copy_(P["parent0"])
             P["nu"].zero_()
+            if "incumbent" in P:
+                P["incumbent"].copy_(P["inc0"])
 
     def prepare(self):
         arr = (Problem * len(self.problems))()
@@ -498,6 +557,9 @@ class Batch:
                 setattr(q, key, P[key].data_ptr())
             q.ld, q.B, q.n_obs = P["ld"], P["B"], P["n_obs"]
             q.obs = None if P["obs"] is None else P["obs"].data_ptr()
+            q.n_rounds = P["n_rounds"]
+            for key in ("incumbent", "flight", "out_reach"):
+                setattr(q, key, P[key].data_ptr() if key in P else None)
         self._arr = arr
         ps = ProblemSet(len(self.problems), arr, self.k, self.grid.data_ptr(), self.grid.shape[0],
                         self.samples, self.mode, self.margin, self.risk)
@@ -505,6 +567,25 @@ class Batch:
 
     def launch(self):
         _check(lib().fn_batch_launch(self.ctx.h, _stream()), "fn_batch_launch")
+
+    def round(self, r):
+        _check(lib().fn_batch_round(self.ctx.h, int(r), _stream()), "fn_batch_round")
+
+    def prune(self, v_tip, blade):
+        pr = make_prune(v_tip, blade)
+        _check(lib().fn_batch_prune(self.ctx.h, C.byref(pr), _stream()), "fn_batch_prune")
+
+    def cycle(self, n_iter, n_round, v_tip, blade):
+        pr = make_prune(v_tip, blade)
+        _check(lib().fn_cycle(self.ctx.h, int(n_iter), int(n_round), C.byref(pr), _stream()),
+               "fn_cycle")
+
+    def capture_cycle(self, stream, n_iter, n_round, v_tip, blade):
+        pr = make_prune(v_tip, blade)
+        with torch.cuda.stream(stream):
+            _check(lib().fn_graph_capture_cycle(self.ctx.h, int(n_iter), int(n_round), C.byref(pr),
+                                                C.c_void_p(stream.cuda_stream)),
+                   "fn_graph_capture_cycle")
 
     def capture(self, stream):
         with torch.cuda.stream(stream):

@@ -297,10 +297,11 @@ def chord_states(arm, root, goals, n: int, rng, sigma: float = 0.15, p_uniform: 
 
 
 def make_candidates(arm, b: int, goal_frac: float, seed: int, qd_scale: float = 0.5,
-                    root=None):
+                    root=None, t_arr=(0.2, 0.8)):
     """Candidate batch: a fraction ``goal_frac`` of goal samples (inverse
     construction, first), the rest uniform -- or, when a root state is given
-    and there are goals, chord samples (``chord_states``).  Returns a dict
+    and there are goals, chord samples (``chord_states``).  Goal arrival
+    times are U[t_arr].  Returns a dict
     with ``x`` [b][14], ``kind`` [b] (0 free, 1 goal), ``t_req`` [b] (0 for
     free) and per-goal flight data (x0, v0, t_fall, v_rel; zeros for free
     samples)."""
@@ -311,7 +312,7 @@ def make_candidates(arm, b: int, goal_frac: float, seed: int, qd_scale: float = 
     t_req = np.zeros(b)
     flight = dict(x0=np.zeros((b, 3)), v0=np.zeros((b, 3)), t_fall=np.zeros(b), v_rel=np.zeros(b))
     if n_goal:
-        xg, tg, fg = goal_states(arm, n_goal, rng)
+        xg, tg, fg = goal_states(arm, n_goal, rng, t_arr=t_arr)
         xs[:n_goal] = xg
         kind[:n_goal] = KIND_GOAL
         t_req[:n_goal] = tg
@@ -449,12 +450,42 @@ def goal_parents(cand, tau: float = 0.1, every: int = 2):
     return _f32(x), _f32(t)
 
 
-def make_rounds(arm, n_rounds: int, batch: int, goal_frac: float, seed: int, root=None):
+def make_rounds(arm, n_rounds: int, batch: int, goal_frac: float, seed: int, root=None,
+                flight=None):
     """Candidates of every round of a planning cycle, each round drawn with
     its own seed (seed * 100 + round); free samples on the chord from `root`
-    to the round's goals when a root is given."""
-    return [make_candidates(arm, batch, goal_frac, seed * 100 + r, root=root)
+    to the round's goals when a root is given; goal arrival times within the
+    flight's [t_enter, t_fall] when a flight is given."""
+    t_arr = (0.2, 0.8) if flight is None else (flight["t_enter"], flight["t_fall"])
+    return [make_candidates(arm, batch, goal_frac, seed * 100 + r, root=root, t_arr=t_arr)
             for r in range(n_rounds)]
+
+
+def blade_midpoint(arm) -> np.ndarray:
+    """The middle of the 0.30 m blade edge in the last link's frame (the
+    blade point p_n that pruning reaches for)."""
+    return _f32(arm["blade_base"] + 0.5 * arm["blade_len"] * arm["blade_dir"])
+
+
+def make_cycle_problem(arm, seed: int, n_tree: int, batch: int, k: int = 8, rounds: int = 4,
+                       n_obs: int = 2, n_t: int = 32, samples: int = 16,
+                       launch_dist=(1.0, 1.6)):
+    """One planning problem for the anytime loop: a tree of a root (node 0,
+    time 0), n_tree - 1 uniform nodes and goal-reaching nodes for every
+    other goal of every round; `rounds` candidate rounds of `batch` (half
+    goals arriving within the flight's reach window, free samples on the
+    chord from the root); the object's flight (launched 1.0-1.6 m from the
+    base by default, so that part of the tree can reach it)."""
+    sh = Shape(f"cycle{seed}", n_tree, batch, k, n_t, 0.02, 1.0, samples, n_obs, 0.5)
+    wl = make_workload(sh, seed, arm=arm)
+    flight = make_flight(seed, launch_dist=launch_dist)
+    rs = make_rounds(arm, rounds, batch, 0.5, seed, root=wl["tree_x"][0], flight=flight)
+    gx, gt = zip(*[goal_parents(c) for c in rs])
+    tree_x = np.concatenate([wl["tree_x"]] + list(gx))
+    tree_t = np.concatenate([wl["tree_t"]] + list(gt))
+    tree_t[0] = 0.0
+    return dict(shape=sh, grid=wl["grid"], obs=wl["obs"], samples=samples, k=k, rounds=rs,
+                tree_x=tree_x, tree_t=_f32(tree_t), flight=flight)
 
 
 def make_workload(shape: Shape, seed: int, arm_seed: int = 0, arm=None):
