@@ -270,6 +270,7 @@ def main():
     res["controller"] = controller_stats(args, ctx, wl, fn, W, torch)
     if args.batch_problems > 0:
         res["batched_round"] = batched_round(args, fn, W, torch)
+    res["planning_cycle"] = planning_cycle(args, fn, W, torch)
     if args.profile:
         # a plain device copy of known size (256 MiB) for calibrating the
         # HBM traffic counters
@@ -551,6 +552,65 @@ def batched_round(args, fn, W, torch):
                         f"0-5 obstacles, seed {args.seed}")
     ctx.close()
     return res
+
+
+def planning_cycle(args, fn, W, torch, V_TIP=4.0):
+    """Whole planning cycles of Algorithm 1 in the paper's configuration
+    (A = 2 anytime iterations of R = 2 rounds, B = 128 candidates, M = 4
+    parents), each starting from the root alone, as one HIP graph: per round
+    kNN, edge search below t_best (free) or the check at t_req - t(p)
+    (goal), attachment, risk of goal nodes and the incumbent; Prune by
+    Eq. (8) after each iteration.  One problem (latency) and 32 problems
+    (throughput), 64 T x 32 samples, 5 obstacles, V_tip 4 m/s.  Trees and
+    incumbents are restored between replays, outside the timed events."""
+    arm = W.make_arm(0)
+    blade = W.blade_midpoint(arm)
+    out = {"config": "A=2, R=2, B=128 (half goals), M=4, 64 T x 32 samples, 5 obstacle spheres, "
+                     "root-only tree at the start of every cycle (root at rest, goal poses within "
+                     "0.8 rad of it, arrivals in the flight's reach window), V_tip 4 m/s, blade "
+                     "point at the middle of the 0.30 m edge",
+           "paper_solve_ms": {"value": 12.0, "note": "median solve time of the whole planner "
+                                                     "(sampling included), RTX 4090 + JAX; "
+                                                     "context only"}}
+    stream = torch.cuda.current_stream()
+    for n_p in (1, 32):
+        probs = [W.make_cycle_problem(arm, args.seed + p, 1, 128, k=4, rounds=4, n_obs=5, n_t=64,
+                                      samples=32, with_goal_parents=False, root_at_rest=True,
+                                      goal_spread=0.8) for p in range(n_p)]
+        ctx = fn.Context(arm, 1024, 128 * n_p, 4, max_edges=512 * n_p, max_problems=n_p)
+        bt = fn.Batch(ctx, fn.dev(probs[0]["grid"]), 32, 4, mode=fn.SEARCH_SCREEN)
+        for c in probs:
+            bt.add_problem(c["tree_x"], c["tree_t"], c["rounds"], c["obs"], capacity=516,
+                           flight=c["flight"])
+        bt.prepare()
+        cap = torch.cuda.Stream()
+        torch.cuda.synchronize()
+        bt.capture_cycle(cap, 2, 2, V_TIP, blade)
+        for _ in range(args.warmup):
+            bt.reset_trees()
+            bt.replay()
+        ts = []
+        for _ in range(max(5, args.steps)):
+            bt.reset_trees()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            bt.replay()
+            e1.record(stream)
+            ts.append((e0, e1))
+        torch.cuda.synchronize()
+        ms = float(np.median([a.elapsed_time(b) for a, b in ts]))
+        inc = np.stack([P["incumbent"].cpu().numpy() for P in bt.problems])
+        nodes = [int(P["n_nodes"].item()) for P in bt.problems]
+        out[f"problems_{n_p}"] = {
+            "ms_per_cycle": ms, "cycles_per_s": n_p / (ms * 1e-3),
+            "edges_per_cycle": 4 * 128 * 4 * n_p,
+            "found": int((inc[:, 1] >= 0).sum()),
+            "J_best_median": (float(np.median(inc[inc[:, 1] >= 0, 0]))
+                              if (inc[:, 1] >= 0).any() else None),
+            "nodes_after_cycle_median": float(np.median(nodes))}
+        ctx.close()
+    return out
 
 
 def surrogate(args, ctx, arm, sh, fn, W, torch):

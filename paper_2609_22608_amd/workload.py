@@ -202,7 +202,8 @@ def _blade_point(arm, q, c):
 
 
 def goal_states(arm, n: int, rng, t_arr=(0.2, 0.8), launch=(4.0, 7.0),
-                cone_deg: float = 30.0, blade_speed=(0.5, 2.0), g=9.81):
+                cone_deg: float = 30.0, blade_speed=(0.5, 2.0), g=9.81, q_center=None,
+                q_spread: float = 0.8):
     """Goal candidates by inverse construction.
 
     A goal configuration q_g is drawn in the joint box; the contact point p
@@ -212,7 +213,8 @@ def goal_states(arm, n: int, rng, t_arr=(0.2, 0.8), launch=(4.0, 7.0),
     p with launch speed U[launch]; the blade moves along its cutting
     direction at U[blade_speed] m/s and qd_g = J^+ v_ee.  Samples whose qd_g
     leaves the velocity box, whose contact point is below 5 cm or whose arc
-    has no real launch solution are redrawn.
+    has no real launch solution are redrawn.  With q_center, q_g is drawn
+    within +-q_spread of it (clipped to 0.9 of the joint box) instead.
 
     Returns (states [n][14], T_req [n], flight dict of per-sample arrays).
     """
@@ -222,7 +224,12 @@ def goal_states(arm, n: int, rng, t_arr=(0.2, 0.8), launch=(4.0, 7.0),
     need = n
     while need > 0:
         m = max(64, 2 * need)
-        q = rng.uniform(0.9 * arm["qmin"], 0.9 * arm["qmax"], (m, DOF))
+        if q_center is None:
+            q = rng.uniform(0.9 * arm["qmin"], 0.9 * arm["qmax"], (m, DOF))
+        else:
+            q = np.clip(np.asarray(q_center, np.float64)[:DOF]
+                        + rng.uniform(-q_spread, q_spread, (m, DOF)),
+                        0.9 * arm["qmin"], 0.9 * arm["qmax"])
         c = rng.uniform(0.0, 1.0, m)
         p, T = _blade_point(arm, q, c)
         nb = np.einsum("...ij,j->...i", T[..., :3, :3], arm["blade_normal"])
@@ -297,11 +304,12 @@ def chord_states(arm, root, goals, n: int, rng, sigma: float = 0.15, p_uniform: 
 
 
 def make_candidates(arm, b: int, goal_frac: float, seed: int, qd_scale: float = 0.5,
-                    root=None, t_arr=(0.2, 0.8)):
+                    root=None, t_arr=(0.2, 0.8), goal_spread=None):
     """Candidate batch: a fraction ``goal_frac`` of goal samples (inverse
     construction, first), the rest uniform -- or, when a root state is given
     and there are goals, chord samples (``chord_states``).  Goal arrival
-    times are U[t_arr].  Returns a dict
+    times are U[t_arr]; with goal_spread (and a root), goal configurations
+    lie within +-goal_spread rad of the root's.  Returns a dict
     with ``x`` [b][14], ``kind`` [b] (0 free, 1 goal), ``t_req`` [b] (0 for
     free) and per-goal flight data (x0, v0, t_fall, v_rel; zeros for free
     samples)."""
@@ -312,7 +320,11 @@ def make_candidates(arm, b: int, goal_frac: float, seed: int, qd_scale: float = 
     t_req = np.zeros(b)
     flight = dict(x0=np.zeros((b, 3)), v0=np.zeros((b, 3)), t_fall=np.zeros(b), v_rel=np.zeros(b))
     if n_goal:
-        xg, tg, fg = goal_states(arm, n_goal, rng, t_arr=t_arr)
+        if goal_spread is not None and root is not None:
+            xg, tg, fg = goal_states(arm, n_goal, rng, t_arr=t_arr, q_center=root,
+                                     q_spread=goal_spread)
+        else:
+            xg, tg, fg = goal_states(arm, n_goal, rng, t_arr=t_arr)
         xs[:n_goal] = xg
         kind[:n_goal] = KIND_GOAL
         t_req[:n_goal] = tg
@@ -451,13 +463,14 @@ def goal_parents(cand, tau: float = 0.1, every: int = 2):
 
 
 def make_rounds(arm, n_rounds: int, batch: int, goal_frac: float, seed: int, root=None,
-                flight=None):
+                flight=None, goal_spread=None):
     """Candidates of every round of a planning cycle, each round drawn with
     its own seed (seed * 100 + round); free samples on the chord from `root`
     to the round's goals when a root is given; goal arrival times within the
     flight's [t_enter, t_fall] when a flight is given."""
     t_arr = (0.2, 0.8) if flight is None else (flight["t_enter"], flight["t_fall"])
-    return [make_candidates(arm, batch, goal_frac, seed * 100 + r, root=root, t_arr=t_arr)
+    return [make_candidates(arm, batch, goal_frac, seed * 100 + r, root=root, t_arr=t_arr,
+                            goal_spread=goal_spread)
             for r in range(n_rounds)]
 
 
@@ -469,18 +482,26 @@ def blade_midpoint(arm) -> np.ndarray:
 
 def make_cycle_problem(arm, seed: int, n_tree: int, batch: int, k: int = 8, rounds: int = 4,
                        n_obs: int = 2, n_t: int = 32, samples: int = 16,
-                       launch_dist=(1.0, 1.6)):
+                       launch_dist=(1.0, 1.6), with_goal_parents: bool = True,
+                       root_at_rest: bool = False, goal_spread=None):
     """One planning problem for the anytime loop: a tree of a root (node 0,
-    time 0), n_tree - 1 uniform nodes and goal-reaching nodes for every
-    other goal of every round; `rounds` candidate rounds of `batch` (half
-    goals arriving within the flight's reach window, free samples on the
-    chord from the root); the object's flight (launched 1.0-1.6 m from the
-    base by default, so that part of the tree can reach it)."""
+    time 0), n_tree - 1 uniform nodes and (unless with_goal_parents is
+    False) goal-reaching nodes for every other goal of every round; `rounds`
+    candidate rounds of `batch` (half goals arriving within the flight's
+    reach window, free samples on the chord from the root); the object's
+    flight (launched 1.0-1.6 m from the base by default, so that part of the
+    tree can reach it).  root_at_rest: the root waits at rest at a pose within
+    +-1 rad of the joint-range centre; goal_spread: goal poses within that
+    many rad of the root's."""
     sh = Shape(f"cycle{seed}", n_tree, batch, k, n_t, 0.02, 1.0, samples, n_obs, 0.5)
     wl = make_workload(sh, seed, arm=arm)
     flight = make_flight(seed, launch_dist=launch_dist)
-    rs = make_rounds(arm, rounds, batch, 0.5, seed, root=wl["tree_x"][0], flight=flight)
-    gx, gt = zip(*[goal_parents(c) for c in rs])
+    if root_at_rest:
+        rq = np.random.default_rng([seed, 11]).uniform(-1.0, 1.0, DOF)
+        wl["tree_x"][0] = _f32(np.concatenate([rq, np.zeros(DOF)]))
+    rs = make_rounds(arm, rounds, batch, 0.5, seed, root=wl["tree_x"][0], flight=flight,
+                     goal_spread=goal_spread)
+    gx, gt = zip(*[goal_parents(c) for c in rs]) if with_goal_parents else ((), ())
     tree_x = np.concatenate([wl["tree_x"]] + list(gx))
     tree_t = np.concatenate([wl["tree_t"]] + list(gt))
     tree_t[0] = 0.0
