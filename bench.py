@@ -91,6 +91,9 @@ def parse():
     p.add_argument("--no-tune", action="store_true", help="default launch mappings (no autotuning)")
     p.add_argument("--tune-cache", default=None,
                    help="JSON cache of tuned launch mappings (read and written)")
+    p.add_argument("--edge-form", type=int, default=0, choices=(0, 1, 2),
+                   help="screened searches: 0 library default, 1 one kernel, 2 triage + queued "
+                        "search (fn_tuning.edge_form)")
     return p.parse_args()
 
 
@@ -122,6 +125,8 @@ def main():
                rho=None, work=torch.empty(E, dtype=torch.int32, device="cuda"),
                screened=torch.empty(E, dtype=torch.int16, device="cuda"))
     stream = torch.cuda.current_stream()
+    if args.edge_form:
+        ctx.set_tuning(edge_form=args.edge_form)
     knn_tuning = None
     if not args.no_tune:
         # launch mapping of the kNN scan for this shape (outside the timed region)

@@ -457,12 +457,17 @@ int surrogate_infer(fn_ctx* ctx, const fn_mlp* mlp, const float* X, int64_t N, c
  * neighbours and distances.  Applies to later plan_knn calls and
  * fn_batch_prepare.  Errors: FN_E_ARG when knn_target_waves is outside
  * [0, 16384], knn_min_chunk is negative or not a multiple of 64, or
- * knn_form is not 0, 1, 2 or 3. */
+ * knn_form is not 0, 1, 2 or 3, or edge_form is not 0, 1 or 2. */
 #define FN_KNN_LARGE_TREE 65536
 typedef struct {
   int32_t knn_target_waves;
   int32_t knn_min_chunk;
   int32_t knn_form;
+  int32_t edge_form;  /* screened and windowed searches of edge_time_batch: 1 one kernel (one
+                       * wavefront per edge); 2 two phases (a triage of every edge by the
+                       * endpoint screen, which finishes the edges it leaves no open slot on,
+                       * then the search of the others); 0 default: 2 from 2^18 edges, else 1.
+                       * The results are the same. */
 } fn_tuning;
 int fn_set_tuning(fn_ctx* ctx, const fn_tuning* t /*host*/);
 

@@ -155,6 +155,9 @@ extern "C" int fn_create(const fn_arm_desc* arm, const fn_caps* caps, fn_ctx** o
   fn_ctx* c = new fn_ctx();
   std::memset(c, 0, sizeof(*c));
   (void)hipGetDevice(&c->device);
+  c->n_cu = 0;
+  (void)hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, c->device);
+  if (c->n_cu <= 0) c->n_cu = 256;
   c->caps = *caps;
   // spheres sorted by link (stable), as the device FK streams them per link
   c->desc = *arm;
@@ -196,6 +199,7 @@ extern "C" int fn_create(const fn_arm_desc* arm, const fn_caps* caps, fn_ctx** o
   FN_ALLOC(c->queue, (size_t)(caps->max_edges > 0 ? caps->max_edges : 1) * sizeof(QEntry));
   FN_ALLOC(c->model_e, (size_t)caps->max_edges * MODEL_FLOATS * sizeof(float));
   FN_ALLOC(c->model_c, (size_t)caps->max_batch * MODEL_FLOATS * sizeof(float));
+  FN_ALLOC(c->tri_items, (size_t)(caps->max_edges > 0 ? caps->max_edges : 1) * sizeof(int32_t));
   FN_ALLOC(c->self_pairs, (size_t)2 * FN_MAX_SELF_PAIRS * sizeof(int16_t));
 #undef FN_ALLOC
   {
@@ -283,6 +287,7 @@ extern "C" void fn_destroy(fn_ctx* c) {
   (void)hipFree(c->q_count);
   (void)hipFree(c->queue);
   (void)hipFree(c->model_e);
+  (void)hipFree(c->tri_items);
   (void)hipFree(c->model_c);
   (void)hipFree(c->self_pairs);
   delete c;

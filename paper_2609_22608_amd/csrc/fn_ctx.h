@@ -43,10 +43,11 @@ static_assert(sizeof(QEntry) == 96, "queue entry layout");
 // search's first kernel clears it) and queue (one entry per edge), the
 // endpoint models of every edge's parent and of every candidate.
 struct EdgeScratch {
-  int32_t* q_count;
+  int32_t* q_count;  // the FP64-stage queue length (64 ints)
   QEntry* queue;
   float* model_e;
   float* model_c;
+  int32_t* tri_items;  // [max edges]: open-slot counts of the two-phase search
 };
 
 int fail(int code, const char* fmt, ...);
@@ -86,6 +87,7 @@ struct fn_batch;
 
 struct fn_ctx {
   int device;
+  int n_cu;           // compute units of the device
   fn_tuning tune;     // launch mappings (0 = defaults)
   fn_batch* batch;    // batched-iteration state (NULL when max_problems = 0)
   int pattern;  // twist pattern code or PAT_GENERIC
@@ -98,6 +100,7 @@ struct fn_ctx {
   float* knn_y;  // per (query, chunk): max |y|^2 of the chunk
   int32_t* q_count;  // [0]: queue length
   fn::QEntry* queue;
+  int32_t* tri_items;  // [max_edges]: open-slot counts of the two-phase search
   // endpoint models: of every edge's parent [max_edges][56], of every
   // candidate [max_batch][56]
   float* model_e;

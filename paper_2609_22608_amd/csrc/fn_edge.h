@@ -73,8 +73,19 @@ struct EdgeArgs {
   // anytime loop (Algorithm 1): a free edge searches only the slots with
   // t(parent) + T <= *t_best; NULL: no bound
   const float* __restrict__ t_best;
+  // two-phase screened search: each edge's number of open slots after the
+  // triage (-1: finished by the triage)
+  int32_t* tri_items;
 };
 
+// ---------------------------------------------------------------------------
+// Two-phase screened search.  The triage screens every slot of an edge with
+// the endpoint models and finishes the edges on which it leaves no open
+// slot (no feasible slot: the same outputs the one-kernel search writes for
+// them); the search then runs on the other edges only.  About half of the
+// one-iteration shape's edges end at the triage.
+// ---------------------------------------------------------------------------
+constexpr int64_t TRIAGE_MIN_EDGES = 1 << 18;  // default form 2 from this many edges
 __device__ __forceinline__ int nodes_of(const EdgeArgs& a) {
   return a.n_nodes_dev ? *a.n_nodes_dev : a.n_nodes;
 }
@@ -742,6 +753,93 @@ __device__ void search_edge(const EdgeArgs& a, int64_t e, int64_t eq, const ArmC
   m = fminf(m, fminf(fabsf(rv - 1.f), fminf(fabsf(rq - 1.f), fabsf(rc - 1.f))));
   write_out(a, e, jstar, post_status(rv, rq, rc) | winbits, m, rho_star, rv, rq, rc, work,
             Tg[jstar]);
+}
+
+// Triage (two-phase screened search): the screen of search_edge over every
+// slot up to jmax of one edge whose parent index p, states x (parent 14
+// floats, candidate 14 floats) and endpoint models are in LDS; with no open
+// slot the edge is finished exactly as search_edge finishes it (count -1),
+// else its open-slot count is recorded.  The parent checks and the
+// state differences are load_edge's.
+template <int PAT, int MODE>
+__device__ void triage_one(const EdgeArgs& a, int64_t e, int p, const ArmConst<float>& A,
+                           const float* s_T, const float* s_mod, const float* x) {
+  const int lane = lane_id();
+  if (lane == 0) a.tri_items[e] = -1;
+  int st0 = p < 0 ? FN_S_NO_PARENT : p >= nodes_of(a) ? FN_S_BAD_INPUT : 0;
+  EdgeState<float> ES;
+  if (st0 == 0) {
+    bool finite = true;
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) {
+      const float q0 = x[i], v0 = x[NJ + i], q1 = x[FN_STATE + i], v1 = x[FN_STATE + NJ + i];
+      finite = finite && isfinite(q0) && isfinite(v0) && isfinite(q1) && isfinite(v1);
+      ES.q0[i] = q0;
+      ES.qd0[i] = v0;
+      ES.dq[i] = q1 - q0;
+      ES.d2[i] = v1 - v0;
+    }
+    if (!finite) st0 = FN_S_BAD_INPUT;
+  }
+  if (st0 != 0) {
+    if (a.out_scr && lane == 0) a.out_scr[e] = 0;
+    write_out(a, e, -1, st0, st0 == FN_S_NO_PARENT ? INFINITY : 0.f, 0, 0, 0, 0, 0);
+    return;
+  }
+  int jmax = a.n_t - 1;
+  if (a.j_max) jmax = min(jmax, (int)a.j_max[e]);
+  jmax = bound_slots(a, e, s_T, jmax);
+  if (jmax < 0) {
+    if (a.out_scr && lane == 0) a.out_scr[e] = 0;
+    write_out(a, e, -1, FN_S_NONE | (MODE == FN_SEARCH_WINDOW ? FN_S_WIN_HIT : 0), INFINITY, 0,
+              0, 0, 0, 0);
+    return;
+  }
+  int open = 0;
+  float mc = INFINITY, lastv = 0.f;
+  for (int j0 = 0; j0 <= jmax; j0 += WAVE) {
+    const int jj = j0 + lane;
+    const bool act = jj <= jmax;
+    float r = 0.f;
+    if (act) {
+      const float T = s_T[jj];
+      r = endpoint_ratio(A, ES, s_mod, s_mod + MODEL_FLOATS, T, __builtin_amdgcn_rcpf(T));
+    }
+    const bool cert = act && r > 1.f + BAND;
+    open += __popcll(__ballot(act && !cert));
+    if (cert) mc = fminf(mc, r - 1.f);
+    if (jj == jmax) lastv = r;
+  }
+  if (open == 0) {
+    const float m = wave_min(mc);
+    const float lv = readlane(lastv, jmax & (WAVE - 1));
+    if (a.out_scr && lane == 0) a.out_scr[e] = (int16_t)(jmax + 1);
+    write_out(a, e, -1, FN_S_NONE | (MODE == FN_SEARCH_WINDOW ? FN_S_WIN_HIT : 0), m, lv, 0, 0,
+              0, 0);
+    return;
+  }
+  if (lane == 0) a.tri_items[e] = open;
+}
+
+// Triage of one edge by one wavefront: parent index, states and endpoint
+// models into LDS (s_mod: 2 * MODEL_FLOATS floats, s_x: 2 * FN_STATE
+// floats), then triage_one.
+template <int PAT, int MODE>
+__device__ void triage_edge(const EdgeArgs& a, int64_t e, const ArmConst<float>& A,
+                            const float* s_T, float* s_mod, float* s_x) {
+  const int lane = lane_id();
+  const int p = a.nbr[e];
+  const int64_t b = e / a.k;
+  if (lane < MODEL_FLOATS) {
+    s_mod[lane] = a.model_e[e * MODEL_FLOATS + lane];
+    s_mod[MODEL_FLOATS + lane] = a.model_c[b * MODEL_FLOATS + lane];
+  }
+  if (lane < FN_STATE) {
+    s_x[FN_STATE + lane] = a.cand[b * FN_STATE + lane];
+    if (p >= 0 && p < nodes_of(a)) s_x[lane] = a.tree[(size_t)lane * a.ld + p];
+  }
+  __builtin_amdgcn_wave_barrier();
+  triage_one<PAT, MODE>(a, e, p, A, s_T, s_mod, s_x);
 }
 
 // Slot ratio of Eq. (7) in FP64 at the S samples (lanes < S), in every lane.

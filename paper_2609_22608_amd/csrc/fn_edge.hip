@@ -9,6 +9,8 @@
 // result whatever order the work is done in.  See fn_edge.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "fn_edge.h"
 
 namespace fn {
@@ -47,6 +49,41 @@ edge_time_kernel(EdgeArgs a, const ArmConst<float>* __restrict__ Ap) {
   if (e < 0) return;
   search_edge<PAT, MODE, false>(a, e, e, *Ap, s_end_all[wave], s_T, s_fix[wave], s_mod[wave],
                                 &s_geo[wave], s_tab + wave * Ap->nsph * (a.n_obs + a.n_caps));
+}
+
+// Two-phase screened search, phase 1: the triage, one wavefront per edge,
+// four per workgroup (light: no full evaluation, no post-checks).
+template <int PAT, int MODE>
+__global__ __launch_bounds__(256) void edge_triage_kernel(EdgeArgs a,
+                                                          const ArmConst<float>* __restrict__ Ap) {
+  __shared__ float s_T[FN_MAX_NT];
+  __shared__ float s_mod[4][2 * MODEL_FLOATS];
+  __shared__ float s_x[4][2 * FN_STATE];
+  for (int t = threadIdx.x; t < a.n_t; t += blockDim.x) s_T[t] = a.grid[t];
+  __syncthreads();
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t e = (int64_t)blockIdx.x * 4 + wave;
+  if (e >= a.E) return;
+  triage_edge<PAT, MODE>(a, e, *Ap, s_T, s_mod[wave], s_x[wave]);
+}
+
+// Two-phase screened search, phase 2: the search of the edges the triage
+// left open, in the one-kernel grid's order; wavefronts of finished edges
+// end at once.
+template <int PAT, int MODE>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void
+edge_search_open_kernel(EdgeArgs a, const ArmConst<float>* __restrict__ Ap) {
+  __shared__ float s_end[FN_MAX_NT];
+  __shared__ float s_T[FN_MAX_NT];
+  __shared__ float s_fix[4];
+  __shared__ float s_mod[2 * MODEL_FLOATS];
+  __shared__ GeoLDS<float> s_geo;
+  extern __shared__ float s_tab[];  // nsph * (n_obs + n_caps) floats
+  const int64_t e = xcd_edge(blockIdx.x, a.k, a.E / a.k);
+  if (e < 0 || __builtin_amdgcn_readfirstlane(a.tri_items[e]) < 0) return;
+  for (int t = threadIdx.x; t < a.n_t; t += blockDim.x) s_T[t] = a.grid[t];
+  __syncthreads();
+  search_edge<PAT, MODE, false>(a, e, e, *Ap, s_end, s_T, s_fix, s_mod, &s_geo, s_tab);
 }
 
 // ---------------------------------------------------------------------------
@@ -306,8 +343,18 @@ static void launch_search(fn_ctx* c, const EdgeArgs& a, int ti, hipStream_t s) {
     hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, s, a.q_count, 1);
   if (ti >= 0) (void)hipEventRecord(c->tev[2 * ti], s);
   const size_t tab = (size_t)EDGE_WAVES * c->desc.n_spheres * (a.n_obs + a.n_caps) * sizeof(float);
-  hipLaunchKernelGGL((edge_time_kernel<PAT, MODE>), dim3((unsigned)xcd_grid(B, a.k)),
-                     dim3(64 * EDGE_WAVES), tab, s, a, c->arm32);
+  // two phases when asked for, or by default for large searches (measured
+  // faster from about 10^6 edges, equal at 3 x 10^4)
+  const int form = c->tune.edge_form > 0 ? c->tune.edge_form : (E >= TRIAGE_MIN_EDGES ? 2 : 1);
+  if (MODE != FN_SEARCH_PLAIN && form == 2) {
+    hipLaunchKernelGGL((edge_triage_kernel<PAT, MODE>), dim3((unsigned)((E + 3) / 4)), dim3(256),
+                       0, s, a, c->arm32);
+    hipLaunchKernelGGL((edge_search_open_kernel<PAT, MODE>), dim3((unsigned)xcd_grid(B, a.k)),
+                       dim3(64), tab, s, a, c->arm32);
+  } else {
+    hipLaunchKernelGGL((edge_time_kernel<PAT, MODE>), dim3((unsigned)xcd_grid(B, a.k)),
+                       dim3(64 * EDGE_WAVES), tab, s, a, c->arm32);
+  }
   if (ti >= 0) (void)hipEventRecord(c->tev[2 * ti + 1], s);
   hipLaunchKernelGGL(edge_recheck_kernel<PAT>, dim3(recheck_waves(E)), dim3(64),
                      (size_t)c->desc.n_spheres * (a.n_obs + a.n_caps) * sizeof(double), s, a,
@@ -378,6 +425,7 @@ int edge_time_run(fn_ctx* c, const float* tree, int64_t ld, int32_t n_nodes, con
   a.out_j = out->j; a.out_st = out->status; a.out_m = out->margin; a.out_rho = out->rho4;
   a.out_work = out->work; a.out_scr = out->screened;
   a.q_count = sc.q_count; a.queue = sc.queue; a.model_e = sc.model_e; a.model_c = sc.model_c;
+  a.tri_items = sc.tri_items;
   hipStream_t s = (hipStream_t)stream;
   const int ti = timed && c->timing && c->n_timed < FN_MAX_TIMED ? c->n_timed++ : -1;
   if (c->pattern == PAT_FR3) launch_search_mode<PAT_FR3>(c, a, ti, s);
@@ -393,7 +441,7 @@ extern "C" int edge_time_batch(fn_ctx* c, const float* tree, int64_t ld, int32_t
                                const fn_search* sr, const fn_obstacles* obs,
                                const fn_edge_out* out, void* stream) {
   if (!c) return fail(FN_E_ARG, "edge_time_batch: NULL context");
-  const EdgeScratch sc{c->q_count, c->queue, c->model_e, c->model_c};
+  const EdgeScratch sc{c->q_count, c->queue, c->model_e, c->model_c, c->tri_items};
   return edge_time_run(c, tree, ld, n_nodes, cand, B, nbr, k, sr, obs, out, stream, sc,
                        c->caps.max_edges, "edge_time_batch", true);
 }

@@ -3,9 +3,9 @@
 // memory (code under graph capture, tight serving loops).
 //
 // The array holds, for at most FN_NOALLOC_MAX_EDGES edges: the FP64-stage
-// counter (256 bytes), its queue (one 96-byte entry per edge) and the
+// counter (256 bytes), its queue (one 96-byte entry per edge), the
 // endpoint models of every edge's parent and of every candidate (56 floats
-// each).  Each device holds its own copy for the life of the process; its
+// each) and the two-phase search's open-slot counts (4 bytes per edge).  Each device holds its own copy for the life of the process; its
 // address is taken once per device with hipGetSymbolAddress (at fn_create,
 // or at the first call on a device), and only that address is used on the
 // host.  Every call on one device shares the array: calls that overlap in
@@ -23,8 +23,10 @@ namespace {
 constexpr size_t kCounterBytes = 256;
 constexpr size_t kQueueBytes = (size_t)FN_NOALLOC_MAX_EDGES * sizeof(fn::QEntry);
 constexpr size_t kModelBytes = (size_t)FN_NOALLOC_MAX_EDGES * fn::MODEL_FLOATS * sizeof(float);
-constexpr size_t kScratchBytes = kCounterBytes + kQueueBytes + 2 * kModelBytes;
-static_assert(kQueueBytes % 256 == 0 && kModelBytes % 256 == 0, "256-byte aligned parts");
+constexpr size_t kTriageBytes = (size_t)FN_NOALLOC_MAX_EDGES * sizeof(int32_t);
+constexpr size_t kScratchBytes = kCounterBytes + kQueueBytes + 2 * kModelBytes + kTriageBytes;
+static_assert(kQueueBytes % 256 == 0 && kModelBytes % 256 == 0 && kTriageBytes % 256 == 0,
+              "256-byte aligned parts");
 
 // never named in host code except by hipGetSymbolAddress below
 static __device__ __align__(256) unsigned char scratch[kScratchBytes];
@@ -83,7 +85,8 @@ extern "C" int edge_time_batch_noalloc(fn_ctx* c, const float* tree, int64_t ld,
   const fn::EdgeScratch sc{reinterpret_cast<int32_t*>(p),
                            reinterpret_cast<fn::QEntry*>(p + kCounterBytes),
                            reinterpret_cast<float*>(p + kCounterBytes + kQueueBytes),
-                           reinterpret_cast<float*>(p + kCounterBytes + kQueueBytes + kModelBytes)};
+                           reinterpret_cast<float*>(p + kCounterBytes + kQueueBytes + kModelBytes),
+                           reinterpret_cast<int32_t*>(p + kCounterBytes + kQueueBytes + 2 * kModelBytes)};
   return fn::edge_time_run(c, tree, ld, n_nodes, cand, B, nbr, k, sr, obs, out, stream, sc,
                            FN_NOALLOC_MAX_EDGES, "edge_time_batch_noalloc", false);
 }

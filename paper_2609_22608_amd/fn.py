@@ -52,7 +52,7 @@ class Caps(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("knn_target_waves", C.c_int32), ("knn_min_chunk", C.c_int32),
-                ("knn_form", C.c_int32)]
+                ("knn_form", C.c_int32), ("edge_form", C.c_int32)]
 
 
 class Search(C.Structure):
@@ -293,10 +293,13 @@ class Context:
         _check(lib().fn_kernel_times(self.h, buf, max_n, C.byref(n)), "fn_kernel_times")
         return [buf[i] for i in range(n.value)]
 
-    def set_tuning(self, knn_target_waves=0, knn_min_chunk=0, knn_form=0):
-        t = Tuning(int(knn_target_waves), int(knn_min_chunk), int(knn_form))
+    def set_tuning(self, knn_target_waves=0, knn_min_chunk=0, knn_form=0, edge_form=None):
+        """Launch mappings (fn_set_tuning); edge_form None keeps the current one."""
+        ef = getattr(self, "edge_form", 0) if edge_form is None else int(edge_form)
+        t = Tuning(int(knn_target_waves), int(knn_min_chunk), int(knn_form), ef)
         _check(lib().fn_set_tuning(self.h, C.byref(t)), "fn_set_tuning")
         self.tuned_knn_form = int(knn_form)
+        self.edge_form = ef
 
     # -- plan_knn -----------------------------------------------------------
     def plan_knn(self, tree, ld, n_nodes, queries, k, out_idx=None, out_d2=None, want_d2=True):

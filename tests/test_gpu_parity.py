@@ -303,6 +303,38 @@ def test_modes_agree_full_iteration(iteration):
     assert wb.sum() < wa.sum()
 
 
+@pytest.mark.parametrize("mode", [fn.SEARCH_SCREEN, fn.SEARCH_WINDOW])
+def test_two_phase_search_equals_one_kernel(iteration, mode):
+    """edge_form 2 (a triage of every edge by the endpoint screen, then the
+    edges with open slots on persistent wavefronts, most open slots first)
+    writes exactly what edge_form 1 (one wavefront per edge) writes, on every
+    edge of the one-iteration batch with its obstacle spheres and 3 capsules,
+    and through the entry point that allocates nothing."""
+    sh = iteration["shape"]
+    ctx = _ctx(iteration)
+    tree, ld, n = fn.tree_soa(iteration["tree_x"])
+    cand = fn.dev(iteration["cand"]["x"])
+    idx, _ = ctx.plan_knn(tree, ld, n, cand, sh.k)
+    caps = fn.dev(W.make_capsules(iteration["arm"], 3, seed=5))
+    rng = np.random.default_rng(1)
+    wl = torch.as_tensor(rng.integers(0, sh.n_t + 1, idx.numel()).astype(np.int16)).cuda()
+    kw = dict(win_lo=wl, win_half=4) if mode == fn.SEARCH_WINDOW else {}
+    outs = []
+    for form, noalloc in ((1, False), (2, False), (2, True)):
+        ctx.set_tuning(edge_form=form)
+        outs.append(_run_edges(ctx, iteration, idx, mode, caps=caps, noalloc=noalloc, **kw))
+    for b in outs[1:]:
+        for key in ("j", "status", "margin", "rho", "work", "screened"):
+            x, y = outs[0][key], b[key]
+            if x.dtype == torch.float32:
+                x, y = x.view(torch.int32), y.view(torch.int32)
+            assert torch.equal(x, y), key
+    a = outs[0]
+    done = int(((a["work"] == 0) & ((a["status"].to(torch.int32) & fn.S_NONE) > 0)).sum())
+    print(f"mode {mode}: {done} of {idx.numel()} edges end at the triage")
+    ctx.close()
+
+
 def check_window_flags(out, lo, half, label):
     """Every edge with a parent carries exactly one of WIN_HIT / WIN_MISS, and
     an edge whose result lies in the network's raw window [lo, lo + 2 half] is
