@@ -145,7 +145,6 @@ def main():
                                         torch)
         if args.save_surrogate:
             net.save(args.save_surrogate)
-    feats = torch.empty((E, 28), dtype=torch.float32, device="cuda")
     win = torch.empty(E, dtype=torch.int16, device="cuda")
     forms = {}
     for name in wanted:
@@ -158,8 +157,8 @@ def main():
             if ev:
                 ev[0].record(stream)
             if mode == fn.SEARCH_WINDOW:
-                fn.edge_features(ctx, tree, ld, n, cand, idx, out=feats)
-                net.infer(feats, grid, half=args.half, want_out=False, win_lo=win)
+                # edge rows gathered inside the inference kernel
+                net.window(tree, ld, n, cand, idx, grid, half=args.half, win_lo=win)
                 if ev:
                     ev[2].record(stream)
                 ctx.edge_time_batch(tree, ld, n, cand, idx, grid, sh.samples, obs, mode=mode,
@@ -221,8 +220,8 @@ def main():
         if mode == fn.SEARCH_WINDOW:
             pre = float(np.mean([a[0].elapsed_time(a[2]) for a in edge_ms]))
             f.update(features_infer_ms=pre)
-            f.update(window_stats(args, ctx, net, tree, ld, n, cand, idx, grid, sh, obs, feats,
-                                  out, fn, torch))
+            f.update(window_stats(args, ctx, net, tree, ld, n, cand, idx, grid, sh, obs, out, fn,
+                                  torch))
         f["roofline"] = {"bound": "alu", "achieved": f["fp32_tflops"], "peak": PEAK_FP32 / 1e12,
                          "unit": "TFLOP/s", "frac": f["fp32_tflops"] * 1e12 / PEAK_FP32}
         forms[name] = f
@@ -269,7 +268,7 @@ def main():
                                "clearance_checked_edges": bf["clearance_checked"]}},
     }
     res["roofline_other"] = other_rooflines(args, ctx, net, tree, ld, n, cand, idx, grid, sh,
-                                            feats, win, fn, torch)
+                                            win, fn, torch)
     res["refine"] = refine_stats(args, ctx, wl, tree, ld, n, cand, idx, grid, sh, obs, out, fn,
                                  torch)
     res["controller"] = controller_stats(args, ctx, wl, fn, W, torch)
@@ -290,7 +289,7 @@ def main():
     ctx.close()
 
 
-def window_stats(args, ctx, net, tree, ld, n, cand, idx, grid, sh, obs, feats, out, fn, torch):
+def window_stats(args, ctx, net, tree, ld, n, cand, idx, grid, sh, obs, out, fn, torch):
     """Window outcome of the timed window runs (out holds the last one) and
     what the network gains: the same exact search with the window placed at
     the first slot the endpoint screen leaves open (no network), and the
@@ -299,7 +298,7 @@ def window_stats(args, ctx, net, tree, ld, n, cand, idx, grid, sh, obs, feats, o
     st = out["status"].cpu().numpy().astype(np.uint16)
     feas = jj >= 0
     miss = (st & fn.S_WIN_MISS) > 0
-    y, w_net = net.infer(feats, grid, half=args.half)
+    y, w_net = net.window(tree, ld, n, cand, idx, grid, half=args.half, want_out=True)
     E = jj.size
     base = ctx.edge_time_batch(tree, ld, n, cand, idx, grid, sh.samples, obs,
                                mode=fn.SEARCH_WINDOW,
@@ -329,10 +328,11 @@ def window_stats(args, ctx, net, tree, ld, n, cand, idx, grid, sh, obs, feats, o
         predicted_infeasible_frac=float((yy[:, 1] < 0.0).mean()))
 
 
-def other_rooflines(args, ctx, net, tree, ld, n, cand, idx, grid, sh, feats, win, fn, torch):
+def other_rooflines(args, ctx, net, tree, ld, n, cand, idx, grid, sh, win, fn, torch):
     """Rooflines of the kNN call (scan + merge; FP32 VALU) and of the fused
-    surrogate inference kernel (BF16 matrix cores), each timed alone with HIP
-    events on the stream the library launches on."""
+    surrogate inference kernel with its edge-row gather (surrogate_window;
+    BF16 matrix cores), each timed alone with HIP events on the stream the
+    library launches on."""
     stream = torch.cuda.current_stream()
 
     def time_it(call, reps):
@@ -362,8 +362,8 @@ def other_rooflines(args, ctx, net, tree, ld, n, cand, idx, grid, sh, feats, win
                        "knn_form": ctx_knn_form,
                        "traffic": traffic_bytes("knn_scan", str(ctx_knn_form))}
     if net is not None:
-        E = feats.shape[0]
-        ms = time_it(lambda: net.infer(feats, grid, half=args.half, want_out=False, win_lo=win),
+        E = idx.numel()
+        ms = time_it(lambda: net.window(tree, ld, n, cand, idx, grid, half=args.half, win_lo=win),
                      reps)
         flop = float(E) * F_MLP_ROW
         res["mlp_infer_fused"] = {"bound": "mfma", "achieved": flop / (ms * 1e-3) / 1e12,

@@ -441,6 +441,16 @@ int surrogate_infer(fn_ctx* ctx, const fn_mlp* mlp, const float* X, int64_t N, c
                     int32_t n_t, int32_t half, float logit_min, float* out, int16_t* out_win_lo,
                     void* stream);
 
+/* The windows of B * k edges straight from the tree and the candidates:
+ * surrogate_infer on the rows edge_features would write (state of tree node
+ * nbr[e], state of candidate e / k; zeros for a padded or out-of-range
+ * parent), gathered inside the inference kernel, so no feature matrix is
+ * written.  Same results as edge_features followed by surrogate_infer. */
+int surrogate_window(fn_ctx* ctx, const fn_mlp* mlp, const float* tree, int64_t ld,
+                     int32_t n_nodes, const float* cand, int32_t B, const int32_t* nbr, int32_t k,
+                     const float* grid, int32_t n_t, int32_t half, float logit_min, float* out,
+                     int16_t* out_win_lo, void* stream);
+
 /* ------------------------------------------------------------------ */
 /* Launch mappings chosen by the autotuner                             */
 /* ------------------------------------------------------------------ */
@@ -457,7 +467,8 @@ int surrogate_infer(fn_ctx* ctx, const fn_mlp* mlp, const float* X, int64_t N, c
  * neighbours and distances.  Applies to later plan_knn calls and
  * fn_batch_prepare.  Errors: FN_E_ARG when knn_target_waves is outside
  * [0, 16384], knn_min_chunk is negative or not a multiple of 64, or
- * knn_form is not 0, 1, 2 or 3, or edge_form is not 0, 1 or 2. */
+ * knn_form is not 0, 1, 2 or 3, edge_form is not 0, 1 or 2, or mlp_rows is
+ * not 0, 32 or 64. */
 #define FN_KNN_LARGE_TREE 65536
 typedef struct {
   int32_t knn_target_waves;
@@ -468,6 +479,9 @@ typedef struct {
                        * endpoint screen, which finishes the edges it leaves no open slot on,
                        * then the search of the others); 0 default: 2 from 2^18 edges, else 1.
                        * The results are the same. */
+  int32_t mlp_rows;   /* rows per workgroup of the fused surrogate inference: 32 or 64; 0
+                       * default (32 while 64 would leave fewer than four workgroups per
+                       * compute unit).  The results are the same. */
 } fn_tuning;
 int fn_set_tuning(fn_ctx* ctx, const fn_tuning* t /*host*/);
 

@@ -50,7 +50,12 @@ constexpr int MAX_SPLIT = 16;
 enum { EPI_F32 = 0, EPI_BIAS_SILU = 1, EPI_BIAS_F32 = 2, EPI_DSILU = 3 };
 constexpr int BM = 64, BN = 64, BK = 32, LDSR = BK + 8;
 
-__device__ __forceinline__ float sigmoidf_(float z) { return 1.f / (1.f + __expf(-z)); }
+// Logistic function with the hardware exponential and reciprocal (1 ulp
+// each): an IEEE division here made the activations the largest part of the
+// fused inference kernel's instructions.
+__device__ __forceinline__ float sigmoidf_(float z) {
+  return __builtin_amdgcn_rcpf(1.f + __expf(-z));
+}
 
 template <bool TA, bool TB, int EPI>
 __global__ __launch_bounds__(256) void gemm_bf16(const bf16* __restrict__ A, int lda,
@@ -291,6 +296,33 @@ __global__ void mlp_to_bf16(const float* __restrict__ p, bf16* __restrict__ wb) 
   if (i < NP_PAD) wb[i] = (bf16)p[i];
 }
 
+// Inference weights packed in the matrix cores' operand order: for a layer
+// of N outputs and K inputs, the B operand of output tile nt (16 outputs)
+// and K step ks (32 inputs) is one contiguous 1 KiB block at
+// ((nt * K/32) + ks) * 512 elements, lane l's 8 values at l * 8 (outputs
+// 16 nt + (l & 15), inputs 32 ks + 8 (l >> 4) + e).  A wavefront's operand
+// read is then one contiguous KiB instead of 16 half-used cache lines.
+constexpr int SW1 = 0, SW2 = SW1 + W * NIN_P, SW3 = SW2 + W * W, SW4 = SW3 + W * W;
+constexpr int NSW = SW4 + 16 * W;
+
+__device__ __forceinline__ int64_t packed_src(int64_t i) {
+  int off, K;
+  int64_t j;
+  if (i < SW2) { off = OFF_W1; K = NIN_P; j = i - SW1; }
+  else if (i < SW3) { off = OFF_W2; K = W; j = i - SW2; }
+  else if (i < SW4) { off = OFF_W3; K = W; j = i - SW3; }
+  else { off = OFF_W4; K = W; j = i - SW4; }
+  const int64_t block = j / 512, within = j % 512;
+  const int l = (int)(within / 8), e = (int)(within % 8);
+  const int64_t nt = block / (K / BK), ks = block % (K / BK);
+  return off + (16 * nt + (l & 15)) * K + BK * ks + 8 * (l >> 4) + e;
+}
+
+__global__ void mlp_pack(const bf16* __restrict__ wb, bf16* __restrict__ wsw) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < NSW) wsw[i] = wb[packed_src(i)];
+}
+
 // padded <-> logical parameter layouts
 __device__ __forceinline__ int64_t log_to_pad(int64_t i) {
   int64_t o = 0;
@@ -350,63 +382,119 @@ __global__ void mlp_window(const float* __restrict__ Y, int rows, const float* _
 }
 
 // ---------------------------------------------------------------------------
-// Fused inference: all four layers of FR rows in one workgroup.  The row
-// tile's activations stay in LDS (one BF16 buffer, row stride HLD); wave w
-// computes output columns [64 w, 64 w + 64) of a 256-wide layer for all FR
-// rows (4 x 4 tiles of 16 x 16, FP32 accumulators), with the weights read
+// Fused inference: all four layers of FR rows (32 or 64) in one workgroup.
+// The row tile's activations stay in LDS (one BF16 buffer, row stride HLD);
+// wave w computes output columns [64 w, 64 w + 64) of a 256-wide layer for
+// all FR rows (FR/16 x 4 tiles of 16 x 16, FP32 accumulators), with the
+// weights read
 // from L2 straight into the MFMA B operands.  Every wave holds its whole
 // output tile in registers until the layer's reads are done, so one barrier
 // later the tile overwrites the layer's input in place.  The MFMA
 // instruction, operand layout and K order are those of gemm_bf16, so the
 // outputs equal the layer-by-layer path bit for bit.
 // ---------------------------------------------------------------------------
-constexpr int FR = 64;        // rows per workgroup
 constexpr int HLD = W + 8;    // LDS row stride of the activation tile (BF16)
 
 // One 256-wide layer, K inputs (a multiple of 32) from Hs, SiLU(z + bias)
 // rounded to BF16 back into Hs.
-template <int K>
-__device__ __forceinline__ void fused_layer(bf16 (*Hs)[HLD], const bf16* __restrict__ Wt, int ldw,
+template <int K, int RT>
+__device__ __forceinline__ void fused_layer(bf16 (*Hs)[HLD], const bf16* __restrict__ Wp,
                                             const float* __restrict__ bias, int wave, int lane) {
-  f32x4 acc[4][4];
+  // rows [64 (wave / 4), + 16 RT), output columns [64 (wave % 4), + 64)
+  Hs += 64 * (wave >> 2);
+  wave &= 3;
+  f32x4 acc[RT][4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < RT; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   const int row = lane & 15, kg = (lane >> 4) * 8, n0 = wave * 64;
+  // Weight operands travel PD K steps ahead of the products (a ring of PD
+  // register sets): one step's 16 products take far less than an L2 read,
+  // so a shallower pipeline leaves the matrix cores waiting.  The
+  // scheduling barriers keep the compiler from sinking the reads back.
+  constexpr int KS = K / BK, PD = KS < 4 ? KS : 4;
+  float bn[4];
 #pragma unroll
-  for (int k0 = 0; k0 < K; k0 += BK) {
-    bf16x8 b[4], a[4];
+  for (int j = 0; j < 4; ++j) bn[j] = bias[n0 + 16 * j + row];
+  bf16x8 b[PD][4];
+#pragma unroll
+  for (int ks = 0; ks < PD; ++ks)
 #pragma unroll
     for (int j = 0; j < 4; ++j)
-      b[j] = *reinterpret_cast<const bf16x8*>(Wt + (size_t)(n0 + 16 * j + row) * ldw + k0 + kg);
+      b[ks][j] = *reinterpret_cast<const bf16x8*>(Wp + ((size_t)(4 * wave + j) * KS + ks) * 512 +
+                                                  lane * 8);
+  __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) a[i] = *reinterpret_cast<const bf16x8*>(&Hs[16 * i + row][k0 + kg]);
+  for (int ks = 0; ks < KS; ++ks) {
+    bf16x8 a[RT];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < RT; ++i)
+      a[i] = *reinterpret_cast<const bf16x8*>(&Hs[16 * i + row][ks * BK + kg]);
+#pragma unroll
+    for (int i = 0; i < RT; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[ks % PD][j], acc[i][j], 0, 0, 0);
+    if (ks + PD < KS) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        b[ks % PD][j] = *reinterpret_cast<const bf16x8*>(
+            Wp + ((size_t)(4 * wave + j) * KS + ks + PD) * 512 + lane * 8);
+    }
+    __builtin_amdgcn_sched_barrier(0);
   }
   __syncthreads();  // every wave has read the layer's input
   // result fragment: lane l holds rows 4 (l >> 4) .. + 3 of column (l & 15)
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int n = n0 + 16 * j + row;
-    const float bn = bias[n];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < RT; ++i)
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const float z = acc[i][j][t] + bn;
+        const float z = acc[i][j][t] + bn[j];
         Hs[16 * i + (lane >> 4) * 4 + t][n] = (bf16)(z * sigmoidf_(z));
       }
   }
   __syncthreads();
 }
 
-__global__ __launch_bounds__(256) void mlp_infer_fused(const float* __restrict__ X, int64_t N,
-                                                       Norm nm, const bf16* __restrict__ wb,
+// Where the input rows come from: a feature matrix X [N][28], or (GATHER)
+// the edges themselves -- row e is the state of tree node nbr[e] followed by
+// that of candidate e / k, zeros for a padded or out-of-range parent (the
+// rows edge_features writes).
+struct RowSrc {
+  const float* X;
+  const float* tree;
+  int64_t ld;
+  int n_nodes;
+  const float* cand;
+  const int32_t* nbr;
+  int k;
+};
+
+template <bool GATHER>
+__device__ __forceinline__ float input_of(const RowSrc& src, int64_t row, int c) {
+  if constexpr (!GATHER) {
+    return src.X[row * NIN + c];
+  } else {
+    const int p = src.nbr[row];
+    if (p < 0 || p >= src.n_nodes) return 0.f;
+    return c < FN_STATE ? src.tree[(size_t)c * src.ld + p]
+                        : src.cand[(row / src.k) * FN_STATE + c - FN_STATE];
+  }
+}
+
+// FR rows per workgroup: one group of four wavefronts per 64 rows (FR = 32:
+// one group on 32 rows); every group reads the layer weights for its rows
+// through the L1, so more groups per workgroup share them.
+template <int FR>
+constexpr int infer_threads() { return FR <= 64 ? 256 : 256 * (FR / 64); }
+
+template <bool GATHER, int FR>
+__global__ __launch_bounds__(infer_threads<FR>()) void mlp_infer_fused(RowSrc src, int64_t N, Norm nm,
+                                                       const bf16* __restrict__ wsw,
                                                        const float* __restrict__ p,
                                                        const float* __restrict__ grid, int n_t,
                                                        int half, float logit_min,
@@ -417,34 +505,38 @@ __global__ __launch_bounds__(256) void mlp_infer_fused(const float* __restrict__
   __shared__ float s_lg[FN_MAX_NT];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int64_t r0 = (int64_t)blockIdx.x * FR;
+  constexpr int NT = infer_threads<FR>();
   // normalised inputs, padded to 32 columns, rounded to BF16 (rows past N: 0)
-  for (int t = tid; t < FR * NIN_P; t += 256) {
+  for (int t = tid; t < FR * NIN_P; t += NT) {
     const int r = t / NIN_P, c = t % NIN_P;
     const int64_t row = r0 + r;
-    Hs[r][c] = (bf16)(c < NIN && row < N ? (X[row * NIN + c] - nm.shift[c]) * nm.scale[c] : 0.f);
+    Hs[r][c] = (bf16)(c < NIN && row < N ? (input_of<GATHER>(src, row, c) - nm.shift[c]) * nm.scale[c]
+                                         : 0.f);
   }
   if (win)
-    for (int t = tid; t < n_t; t += 256) s_lg[t] = logf(grid[t]);
+    for (int t = tid; t < n_t; t += NT) s_lg[t] = logf(grid[t]);
   __syncthreads();
-  fused_layer<NIN_P>(Hs, wb + OFF_W1, NIN_P, p + OFF_B1, wave, lane);
-  fused_layer<W>(Hs, wb + OFF_W2, W, p + OFF_B2, wave, lane);
-  fused_layer<W>(Hs, wb + OFF_W3, W, p + OFF_B3, wave, lane);
-  {
-    // output layer: wave w takes rows [16 w, 16 w + 16), output columns 0..15
-    // (W4 is padded with zero rows; columns 0 and 1 are the outputs)
+  constexpr int RT = (FR < 64 ? FR : 64) / 16;
+  fused_layer<NIN_P, RT>(Hs, wsw + SW1, p + OFF_B1, wave, lane);
+  fused_layer<W, RT>(Hs, wsw + SW2, p + OFF_B2, wave, lane);
+  fused_layer<W, RT>(Hs, wsw + SW3, p + OFF_B3, wave, lane);
+  for (int rt = wave; rt < FR / 16; rt += NT / 64) {
+    // output layer: wave w takes the row tiles rt = w, w + waves, ...,
+    // output columns 0..15 (W4 is padded with zero rows; columns 0 and 1 are
+    // the outputs)
     f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
     const int row = lane & 15, kg = (lane >> 4) * 8;
-    const bf16* W4 = wb + OFF_W4;
+    const bf16* W4 = wsw + SW4;
 #pragma unroll
     for (int k0 = 0; k0 < W; k0 += BK) {
-      const bf16x8 a = *reinterpret_cast<const bf16x8*>(&Hs[16 * wave + row][k0 + kg]);
-      const bf16x8 b = *reinterpret_cast<const bf16x8*>(W4 + (size_t)row * W + k0 + kg);
+      const bf16x8 a = *reinterpret_cast<const bf16x8*>(&Hs[16 * rt + row][k0 + kg]);
+      const bf16x8 b = *reinterpret_cast<const bf16x8*>(W4 + (size_t)(k0 / BK) * 512 + lane * 8);
       acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
     }
     if (row < NOUT) {
       const float bn = p[OFF_B4 + row];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) s_y[16 * wave + (lane >> 4) * 4 + t][row] = acc[t] + bn;
+      for (int t = 0; t < 4; ++t) s_y[16 * rt + (lane >> 4) * 4 + t][row] = acc[t] + bn;
     }
   }
   __syncthreads();
@@ -499,6 +591,8 @@ struct fn_mlp {
   Norm norm;
   float *p, *m, *v, *g;   // padded FP32 params, moments, gradient
   bf16* wb;               // BF16 weights (padded layout)
+  bf16* wsw;              // BF16 weights packed for the fused inference (mlp_pack)
+  int64_t ver, wsw_ver;   // weight version, version wsw was packed from
   int64_t step;
   int rows;               // workspace rows
   bf16 *Xb, *H1, *H2, *H3, *dYb, *dZb0, *dZb1;
@@ -514,7 +608,7 @@ static int mlp_alloc(fn_mlp* n) {
 #define A(ptr, bytes)                                  \
   if (e == hipSuccess) e = hipMalloc((void**)&(ptr), (bytes));
   A(n->p, NP_PAD * 4) A(n->m, NP_PAD * 4) A(n->v, NP_PAD * 4) A(n->g, NP_PAD * 4)
-  A(n->wb, NP_PAD * 2) A(n->Xb, R * NIN_P * 2) A(n->H1, R * W * 2) A(n->H2, R * W * 2)
+  A(n->wb, NP_PAD * 2) A(n->wsw, NSW * 2) A(n->Xb, R * NIN_P * 2) A(n->H1, R * W * 2) A(n->H2, R * W * 2)
   A(n->H3, R * W * 2) A(n->dYb, R * NOUT_P * 2) A(n->dZb0, R * W * 2) A(n->dZb1, R * W * 2)
   A(n->Z1, R * W * 4) A(n->Z2, R * W * 4) A(n->Z3, R * W * 4) A(n->Y, R * NOUT_P * 4)
   A(n->dYf, R * NOUT_P * 4) A(n->dZf0, R * W * 4) A(n->dZf1, R * W * 4) A(n->tgt, R * 4)
@@ -527,7 +621,7 @@ static int mlp_alloc(fn_mlp* n) {
 extern "C" void fn_mlp_destroy(fn_mlp* n) {
   if (!n) return;
   (void)hipDeviceSynchronize();
-  void* ps[] = {n->p, n->m, n->v, n->g, n->wb, n->Xb, n->H1, n->H2, n->H3, n->dYb, n->dZb0,
+  void* ps[] = {n->p, n->m, n->v, n->g, n->wb, n->wsw, n->Xb, n->H1, n->H2, n->H3, n->dYb, n->dZb0,
                 n->dZb1, n->Z1, n->Z2, n->Z3, n->Y, n->dYf, n->dZf0, n->dZf1, n->tgt, n->feas,
                 n->part, n->acc3, n->nf, n->colpart};
   for (void* q : ps)
@@ -557,6 +651,7 @@ static int mlp_upload_logical(fn_mlp* n, const float* host) {
     e = hipDeviceSynchronize();
   }
   (void)hipFree(d);
+  ++n->ver;
   n->step = 0;
   return e == hipSuccess ? FN_OK : hip_fail(e, "fn_mlp: upload");
 }
@@ -766,6 +861,7 @@ extern "C" int surrogate_train(fn_ctx* c, fn_mlp* n, const float* X, const int16
                          n->dYf, n->dYb, n->acc3, 1.f / (float)per_epoch);
       mlp_backward(n, bs, s);
       n->step += 1;
+      ++n->ver;
       hipLaunchKernelGGL(mlp_adam, dim3((NP_PAD + 255) / 256), dim3(256), 0, s, n->p, n->m, n->v,
                          n->g, n->wb, n->step, total, cfg->lr, cfg->beta1, cfg->beta2, cfg->eps,
                          cfg->cosine);
@@ -777,6 +873,31 @@ extern "C" int surrogate_train(fn_ctx* c, fn_mlp* n, const float* X, const int16
   return e == hipSuccess ? FN_OK : hip_fail(e, "surrogate_train launch");
 }
 
+// 32 rows per workgroup while that still leaves fewer than four workgroups
+// per compute unit at 64 (more wavefronts to hide the weight loads), else 64
+// (half the weight reads per row).
+template <bool GATHER>
+static void launch_infer(fn_ctx* c, fn_mlp* n, const RowSrc& src, int64_t N, const float* grid,
+                         int n_t, int half, float logit_min, float* out, int16_t* win,
+                         hipStream_t s) {
+  if (n->wsw_ver != n->ver) {
+    // weights changed since they were last packed (stream-ordered after the
+    // update that changed them)
+    hipLaunchKernelGGL(mlp_pack, dim3((NSW + 255) / 256), dim3(256), 0, s, n->wb, n->wsw);
+    n->wsw_ver = n->ver;
+  }
+  const int fr = c->tune.mlp_rows > 0 ? c->tune.mlp_rows : 64;
+#define FN_INFER(FRR)                                                                            \
+  hipLaunchKernelGGL((mlp_infer_fused<GATHER, FRR>), dim3((unsigned)((N + FRR - 1) / FRR)),       \
+                     dim3(infer_threads<FRR>()), 0, s, src, N, n->norm, n->wsw, n->p, grid, n_t, \
+                     half, logit_min, out, win)
+  if (fr == 32) FN_INFER(32);
+  else if (fr == 128) FN_INFER(128);
+  else if (fr == 256) FN_INFER(256);
+  else FN_INFER(64);
+#undef FN_INFER
+}
+
 extern "C" int surrogate_infer(fn_ctx* c, const fn_mlp* nc, const float* X, int64_t N,
                                const float* grid, int32_t n_t, int32_t half, float logit_min,
                                float* out, int16_t* out_win_lo, void* stream) {
@@ -784,12 +905,33 @@ extern "C" int surrogate_infer(fn_ctx* c, const fn_mlp* nc, const float* X, int6
   if (!c || !n || !X || !grid) return fail(FN_E_ARG, "surrogate_infer: NULL argument");
   if (N < 0 || n_t < 2 || n_t > FN_MAX_NT || half < 0) return fail(FN_E_SHAPE, "surrogate_infer: N / n_t / half");
   if (N == 0) return FN_OK;
-  if ((N + FR - 1) / FR > 0x7fffffff) return fail(FN_E_SHAPE, "surrogate_infer: N = %lld", (long long)N);
+  if ((N + 31) / 32 > 0x7fffffff) return fail(FN_E_SHAPE, "surrogate_infer: N = %lld", (long long)N);
   hipStream_t s = (hipStream_t)stream;
-  hipLaunchKernelGGL(mlp_infer_fused, dim3((unsigned)((N + FR - 1) / FR)), dim3(256), 0, s, X, N,
-                     n->norm, n->wb, n->p, grid, n_t, half, logit_min, out, out_win_lo);
+  const RowSrc src{X, nullptr, 0, 0, nullptr, nullptr, 1};
+  launch_infer<false>(c, n, src, N, grid, n_t, half, logit_min, out, out_win_lo, s);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? FN_OK : hip_fail(e, "surrogate_infer launch");
+}
+
+extern "C" int surrogate_window(fn_ctx* c, const fn_mlp* nc, const float* tree, int64_t ld,
+                                int32_t n_nodes, const float* cand, int32_t B,
+                                const int32_t* nbr, int32_t k, const float* grid, int32_t n_t,
+                                int32_t half, float logit_min, float* out, int16_t* out_win_lo,
+                                void* stream) {
+  fn_mlp* n = const_cast<fn_mlp*>(nc);
+  if (!c || !n || !cand || !nbr || !grid || (n_nodes > 0 && !tree))
+    return fail(FN_E_ARG, "surrogate_window: NULL argument");
+  if (B < 0 || k < 1 || k > FN_MAX_K || n_nodes < 0 || ld < n_nodes || n_t < 2 ||
+      n_t > FN_MAX_NT || half < 0)
+    return fail(FN_E_SHAPE, "surrogate_window: B = %d, k = %d, n_nodes = %d, n_t = %d, half = %d",
+                B, k, n_nodes, n_t, half);
+  const int64_t N = (int64_t)B * k;
+  if (N == 0) return FN_OK;
+  hipStream_t s = (hipStream_t)stream;
+  const RowSrc src{nullptr, tree, ld, n_nodes, cand, nbr, k};
+  launch_infer<true>(c, n, src, N, grid, n_t, half, logit_min, out, out_win_lo, s);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? FN_OK : hip_fail(e, "surrogate_window launch");
 }
 
 extern "C" int fn_mlp_save(const fn_mlp* n, const char* path) {
@@ -838,6 +980,7 @@ extern "C" int fn_mlp_load(fn_ctx* ctx, const char* path, fn_mlp** out) {
     fn_mlp_destroy(n);
     return hip_fail(e, "fn_mlp_load");
   }
+  ++n->ver;
   n->step = step;
   *out = n;
   return FN_OK;

@@ -52,7 +52,7 @@ class Caps(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("knn_target_waves", C.c_int32), ("knn_min_chunk", C.c_int32),
-                ("knn_form", C.c_int32), ("edge_form", C.c_int32)]
+                ("knn_form", C.c_int32), ("edge_form", C.c_int32), ("mlp_rows", C.c_int32)]
 
 
 class Search(C.Structure):
@@ -178,6 +178,8 @@ def lib():
             L.surrogate_train.argtypes = [vp, vp, vp, vp, i64, C.POINTER(TrainCfg), vp, vp]
             L.surrogate_grad.argtypes = [vp, vp, vp, vp, i32, vp, i32, vp, vp, vp]
             L.surrogate_infer.argtypes = [vp, vp, vp, i64, vp, i32, i32, C.c_float, vp, vp, vp]
+            L.surrogate_window.argtypes = [vp, vp, vp, i64, i32, vp, i32, vp, i32, vp, i32, i32,
+                                           C.c_float, vp, vp, vp]
             L.fn_set_tuning.argtypes = [vp, C.POINTER(Tuning)]
             L.fn_batch_prepare.argtypes = [vp, C.POINTER(ProblemSet)]
             L.fn_batch_launch.argtypes = [vp, vp]
@@ -293,13 +295,17 @@ class Context:
         _check(lib().fn_kernel_times(self.h, buf, max_n, C.byref(n)), "fn_kernel_times")
         return [buf[i] for i in range(n.value)]
 
-    def set_tuning(self, knn_target_waves=0, knn_min_chunk=0, knn_form=0, edge_form=None):
-        """Launch mappings (fn_set_tuning); edge_form None keeps the current one."""
+    def set_tuning(self, knn_target_waves=0, knn_min_chunk=0, knn_form=0, edge_form=None,
+                   mlp_rows=None):
+        """Launch mappings (fn_set_tuning); edge_form / mlp_rows None keep the
+        current ones."""
         ef = getattr(self, "edge_form", 0) if edge_form is None else int(edge_form)
-        t = Tuning(int(knn_target_waves), int(knn_min_chunk), int(knn_form), ef)
+        mr = getattr(self, "mlp_rows", 0) if mlp_rows is None else int(mlp_rows)
+        t = Tuning(int(knn_target_waves), int(knn_min_chunk), int(knn_form), ef, mr)
         _check(lib().fn_set_tuning(self.h, C.byref(t)), "fn_set_tuning")
         self.tuned_knn_form = int(knn_form)
         self.edge_form = ef
+        self.mlp_rows = mr
 
     # -- plan_knn -----------------------------------------------------------
     def plan_knn(self, tree, ld, n_nodes, queries, k, out_idx=None, out_d2=None, want_d2=True):
@@ -462,6 +468,22 @@ class Surrogate:
         _check(lib().surrogate_train(self.ctx.h, self.h, _ptr(X), _ptr(y_j), X.shape[0],
                                      C.byref(cfg), _ptr(losses), _stream()), "surrogate_train")
         return losses
+
+    def window(self, tree, ld, n_nodes, cand, nbr, grid, half=4, logit_min=0.0, want_out=False,
+               win_lo=None, out=None):
+        """surrogate_window: the windows of every (candidate, parent) edge,
+        with the feature rows gathered inside the inference kernel."""
+        B, k = nbr.shape
+        N = B * k
+        if out is None and want_out:
+            out = torch.empty((N, 2), dtype=torch.float32, device=cand.device)
+        if win_lo is None:
+            win_lo = torch.empty(N, dtype=torch.int16, device=cand.device)
+        _check(lib().surrogate_window(self.ctx.h, self.h, _ptr(tree), int(ld), int(n_nodes),
+                                      _ptr(cand), B, _ptr(nbr), k, _ptr(grid), grid.shape[0],
+                                      int(half), float(logit_min), _ptr(out), _ptr(win_lo),
+                                      _stream()), "surrogate_window")
+        return out, win_lo
 
     def infer(self, X, grid, half=4, logit_min=0.0, want_out=True, win_lo=None, out=None):
         N = X.shape[0]

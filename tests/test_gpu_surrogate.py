@@ -85,6 +85,38 @@ def test_fused_inference_ragged_rows_and_windows(setup, N):
     assert np.array_equal(got[~tie], exp[~tie])
 
 
+@pytest.mark.parametrize("B,k", [(1, 1), (37, 8), (512, 8)])
+def test_window_gathers_edge_rows_like_features_then_infer(setup, B, k):
+    """surrogate_window (edge rows gathered inside the inference kernel)
+    returns bit for bit what edge_features followed by surrogate_infer
+    returns, padded and out-of-range parents included, with 32 to 256 rows
+    per workgroup."""
+    arm, ctx = setup
+    params = M.init_params(31)
+    net = fn.Surrogate(ctx)
+    net.set_params(M.pack(params))
+    rng = np.random.default_rng(B)
+    tree_x = W._f32(W.uniform_states(arm, 300, rng))
+    tree, ld, n = fn.tree_soa(tree_x)
+    cand = fn.dev(W._f32(W.uniform_states(arm, B, rng)))
+    nbr = rng.integers(0, n, (B, k)).astype(np.int32)
+    nbr.reshape(-1)[::7] = -1        # padded parents
+    nbr.reshape(-1)[3::11] = n + 5   # beyond the node count
+    idx = fn.dev(nbr, torch.int32)
+    grid = fn.dev(W.t_grid(64, 0.02, 1.0))
+    X = fn.edge_features(ctx, tree, ld, n, cand, idx)
+    ys = []
+    for rows in (32, 64, 128, 256):  # rows per workgroup of the fused kernel
+        ctx.set_tuning(mlp_rows=rows)
+        ys.append(net.infer(X, grid, half=4, logit_min=0.05))
+        ys.append(net.window(tree, ld, n, cand, idx, grid, half=4, logit_min=0.05, want_out=True))
+    ctx.set_tuning(mlp_rows=0)
+    torch.cuda.synchronize()
+    for y, w in ys[1:]:
+        assert torch.equal(ys[0][0].view(torch.int32), y.view(torch.int32))
+        assert torch.equal(ys[0][1], w)
+
+
 def test_gradient_matches_oracle(setup):
     arm, ctx = setup
     params = M.init_params(12)
