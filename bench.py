@@ -48,6 +48,10 @@ F_MLP_ROW = 277504
 # summed (FMA = 2).
 F_KNN_PAIR = 42
 PEAK_BF16 = 2500e12  # MI355X dense BF16 matrix peak, FLOP/s
+# Initial (cosine-decayed) learning rate of the surrogate's training: from
+# 1e-3 to 1e-2 at minibatch 4,096 the held-out window misses fall to a
+# plateau from 3e-3 on (16.4% -> 13.4% of feasible edges).
+LR_SURROGATE = 3e-3
 # One controller step: Eq. (9) and the taper bounds 7 x 20, sin/cos 21,
 # rigid-body recursion 1,005, armature 14, friction 56, clips and power 7 x 8.
 F_CONTROL = 1252
@@ -622,7 +626,7 @@ def surrogate(args, ctx, arm, sh, fn, W, torch):
     """The T-window network: loaded from a checkpoint, or trained here to the
     recipe (one-iteration batches with seeds disjoint from the benchmark's,
     labelled by the exact search, 20 epochs of minibatch 4,096, Adam with a
-    cosine-decayed learning rate of 1e-3) by the library's own kernels."""
+    cosine-decayed learning rate from 3e-3) by the library's own kernels."""
     if args.surrogate and os.path.exists(args.surrogate):
         return fn.Surrogate.load(ctx, args.surrogate), {"checkpoint": args.surrogate}
     from paper_2609_22608_amd import train_surrogate as TS
@@ -634,7 +638,7 @@ def surrogate(args, ctx, arm, sh, fn, W, torch):
     t_data = time.perf_counter() - t0
     net = fn.Surrogate(ctx, seed=1)
     t1 = time.perf_counter()
-    losses = net.train(X, y, grid, epochs=args.train_epochs, batch=4096, lr=1e-3)
+    losses = net.train(X, y, grid, epochs=args.train_epochs, batch=4096, lr=LR_SURROGATE)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
     L = losses.cpu().numpy()
@@ -642,6 +646,7 @@ def surrogate(args, ctx, arm, sh, fn, W, torch):
     info = {"train_edges": int(X.shape[0]), "epochs": args.train_epochs,
             "seeds": f"1000..{999 + args.train_batches}",
             "feasible_frac": float((y >= 0).float().mean().item()),
+            "lr": LR_SURROGATE,
             "loss_first_last": [float(L[0, 0]), float(L[-1, 0])],
             "label_s": t_data, "train_s": t_train,
             "train_bf16_tflops": rows * 3 * F_MLP_ROW / t_train / 1e12}

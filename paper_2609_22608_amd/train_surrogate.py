@@ -149,7 +149,7 @@ def main():
     ap.add_argument("--edges", type=int, default=10_000_000)
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--batch", type=int, default=4096)
-    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--eval-batches", type=int, default=8)
     ap.add_argument("--half", type=int, default=4)
     ap.add_argument("--save", default=None)
