@@ -364,7 +364,8 @@ def other_rooflines(args, ctx, net, tree, ld, n, cand, idx, grid, sh, win, fn, t
                        "frac": flop / (ms * 1e-3) / PEAK_FP32, "ms": ms,
                        "pairs": sh.batch * n, "flop_per_pair": F_KNN_PAIR,
                        "knn_form": ctx_knn_form,
-                       "traffic": traffic_bytes("knn_scan", str(ctx_knn_form))}
+                       "traffic": traffic_bytes("knn_scan_mfma" if ctx_knn_form == 3 else "knn_scan",
+                                                str(ctx_knn_form))}
     if net is not None:
         E = idx.numel()
         ms = time_it(lambda: net.window(tree, ld, n, cand, idx, grid, half=args.half, win_lo=win),
@@ -382,6 +383,8 @@ def other_rooflines(args, ctx, net, tree, ld, n, cand, idx, grid, sh, win, fn, t
 KERNEL_SOURCES = {
     "edge_time_kernel": ("fn_internal.h", "fn_ctx.h", "fn_edge.h", "fn_edge.hip"),
     "knn_scan": ("fn_internal.h", "fn_ctx.h", "fn_knn.h", "fn_knn.hip"),
+    # the matrix-core form's record (stress shape): same sources
+    "knn_scan_mfma": ("fn_internal.h", "fn_ctx.h", "fn_knn.h", "fn_knn.hip"),
 }
 
 
