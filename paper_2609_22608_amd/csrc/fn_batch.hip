@@ -195,90 +195,157 @@ __global__ __launch_bounds__(256) void batch_model_kernel(ProbTable pt,
   }
 }
 
-// Attachment and scoring, one workgroup per problem: candidate b picks the
-// valid parent with the smallest t(parent) + T (ties: lower kNN rank); the
-// attached candidates are appended in candidate order (block prefix sum),
-// and every attached goal node is scored.
 constexpr int INS_THREADS = 256;
+
+// Per-chunk results of the attachment kernel and the count of a problem's
+// chunks that have finished (reset by the last one, so every launch starts
+// from zero).
+struct InsScratch {
+  int32_t* cnt;   // attached candidates of the chunk
+  float* bj;      // the chunk's best goal node: J, node, time-to-come
+  int32_t* bn;
+  float* bt;
+  int32_t* done;  // per problem
+};
+
+// Attachment and scoring, one workgroup per (problem, chunk of INS_THREADS
+// candidates): candidate b picks the valid parent with the smallest
+// t(parent) + T (ties: lower kNN rank; a candidate with a valid edge always
+// attaches); the attached candidates are appended in candidate order -- a
+// chunk counts the attached candidates of the chunks before it (a candidate
+// attaches exactly when one of its edges is valid, so this needs no parent
+// times), then ranks its own by ballot -- and every attached goal node is
+// scored.  The last chunk of a problem to finish (a counter per problem)
+// reduces the chunks' best goal nodes in chunk order, moves the node count
+// and updates the incumbent.
 __global__ __launch_bounds__(INS_THREADS) void batch_insert_kernel(const InsProb* __restrict__ P,
-                                                                   int k, fn_risk w) {
-  __shared__ int s_scan[INS_THREADS];
+                                                                   int n,
+                                                                   const int64_t* __restrict__ chunk_off,
+                                                                   InsScratch sc, int k, fn_risk w) {
+  __shared__ int s_cnt[INS_THREADS / 64];
   __shared__ float s_bj[INS_THREADS];
   __shared__ int s_bn[INS_THREADS];
   __shared__ float s_bt[INS_THREADS];
-  const InsProb& q = P[blockIdx.x];
-  const int tid = threadIdx.x;
-  const int n0 = *q.n_nodes;
-  __syncthreads();
+  __shared__ int s_last;
+  const int64_t blk = blockIdx.x;
+  if (blk >= chunk_off[n]) return;
+  const int p = bsearch_off(chunk_off, n, blk);
+  const int64_t c0 = chunk_off[p];
+  const int c = (int)(blk - c0), nch = (int)(chunk_off[p + 1] - c0);
+  const InsProb q = P[p];  // by value: the stores below cannot alias it
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int NW = INS_THREADS / 64;
   const uint16_t fail = FN_S_NONE | FN_S_VEL | FN_S_POS | FN_S_COLL | FN_S_BAD_INPUT | FN_S_NO_PARENT;
-  int running = 0;
-  float best_j = -INFINITY, best_t = 0.f;
-  int best_n = -1;
-  for (int base = 0; base < q.B; base += INS_THREADS) {
-    const int b = base + tid;
-    int pick = -1;
-    float cost = INFINITY;
-    if (b < q.B) {
-      for (int i = 0; i < k; ++i) {
-        const int64_t e = (int64_t)b * k + i;
-        if (q.j[e] < 0 || (q.status[e] & fail)) continue;
-        const float c = q.t_node[q.nbr[e]] + q.T[e];
-        if (c < cost) {
-          cost = c;
-          pick = i;
-        }
-      }
-    }
-    // exclusive prefix sum of the attach flags (Hillis-Steele, fixed order)
-    s_scan[tid] = pick >= 0 ? 1 : 0;
-    __syncthreads();
-    for (int o = 1; o < INS_THREADS; o <<= 1) {
-      const int v = tid >= o ? s_scan[tid - o] : 0;
-      __syncthreads();
-      s_scan[tid] += v;
-      __syncthreads();
-    }
-    const int incl = s_scan[tid];
-    const int total = s_scan[INS_THREADS - 1];
-    __syncthreads();
-    if (b < q.B) {
-      const int64_t pos = (int64_t)n0 + running + incl - 1;
-      float J = -INFINITY;
-      int node = -1;
-      if (pick >= 0 && pos < q.ld) {
-        node = (int)pos;
-        const int64_t e = (int64_t)b * k + pick;
-        const int par = q.nbr[e];
-        for (int c = 0; c < FN_STATE; ++c) q.tree[(size_t)c * q.ld + pos] = q.cand[(size_t)b * FN_STATE + c];
-        q.t_node[pos] = cost;
-        q.parent[pos] = par;
-        const float nu = fmaxf(q.nu[par], q.rho4[4 * e + 1]);
-        q.nu[pos] = nu;
-        if (q.kind[b] == 1) {
-          J = (float)risk_eval(w, cost, q.v_rel[b], nu, q.vz0[b], q.t_fall[b]);
-          if (J > best_j || (J == best_j && node < best_n)) {
-            best_j = J;
-            best_n = node;
-            best_t = cost;
+  const int n0 = *q.n_nodes;
+  // attached candidates of the chunks before this one (four candidates per
+  // thread and eight edges of each per step, loads issued together)
+  const int lim = c * INS_THREADS;
+  int prev = 0;
+  for (int b0 = tid; b0 < lim; b0 += 4 * INS_THREADS) {
+    bool any[4] = {false, false, false, false};
+    for (int i0 = 0; i0 < k; i0 += 8) {
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const int b = b0 + s4 * INS_THREADS;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          if (b < lim && i0 + u < k) {
+            const int64_t e = (int64_t)b * k + i0 + u;
+            any[s4] |= (q.j[e] >= 0) & ((q.status[e] & fail) == 0);
           }
         }
       }
-      q.out_node[b] = node;
-      q.out_J[b] = J;
     }
-    running += total;
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) prev += any[s4] ? 1 : 0;
   }
-  // best goal node of the round (fixed-order tree reduction)
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) prev += __shfl_xor(prev, o);
+  if (lane == 0) s_cnt[wave] = prev;
+  __syncthreads();
+  int before = 0;
+#pragma unroll
+  for (int v = 0; v < NW; ++v) before += s_cnt[v];
+  __syncthreads();
+  // this chunk: the pick of candidate b (eight edges at a time: their loads,
+  // then the parents' times, then the comparisons in rank order)
+  const int b = lim + tid;
+  int pick = -1;
+  float cost = INFINITY;
+  if (b < q.B) {
+    for (int i0 = 0; i0 < k; i0 += 8) {
+      bool ok[8];
+      int par[8];
+      float Tv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t e = (int64_t)b * k + i0 + u;
+        ok[u] = i0 + u < k && q.j[e] >= 0 && !(q.status[e] & fail);
+        par[u] = ok[u] ? q.nbr[e] : 0;
+        Tv[u] = ok[u] ? q.T[e] : 0.f;
+      }
+      float tn[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) tn[u] = ok[u] ? q.t_node[par[u]] : 0.f;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const float cu = tn[u] + Tv[u];
+        if (ok[u] && (pick < 0 || cu < cost)) {
+          cost = cu;
+          pick = i0 + u;
+        }
+      }
+    }
+  }
+  // rank among the chunk's attached candidates: ballot within a wavefront,
+  // counts of the wavefronts before through LDS
+  const uint64_t m = __ballot(pick >= 0);
+  int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                       __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+  if (lane == 0) s_cnt[wave] = (int)__popcll(m);
+  __syncthreads();
+  int own = 0;
+#pragma unroll
+  for (int v = 0; v < NW; ++v) {
+    rank += v < wave ? s_cnt[v] : 0;
+    own += s_cnt[v];
+  }
+  float best_j = -INFINITY, best_t = 0.f;
+  int best_n = -1;
+  if (b < q.B) {
+    const int64_t pos = (int64_t)n0 + before + rank;
+    float J = -INFINITY;
+    int node = -1;
+    if (pick >= 0 && pos < q.ld) {
+      node = (int)pos;
+      const int64_t e = (int64_t)b * k + pick;
+      const int par = q.nbr[e];
+      for (int cc = 0; cc < FN_STATE; ++cc) q.tree[(size_t)cc * q.ld + pos] = q.cand[(size_t)b * FN_STATE + cc];
+      q.t_node[pos] = cost;
+      q.parent[pos] = par;
+      const float nu = fmaxf(q.nu[par], q.rho4[4 * e + 1]);
+      q.nu[pos] = nu;
+      if (q.kind[b] == 1) {
+        J = (float)risk_eval(w, cost, q.v_rel[b], nu, q.vz0[b], q.t_fall[b]);
+        best_j = J;
+        best_n = node;
+        best_t = cost;
+      }
+    }
+    q.out_node[b] = node;
+    q.out_J[b] = J;
+  }
+  // best goal node of the chunk (fixed-order tree reduction)
   s_bj[tid] = best_j;
   s_bn[tid] = best_n;
   s_bt[tid] = best_t;
   __syncthreads();
   for (int o = INS_THREADS / 2; o > 0; o >>= 1) {
     if (tid < o) {
-      const float a = s_bj[tid], c = s_bj[tid + o];
+      const float a = s_bj[tid], cj = s_bj[tid + o];
       const int an = s_bn[tid], cn = s_bn[tid + o];
-      if (c > a || (c == a && cn >= 0 && (an < 0 || cn < an))) {
-        s_bj[tid] = c;
+      if (cj > a || (cj == a && cn >= 0 && (an < 0 || cn < an))) {
+        s_bj[tid] = cj;
         s_bn[tid] = cn;
         s_bt[tid] = s_bt[tid + o];
       }
@@ -286,19 +353,43 @@ __global__ __launch_bounds__(INS_THREADS) void batch_insert_kernel(const InsProb
     __syncthreads();
   }
   if (tid == 0) {
-    *q.n_nodes = (int)min<int64_t>(q.ld, (int64_t)n0 + running);
-    q.out_best[0] = s_bj[0];
-    q.out_best[1] = (float)s_bn[0];
-    // incumbent: the rendezvous node of largest J in the tree (earlier
-    // nodes win ties) and t_best = its time-to-come
-    if (q.inc) {
-      if (s_bn[0] >= 0 && s_bj[0] > q.inc[0]) {
-        q.inc[0] = s_bj[0];
-        q.inc[1] = (float)s_bn[0];
-        q.inc[2] = s_bt[0];
-      }
-      q.inc[3] += 1.f;
+    sc.cnt[blk] = own;
+    sc.bj[blk] = s_bj[0];
+    sc.bn[blk] = s_bn[0];
+    sc.bt[blk] = s_bt[0];
+    __threadfence();
+    s_last = atomicAdd(&sc.done[p], 1) == nch - 1;
+  }
+  __syncthreads();
+  if (!s_last || tid != 0) return;
+  // the problem's last chunk: every chunk's results are visible
+  __threadfence();
+  int total = 0, bn = -1;
+  float bj = -INFINITY, btm = 0.f;
+  for (int i = 0; i < nch; ++i) {
+    const int64_t ci = c0 + i;
+    total += __hip_atomic_load(&sc.cnt[ci], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const float cj = __hip_atomic_load(&sc.bj[ci], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int cn = __hip_atomic_load(&sc.bn[ci], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (cj > bj || (cj == bj && cn >= 0 && (bn < 0 || cn < bn))) {
+      bj = cj;
+      bn = cn;
+      btm = __hip_atomic_load(&sc.bt[ci], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+  }
+  sc.done[p] = 0;
+  *q.n_nodes = (int)min<int64_t>(q.ld, (int64_t)n0 + total);
+  q.out_best[0] = bj;
+  q.out_best[1] = (float)bn;
+  // incumbent: the rendezvous node of largest J in the tree (earlier nodes
+  // win ties) and t_best = its time-to-come
+  if (q.inc) {
+    if (bn >= 0 && bj > q.inc[0]) {
+      q.inc[0] = bj;
+      q.inc[1] = (float)bn;
+      q.inc[2] = btm;
+    }
+    q.inc[3] += 1.f;
   }
 }
 
@@ -384,7 +475,7 @@ __global__ __launch_bounds__(256) void reach_kernel(const float* __restrict__ tr
 
 __global__ __launch_bounds__(PRUNE_THREADS) void prune_clear(const PruneProb* __restrict__ P,
                                                              PruneScratch sc) {
-  const PruneProb& q = P[blockIdx.y];
+  const PruneProb q = P[blockIdx.y];
   const int64_t n = (int64_t)blockIdx.x * PRUNE_THREADS + threadIdx.x;
   if (n < q.ld) sc.walked[q.off + n] = 0;
 }
@@ -397,7 +488,7 @@ __global__ __launch_bounds__(PRUNE_THREADS) void prune_mark(const PruneProb* __r
                                                             PruneScratch sc, fn_prune pr,
                                                             const ArmConst<float>* __restrict__ Ap,
                                                             const ArmConst<double>* __restrict__ Dp) {
-  const PruneProb& q = P[blockIdx.y];
+  const PruneProb q = P[blockIdx.y];
   const int64_t n = (int64_t)blockIdx.x * PRUNE_THREADS + threadIdx.x;
   const int N = *q.n_nodes;
   if (n >= N) return;
@@ -437,7 +528,7 @@ __device__ __forceinline__ int block_rank(bool f, int* s_w, int* count) {
 __global__ __launch_bounds__(PRUNE_THREADS) void prune_count(const PruneProb* __restrict__ P,
                                                              PruneScratch sc) {
   __shared__ int s_w[PRUNE_THREADS / 64];
-  const PruneProb& q = P[blockIdx.y];
+  const PruneProb q = P[blockIdx.y];
   if ((int64_t)blockIdx.x * PRUNE_THREADS >= q.ld) return;  // whole block: uniform exit
   const int64_t n = (int64_t)blockIdx.x * PRUNE_THREADS + threadIdx.x;
   int count;
@@ -449,7 +540,7 @@ __global__ __launch_bounds__(PRUNE_THREADS) void prune_count(const PruneProb* __
 __global__ __launch_bounds__(PRUNE_THREADS) void prune_scan(const PruneProb* __restrict__ P,
                                                             PruneScratch sc) {
   __shared__ int s_v[PRUNE_THREADS];
-  const PruneProb& q = P[blockIdx.x];
+  const PruneProb q = P[blockIdx.x];
   const int nb = (int)((q.ld + PRUNE_THREADS - 1) / PRUNE_THREADS);
   const int tid = threadIdx.x;
   int running = 0;
@@ -477,7 +568,7 @@ __global__ __launch_bounds__(PRUNE_THREADS) void prune_scan(const PruneProb* __r
 __global__ __launch_bounds__(PRUNE_THREADS) void prune_map(const PruneProb* __restrict__ P,
                                                            PruneScratch sc) {
   __shared__ int s_w[PRUNE_THREADS / 64];
-  const PruneProb& q = P[blockIdx.y];
+  const PruneProb q = P[blockIdx.y];
   if ((int64_t)blockIdx.x * PRUNE_THREADS >= q.ld) return;
   const int64_t n = (int64_t)blockIdx.x * PRUNE_THREADS + threadIdx.x;
   const bool k = prune_kept(q, sc, n, sc.meta[2 * blockIdx.y]);
@@ -489,7 +580,7 @@ __global__ __launch_bounds__(PRUNE_THREADS) void prune_map(const PruneProb* __re
 // Kept node n -> its new row in the scratch columns (parent renumbered).
 __global__ __launch_bounds__(PRUNE_THREADS) void prune_gather(const PruneProb* __restrict__ P,
                                                               PruneScratch sc) {
-  const PruneProb& q = P[blockIdx.y];
+  const PruneProb q = P[blockIdx.y];
   const int64_t n = (int64_t)blockIdx.x * PRUNE_THREADS + threadIdx.x;
   const int N = sc.meta[2 * blockIdx.y];
   if (n >= N) return;
@@ -508,7 +599,7 @@ __global__ __launch_bounds__(PRUNE_THREADS) void prune_gather(const PruneProb* _
 // count and the incumbent's index updated.
 __global__ __launch_bounds__(PRUNE_THREADS) void prune_commit(const PruneProb* __restrict__ P,
                                                               PruneScratch sc) {
-  const PruneProb& q = P[blockIdx.y];
+  const PruneProb q = P[blockIdx.y];
   const int64_t i = (int64_t)blockIdx.x * PRUNE_THREADS + threadIdx.x;
   const int N = sc.meta[2 * blockIdx.y], M = sc.meta[2 * blockIdx.y + 1];
   const float* rows = sc.rows + (size_t)PRUNE_COLS * q.off;
@@ -553,6 +644,11 @@ struct fn_batch {
   int64_t prune_nodes = 0, prune_blocks = 0;  // scratch capacity
   int64_t max_blocks = 0;                     // node blocks of the largest tree
   int64_t *pair_off = nullptr, *query_off = nullptr, *edge_off = nullptr;  // pair_off: scan work items
+  // attachment: chunks of INS_THREADS candidates per problem (prefix offsets)
+  // and their per-chunk results; capacity ins_cap chunks
+  int64_t* chunk_off = nullptr;
+  int64_t chunks = 0, ins_cap = 0;
+  InsScratch isc{};
   EdgeArgs a0{};  // queue pointers for the FP64 stage
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -572,6 +668,16 @@ int batch_alloc(fn_ctx* c) {
   if (e == hipSuccess) e = hipMalloc((void**)&b->edge_off, sizeof(int64_t) * (np + 1));
   if (e == hipSuccess) e = hipMalloc((void**)&b->prune, sizeof(PruneProb) * np);
   if (e == hipSuccess) e = hipMalloc((void**)&b->psc.meta, sizeof(int32_t) * 2 * np);
+  // every problem's candidates in chunks of INS_THREADS: at most
+  // max_batch / INS_THREADS + max_problems chunks in all
+  b->ins_cap = (int64_t)c->caps.max_batch / INS_THREADS + np;
+  if (e == hipSuccess) e = hipMalloc((void**)&b->chunk_off, sizeof(int64_t) * (np + 1));
+  if (e == hipSuccess) e = hipMalloc((void**)&b->isc.cnt, sizeof(int32_t) * b->ins_cap);
+  if (e == hipSuccess) e = hipMalloc((void**)&b->isc.bj, sizeof(float) * b->ins_cap);
+  if (e == hipSuccess) e = hipMalloc((void**)&b->isc.bn, sizeof(int32_t) * b->ins_cap);
+  if (e == hipSuccess) e = hipMalloc((void**)&b->isc.bt, sizeof(float) * b->ins_cap);
+  if (e == hipSuccess) e = hipMalloc((void**)&b->isc.done, sizeof(int32_t) * np);
+  if (e == hipSuccess) e = hipMemset(b->isc.done, 0, sizeof(int32_t) * np);
   b->tab_cap = np;
   return e == hipSuccess ? FN_OK : fail(FN_E_NOMEM, "fn_create: batch tables: %s", hipGetErrorString(e));
 }
@@ -582,7 +688,8 @@ void batch_free(fn_ctx* c) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   void* ps[] = {b->knn, b->ins, b->args, b->pair_off, b->query_off, b->edge_off, b->prune,
-                b->psc.keep0, b->psc.walked, b->psc.map, b->psc.blk, b->psc.meta, b->psc.rows};
+                b->psc.keep0, b->psc.walked, b->psc.map, b->psc.blk, b->psc.meta, b->psc.rows,
+                b->chunk_off, b->isc.cnt, b->isc.bj, b->isc.bn, b->isc.bt, b->isc.done};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   delete b;
@@ -680,6 +787,12 @@ extern "C" int fn_batch_prepare(fn_ctx* c, const fn_problem_set* ps) {
                     q.out_node, q.out_J, q.out_best, q.incumbent};
   }
   if (eo[n] > c->caps.max_edges) return fail(FN_E_SHAPE, "fn_batch_prepare: %lld edges (cap %lld)", (long long)eo[n], (long long)c->caps.max_edges);
+  std::vector<int64_t> co(n + 1);
+  co[0] = 0;
+  for (int p = 0; p < n; ++p)
+    co[p + 1] = co[p] + (ps->problems[p].B + INS_THREADS - 1) / INS_THREADS;
+  if (co[n] > bt->ins_cap)
+    return fail(FN_E_SHAPE, "fn_batch_prepare: %lld candidate chunks (cap %lld)", (long long)co[n], (long long)bt->ins_cap);
   if (sumB > c->caps.max_batch || part > cap_part || ys > cap_y)
     return fail(FN_E_SHAPE, "fn_batch_prepare: %lld candidates in total (cap %d)", (long long)sumB, c->caps.max_batch);
   // round r's tables: the same problems with candidate arrays advanced by r
@@ -752,7 +865,9 @@ extern "C" int fn_batch_prepare(fn_ctx* c, const fn_problem_set* ps) {
   if (e == hipSuccess) e = hipMemcpy(bt->pair_off, po.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(bt->query_off, qo.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(bt->edge_off, eo.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(bt->chunk_off, co.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "fn_batch_prepare: upload");
+  bt->chunks = co[n];
   bt->n = n;
   bt->K1 = K1;
   bt->k = ps->k;
@@ -824,7 +939,8 @@ static int launch_round(fn_ctx* c, fn_batch* bt, int r, hipStream_t s) {
     if (bt->mode == FN_SEARCH_PLAIN) launch_batch_search<PAT_GENERIC, FN_SEARCH_PLAIN>(c, bt, et, s);
     else launch_batch_search<PAT_GENERIC, FN_SEARCH_SCREEN>(c, bt, et, s);
   }
-  hipLaunchKernelGGL(batch_insert_kernel, dim3(bt->n), dim3(INS_THREADS), 0, s, it, bt->k, bt->risk);
+  hipLaunchKernelGGL(batch_insert_kernel, dim3((unsigned)bt->chunks), dim3(INS_THREADS), 0, s, it,
+                     bt->n, bt->chunk_off, bt->isc, bt->k, bt->risk);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? FN_OK : hip_fail(e, "fn_batch_round");
 }
