@@ -393,6 +393,50 @@ def test_window_tiny_all_edges_vs_oracle(tiny, half, with_jmax):
     print(f"{label}: hits {hit.sum()}, misses {miss.sum()}")
 
 
+@pytest.mark.parametrize("mode,form", [(fn.SEARCH_PLAIN, 0), (fn.SEARCH_SCREEN, 1),
+                                       (fn.SEARCH_SCREEN, 2), (fn.SEARCH_WINDOW, 1),
+                                       (fn.SEARCH_WINDOW, 2)])
+def test_edge_time_largest_grid_and_samples(tiny, mode, form):
+    """The largest sizes the search takes: FN_MAX_NT = 256 slots (four 64-slot
+    words of the slot mask, four screen passes) and FN_MAX_SAMPLES = 64
+    samples (one slot per full pass), with 20 obstacle spheres, in every
+    search form, against the FP64 oracle on 128 tiny-shape edges (a ragged
+    last screen pass is covered by j_max = 200 on a quarter of them)."""
+    sh = tiny["shape"]
+    n_t, S = 256, 64
+    grid = W.t_grid(n_t, 0.01, 1.2)
+    obs = W.make_obstacles(tiny["arm"], 20, seed=17, r=(0.03, 0.2))
+    B = 32
+    ctx = _ctx(tiny, B=B)
+    ctx.set_tuning(edge_form=form if mode != fn.SEARCH_PLAIN else 0)
+    cand_x = tiny["cand"]["x"][:B]
+    ridx, _ = O.plan_knn(tiny["tree_x"], cand_x, sh.k)
+    E = ridx.size
+    jm = np.full(E, n_t - 1, np.int16)
+    jm[::4] = 200
+    kw = {}
+    lo = None
+    if mode == fn.SEARCH_WINDOW:
+        lo = np.random.default_rng(23).integers(0, n_t + 4, E).astype(np.int16)
+        lo[:8] = 0
+        kw = dict(win_lo=fn.dev(lo, torch.int16), win_half=4)
+    tree, ld, n = fn.tree_soa(tiny["tree_x"])
+    out = ctx.edge_time_batch(tree, ld, n, fn.dev(cand_x), fn.dev(ridx, torch.int32),
+                              fn.dev(grid), S, fn.dev(obs), mode=mode,
+                              j_max=fn.dev(jm, torch.int16), **kw)
+    torch.cuda.synchronize()
+    ctx.set_tuning(edge_form=0)
+    x0, x1, ok = O.edges_of(tiny["tree_x"], cand_x, ridx)
+    ref = O.edge_time(O.make_oarm(tiny["arm"]), x0, x1, grid, S, obs=obs, parent_ok=ok,
+                      jmax=jm)
+    label = f"n_t {n_t} S {S} mode {mode} form {form}"
+    gj, _ = compare_edges(out, ref, label=label)
+    assert (gj >= 0).any() and (gj < 0).any(), label
+    if mode == fn.SEARCH_WINDOW:
+        check_window_flags(out, lo.astype(np.int64), 4, label)
+    ctx.close()
+
+
 def test_edge_time_bad_input_and_padding(tiny):
     sh = tiny["shape"]
     ctx = _ctx(tiny)
