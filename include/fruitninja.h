@@ -227,7 +227,8 @@ typedef struct {
  * evaluated in FP32; any ratio within 1e-3 of 1 is re-evaluated in FP64
  * before it decides.  Returns FN_E_SHAPE for B*k > max_edges, n_t out of
  * 1..FN_MAX_NT, S out of 2..FN_MAX_SAMPLES, too many obstacles; FN_E_ARG for
- * NULL required pointers or window mode without win_lo. */
+ * NULL required pointers or window mode without win_lo.  B = 0 is a no-op
+ * once the sizes check (the arrays may then be NULL). */
 int edge_time_batch(fn_ctx* ctx, const float* tree, int64_t ld, int32_t n_nodes,
                     const float* cand, int32_t B, const int32_t* nbr, int32_t k,
                     const fn_search* search, const fn_obstacles* obs, const fn_edge_out* out,
@@ -436,7 +437,8 @@ int surrogate_grad(fn_ctx* ctx, fn_mlp* mlp, const float* X, const int16_t* y_j,
 /* Inference on N rows: out device [N][2] = (standardised log T*, logit) or
  * NULL; out_win_lo device [N] or NULL: lowest slot of the window, i.e. the
  * grid slot nearest the predicted T* minus `half` (clamped at 0), or n_t
- * (predicted infeasible) when the logit is below logit_min. */
+ * (predicted infeasible) when the logit is below logit_min.  N = 0 is a
+ * no-op once the sizes check (X and grid may then be NULL). */
 int surrogate_infer(fn_ctx* ctx, const fn_mlp* mlp, const float* X, int64_t N, const float* grid,
                     int32_t n_t, int32_t half, float logit_min, float* out, int16_t* out_win_lo,
                     void* stream);
@@ -445,7 +447,8 @@ int surrogate_infer(fn_ctx* ctx, const fn_mlp* mlp, const float* X, int64_t N, c
  * surrogate_infer on the rows edge_features would write (state of tree node
  * nbr[e], state of candidate e / k; zeros for a padded or out-of-range
  * parent), gathered inside the inference kernel, so no feature matrix is
- * written.  Same results as edge_features followed by surrogate_infer. */
+ * written.  Same results as edge_features followed by surrogate_infer.
+ * B = 0 is a no-op once the sizes check. */
 int surrogate_window(fn_ctx* ctx, const fn_mlp* mlp, const float* tree, int64_t ld,
                      int32_t n_nodes, const float* cand, int32_t B, const int32_t* nbr, int32_t k,
                      const float* grid, int32_t n_t, int32_t half, float logit_min, float* out,

@@ -409,10 +409,11 @@ int edge_time_run(fn_ctx* c, const float* tree, int64_t ld, int32_t n_nodes, con
   if (sr->n_t < 1 || sr->n_t > FN_MAX_NT) return fail(FN_E_SHAPE, "%s: n_t = %d (1..%d)", who, sr->n_t, FN_MAX_NT);
   if (sr->samples < 2 || sr->samples > FN_MAX_SAMPLES) return fail(FN_E_SHAPE, "%s: S = %d (2..%d)", who, sr->samples, FN_MAX_SAMPLES);
   if (sr->mode < FN_SEARCH_PLAIN || sr->mode > FN_SEARCH_WINDOW) return fail(FN_E_ARG, "%s: mode %d", who, sr->mode);
-  if (sr->mode == FN_SEARCH_WINDOW && (!sr->win_lo || sr->win_half < 0)) return fail(FN_E_ARG, "%s: window mode needs win_lo and win_half >= 0", who);
+  if (sr->mode == FN_SEARCH_WINDOW && sr->win_half < 0) return fail(FN_E_ARG, "%s: window mode needs win_half >= 0", who);
   int rc = check_obstacles(obs, who);
   if (rc) return rc;
-  if (E == 0) return FN_OK;
+  if (E == 0) return FN_OK;  // nothing to read or write: the arrays may be NULL
+  if (sr->mode == FN_SEARCH_WINDOW && !sr->win_lo) return fail(FN_E_ARG, "%s: window mode needs win_lo", who);
   if (!cand || !nbr || !sr->grid || !out->j || !out->status || !out->margin || (n_nodes > 0 && !tree))
     return fail(FN_E_ARG, "%s: NULL array", who);
   if (ld < n_nodes) return fail(FN_E_ARG, "%s: ld < n_nodes", who);

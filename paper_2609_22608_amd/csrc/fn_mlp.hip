@@ -902,9 +902,10 @@ extern "C" int surrogate_infer(fn_ctx* c, const fn_mlp* nc, const float* X, int6
                                const float* grid, int32_t n_t, int32_t half, float logit_min,
                                float* out, int16_t* out_win_lo, void* stream) {
   fn_mlp* n = const_cast<fn_mlp*>(nc);
-  if (!c || !n || !X || !grid) return fail(FN_E_ARG, "surrogate_infer: NULL argument");
+  if (!c || !n) return fail(FN_E_ARG, "surrogate_infer: NULL argument");
   if (N < 0 || n_t < 2 || n_t > FN_MAX_NT || half < 0) return fail(FN_E_SHAPE, "surrogate_infer: N / n_t / half");
-  if (N == 0) return FN_OK;
+  if (N == 0) return FN_OK;  // nothing to read or write: the arrays may be NULL
+  if (!X || !grid) return fail(FN_E_ARG, "surrogate_infer: NULL argument");
   if ((N + 31) / 32 > 0x7fffffff) return fail(FN_E_SHAPE, "surrogate_infer: N = %lld", (long long)N);
   hipStream_t s = (hipStream_t)stream;
   const RowSrc src{X, nullptr, 0, 0, nullptr, nullptr, 1};
@@ -919,14 +920,15 @@ extern "C" int surrogate_window(fn_ctx* c, const fn_mlp* nc, const float* tree, 
                                 int32_t half, float logit_min, float* out, int16_t* out_win_lo,
                                 void* stream) {
   fn_mlp* n = const_cast<fn_mlp*>(nc);
-  if (!c || !n || !cand || !nbr || !grid || (n_nodes > 0 && !tree))
-    return fail(FN_E_ARG, "surrogate_window: NULL argument");
+  if (!c || !n) return fail(FN_E_ARG, "surrogate_window: NULL argument");
   if (B < 0 || k < 1 || k > FN_MAX_K || n_nodes < 0 || ld < n_nodes || n_t < 2 ||
       n_t > FN_MAX_NT || half < 0)
     return fail(FN_E_SHAPE, "surrogate_window: B = %d, k = %d, n_nodes = %d, n_t = %d, half = %d",
                 B, k, n_nodes, n_t, half);
   const int64_t N = (int64_t)B * k;
-  if (N == 0) return FN_OK;
+  if (N == 0) return FN_OK;  // nothing to read or write: the arrays may be NULL
+  if (!cand || !nbr || !grid || (n_nodes > 0 && !tree))
+    return fail(FN_E_ARG, "surrogate_window: NULL argument");
   hipStream_t s = (hipStream_t)stream;
   const RowSrc src{nullptr, tree, ld, n_nodes, cand, nbr, k};
   launch_infer<true>(c, n, src, N, grid, n_t, half, logit_min, out, out_win_lo, s);

@@ -564,6 +564,49 @@ def test_risk_score():
         assert (err <= 1e-5 * np.maximum(1.0, np.abs(ref))).all()
 
 
+def test_empty_inputs_are_no_ops(tiny):
+    """Zero candidates, edges, rows or states: every entry point returns
+    without error and writes nothing (sentinel outputs stay as they were)."""
+    sh = tiny["shape"]
+    ctx = _ctx(tiny)
+    tree, ld, n = fn.tree_soa(tiny["tree_x"])
+    grid = fn.dev(tiny["grid"])
+    q0 = torch.empty((0, 14), dtype=torch.float32, device="cuda")
+    nb0 = torch.empty((0, sh.k), dtype=torch.int32, device="cuda")
+    idx, d2 = ctx.plan_knn(tree, ld, n, q0, sh.k)
+    assert idx.shape == (0, sh.k) and d2.shape == (0, sh.k)
+    for mode in (fn.SEARCH_PLAIN, fn.SEARCH_SCREEN, fn.SEARCH_WINDOW):
+        kw = dict(win_lo=torch.empty(0, dtype=torch.int16, device="cuda"), win_half=4) \
+            if mode == fn.SEARCH_WINDOW else {}
+        out = ctx.edge_time_batch(tree, ld, n, q0, nb0, grid, sh.samples, mode=mode, **kw)
+        assert out["j"].numel() == 0
+    out = ctx.edge_time_batch(tree, ld, n, q0, nb0, grid, sh.samples, mode=fn.SEARCH_SCREEN,
+                              noalloc=True)
+    assert out["j"].numel() == 0
+    x = torch.empty((0, 14), dtype=torch.float32, device="cuda")
+    T = torch.empty(0, dtype=torch.float32, device="cuda")
+    chk = ctx.edge_check(x, x, T, sh.samples)
+    assert chk["status"].numel() == 0
+    sent = torch.full((4,), -7.0, device="cuda")
+    rk = ctx.risk_score(fn.make_risk(sigma_mode=1, s0=0.01, s1=0.05), T, T, T, T, T,
+                        out=sent[:0])
+    torch.cuda.synchronize()
+    assert (sent == -7.0).all() and rk.numel() == 0
+    rf = ctx.edge_refine(tree, ld, n, q0, nb0, torch.empty(0, dtype=torch.int16, device="cuda"),
+                         grid, sh.samples)
+    assert rf["T"].numel() == 0
+    z7 = torch.empty((0, 7), dtype=torch.float32, device="cuda")
+    tau, qdd, cst = fn.control(ctx, z7, z7, z7, z7, z7, T, 1e-3, [1000.0] * 7)
+    assert tau.numel() == 0 and cst.numel() == 0
+    net = fn.Surrogate(ctx, seed=1)
+    o, w = net.infer(torch.empty((0, 28), dtype=torch.float32, device="cuda"), grid)
+    assert o.numel() == 0 and w.numel() == 0
+    o, w = net.window(tree, ld, n, q0, nb0, grid, want_out=True)
+    assert o.numel() == 0 and w.numel() == 0
+    net.close()
+    ctx.close()
+
+
 def test_errors_are_returned_not_thrown(tiny):
     ctx = _ctx(tiny)
     tree, ld, n = fn.tree_soa(tiny["tree_x"])
