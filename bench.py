@@ -141,6 +141,17 @@ def main():
         knn_tuning = ch.as_dict()
     modes = {"plain": fn.SEARCH_PLAIN, "screen": fn.SEARCH_SCREEN, "window": fn.SEARCH_WINDOW}
     wanted = args.modes.split(",")
+    edge_tuning = None
+    if not args.no_tune and not args.edge_form and ("screen" in wanted or "window" in wanted):
+        # the screened searches' form (one kernel, or triage then search) for
+        # this shape, timed on the screened search (outside the timed region)
+        from paper_2609_22608_amd import autotune
+
+        ctx.plan_knn(tree, ld, n, cand, sh.k, out_idx=idx, want_d2=False)
+        ch, _ = autotune.tune_edge(ctx, tree, ld, n, cand, idx, grid, sh.samples, obs,
+                                   mode=fn.SEARCH_SCREEN, reps=3,
+                                   cache=autotune.Cache(args.tune_cache))
+        edge_tuning = {"edge_form": ch.edge_form, "ms": ch.ms}
     surrogate_info = None
     net = None
     if "window" in wanted:
@@ -250,7 +261,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "search": best, "edges": E,
-                   "seed": args.seed, "knn_tuning": knn_tuning},
+                   "seed": args.seed, "knn_tuning": knn_tuning, "edge_tuning": edge_tuning},
         "diagnostics": diagnostics(out, sh, fn),  # decisions are the same in every form
         "forms": forms,
         "speedup": speed,

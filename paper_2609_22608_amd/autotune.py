@@ -4,9 +4,11 @@ The kNN scan splits the tree into node chunks so that enough wavefronts run
 to fill the 256 compute units; how many, and how small a chunk may get, is a
 trade between occupancy and the cost of merging partial lists, and the best
 point moves with the tree size, the batch size and (for a batched round) the
-number of problems.  The edge search has two exact forms (plain ascending
+number of problems.  The edge search has two exact modes (plain ascending
 scan and endpoint-screened scan) whose ratio moves with the workload's
-feasibility mix.  This module times the candidates on the device with HIP
+feasibility mix, and the screened modes two exact forms (one kernel, or a
+triage kernel before the search of the open edges) whose ratio moves with
+the number of edges.  This module times the candidates on the device with HIP
 events on the launching stream, keeps the fastest, and caches the choice
 per shape in a JSON file so later runs skip the search.
 
@@ -52,10 +54,11 @@ class Choice:
     mode: int
     ms: float
     knn_form: int = 0
+    edge_form: int = 0  # search form of edge_time_batch (tune_edge); 0 = not tuned
 
     def as_dict(self):
         return dict(knn_target_waves=self.knn_target_waves, knn_min_chunk=self.knn_min_chunk,
-                    knn_form=self.knn_form, mode=self.mode, ms=self.ms)
+                    knn_form=self.knn_form, mode=self.mode, ms=self.ms, edge_form=self.edge_form)
 
 
 class Cache:
@@ -130,6 +133,41 @@ def tune_knn(ctx: fn.Context, tree, ld, n_nodes, cand, k, reps=5, cache: Cache |
     if cache:
         cache.put(key, ch)
     return ch, {f"{a}/{b}/{f}": v for (a, b, f), v in times.items()}
+
+
+def tune_edge(ctx: fn.Context, tree, ld, n_nodes, cand, nbr, grid, samples, obs=None,
+              mode=fn.SEARCH_SCREEN, reps=5, cache: Cache | None = None, win_lo=None, win_half=4):
+    """Faster edge form of edge_time_batch for one shape and search mode: 1
+    (one kernel, a wavefront per edge) or 2 (the triage of every edge, then
+    the search of the open ones); both give identical results.  Leaves it set
+    on ctx (the kNN mapping is kept)."""
+    B, k = nbr.shape
+    n_obs = 0 if obs is None else int(obs.shape[0])
+    key = (f"edge|n{n_nodes}|B{B}|k{k}|nt{grid.shape[0]}|S{samples}|o{n_obs}|m{mode}|"
+           f"{_device_tag()}")
+    hit = cache.get(key) if cache else None
+    if hit is not None:
+        ctx.set_tuning(edge_form=hit.edge_form)
+        return hit, {}
+    E = B * k
+    d = cand.device
+    out = dict(j=torch.empty(E, dtype=torch.int16, device=d),
+               status=torch.empty(E, dtype=torch.int16, device=d),
+               margin=torch.empty(E, dtype=torch.float32, device=d), rho=None, work=None,
+               screened=None)
+    kw = dict(win_lo=win_lo, win_half=win_half) if mode == fn.SEARCH_WINDOW else {}
+    times = {}
+    for form in (1, 2):
+        ctx.set_tuning(edge_form=form)
+        times[form] = _time(lambda: ctx.edge_time_batch(tree, ld, n_nodes, cand, nbr, grid,
+                                                        samples, obs, mode=mode, out=out, **kw),
+                            reps)
+    form, ms = min(times.items(), key=lambda kv: kv[1])
+    ch = Choice(0, 0, mode, ms, 0, form)
+    ctx.set_tuning(edge_form=form)
+    if cache:
+        cache.put(key, ch)
+    return ch, {f"edge_form {f}": v for f, v in times.items()}
 
 
 def tune_batch(bt: fn.Batch, reps=3, cache: Cache | None = None, candidates=None,

@@ -59,6 +59,21 @@ def test_autotuner_picks_a_candidate_and_caches_it(iteration, tmp_path):
     ctx.set_tuning(0, 0)
 
 
+def test_edge_form_tuner_picks_a_form_and_caches_it(iteration, tmp_path):
+    sh, wl, ctx, tree, ld, n, cand = iteration
+    idx, _ = ctx.plan_knn(tree, ld, n, cand, sh.k, want_d2=False)
+    grid, obs = fn.dev(wl["grid"]), fn.dev(wl["obs"])
+    cache = autotune.Cache(str(tmp_path / "e.json"))
+    ch, times = autotune.tune_edge(ctx, tree, ld, n, cand, idx, grid, sh.samples, obs,
+                                   reps=1, cache=cache)
+    assert ch.edge_form in (1, 2) and set(times) == {"edge_form 1", "edge_form 2"}
+    assert ctx.edge_form == ch.edge_form
+    ch2, times2 = autotune.tune_edge(ctx, tree, ld, n, cand, idx, grid, sh.samples, obs,
+                                     cache=autotune.Cache(str(tmp_path / "e.json")))
+    assert ch2 == ch and times2 == {}  # from the cache file
+    ctx.set_tuning(edge_form=0)
+
+
 def test_kernel_timing_events(iteration):
     sh, wl, ctx, tree, ld, n, cand = iteration
     idx, _ = ctx.plan_knn(tree, ld, n, cand, sh.k, want_d2=False)
