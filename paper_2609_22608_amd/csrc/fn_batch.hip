@@ -136,7 +136,11 @@ __global__ __launch_bounds__(64) void batch_knn_merge(const KnnProb* __restrict_
                                                       const int64_t* __restrict__ query_off,
                                                       const float* __restrict__ part_d,
                                                       const int32_t* __restrict__ part_i,
-                                                      const float* __restrict__ part_y, int k) {
+                                                      const float* __restrict__ part_y, int k,
+                                                      int32_t* __restrict__ q_count) {
+  // the FP64-stage queue of the round's search starts empty (cleared here,
+  // one launch before the search, instead of by a launch of its own)
+  if (blockIdx.x == 0 && threadIdx.x == 0) *q_count = 0;
   const int64_t qg = blockIdx.x;
   if (qg >= query_off[n]) return;
   const int p = bsearch_off(query_off, n, qg);
@@ -900,7 +904,7 @@ static void launch_batch_knn(fn_ctx* c, fn_batch* bt, const KnnProb* tab, hipStr
     hipLaunchKernelGGL(batch_knn_scan<K1>, dim3((unsigned)((bt->pairs + 3) / 4)), dim3(256), 0, s,
                        tab, bt->n, bt->pair_off, c->knn_d, c->knn_i, c->knn_y);
   hipLaunchKernelGGL(batch_knn_merge<K1>, dim3((unsigned)bt->queries), dim3(64), 0, s, tab,
-                     bt->n, bt->query_off, c->knn_d, c->knn_i, c->knn_y, bt->k);
+                     bt->n, bt->query_off, c->knn_d, c->knn_i, c->knn_y, bt->k, c->q_count);
 }
 
 // model kernel (screening), search, FP64 stage over all problems
@@ -931,7 +935,7 @@ static int launch_round(fn_ctx* c, fn_batch* bt, int r, hipStream_t s) {
 #undef FN_K
     default: return fail(FN_E_SHAPE, "fn_batch_round: k");
   }
-  hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, s, c->q_count, 1);
+  // (the kNN merge has cleared the FP64-stage queue)
   if (bt->pattern == PAT_FR3) {
     if (bt->mode == FN_SEARCH_PLAIN) launch_batch_search<PAT_FR3, FN_SEARCH_PLAIN>(c, bt, et, s);
     else launch_batch_search<PAT_FR3, FN_SEARCH_SCREEN>(c, bt, et, s);
