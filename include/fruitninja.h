@@ -558,7 +558,8 @@ typedef struct {
 
 /* Uploads the problem tables (synchronous).  Sizes and pointers stay fixed
  * until the next prepare; tree contents and node counts are read on the
- * device at every launch.  FN_E_SHAPE beyond max_problems / max_edges /
+ * device at every launch.  A graph captured before is discarded (capture
+ * again after a prepare).  FN_E_SHAPE beyond max_problems / max_edges /
  * max_batch (sum of B). */
 int fn_batch_prepare(fn_ctx* ctx, const fn_problem_set* ps);
 /* Enqueues one iteration for the prepared problems: 5 kernels for kNN, the

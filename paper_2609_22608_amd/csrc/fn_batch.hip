@@ -872,6 +872,9 @@ extern "C" int fn_batch_prepare(fn_ctx* c, const fn_problem_set* ps) {
   if (e == hipSuccess) e = hipMemcpy(bt->chunk_off, co.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "fn_batch_prepare: upload");
   bt->chunks = co[n];
+  // a graph captured before holds the previous launch geometry
+  if (bt->exec) { (void)hipGraphExecDestroy(bt->exec); bt->exec = nullptr; }
+  if (bt->graph) { (void)hipGraphDestroy(bt->graph); bt->graph = nullptr; }
   bt->n = n;
   bt->K1 = K1;
   bt->k = ps->k;

@@ -109,7 +109,20 @@ def test_tuning_and_problem_set_are_validated(iteration):
         bt.launch()
     with pytest.raises(fn.FnError, match="nothing captured"):
         bt.replay()
-    for wl2 in probs + probs:  # four problems, cap two
+    for wl2 in probs:
+        bt.add_problem(wl2["tree_x"], wl2["tree_t"], wl2["cand"], wl2["obs"],
+                       capacity=wl2["shape"].n_nodes + 64)
+    bt.prepare()
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    bt.capture(s)
+    bt.replay()
+    torch.cuda.synchronize()
+    # a prepare discards the captured graph (it holds the old launch geometry)
+    bt.prepare()
+    with pytest.raises(fn.FnError, match="nothing captured"):
+        bt.replay()
+    for wl2 in probs:  # four problems, cap two
         bt.add_problem(wl2["tree_x"], wl2["tree_t"], wl2["cand"], wl2["obs"],
                        capacity=wl2["shape"].n_nodes + 64)
     with pytest.raises(fn.FnError, match="problems"):
