@@ -403,7 +403,10 @@ __global__ __launch_bounds__(INS_THREADS) void batch_insert_kernel(const InsProb
 // most t_best; node 0 (the measured state), the incumbent and every ancestor
 // of a kept node stay too.  Kept nodes are compacted in their order and
 // parents renumbered.  Grid: (node blocks of 256, problems); node counts are
-// read on the device.
+// read on the device.  Five launches: marks (reach time, keep rule, ancestor
+// walks), block counts, new indices (each block sums the counts before it),
+// gather into scratch rows, commit (which also clears the ancestor marks for
+// the next Prune).
 // ---------------------------------------------------------------------------
 constexpr int PRUNE_THREADS = 256;
 constexpr int PRUNE_COLS = FN_STATE + 3;  // state, t, nu, parent (as bits)
@@ -477,12 +480,6 @@ __global__ __launch_bounds__(256) void reach_kernel(const float* __restrict__ tr
   out[i] = node_reach<PAT>(*Ap, *Dp, tree, ld, i, t_node[i], flight, pr, __builtin_nanf(""), &T64);
 }
 
-__global__ __launch_bounds__(PRUNE_THREADS) void prune_clear(const PruneProb* __restrict__ P,
-                                                             PruneScratch sc) {
-  const PruneProb q = P[blockIdx.y];
-  const int64_t n = (int64_t)blockIdx.x * PRUNE_THREADS + threadIdx.x;
-  if (n < q.ld) sc.walked[q.off + n] = 0;
-}
 
 // keep0 of every node; a kept node then marks its ancestors: the first
 // walker to claim a node (atomic exchange) goes on above it, every other one
@@ -540,45 +537,49 @@ __global__ __launch_bounds__(PRUNE_THREADS) void prune_count(const PruneProb* __
   if (threadIdx.x == 0) sc.blk[q.blk_off + blockIdx.x] = count;
 }
 
-// Exclusive scan of one problem's block counts (one workgroup per problem).
-__global__ __launch_bounds__(PRUNE_THREADS) void prune_scan(const PruneProb* __restrict__ P,
-                                                            PruneScratch sc) {
-  __shared__ int s_v[PRUNE_THREADS];
-  const PruneProb q = P[blockIdx.x];
-  const int nb = (int)((q.ld + PRUNE_THREADS - 1) / PRUNE_THREADS);
-  const int tid = threadIdx.x;
-  int running = 0;
-  for (int base = 0; base < nb; base += PRUNE_THREADS) {
-    const int i = base + tid;
-    const int v = i < nb ? sc.blk[q.blk_off + i] : 0;
-    s_v[tid] = v;
-    __syncthreads();
-    for (int o = 1; o < PRUNE_THREADS; o <<= 1) {
-      const int t = tid >= o ? s_v[tid - o] : 0;
-      __syncthreads();
-      s_v[tid] += t;
-      __syncthreads();
-    }
-    if (i < nb) sc.blk[q.blk_off + i] = running + s_v[tid] - v;
-    running += s_v[PRUNE_THREADS - 1];
-    __syncthreads();
-  }
-  if (tid == 0) {
-    sc.meta[2 * blockIdx.x] = *q.n_nodes;
-    sc.meta[2 * blockIdx.x + 1] = running;
-  }
+// Sum of v over the workgroup (every thread gets it).
+__device__ __forceinline__ int block_sum(int v, int* s_w) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  __syncthreads();
+  if (lane == 0) s_w[w] = v;
+  __syncthreads();
+  int t = 0;
+#pragma unroll
+  for (int i = 0; i < PRUNE_THREADS / 64; ++i) t += s_w[i];
+  return t;
 }
 
+// Kept node n -> its new index: the kept nodes of the blocks before this
+// one (summed here from the block counts, a few hundred at most) plus its
+// rank in the block.  Block 0 records the node count before and after.
 __global__ __launch_bounds__(PRUNE_THREADS) void prune_map(const PruneProb* __restrict__ P,
                                                            PruneScratch sc) {
   __shared__ int s_w[PRUNE_THREADS / 64];
   const PruneProb q = P[blockIdx.y];
   if ((int64_t)blockIdx.x * PRUNE_THREADS >= q.ld) return;
-  const int64_t n = (int64_t)blockIdx.x * PRUNE_THREADS + threadIdx.x;
-  const bool k = prune_kept(q, sc, n, sc.meta[2 * blockIdx.y]);
+  const int tid = threadIdx.x;
+  const int nb = (int)((q.ld + PRUNE_THREADS - 1) / PRUNE_THREADS);
+  const int N0 = *q.n_nodes;
+  int part = 0;
+  for (int i = tid; i < (int)blockIdx.x; i += PRUNE_THREADS) part += sc.blk[q.blk_off + i];
+  const int before = block_sum(part, s_w);
+  if (blockIdx.x == 0) {
+    int tot = 0;
+    for (int i = tid; i < nb; i += PRUNE_THREADS) tot += sc.blk[q.blk_off + i];
+    tot = block_sum(tot, s_w);
+    if (tid == 0) {
+      sc.meta[2 * blockIdx.y] = N0;
+      sc.meta[2 * blockIdx.y + 1] = tot;
+    }
+  }
+  const int64_t n = (int64_t)blockIdx.x * PRUNE_THREADS + tid;
+  const bool k = prune_kept(q, sc, n, N0);
+  __syncthreads();
   int count;
   const int r = block_rank(k, s_w, &count);
-  if (n < q.ld) sc.map[q.off + n] = k ? sc.blk[q.blk_off + blockIdx.x] + r : -1;
+  if (n < q.ld) sc.map[q.off + n] = k ? before + r : -1;
 }
 
 // Kept node n -> its new row in the scratch columns (parent renumbered).
@@ -615,6 +616,8 @@ __global__ __launch_bounds__(PRUNE_THREADS) void prune_commit(const PruneProb* _
   } else if (i < N) {
     q.parent[i] = -1;
   }
+  // the ancestor marks start the next Prune cleared
+  if (i < q.ld) sc.walked[q.off + i] = 0;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     *q.n_nodes = M;
     const int in = (int)q.inc[1];
@@ -866,6 +869,8 @@ extern "C" int fn_batch_prepare(fn_ctx* c, const fn_problem_set* ps) {
   if (e == hipSuccess) e = hipMemcpy(bt->ins, ir.data(), sizeof(InsProb) * ir.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(bt->args, er.data(), sizeof(EdgeArgs) * er.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(bt->prune, pp.data(), sizeof(PruneProb) * n, hipMemcpyHostToDevice);
+  // Prune's ancestor marks start cleared; every Prune's commit clears them again
+  if (e == hipSuccess && loop) e = hipMemset(bt->psc.walked, 0, sizeof(int32_t) * nodes);
   if (e == hipSuccess) e = hipMemcpy(bt->pair_off, po.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(bt->query_off, qo.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(bt->edge_off, eo.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice);
@@ -959,13 +964,12 @@ static bool prune_args_ok(const fn_prune* pr) {
 
 static int launch_prune(fn_ctx* c, fn_batch* bt, const fn_prune& pr, hipStream_t s) {
   const dim3 g((unsigned)bt->max_blocks, (unsigned)bt->n);
-  hipLaunchKernelGGL(prune_clear, g, dim3(PRUNE_THREADS), 0, s, bt->prune, bt->psc);
+  // (the ancestor marks were cleared by the last Prune's commit, or at prepare)
   if (c->pattern == PAT_FR3)
     hipLaunchKernelGGL(prune_mark<PAT_FR3>, g, dim3(PRUNE_THREADS), 0, s, bt->prune, bt->psc, pr, c->arm32, c->arm64);
   else
     hipLaunchKernelGGL(prune_mark<PAT_GENERIC>, g, dim3(PRUNE_THREADS), 0, s, bt->prune, bt->psc, pr, c->arm32, c->arm64);
   hipLaunchKernelGGL(prune_count, g, dim3(PRUNE_THREADS), 0, s, bt->prune, bt->psc);
-  hipLaunchKernelGGL(prune_scan, dim3((unsigned)bt->n), dim3(PRUNE_THREADS), 0, s, bt->prune, bt->psc);
   hipLaunchKernelGGL(prune_map, g, dim3(PRUNE_THREADS), 0, s, bt->prune, bt->psc);
   hipLaunchKernelGGL(prune_gather, g, dim3(PRUNE_THREADS), 0, s, bt->prune, bt->psc);
   hipLaunchKernelGGL(prune_commit, g, dim3(PRUNE_THREADS), 0, s, bt->prune, bt->psc);
