@@ -95,9 +95,9 @@ def parse():
     p.add_argument("--no-tune", action="store_true", help="default launch mappings (no autotuning)")
     p.add_argument("--tune-cache", default=None,
                    help="JSON cache of tuned launch mappings (read and written)")
-    p.add_argument("--edge-form", type=int, default=0, choices=(0, 1, 2),
-                   help="screened searches: 0 library default, 1 one kernel, 2 triage + queued "
-                        "search (fn_tuning.edge_form)")
+    p.add_argument("--edge-form", type=int, default=0, choices=(0, 1, 2, 3),
+                   help="screened searches: 0 library default, 1 one kernel, 2 triage + search "
+                        "of the open edges, 3 the same longest-first (fn_tuning.edge_form)")
     return p.parse_args()
 
 
@@ -152,6 +152,10 @@ def main():
                                    mode=fn.SEARCH_SCREEN, reps=3,
                                    cache=autotune.Cache(args.tune_cache))
         edge_tuning = {"edge_form": ch.edge_form, "ms": ch.ms}
+    # the screened searches' form, always set explicitly so that the line
+    # names the kernels it timed (untuned: the ordered two-phase form)
+    edge_form = args.edge_form or (edge_tuning["edge_form"] if edge_tuning else 3)
+    ctx.set_tuning(edge_form=edge_form)
     surrogate_info = None
     net = None
     if "window" in wanted:
@@ -226,11 +230,12 @@ def main():
         flop = (work * F_EVAL + scr * F_SCREEN + n_post * F_JOINTS
                 + n_clear * f_clear(sh.samples, sh.n_obs, n_sph))
         f = dict(edges_per_s=E / (ms * 1e-3), ms_per_step=ms, edge_search_ms=e_ms,
-                 edge_time_kernel_ms=kern_ms, evaluations=work, screened_slots=scr,
+                 search_span_ms=kern_ms, evaluations=work, screened_slots=scr,
                  post_checked=n_post, clearance_checked=n_clear, kernel_gflop=flop / 1e9,
                  wall_s=wall,
                  fp32_tflops=flop / (kern_ms * 1e-3) / 1e12,
                  model_states=(E + sh.batch) if mode != fn.SEARCH_PLAIN else 0,
+                 edge_form=edge_form if mode != fn.SEARCH_PLAIN else 1,
                  recheck64=int(((st & fn.S_RECHECK64) > 0).sum()))
         if mode == fn.SEARCH_WINDOW:
             pre = float(np.mean([a[0].elapsed_time(a[2]) for a in edge_ms]))
@@ -266,11 +271,12 @@ def main():
         "forms": forms,
         "speedup": speed,
         "surrogate": surrogate_info,
-        "roofline": {"bound": "alu", "kernel": "edge_time_kernel",
-                     "form": best, "achieved": bf["fp32_tflops"], "peak": PEAK_FP32 / 1e12,
+        "roofline": {"bound": "alu", "kernel": EDGE_SPAN_KERNELS[bf["edge_form"]],
+                     "form": best, "edge_form": bf["edge_form"], "achieved": bf["fp32_tflops"],
+                     "peak": PEAK_FP32 / 1e12,
                      "unit": "TFLOP/s", "frac": bf["fp32_tflops"] * 1e12 / PEAK_FP32,
-                     "traffic": traffic_bytes("edge_time_kernel", best),
-                     "kernel_ms": bf["edge_time_kernel_ms"],
+                     "traffic": traffic_bytes("edge_search", f"{best}/{bf['edge_form']}"),
+                     "kernel_ms": bf["search_span_ms"],
                      "flop_per_launch": bf["kernel_gflop"] * 1e9,
                      "flop_model": {"eval": F_EVAL, "screened_slot": F_SCREEN,
                                     "post_checked_edge": F_JOINTS,
@@ -389,10 +395,22 @@ def other_rooflines(args, ctx, net, tree, ld, n, cand, idx, grid, sh, win, fn, t
     return res
 
 
+# Kernels between the library's timing events of one screened search, per
+# edge form (the endpoint models before and the FP64 stage after them are
+# outside the span)
+EDGE_SPAN_KERNELS = {
+    1: "edge_time_kernel",
+    2: "edge_triage_kernel + edge_search_open_kernel",
+    3: "edge_triage_kernel + tri_hist_kernel + tri_scatter_kernel + edge_search_open_kernel "
+       "(ordered)",
+}
+
+
 # Sources each counter record depends on: a stored traffic figure applies
 # only to the kernel code it was measured on.
 KERNEL_SOURCES = {
-    "edge_time_kernel": ("fn_internal.h", "fn_ctx.h", "fn_edge.h", "fn_edge.hip"),
+    # the kernels of the timed edge-search span (EDGE_SPAN_KERNELS)
+    "edge_search": ("fn_internal.h", "fn_ctx.h", "fn_edge.h", "fn_edge.hip"),
     "knn_scan": ("fn_internal.h", "fn_ctx.h", "fn_knn.h", "fn_knn.hip"),
     # the matrix-core form's record (stress shape): same sources
     "knn_scan_mfma": ("fn_internal.h", "fn_ctx.h", "fn_knn.h", "fn_knn.hip"),
@@ -481,7 +499,7 @@ def controller_stats(args, ctx, wl, fn, W, torch, n=1 << 20):
                          ("power", fn.C_POWER))}}
 
 
-def kernel_source_hash(kernel="edge_time_kernel"):
+def kernel_source_hash(kernel="edge_search"):
     """Hash of the code a kernel is built from (comments and blank lines
     dropped)."""
     import hashlib

@@ -470,7 +470,7 @@ int surrogate_window(fn_ctx* ctx, const fn_mlp* mlp, const float* tree, int64_t 
  * neighbours and distances.  Applies to later plan_knn calls and
  * fn_batch_prepare.  Errors: FN_E_ARG when knn_target_waves is outside
  * [0, 16384], knn_min_chunk is negative or not a multiple of 64, or
- * knn_form is not 0, 1, 2 or 3, edge_form is not 0, 1 or 2, or mlp_rows is
+ * knn_form is not 0, 1, 2 or 3, edge_form is not 0, 1, 2 or 3, or mlp_rows is
  * not 0, 32 or 64. */
 #define FN_KNN_LARGE_TREE 65536
 typedef struct {
@@ -480,7 +480,9 @@ typedef struct {
   int32_t edge_form;  /* screened and windowed searches of edge_time_batch: 1 one kernel (one
                        * wavefront per edge); 2 two phases (a triage of every edge by the
                        * endpoint screen, which finishes the edges it leaves no open slot on,
-                       * then the search of the others); 0 default: 2 from 2^18 edges, else 1.
+                       * then the search of the others); 3 two phases with the open edges
+                       * searched in descending order of their open-slot count (a counting
+                       * sort between the phases); 0 default: 3 from 2^15 edges, else 1.
                        * The results are the same. */
   int32_t mlp_rows;   /* rows per workgroup of the fused surrogate inference: 32 or 64; 0
                        * default (32 while 64 would leave fewer than four workgroups per

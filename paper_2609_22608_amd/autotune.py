@@ -6,9 +6,9 @@ trade between occupancy and the cost of merging partial lists, and the best
 point moves with the tree size, the batch size and (for a batched round) the
 number of problems.  The edge search has two exact modes (plain ascending
 scan and endpoint-screened scan) whose ratio moves with the workload's
-feasibility mix, and the screened modes two exact forms (one kernel, or a
-triage kernel before the search of the open edges) whose ratio moves with
-the number of edges.  This module times the candidates on the device with HIP
+feasibility mix, and the screened modes three exact forms (one kernel; a
+triage kernel before the search of the open edges; the same with the open
+edges sorted longest-first) whose ratio moves with the number of edges.  This module times the candidates on the device with HIP
 events on the launching stream, keeps the fastest, and caches the choice
 per shape in a JSON file so later runs skip the search.
 
@@ -36,6 +36,9 @@ KNN_CANDIDATES_MFMA = ((512, 512), (1024, 512), (2048, 512), (2048, 1024), (4096
 # kNN scan forms: 1 = VALU keys, per-wavefront node loads; 2 = VALU keys,
 # workgroup node tiles in LDS; 3 = matrix-core keys
 KNN_FORMS = (1, 2, 3)
+# edge forms of the screened searches: 1 = one kernel; 2 = triage, then the
+# search of the open edges; 3 = the same, open edges longest-first
+EDGE_FORMS = (1, 2, 3)
 
 
 def knn_grid(candidates=None):
@@ -137,10 +140,11 @@ def tune_knn(ctx: fn.Context, tree, ld, n_nodes, cand, k, reps=5, cache: Cache |
 
 def tune_edge(ctx: fn.Context, tree, ld, n_nodes, cand, nbr, grid, samples, obs=None,
               mode=fn.SEARCH_SCREEN, reps=5, cache: Cache | None = None, win_lo=None, win_half=4):
-    """Faster edge form of edge_time_batch for one shape and search mode: 1
-    (one kernel, a wavefront per edge) or 2 (the triage of every edge, then
-    the search of the open ones); both give identical results.  Leaves it set
-    on ctx (the kNN mapping is kept)."""
+    """Fastest edge form of edge_time_batch for one shape and search mode: 1
+    (one kernel, a wavefront per edge), 2 (the triage of every edge, then the
+    search of the open ones) or 3 (as 2, the open edges in descending order
+    of their open-slot count); all give identical results.  Leaves it set on
+    ctx (the kNN mapping is kept)."""
     B, k = nbr.shape
     n_obs = 0 if obs is None else int(obs.shape[0])
     key = (f"edge|n{n_nodes}|B{B}|k{k}|nt{grid.shape[0]}|S{samples}|o{n_obs}|m{mode}|"
@@ -157,7 +161,7 @@ def tune_edge(ctx: fn.Context, tree, ld, n_nodes, cand, nbr, grid, samples, obs=
                screened=None)
     kw = dict(win_lo=win_lo, win_half=win_half) if mode == fn.SEARCH_WINDOW else {}
     times = {}
-    for form in (1, 2):
+    for form in EDGE_FORMS:
         ctx.set_tuning(edge_form=form)
         times[form] = _time(lambda: ctx.edge_time_batch(tree, ld, n_nodes, cand, nbr, grid,
                                                         samples, obs, mode=mode, out=out, **kw),

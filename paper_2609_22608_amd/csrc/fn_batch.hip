@@ -1105,7 +1105,7 @@ extern "C" int fn_set_tuning(fn_ctx* c, const fn_tuning* t) {
   if (!c || !t) return fail(FN_E_ARG, "fn_set_tuning: NULL argument");
   if (t->knn_target_waves < 0 || t->knn_target_waves > KNN_TARGET_MAX || t->knn_min_chunk < 0 ||
       (t->knn_min_chunk & 63) != 0 || t->knn_form < 0 || t->knn_form > 3 || t->edge_form < 0 ||
-      t->edge_form > 2 || (t->mlp_rows != 0 && t->mlp_rows != 32 && t->mlp_rows != 64 &&
+      t->edge_form > 3 || (t->mlp_rows != 0 && t->mlp_rows != 32 && t->mlp_rows != 64 &&
                               t->mlp_rows != 128 && t->mlp_rows != 256))
     return fail(FN_E_ARG, "fn_set_tuning: target waves in [0, %d], min chunk >= 0 and a multiple of 64, kNN form 0..3, edge form 0..2, MLP rows 0, 32, 64, 128 or 256", KNN_TARGET_MAX);
   c->tune = *t;

@@ -199,7 +199,7 @@ extern "C" int fn_create(const fn_arm_desc* arm, const fn_caps* caps, fn_ctx** o
   FN_ALLOC(c->queue, (size_t)(caps->max_edges > 0 ? caps->max_edges : 1) * sizeof(QEntry));
   FN_ALLOC(c->model_e, (size_t)caps->max_edges * MODEL_FLOATS * sizeof(float));
   FN_ALLOC(c->model_c, (size_t)caps->max_batch * MODEL_FLOATS * sizeof(float));
-  FN_ALLOC(c->tri_items, (size_t)(caps->max_edges > 0 ? caps->max_edges : 1) * sizeof(int32_t));
+  FN_ALLOC(c->tri_items, tri_ints(caps->max_edges > 0 ? caps->max_edges : 1) * sizeof(int32_t));
   FN_ALLOC(c->self_pairs, (size_t)2 * FN_MAX_SELF_PAIRS * sizeof(int16_t));
 #undef FN_ALLOC
   {

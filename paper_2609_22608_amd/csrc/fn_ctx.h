@@ -39,6 +39,22 @@ struct QEntry {
 };
 static_assert(sizeof(QEntry) == 96, "queue entry layout");
 
+// Ordered two-phase search (form 3): between the triage and the search, a
+// counting sort puts the open edges in descending order of their open-slot
+// count (TRI_BINS equal ranges over 1..n_t), so that the longest searches
+// start first and the short ones fill in behind them instead of a few long
+// ones starting last.  The sort runs over at most TRI_MAX_BLOCKS blocks of
+// at least TRI_MIN_CHUNK edges each.
+constexpr int TRI_BINS = 64;
+constexpr int TRI_MAX_BLOCKS = 256;
+constexpr int64_t TRI_MIN_CHUNK = 1024;
+// ints of the two-phase scratch for max_edges edges: the open-slot counts
+// [max_edges], the order [max_edges], the per-block bin counts
+// [TRI_MAX_BLOCKS][TRI_BINS] and the open-edge count (64 ints)
+__host__ __device__ constexpr size_t tri_ints(int64_t max_edges) {
+  return 2 * (size_t)max_edges + (size_t)TRI_MAX_BLOCKS * TRI_BINS + 64;
+}
+
 // Scratch of one edge search: the FP64-stage counter (first int32; the
 // search's first kernel clears it) and queue (one entry per edge), the
 // endpoint models of every edge's parent and of every candidate.
@@ -47,7 +63,7 @@ struct EdgeScratch {
   QEntry* queue;
   float* model_e;
   float* model_c;
-  int32_t* tri_items;  // [max edges]: open-slot counts of the two-phase search
+  int32_t* tri_items;  // [tri_ints(max edges)]: the two-phase search's counts, order, bins
 };
 
 int fail(int code, const char* fmt, ...);

@@ -74,8 +74,12 @@ struct EdgeArgs {
   // t(parent) + T <= *t_best; NULL: no bound
   const float* __restrict__ t_best;
   // two-phase screened search: each edge's number of open slots after the
-  // triage (-1: finished by the triage)
+  // triage (-1: finished by the triage); the ordered form's edge order and
+  // per-block bin counts, the open-edge count at tri_hist[TRI_MAX_BLOCKS *
+  // TRI_BINS]
   int32_t* tri_items;
+  int32_t* tri_order;
+  int32_t* tri_hist;
 };
 
 // ---------------------------------------------------------------------------
@@ -85,7 +89,9 @@ struct EdgeArgs {
 // them); the search then runs on the other edges only.  About half of the
 // one-iteration shape's edges end at the triage.
 // ---------------------------------------------------------------------------
-constexpr int64_t TRIAGE_MIN_EDGES = 1 << 18;  // default form 2 from this many edges
+// default form 3 from this many edges (measured faster than forms 1 and 2 at
+// 32,768 and 1,048,576 edges), form 1 below
+constexpr int64_t TRIAGE_MIN_EDGES = 1 << 15;
 __device__ __forceinline__ int nodes_of(const EdgeArgs& a) {
   return a.n_nodes_dev ? *a.n_nodes_dev : a.n_nodes;
 }

@@ -67,10 +67,76 @@ __global__ __launch_bounds__(256) void edge_triage_kernel(EdgeArgs a,
   triage_edge<PAT, MODE>(a, e, *Ap, s_T, s_mod[wave], s_x[wave]);
 }
 
+// Ordered two-phase search (form 3), between the triage and the search: a
+// counting sort of the open edges, heaviest bin first.  Bin of an open-slot
+// count (1..n_t): TRI_BINS equal ranges.
+__device__ __forceinline__ int tri_bin(int open, int n_t) {
+  return min((open - 1) * TRI_BINS / n_t, TRI_BINS - 1);
+}
+
+// Bin counts of the open edges of each block's chunk of edges (an LDS
+// histogram; no global atomics).
+__global__ __launch_bounds__(256) void tri_hist_kernel(const int32_t* __restrict__ items,
+                                                       int64_t E, int64_t chunk, int n_t,
+                                                       int32_t* __restrict__ hist) {
+  __shared__ int h[TRI_BINS];
+  if (threadIdx.x < TRI_BINS) h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min(E, lo + chunk);
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    const int v = items[i];
+    if (v > 0) atomicAdd(&h[tri_bin(v, n_t)], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x < TRI_BINS) hist[(size_t)blockIdx.x * TRI_BINS + threadIdx.x] = h[threadIdx.x];
+}
+
+// Places of each block's open edges: an edge of bin b goes after every edge
+// of the heavier bins and of bin b in the earlier blocks (each block sums
+// the bin counts itself; within a block and bin the places are taken by LDS
+// atomics in no fixed order, which changes no result).  Block 0 writes the
+// number of open edges to *n_open.
+__global__ __launch_bounds__(256) void tri_scatter_kernel(const int32_t* __restrict__ items,
+                                                          int64_t E, int64_t chunk, int n_t,
+                                                          const int32_t* __restrict__ hist,
+                                                          int nblk, int32_t* __restrict__ order,
+                                                          int32_t* __restrict__ n_open) {
+  static_assert(TRI_BINS == 64, "one bin per lane of the first wavefront");
+  __shared__ int s_tot[4][TRI_BINS], s_bef[4][TRI_BINS];
+  __shared__ int s_cur[TRI_BINS];
+  const int t = threadIdx.x, bin = t & (TRI_BINS - 1), part = t >> 6;
+  int tot = 0, bef = 0;
+  for (int j = part; j < nblk; j += 4) {
+    const int v = hist[(size_t)j * TRI_BINS + bin];
+    tot += v;
+    if (j < (int)blockIdx.x) bef += v;
+  }
+  s_tot[part][bin] = tot;
+  s_bef[part][bin] = bef;
+  __syncthreads();
+  if (t < TRI_BINS) {
+    int above = 0, all = 0;
+    for (int c = 0; c < TRI_BINS; ++c) {
+      const int n = s_tot[0][c] + s_tot[1][c] + s_tot[2][c] + s_tot[3][c];
+      all += n;
+      if (c > bin) above += n;
+    }
+    s_cur[bin] = above + s_bef[0][bin] + s_bef[1][bin] + s_bef[2][bin] + s_bef[3][bin];
+    if (blockIdx.x == 0 && t == 0) *n_open = all;
+  }
+  __syncthreads();
+  const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min(E, lo + chunk);
+  for (int64_t i = lo + t; i < hi; i += blockDim.x) {
+    const int v = items[i];
+    if (v > 0) order[atomicAdd(&s_cur[tri_bin(v, n_t)], 1)] = (int32_t)i;
+  }
+}
+
 // Two-phase screened search, phase 2: the search of the edges the triage
-// left open, in the one-kernel grid's order; wavefronts of finished edges
-// end at once.
-template <int PAT, int MODE>
+// left open; ORDERED: workgroup w takes the w-th edge of the sorted order
+// (form 3), else the one-kernel grid's order, where wavefronts of finished
+// edges end at once (form 2).
+template <int PAT, int MODE, bool ORDERED>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void
 edge_search_open_kernel(EdgeArgs a, const ArmConst<float>* __restrict__ Ap) {
   __shared__ float s_end[FN_MAX_NT];
@@ -79,8 +145,15 @@ edge_search_open_kernel(EdgeArgs a, const ArmConst<float>* __restrict__ Ap) {
   __shared__ float s_mod[2 * MODEL_FLOATS];
   __shared__ GeoLDS<float> s_geo;
   extern __shared__ float s_tab[];  // nsph * (n_obs + n_caps) floats
-  const int64_t e = xcd_edge(blockIdx.x, a.k, a.E / a.k);
-  if (e < 0 || __builtin_amdgcn_readfirstlane(a.tri_items[e]) < 0) return;
+  int64_t e;
+  if constexpr (ORDERED) {
+    const int n_open = __builtin_amdgcn_readfirstlane(a.tri_hist[TRI_MAX_BLOCKS * TRI_BINS]);
+    if ((int64_t)blockIdx.x >= n_open) return;
+    e = __builtin_amdgcn_readfirstlane(a.tri_order[blockIdx.x]);
+  } else {
+    e = xcd_edge(blockIdx.x, a.k, a.E / a.k);
+    if (e < 0 || __builtin_amdgcn_readfirstlane(a.tri_items[e]) < 0) return;
+  }
   for (int t = threadIdx.x; t < a.n_t; t += blockDim.x) s_T[t] = a.grid[t];
   __syncthreads();
   search_edge<PAT, MODE, false>(a, e, e, *Ap, s_end, s_T, s_fix, s_mod, &s_geo, s_tab);
@@ -343,14 +416,26 @@ static void launch_search(fn_ctx* c, const EdgeArgs& a, int ti, hipStream_t s) {
     hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, s, a.q_count, 1);
   if (ti >= 0) (void)hipEventRecord(c->tev[2 * ti], s);
   const size_t tab = (size_t)EDGE_WAVES * c->desc.n_spheres * (a.n_obs + a.n_caps) * sizeof(float);
-  // two phases when asked for, or by default for large searches (measured
-  // faster from about 10^6 edges, equal at 3 x 10^4)
-  const int form = c->tune.edge_form > 0 ? c->tune.edge_form : (E >= TRIAGE_MIN_EDGES ? 2 : 1);
-  if (MODE != FN_SEARCH_PLAIN && form == 2) {
+  // two phases when asked for, or by default (ordered) for large searches
+  int form = c->tune.edge_form > 0 ? c->tune.edge_form : (E >= TRIAGE_MIN_EDGES ? 3 : 1);
+  if (form == 3 && E > INT32_MAX) form = 2;  // the order holds int32 edge ids
+  if (MODE != FN_SEARCH_PLAIN && form >= 2) {
     hipLaunchKernelGGL((edge_triage_kernel<PAT, MODE>), dim3((unsigned)((E + 3) / 4)), dim3(256),
                        0, s, a, c->arm32);
-    hipLaunchKernelGGL((edge_search_open_kernel<PAT, MODE>), dim3((unsigned)xcd_grid(B, a.k)),
-                       dim3(64), tab, s, a, c->arm32);
+    if (form == 3) {
+      const int64_t chunk = std::max(TRI_MIN_CHUNK, (E + TRI_MAX_BLOCKS - 1) / TRI_MAX_BLOCKS);
+      const int nblk = (int)((E + chunk - 1) / chunk);
+      int32_t* n_open = a.tri_hist + TRI_MAX_BLOCKS * TRI_BINS;
+      hipLaunchKernelGGL(tri_hist_kernel, dim3(nblk), dim3(256), 0, s, a.tri_items, E, chunk,
+                         a.n_t, a.tri_hist);
+      hipLaunchKernelGGL(tri_scatter_kernel, dim3(nblk), dim3(256), 0, s, a.tri_items, E, chunk,
+                         a.n_t, a.tri_hist, nblk, a.tri_order, n_open);
+      hipLaunchKernelGGL((edge_search_open_kernel<PAT, MODE, true>), dim3((unsigned)E), dim3(64),
+                         tab, s, a, c->arm32);
+    } else {
+      hipLaunchKernelGGL((edge_search_open_kernel<PAT, MODE, false>),
+                         dim3((unsigned)xcd_grid(B, a.k)), dim3(64), tab, s, a, c->arm32);
+    }
   } else {
     hipLaunchKernelGGL((edge_time_kernel<PAT, MODE>), dim3((unsigned)xcd_grid(B, a.k)),
                        dim3(64 * EDGE_WAVES), tab, s, a, c->arm32);
@@ -427,6 +512,8 @@ int edge_time_run(fn_ctx* c, const float* tree, int64_t ld, int32_t n_nodes, con
   a.out_work = out->work; a.out_scr = out->screened;
   a.q_count = sc.q_count; a.queue = sc.queue; a.model_e = sc.model_e; a.model_c = sc.model_c;
   a.tri_items = sc.tri_items;
+  a.tri_order = sc.tri_items + max_edges;
+  a.tri_hist = sc.tri_items + 2 * max_edges;
   hipStream_t s = (hipStream_t)stream;
   const int ti = timed && c->timing && c->n_timed < FN_MAX_TIMED ? c->n_timed++ : -1;
   if (c->pattern == PAT_FR3) launch_search_mode<PAT_FR3>(c, a, ti, s);

@@ -5,8 +5,10 @@
 // The array holds, for at most FN_NOALLOC_MAX_EDGES edges: the FP64-stage
 // counter (256 bytes), its queue (one 96-byte entry per edge), the
 // endpoint models of every edge's parent and of every candidate (56 floats
-// each) and the two-phase search's open-slot counts (4 bytes per edge).  Each device holds its own copy for the life of the process; its
-// address is taken once per device with hipGetSymbolAddress (at fn_create,
+// each) and the two-phase search's open-slot counts and edge order (8 bytes
+// per edge, and 64 KiB of bin counts).  Each device holds its own copy for
+// the life of the process; its address is taken once per device with
+// hipGetSymbolAddress (at fn_create,
 // or at the first call on a device), and only that address is used on the
 // host.  Every call on one device shares the array: calls that overlap in
 // time on one device (other streams, other threads) race.  The counter is
@@ -23,7 +25,7 @@ namespace {
 constexpr size_t kCounterBytes = 256;
 constexpr size_t kQueueBytes = (size_t)FN_NOALLOC_MAX_EDGES * sizeof(fn::QEntry);
 constexpr size_t kModelBytes = (size_t)FN_NOALLOC_MAX_EDGES * fn::MODEL_FLOATS * sizeof(float);
-constexpr size_t kTriageBytes = (size_t)FN_NOALLOC_MAX_EDGES * sizeof(int32_t);
+constexpr size_t kTriageBytes = fn::tri_ints(FN_NOALLOC_MAX_EDGES) * sizeof(int32_t);
 constexpr size_t kScratchBytes = kCounterBytes + kQueueBytes + 2 * kModelBytes + kTriageBytes;
 static_assert(kQueueBytes % 256 == 0 && kModelBytes % 256 == 0 && kTriageBytes % 256 == 0,
               "256-byte aligned parts");

@@ -295,17 +295,19 @@ class Context:
         _check(lib().fn_kernel_times(self.h, buf, max_n, C.byref(n)), "fn_kernel_times")
         return [buf[i] for i in range(n.value)]
 
-    def set_tuning(self, knn_target_waves=0, knn_min_chunk=0, knn_form=0, edge_form=None,
-                   mlp_rows=None):
-        """Launch mappings (fn_set_tuning); edge_form / mlp_rows None keep the
-        current ones."""
-        ef = getattr(self, "edge_form", 0) if edge_form is None else int(edge_form)
-        mr = getattr(self, "mlp_rows", 0) if mlp_rows is None else int(mlp_rows)
-        t = Tuning(int(knn_target_waves), int(knn_min_chunk), int(knn_form), ef, mr)
+    def set_tuning(self, knn_target_waves=None, knn_min_chunk=None, knn_form=None,
+                   edge_form=None, mlp_rows=None):
+        """Launch mappings (fn_set_tuning); a field left None keeps its current
+        value (0, the library default, before the first call)."""
+        cur = getattr(self, "_tuning", (0, 0, 0, 0, 0))
+        new = tuple(c if v is None else int(v) for c, v in
+                    zip(cur, (knn_target_waves, knn_min_chunk, knn_form, edge_form, mlp_rows)))
+        t = Tuning(*new)
         _check(lib().fn_set_tuning(self.h, C.byref(t)), "fn_set_tuning")
-        self.tuned_knn_form = int(knn_form)
-        self.edge_form = ef
-        self.mlp_rows = mr
+        self._tuning = new
+        self.tuned_knn_form = new[2]
+        self.edge_form = new[3]
+        self.mlp_rows = new[4]
 
     # -- plan_knn -----------------------------------------------------------
     def plan_knn(self, tree, ld, n_nodes, queries, k, out_idx=None, out_d2=None, want_d2=True):

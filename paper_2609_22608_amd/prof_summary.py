@@ -3,11 +3,12 @@
     # per-kernel durations from --kernel-trace --stats (csv output)
     python -m paper_2609_22608_amd.prof_summary durations DIR --title "..." --command "..."
 
-    # HBM traffic of one kernel from two --pmc runs (FETCH_SIZE, WRITE_SIZE),
-    # calibrated by the 256 MiB device copy that `bench.py --profile` runs
+    # HBM traffic of one kernel (or of the kernels of one timed span, summed)
+    # from two --pmc runs (FETCH_SIZE, WRITE_SIZE), calibrated by the 256 MiB
+    # device copy that `bench.py --profile` runs
     python -m paper_2609_22608_amd.prof_summary traffic FETCH_DIR WRITE_DIR \\
-        --kernel "edge_time_kernel<5720, 1>" --form screen --command "..." \\
-        --json profiles/traffic.json
+        --kernel "edge_triage_kernel<5720, 1>" --kernel "tri_hist_kernel" ... \\
+        --key edge_search --form screen/3 --command "..." --json profiles/traffic.json
     python -m paper_2609_22608_amd.prof_summary traffic FETCH_DIR WRITE_DIR \\
         --kernel "knn_scan<12, 4>" --key knn_scan --form 1 --json profiles/traffic.json
 
@@ -89,29 +90,38 @@ def traffic(args):
     kib = COPY_BYTES / 1024
     f_scale = f_cal / kib  # counter KiB per KiB moved
     w_scale = w_cal / kib
-    key = short(args.kernel, 200)
-    if key not in fetch or key not in write:
-        raise SystemExit(f"{key} not found; kernels: {sorted(fetch)}")
-    fk = statistics.mean(fetch[key])
-    wk = statistics.mean(write[key])
-    fb = fk / f_scale * 1024
-    wb = wk / w_scale * 1024
     print(f"calibration copy (grid {grid}): FETCH_SIZE {f_cal:.0f} KiB, WRITE_SIZE {w_cal:.0f} KiB "
           f"for {kib:.0f} KiB moved each way -> scale 1/{f_scale:.3f}, 1/{w_scale:.3f}")
-    print(f"{key}: FETCH_SIZE {fk:.0f} KiB, WRITE_SIZE {wk:.0f} KiB per dispatch "
-          f"-> {fb / 1e6:.3f} MB read + {wb / 1e6:.3f} MB written = {(fb + wb) / 1e6:.3f} MB")
+    # the kernels of one timed span each run once per span: their means add
+    fk = wk = 0.0
+    counts = []
+    for kname in args.kernel:
+        key = short(kname, 200)
+        if key not in fetch or key not in write:
+            raise SystemExit(f"{key} not found; kernels: {sorted(fetch)}")
+        f1, w1 = statistics.mean(fetch[key]), statistics.mean(write[key])
+        print(f"{key}: FETCH_SIZE {f1:.0f} KiB, WRITE_SIZE {w1:.0f} KiB per dispatch "
+              f"({len(fetch[key])}, {len(write[key])} dispatches)")
+        fk += f1
+        wk += w1
+        counts.append([len(fetch[key]), len(write[key])])
+    fb = fk / f_scale * 1024
+    wb = wk / w_scale * 1024
+    print(f"per launch: {fb / 1e6:.3f} MB read + {wb / 1e6:.3f} MB written = "
+          f"{(fb + wb) / 1e6:.3f} MB")
     if args.json:
         sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
         from bench import kernel_source_hash
 
-        base = args.key or args.kernel.split("<")[0]
+        base = args.key or args.kernel[0].split("<")[0]
         data = {}
         if os.path.exists(args.json):
             data = json.load(open(args.json))
-        data[base] = dict(kernel=args.kernel, form=args.form, source_hash=kernel_source_hash(base),
-                          fetch_kib=fk, write_kib=wk, fetch_scale=f_scale, write_scale=w_scale,
-                          bytes_per_launch=fb + wb, command=args.command,
-                          dispatches=[len(fetch[key]), len(write[key])], grid=args.grid)
+        data[base] = dict(kernel=" + ".join(args.kernel), form=args.form,
+                          source_hash=kernel_source_hash(base), fetch_kib=fk, write_kib=wk,
+                          fetch_scale=f_scale, write_scale=w_scale, bytes_per_launch=fb + wb,
+                          command=args.command,
+                          dispatches=counts[0] if len(counts) == 1 else counts, grid=args.grid)
         with open(args.json, "w") as f:
             json.dump(data, f, indent=1, sort_keys=True)
 
@@ -127,7 +137,8 @@ def main():
     t = sub.add_parser("traffic")
     t.add_argument("fetch")
     t.add_argument("write")
-    t.add_argument("--kernel", required=True)
+    t.add_argument("--kernel", required=True, action="append",
+                   help="kernel name; repeated: the kernels of one timed span, summed")
     t.add_argument("--form", required=True)
     t.add_argument("--grid", type=int, default=None,
                    help="only dispatches of this grid size (work-items), e.g. the tuned mapping")

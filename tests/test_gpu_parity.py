@@ -306,10 +306,11 @@ def test_modes_agree_full_iteration(iteration):
 @pytest.mark.parametrize("mode", [fn.SEARCH_SCREEN, fn.SEARCH_WINDOW])
 def test_two_phase_search_equals_one_kernel(iteration, mode):
     """edge_form 2 (a triage of every edge by the endpoint screen, then the
-    edges with open slots on persistent wavefronts, most open slots first)
-    writes exactly what edge_form 1 (one wavefront per edge) writes, on every
-    edge of the one-iteration batch with its obstacle spheres and 3 capsules,
-    and through the entry point that allocates nothing."""
+    search of the edges it leaves open) and edge_form 3 (the same with the
+    open edges searched in descending order of their open-slot count) write
+    exactly what edge_form 1 (one wavefront per edge) writes, on every edge
+    of the one-iteration batch with its obstacle spheres and 3 capsules, and
+    through the entry point that allocates nothing."""
     sh = iteration["shape"]
     ctx = _ctx(iteration)
     tree, ld, n = fn.tree_soa(iteration["tree_x"])
@@ -320,7 +321,7 @@ def test_two_phase_search_equals_one_kernel(iteration, mode):
     wl = torch.as_tensor(rng.integers(0, sh.n_t + 1, idx.numel()).astype(np.int16)).cuda()
     kw = dict(win_lo=wl, win_half=4) if mode == fn.SEARCH_WINDOW else {}
     outs = []
-    for form, noalloc in ((1, False), (2, False), (2, True)):
+    for form, noalloc in ((1, False), (2, False), (2, True), (3, False), (3, True)):
         ctx.set_tuning(edge_form=form)
         outs.append(_run_edges(ctx, iteration, idx, mode, caps=caps, noalloc=noalloc, **kw))
     for b in outs[1:]:
@@ -394,8 +395,9 @@ def test_window_tiny_all_edges_vs_oracle(tiny, half, with_jmax):
 
 
 @pytest.mark.parametrize("mode,form", [(fn.SEARCH_PLAIN, 0), (fn.SEARCH_SCREEN, 1),
-                                       (fn.SEARCH_SCREEN, 2), (fn.SEARCH_WINDOW, 1),
-                                       (fn.SEARCH_WINDOW, 2)])
+                                       (fn.SEARCH_SCREEN, 2), (fn.SEARCH_SCREEN, 3),
+                                       (fn.SEARCH_WINDOW, 1), (fn.SEARCH_WINDOW, 2),
+                                       (fn.SEARCH_WINDOW, 3)])
 def test_edge_time_largest_grid_and_samples(tiny, mode, form):
     """The largest sizes the search takes: FN_MAX_NT = 256 slots (four 64-slot
     words of the slot mask, four screen passes) and FN_MAX_SAMPLES = 64

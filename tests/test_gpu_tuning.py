@@ -43,7 +43,7 @@ def test_knn_result_is_independent_of_the_launch_mapping(iteration):
             ref = got
         else:
             assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (tw, mc, form)
-    ctx.set_tuning(0, 0)
+    ctx.set_tuning(0, 0, 0)
 
 
 def test_autotuner_picks_a_candidate_and_caches_it(iteration, tmp_path):
@@ -56,7 +56,7 @@ def test_autotuner_picks_a_candidate_and_caches_it(iteration, tmp_path):
     assert ch.ms == min(times.values())
     ch2, times2 = autotune.tune_knn(ctx, tree, ld, n, cand, sh.k, cache=cache)
     assert ch2 == ch and times2 == {}  # from the cache
-    ctx.set_tuning(0, 0)
+    ctx.set_tuning(0, 0, 0)
 
 
 def test_edge_form_tuner_picks_a_form_and_caches_it(iteration, tmp_path):
@@ -64,14 +64,18 @@ def test_edge_form_tuner_picks_a_form_and_caches_it(iteration, tmp_path):
     idx, _ = ctx.plan_knn(tree, ld, n, cand, sh.k, want_d2=False)
     grid, obs = fn.dev(wl["grid"]), fn.dev(wl["obs"])
     cache = autotune.Cache(str(tmp_path / "e.json"))
+    ctx.set_tuning(2048, 512, 1)  # a kNN mapping the edge tuner must keep
     ch, times = autotune.tune_edge(ctx, tree, ld, n, cand, idx, grid, sh.samples, obs,
                                    reps=1, cache=cache)
-    assert ch.edge_form in (1, 2) and set(times) == {"edge_form 1", "edge_form 2"}
+    assert ctx._tuning[:3] == (2048, 512, 1)
+    assert ch.edge_form in autotune.EDGE_FORMS
+    assert set(times) == {f"edge_form {f}" for f in autotune.EDGE_FORMS}
     assert ctx.edge_form == ch.edge_form
     ch2, times2 = autotune.tune_edge(ctx, tree, ld, n, cand, idx, grid, sh.samples, obs,
                                      cache=autotune.Cache(str(tmp_path / "e.json")))
     assert ch2 == ch and times2 == {}  # from the cache file
-    ctx.set_tuning(edge_form=0)
+    assert ctx._tuning[:3] == (2048, 512, 1)
+    ctx.set_tuning(0, 0, 0, edge_form=0)
 
 
 def test_kernel_timing_events(iteration):
@@ -99,6 +103,9 @@ def test_tuning_and_problem_set_are_validated(iteration):
         ctx.set_tuning(1 << 20, 512)
     with pytest.raises(fn.FnError, match="form"):
         ctx.set_tuning(4096, 512, 4)
+    with pytest.raises(fn.FnError, match="form"):
+        ctx.set_tuning(edge_form=4)
+    ctx.set_tuning(edge_form=0)
     with pytest.raises(fn.FnError, match="max_problems = 0"):
         fn.Batch(ctx, fn.dev(wl["grid"]), sh.samples, sh.k).prepare()
     arm, probs = W.make_problem_set(2, 5, nodes=(300, 600), batch=(40, 60))
