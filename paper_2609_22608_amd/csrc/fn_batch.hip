@@ -161,7 +161,7 @@ batch_edge_kernel(ProbTable pt, const float* __restrict__ grid, int n_t,
   __shared__ float s_end_all[EDGE_WAVES][FN_MAX_NT];
   __shared__ float s_T[FN_MAX_NT];
   __shared__ float s_fix[EDGE_WAVES][4];
-  __shared__ float s_mod[EDGE_WAVES][2 * MODEL_FLOATS];
+  __shared__ float s_mod[EDGE_WAVES][SCREEN_FLOATS];
   __shared__ GeoLDS<float> s_geo[EDGE_WAVES];
   extern __shared__ float s_tab[];  // EDGE_WAVES * nsph * max_obs floats
   for (int t = threadIdx.x; t < n_t; t += blockDim.x) s_T[t] = grid[t];

@@ -522,7 +522,7 @@ __device__ __forceinline__ void model_state(const EdgeArgs& a, int64_t st, int r
 // The search of one edge by one wavefront (see the stage list above).
 // eq: the edge's id in the FP64-stage queue; s_end: this wavefront's
 // FN_MAX_NT floats of LDS; s_T: the grid in LDS; s_fix: four floats of LDS;
-// s_mod: 2 * MODEL_FLOATS floats of LDS; geo, tab: the clearance tables (LDS;
+// s_mod: SCREEN_FLOATS floats of LDS; geo, tab: the clearance tables (LDS;
 // tab: nsph * n_obs floats).
 // MODE is the search mode (a
 // compile-time constant, so each mode is its own kernel); GOALS: edges of
@@ -579,6 +579,10 @@ __device__ void search_edge(const EdgeArgs& a, int64_t e, int64_t eq, const ArmC
     s_mod[MODEL_FLOATS + lane] = a.model_c[(e / a.k) * MODEL_FLOATS + lane];
   }
   __builtin_amdgcn_wave_barrier();
+  if (mode != FN_SEARCH_PLAIN) {
+    endpoint_table(lane, ES, s_mod, s_mod + MODEL_FLOATS, s_mod + 2 * MODEL_FLOATS);
+    __builtin_amdgcn_wave_barrier();
+  }
   SlotMask todo{~0ull, ~0ull, ~0ull, ~0ull};
 
   int wlo = 0, whi = -1;
@@ -630,7 +634,8 @@ __device__ void search_edge(const EdgeArgs& a, int64_t e, int64_t eq, const ArmC
       float r = 0.f;
       if (act) {
         const float T = Tg[my];
-        r = endpoint_ratio(A, ES, s_mod, s_mod + MODEL_FLOATS, T, __builtin_amdgcn_rcpf(T));
+        r = endpoint_ratio(A, ES, s_mod, s_mod + MODEL_FLOATS, s_mod + 2 * MODEL_FLOATS,
+                           __builtin_amdgcn_rcpf(T));
         s_end[my] = r;
       }
       scr += __popcll(__ballot(act));
@@ -769,7 +774,7 @@ __device__ void search_edge(const EdgeArgs& a, int64_t e, int64_t eq, const ArmC
 // state differences are load_edge's.
 template <int PAT, int MODE>
 __device__ void triage_one(const EdgeArgs& a, int64_t e, int p, const ArmConst<float>& A,
-                           const float* s_T, const float* s_mod, const float* x) {
+                           const float* s_T, float* s_mod, const float* x) {
   const int lane = lane_id();
   if (lane == 0) a.tri_items[e] = -1;
   int st0 = p < 0 ? FN_S_NO_PARENT : p >= nodes_of(a) ? FN_S_BAD_INPUT : 0;
@@ -801,6 +806,8 @@ __device__ void triage_one(const EdgeArgs& a, int64_t e, int p, const ArmConst<f
               0, 0, 0, 0);
     return;
   }
+  endpoint_table(lane, ES, s_mod, s_mod + MODEL_FLOATS, s_mod + 2 * MODEL_FLOATS);
+  __builtin_amdgcn_wave_barrier();
   int open = 0;
   float mc = INFINITY, lastv = 0.f;
   for (int j0 = 0; j0 <= jmax; j0 += WAVE) {
@@ -809,7 +816,8 @@ __device__ void triage_one(const EdgeArgs& a, int64_t e, int p, const ArmConst<f
     float r = 0.f;
     if (act) {
       const float T = s_T[jj];
-      r = endpoint_ratio(A, ES, s_mod, s_mod + MODEL_FLOATS, T, __builtin_amdgcn_rcpf(T));
+      r = endpoint_ratio(A, ES, s_mod, s_mod + MODEL_FLOATS, s_mod + 2 * MODEL_FLOATS,
+                         __builtin_amdgcn_rcpf(T));
     }
     const bool cert = act && r > 1.f + BAND;
     open += __popcll(__ballot(act && !cert));
@@ -828,7 +836,7 @@ __device__ void triage_one(const EdgeArgs& a, int64_t e, int p, const ArmConst<f
 }
 
 // Triage of one edge by one wavefront: parent index, states and endpoint
-// models into LDS (s_mod: 2 * MODEL_FLOATS floats, s_x: 2 * FN_STATE
+// models into LDS (s_mod: SCREEN_FLOATS floats, s_x: 2 * FN_STATE
 // floats), then triage_one.
 template <int PAT, int MODE>
 __device__ void triage_edge(const EdgeArgs& a, int64_t e, const ArmConst<float>& A,

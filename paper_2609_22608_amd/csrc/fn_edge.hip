@@ -39,7 +39,7 @@ edge_time_kernel(EdgeArgs a, const ArmConst<float>* __restrict__ Ap) {
   __shared__ float s_end_all[EDGE_WAVES][FN_MAX_NT];
   __shared__ float s_T[FN_MAX_NT];
   __shared__ float s_fix[EDGE_WAVES][4];
-  __shared__ float s_mod[EDGE_WAVES][2 * MODEL_FLOATS];
+  __shared__ float s_mod[EDGE_WAVES][SCREEN_FLOATS];
   __shared__ GeoLDS<float> s_geo[EDGE_WAVES];
   extern __shared__ float s_tab[];  // EDGE_WAVES * nsph * (n_obs + n_caps) floats
   for (int t = threadIdx.x; t < a.n_t; t += blockDim.x) s_T[t] = a.grid[t];
@@ -57,7 +57,7 @@ template <int PAT, int MODE>
 __global__ __launch_bounds__(256) void edge_triage_kernel(EdgeArgs a,
                                                           const ArmConst<float>* __restrict__ Ap) {
   __shared__ float s_T[FN_MAX_NT];
-  __shared__ float s_mod[4][2 * MODEL_FLOATS];
+  __shared__ float s_mod[4][SCREEN_FLOATS];
   __shared__ float s_x[4][2 * FN_STATE];
   for (int t = threadIdx.x; t < a.n_t; t += blockDim.x) s_T[t] = a.grid[t];
   __syncthreads();
@@ -115,14 +115,16 @@ __global__ __launch_bounds__(256) void tri_scatter_kernel(const int32_t* __restr
   s_bef[part][bin] = bef;
   __syncthreads();
   if (t < TRI_BINS) {
-    int above = 0, all = 0;
-    for (int c = 0; c < TRI_BINS; ++c) {
-      const int n = s_tot[0][c] + s_tot[1][c] + s_tot[2][c] + s_tot[3][c];
-      all += n;
-      if (c > bin) above += n;
+    // lane = bin: the count of bins bin..63 by a suffix scan over the lanes
+    const int n = s_tot[0][bin] + s_tot[1][bin] + s_tot[2][bin] + s_tot[3][bin];
+    int x = n;
+#pragma unroll
+    for (int off = 1; off < TRI_BINS; off <<= 1) {
+      const int y = __shfl_down(x, off);
+      if (bin + off < TRI_BINS) x += y;
     }
-    s_cur[bin] = above + s_bef[0][bin] + s_bef[1][bin] + s_bef[2][bin] + s_bef[3][bin];
-    if (blockIdx.x == 0 && t == 0) *n_open = all;
+    s_cur[bin] = x - n + s_bef[0][bin] + s_bef[1][bin] + s_bef[2][bin] + s_bef[3][bin];
+    if (blockIdx.x == 0 && t == 0) *n_open = x;  // lane 0: every bin
   }
   __syncthreads();
   const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min(E, lo + chunk);
@@ -142,7 +144,7 @@ edge_search_open_kernel(EdgeArgs a, const ArmConst<float>* __restrict__ Ap) {
   __shared__ float s_end[FN_MAX_NT];
   __shared__ float s_T[FN_MAX_NT];
   __shared__ float s_fix[4];
-  __shared__ float s_mod[2 * MODEL_FLOATS];
+  __shared__ float s_mod[SCREEN_FLOATS];
   __shared__ GeoLDS<float> s_geo;
   extern __shared__ float s_tab[];  // nsph * (n_obs + n_caps) floats
   int64_t e;

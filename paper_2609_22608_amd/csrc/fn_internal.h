@@ -323,34 +323,52 @@ __device__ __forceinline__ R eval_rho(const ArmConst<R>& A, const EdgeState<R>& 
   return rmax(rt, rp);
 }
 
+// Screen of a slot from the two endpoint models (m0: state q0, qd0; m1:
+// state q1, qd1 = qd0 + d2; each the columns of M + diag(I_m) and the bias
+// b, MODEL_FLOATS floats).  At an endpoint the torque is b + M qdd, and the
+// cubic's endpoint accelerations are affine in 1 / T^2 and 1 / T:
+//   qdd(0) = 6 dq / T^2 - (6 qd0 + 2 d2) / T,
+//   qdd(1) = -6 dq / T^2 + (6 qd0 + 4 d2) / T,
+// so per edge P0 = M0 (6 dq), Q0 = M0 (6 qd0 + 2 d2), P1 = M1 (6 dq) and
+// Q1 = M1 (6 qd0 + 4 d2) give both endpoint torques of any duration with two
+// FMAs per joint.  SCREEN_FLOATS of LDS per wavefront hold the two models
+// and these 28 coefficients.
+constexpr int SCREEN_FLOATS = 2 * MODEL_FLOATS + 32;
+
+// The coefficients of one edge into tab (LDS): lane 7 w + i (w < 4) of the
+// wavefront forms coefficient w (P0, Q0, P1, Q1) of joint i.  The caller
+// orders the LDS writes before the reads (a wave barrier).
+__device__ __forceinline__ void endpoint_table(int lane, const EdgeState<float>& E,
+                                               const float* __restrict__ m0,
+                                               const float* __restrict__ m1, float* tab) {
+  if (lane < 4 * NJ) {
+    const int w = lane / NJ, i = lane - NJ * w;
+    const float* m = w < 2 ? m0 : m1;
+    const float kd = w == 1 ? 2.f : 4.f;
+    float s = 0.f;
+#pragma unroll
+    for (int c = 0; c < NJ; ++c) {
+      const float v = (w & 1) ? fmaf(kd, E.d2[c], 6.f * E.qd0[c]) : 6.f * E.dq[c];
+      s = fmaf(m[NJ * c + i], v, s);
+    }
+    tab[lane] = s;
+  }
+}
+
 // Larger of the torque and power ratios (Def. 6) at u = 0 and u = 1 of
-// duration T from the two endpoint models (m0: state q0, qd0; m1: state
-// q1, qd1 = qd0 + d2); the models are read from LDS (same address in
-// every lane).
+// duration 1 / invT from the endpoint models (biases at m0[49..], m1[49..])
+// and the edge's coefficients (endpoint_table); all read from LDS at the
+// same address in every lane.
 __device__ __forceinline__ float endpoint_ratio(const ArmConst<float>& A, const EdgeState<float>& E,
                                                 const float* __restrict__ m0,
-                                                const float* __restrict__ m1, float T,
-                                                float invT) {
+                                                const float* __restrict__ m1,
+                                                const float* __restrict__ tab, float invT) {
   const float invT2 = invT * invT;
-  float a0[NJ], a1[NJ];
-#pragma unroll
-  for (int c = 0; c < NJ; ++c) {
-    // qdd(0) = 2 A2 / T^2, qdd(1) = (2 A2 + 6 A3) / T^2 with A2 = 3 d1 - d2 T,
-    // A3 = d2 T - 2 d1, d1 = dq - qd0 T
-    const float d1 = E.dq[c] - E.qd0[c] * T;
-    const float d2T = E.d2[c] * T;
-    a0[c] = (6.f * d1 - 2.f * d2T) * invT2;
-    a1[c] = (4.f * d2T - 6.f * d1) * invT2;
-  }
   float r = 0.f, p0 = 0.f, p1 = 0.f;
 #pragma unroll
   for (int i = 0; i < NJ; ++i) {
-    float t0 = m0[49 + i], t1 = m1[49 + i];
-#pragma unroll
-    for (int c = 0; c < NJ; ++c) {
-      t0 = fmaf(m0[7 * c + i], a0[c], t0);
-      t1 = fmaf(m1[7 * c + i], a1[c], t1);
-    }
+    const float t0 = fmaf(tab[i], invT2, fmaf(-tab[NJ + i], invT, m0[49 + i]));
+    const float t1 = fmaf(-tab[2 * NJ + i], invT2, fmaf(tab[3 * NJ + i], invT, m1[49 + i]));
     r = fmaxf(r, fmaxf(fabsf(t0), fabsf(t1)) * A.L[i].inv_taumax);
     p0 = fmaf(t0, E.qd0[i], p0);
     p1 = fmaf(t1, E.qd0[i] + E.d2[i], p1);
