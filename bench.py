@@ -30,9 +30,13 @@ PEAK_FP32 = 157.3e12  # MI355X FP32 vector peak (packed), FLOP/s
 # One evaluation point of Eq. (4)-(7): cubic 169, sin/cos 21, RNEA 1,005,
 # armature 14, friction 56, ratios and power 30.
 F_EVAL = 1295
-# One slot screened from the endpoint models: both endpoint accelerations
-# (79), two 7x7 products with the bias (196), ratios and power (59).
-F_SCREEN = 334
+# One slot screened from the endpoint models and the edge's coefficients:
+# the reciprocal of T and 1/T^2 (2), both endpoint torques by two FMAs per
+# joint (56), ratios and power (59).
+F_SCREEN = 117
+# The coefficients of one screened edge: 28 products of 7 terms with their
+# operands (6 dq: 3 per term; 6 qd0 + 2 d2 or 6 qd0 + 4 d2: 5 per term).
+F_SCREEN_EDGE = 784
 # One endpoint model (per state): 8 lanes x (sin/cos 21 + rigid RNEA 1,005)
 # + armature 7 + friction 56.
 F_MODEL = 8271
@@ -227,10 +231,12 @@ def main():
         # the clearance runs only where the limit checks passed
         n_clear = int((post & ((st & (fn.S_VEL | fn.S_POS)) == 0)).sum())
         n_sph = len(wl["arm"]["sph"])
-        flop = (work * F_EVAL + scr * F_SCREEN + n_post * F_JOINTS
+        n_scr_edges = int((out["screened"] > 0).sum().item())
+        flop = (work * F_EVAL + scr * F_SCREEN + n_scr_edges * F_SCREEN_EDGE + n_post * F_JOINTS
                 + n_clear * f_clear(sh.samples, sh.n_obs, n_sph))
         f = dict(edges_per_s=E / (ms * 1e-3), ms_per_step=ms, edge_search_ms=e_ms,
                  search_span_ms=kern_ms, evaluations=work, screened_slots=scr,
+                 screened_edges=n_scr_edges,
                  post_checked=n_post, clearance_checked=n_clear, kernel_gflop=flop / 1e9,
                  wall_s=wall,
                  fp32_tflops=flop / (kern_ms * 1e-3) / 1e12,
@@ -279,12 +285,14 @@ def main():
                      "kernel_ms": bf["search_span_ms"],
                      "flop_per_launch": bf["kernel_gflop"] * 1e9,
                      "flop_model": {"eval": F_EVAL, "screened_slot": F_SCREEN,
+                                    "screened_edge": F_SCREEN_EDGE,
                                     "post_checked_edge": F_JOINTS,
                                     "clearance_edge": f_clear(sh.samples, sh.n_obs,
                                                               len(wl["arm"]["sph"])),
                                     "model_state": F_MODEL},
                      "units": {"evaluations": bf["evaluations"],
                                "screened_slots": bf["screened_slots"],
+                               "screened_edges": bf["screened_edges"],
                                "post_checked_edges": bf["post_checked"],
                                "clearance_checked_edges": bf["clearance_checked"]}},
     }
