@@ -59,6 +59,11 @@ LR_SURROGATE = 3e-3
 # One controller step: Eq. (9) and the taper bounds 7 x 20, sin/cos 21,
 # rigid-body recursion 1,005, armature 14, friction 56, clips and power 7 x 8.
 F_CONTROL = 1252
+# HBM bytes of one controller step: q, qd, the previous torque, the
+# rendezvous state (7 floats each) and the horizon in; torque and
+# acceleration (7 floats each) and a 2-byte status out.
+B_CONTROL = 4 * (5 * 7 + 1) + 4 * 2 * 7 + 2
+PEAK_HBM = 8.0e12  # MI355X HBM3E, bytes/s
 
 
 def f_clear(S, n_obs, n_sph):
@@ -502,6 +507,9 @@ def controller_stats(args, ctx, wl, fn, W, torch, n=1 << 20):
     return {"instances": n, "ms": ms, "instances_per_s": n / (ms * 1e-3),
             "fp32_tflops": n * F_CONTROL / (ms * 1e-3) / 1e12,
             "frac": n * F_CONTROL / (ms * 1e-3) / PEAK_FP32, "flop_per_instance": F_CONTROL,
+            "hbm": {"bytes_per_instance": B_CONTROL,
+                    "achieved_gbs": n * B_CONTROL / (ms * 1e-3) / 1e9,
+                    "frac": n * B_CONTROL / (ms * 1e-3) / PEAK_HBM},
             "clipped": {name: float(((stn & b) > 0).mean()) for name, b in
                         (("acc", fn.C_ACC), ("slew", fn.C_SLEW), ("torque", fn.C_TORQUE),
                          ("power", fn.C_POWER))}}
