@@ -84,6 +84,14 @@ __device__ __forceinline__ float fdiv(float a, float b) { return a * __builtin_a
 __device__ __forceinline__ double fdiv(double a, double b) { return a / b; }
 template <typename R>
 __device__ __forceinline__ R rmax(R a, R b) { return a > b ? a : b; }
+// Larger of two FP32 ratios, each non-negative or a NaN from arithmetic
+// (sign clear): their bit patterns as signed integers order like the values
+// and a NaN lies above +inf, so one integer max gives the maximum and keeps
+// a NaN (the slot then fails every "<= 1" test), with no compare-and-select
+// and no canonicalising of the operands.
+__device__ __forceinline__ float ratio_max(float a, float b) {
+  return __int_as_float(max(__float_as_int(a), __float_as_int(b)));
+}
 
 // ---------------------------------------------------------------------------
 // Rotation by ^{i-1}R_i = Rx(alpha) Rz(theta) and its transpose, with the
@@ -308,19 +316,22 @@ __device__ __forceinline__ void eval_point(const ArmConst<R>& A, const EdgeState
   R t = 0, pw = 0;
 #pragma unroll
   for (int i = 0; i < NJ; ++i) {
-    t = rmax(t, rabs(tau[i]) * A.L[i].inv_taumax);
+    if constexpr (sizeof(R) == 4) t = ratio_max(t, fabsf(tau[i]) * A.L[i].inv_taumax);
+    else t = rmax(t, rabs(tau[i]) * A.L[i].inv_taumax);
     pw += tau[i] * sd[i];
     if (tau_out) tau_out[i] = tau[i];
   }
   rt = t;
-  rp = rabs(pw) * A.inv_wmax;
+  if constexpr (sizeof(R) == 4) rp = fabsf(pw) * A.inv_wmax;
+  else rp = rabs(pw) * A.inv_wmax;
 }
 template <typename R, int PAT>
 __device__ __forceinline__ R eval_rho(const ArmConst<R>& A, const EdgeState<R>& E, R T, R invT,
                                       R u) {
   R rt, rp;
   eval_point<R, PAT>(A, E, T, invT, u, rt, rp, nullptr);
-  return rmax(rt, rp);
+  if constexpr (sizeof(R) == 4) return ratio_max(rt, rp);
+  else return rmax(rt, rp);
 }
 
 // Screen of a slot from the two endpoint models (m0: state q0, qd0; m1:
@@ -594,20 +605,20 @@ __device__ __forceinline__ double wave_min(double v) {
   v = fmin(v, xlane<16>(v));
   return fmin(readlane(v, 0), readlane(v, 32));
 }
-// The same through LDS permutes: no VALU moves, for VALU-bound loops.
+// Ratio maxima over aligned groups of `width` lanes (width a wave-uniform
+// power of two <= 64; every value a ratio, see ratio_max).  Through LDS
+// permutes (no VALU moves, for VALU-bound loops) or by lane exchanges.
 __device__ __forceinline__ float group_max_lds(float v, int width) {
-  for (int o = 1; o < width; o <<= 1) v = fmaxf(v, __shfl_xor(v, o));
+  for (int o = 1; o < width; o <<= 1) v = ratio_max(v, __shfl_xor(v, o));
   return v;
 }
-// max over aligned groups of `width` lanes (width a wave-uniform power of two
-// <= 64)
 __device__ __forceinline__ float group_max(float v, int width) {
-  if (width > 1) v = fmaxf(v, xlane<1>(v));
-  if (width > 2) v = fmaxf(v, xlane<2>(v));
-  if (width > 4) v = fmaxf(v, xlane<4>(v));
-  if (width > 8) v = fmaxf(v, xlane<8>(v));
-  if (width > 16) v = fmaxf(v, xlane<16>(v));
-  if (width > 32) v = fmaxf(readlane(v, 0), readlane(v, 32));
+  if (width > 1) v = ratio_max(v, xlane<1>(v));
+  if (width > 2) v = ratio_max(v, xlane<2>(v));
+  if (width > 4) v = ratio_max(v, xlane<4>(v));
+  if (width > 8) v = ratio_max(v, xlane<8>(v));
+  if (width > 16) v = ratio_max(v, xlane<16>(v));
+  if (width > 32) v = ratio_max(readlane(v, 0), readlane(v, 32));
   return v;
 }
 
