@@ -82,6 +82,10 @@ __device__ __forceinline__ R rabs(R x) { return x < R(0) ? -x : x; }
 // a / b: hardware reciprocal (1 ulp) in FP32, IEEE division in FP64
 __device__ __forceinline__ float fdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 __device__ __forceinline__ double fdiv(double a, double b) { return a / b; }
+// square root of x >= 0: the hardware square root (1 ulp) in FP32, IEEE in
+// FP64
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
 template <typename R>
 __device__ __forceinline__ R rmax(R a, R b) { return a > b ? a : b; }
 // Larger of two FP32 ratios, each non-negative or a NaN from arithmetic
@@ -392,10 +396,10 @@ template <typename R>
 __device__ __forceinline__ R vel_ratio(const ArmConst<R>& A, int i, R q, R v) {
   if (v == R(0)) return R(0);
   const R dist = v >= R(0) ? (A.qmax[i] - q) : (q - A.qmin[i]);
-  R lim = sqrt(A.two_acc[i] * rmax(R(0), dist));
+  R lim = fsqrt(A.two_acc[i] * rmax(R(0), dist));
   lim = lim < A.qdmax[i] ? lim : A.qdmax[i];
   if (!(lim > R(0))) return R(INFINITY);
-  return rabs(v) / lim;
+  return fdiv(rabs(v), lim);
 }
 
 // One candidate extremum of joint i's cubic at duration T (boundary state
@@ -411,22 +415,26 @@ __device__ __forceinline__ R vel_ratio(const ArmConst<R>& A, int i, R q, R v) {
 template <typename R>
 __device__ __forceinline__ void joint_point(const ArmConst<R>& A, int i, int p, R q0, R qd0, R dq,
                                             R d2v, R T, R& v, R& q) {
-  const R invT = R(1) / T;
+  // quotients and roots: fdiv / fsqrt (1 ulp in FP32, IEEE in FP64); each
+  // quotient is used only where its divisor is nonzero, and a candidate time
+  // off by an ulp moves its value by far less (the derivative vanishes at an
+  // extremum)
+  const R invT = fdiv(R(1), T);
   const R c0 = q0, c1 = qd0;
   const R d1 = dq - c1 * T;
   const R c2 = (R(3) * d1 * invT - d2v) * invT;
   const R c3 = (d2v - R(2) * d1 * invT) * invT * invT;
   // velocity vertex
-  const R tv = -c2 / (R(3) * c3);
+  const R tv = fdiv(-c2, R(3) * c3);
   const bool tv_ok = c3 != R(0) && tv > R(0) && tv < T;
   // roots of the velocity 3 c3 t^2 + 2 c2 t + c1
   const R qa = R(3) * c3, qb = R(2) * c2, qc = c1;
-  const R tl = -qc / qb;  // qa = 0: the linear root
+  const R tl = fdiv(-qc, qb);  // qa = 0: the linear root
   const bool tl_ok = qb != R(0) && tl >= R(0) && tl <= T;
   const R disc = qb * qb - R(4) * qa * qc;
-  const R sq = sqrt(disc >= R(0) ? disc : R(0));
+  const R sq = fsqrt(disc >= R(0) ? disc : R(0));
   const R qq = R(-0.5) * (qb + (qb >= R(0) ? sq : -sq));
-  const R t1 = qq / qa, t2 = qc / qq;
+  const R t1 = fdiv(qq, qa), t2 = fdiv(qc, qq);
   const bool quad = qa != R(0) && disc >= R(0) && qq != R(0);
   const bool t1_ok = quad && t1 >= R(0) && t1 <= T;
   const bool t2_ok = quad && t2 >= R(0) && t2 <= T;
