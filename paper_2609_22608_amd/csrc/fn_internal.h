@@ -621,12 +621,21 @@ __device__ __forceinline__ float group_max_lds(float v, int width) {
   return v;
 }
 __device__ __forceinline__ float group_max(float v, int width) {
+  if (width >= 32) {
+    // the common widths (32 and 64 samples) under one wave-uniform test
+    v = ratio_max(v, xlane<1>(v));
+    v = ratio_max(v, xlane<2>(v));
+    v = ratio_max(v, xlane<4>(v));
+    v = ratio_max(v, xlane<8>(v));
+    v = ratio_max(v, xlane<16>(v));
+    if (width > 32) v = ratio_max(readlane(v, 0), readlane(v, 32));
+    return v;
+  }
   if (width > 1) v = ratio_max(v, xlane<1>(v));
   if (width > 2) v = ratio_max(v, xlane<2>(v));
   if (width > 4) v = ratio_max(v, xlane<4>(v));
   if (width > 8) v = ratio_max(v, xlane<8>(v));
   if (width > 16) v = ratio_max(v, xlane<16>(v));
-  if (width > 32) v = ratio_max(readlane(v, 0), readlane(v, 32));
   return v;
 }
 
