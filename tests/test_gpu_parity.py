@@ -394,6 +394,38 @@ def test_window_tiny_all_edges_vs_oracle(tiny, half, with_jmax):
     print(f"{label}: hits {hit.sum()}, misses {miss.sum()}")
 
 
+@pytest.mark.parametrize("B", [4093, 2500, 127])
+def test_ordered_search_ragged_edge_counts(iteration, B):
+    """The ordered two-phase form (edge_form 3) sorts the open edges over
+    blocks of at least 1,024 edges.  Edge counts that leave the last block
+    partial -- 4,093 and 2,500 candidates x 8 (32 and 20 blocks) and 127 x 8
+    (one block) -- give exactly what the one-kernel form gives, in both
+    screened modes."""
+    sh = iteration["shape"]
+    ctx = _ctx(iteration)
+    tree, ld, n = fn.tree_soa(iteration["tree_x"])
+    cand = fn.dev(iteration["cand"]["x"][:B])
+    idx, _ = ctx.plan_knn(tree, ld, n, cand, sh.k)
+    grid, obs = fn.dev(iteration["grid"]), fn.dev(iteration["obs"])
+    rng = np.random.default_rng(B)
+    lo = torch.as_tensor(rng.integers(0, sh.n_t + 1, idx.numel()).astype(np.int16)).cuda()
+    for mode in (fn.SEARCH_SCREEN, fn.SEARCH_WINDOW):
+        kw = dict(win_lo=lo, win_half=4) if mode == fn.SEARCH_WINDOW else {}
+        outs = []
+        for form in (1, 3):
+            ctx.set_tuning(edge_form=form)
+            outs.append(ctx.edge_time_batch(tree, ld, n, cand, idx, grid, sh.samples, obs,
+                                            mode=mode, **kw))
+            torch.cuda.synchronize()
+        for key in ("j", "status", "margin", "rho", "work", "screened"):
+            x, y = outs[0][key], outs[1][key]
+            if x.dtype == torch.float32:
+                x, y = x.view(torch.int32), y.view(torch.int32)
+            assert torch.equal(x, y), (B, mode, key)
+    ctx.set_tuning(edge_form=0)
+    ctx.close()
+
+
 @pytest.mark.parametrize("mode,form", [(fn.SEARCH_PLAIN, 0), (fn.SEARCH_SCREEN, 1),
                                        (fn.SEARCH_SCREEN, 2), (fn.SEARCH_SCREEN, 3),
                                        (fn.SEARCH_WINDOW, 1), (fn.SEARCH_WINDOW, 2),
