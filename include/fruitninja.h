@@ -483,7 +483,8 @@ typedef struct {
                        * then the search of the others); 3 two phases with the open edges
                        * searched in descending order of their open-slot count (a counting
                        * sort between the phases); 0 default: 3 from 2^15 edges, else 1.
-                       * The results are the same. */
+                       * Batched rounds (fn_batch_prepare) search in the ordered form when
+                       * it is 3 and in one kernel otherwise.  The results are the same. */
   int32_t mlp_rows;   /* rows per workgroup of the fused surrogate inference: 32 or 64; 0
                        * default (32 while 64 would leave fewer than four workgroups per
                        * compute unit).  The results are the same. */

@@ -176,7 +176,10 @@ def tune_edge(ctx: fn.Context, tree, ld, n_nodes, cand, nbr, grid, samples, obs=
 
 def tune_batch(bt: fn.Batch, reps=3, cache: Cache | None = None, candidates=None,
                modes=(fn.SEARCH_PLAIN, fn.SEARCH_SCREEN)):
-    """Fastest (kNN mapping, search form) for a prepared batched round.
+    """Fastest (kNN mapping, search mode, edge form) for a prepared batched
+    round: every kNN mapping in each mode with the one-kernel search, then
+    the ordered two-phase search (edge form 3) with the screened mode's best
+    mapping.
 
     Each timing restores the initial trees first, so every candidate times
     the same round.  Leaves the winner prepared on ``bt``."""
@@ -184,24 +187,33 @@ def tune_batch(bt: fn.Batch, reps=3, cache: Cache | None = None, candidates=None
     key = f"batch|{sig}|k{bt.k}|nt{bt.grid.shape[0]}|S{bt.samples}|{_device_tag()}"
     hit = cache.get(key) if cache else None
     if hit is not None:
-        bt.ctx.set_tuning(hit.knn_target_waves, hit.knn_min_chunk, hit.knn_form)
+        bt.ctx.set_tuning(hit.knn_target_waves, hit.knn_min_chunk, hit.knn_form,
+                          edge_form=hit.edge_form)
         bt.mode = hit.mode
         bt.prepare()
         return hit, {}
+
+    def run(tw, mc, mode, form, ef):
+        bt.ctx.set_tuning(tw, mc, form, edge_form=ef)
+        bt.mode = mode
+        bt.prepare()
+        times[(tw, mc, mode, form, ef)] = _time(bt.launch, reps, setup=bt.reset_trees)
+
     times = {}
     for mode in modes:
         for tw, mc, form in knn_grid(candidates):
-            bt.ctx.set_tuning(tw, mc, form)
-            bt.mode = mode
-            bt.prepare()
-            times[(tw, mc, mode, form)] = _time(bt.launch, reps, setup=bt.reset_trees)
-    (tw, mc, mode, form), ms = min(times.items(), key=lambda kv: kv[1])
-    ch = Choice(tw, mc, mode, ms, form)
-    bt.ctx.set_tuning(tw, mc, form)
+            run(tw, mc, mode, form, 1)
+    screened = {kk: v for kk, v in times.items() if kk[2] != fn.SEARCH_PLAIN}
+    if screened:
+        tw, mc, mode, form, _ = min(screened.items(), key=lambda kv: kv[1])[0]
+        run(tw, mc, mode, form, 3)
+    (tw, mc, mode, form, ef), ms = min(times.items(), key=lambda kv: kv[1])
+    ch = Choice(tw, mc, mode, ms, form, ef)
+    bt.ctx.set_tuning(tw, mc, form, edge_form=ef)
     bt.mode = mode
     bt.prepare()
     bt.reset_trees()
     if cache:
         cache.put(key, ch)
-    return ch, {f"{a}/{b}/{'plain' if m == fn.SEARCH_PLAIN else 'screen'}/{f}": v
-                for (a, b, m, f), v in times.items()}
+    return ch, {f"{a}/{b}/{'plain' if m == fn.SEARCH_PLAIN else 'screen'}/{f}/e{e}": v
+                for (a, b, m, f, e), v in times.items()}

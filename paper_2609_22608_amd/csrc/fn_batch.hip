@@ -178,6 +178,57 @@ batch_edge_kernel(ProbTable pt, const float* __restrict__ grid, int n_t,
                                s_tab + wave * Ap->nsph * max_obs);
 }
 
+// Ordered two-phase search over every problem's edges (edge_form 3), phase
+// 1: the triage of each free edge (as for one problem, into the global
+// open-slot counts: each problem's tri_items points at its range); a goal
+// candidate's edge is only marked open (count 1), the search checks it once
+// at its fixed duration.  Four wavefronts (edges) per workgroup.
+template <int PAT, int MODE>
+__global__ __launch_bounds__(256) void batch_triage_kernel(ProbTable pt,
+                                                           const float* __restrict__ grid, int n_t,
+                                                           const ArmConst<float>* __restrict__ Ap) {
+  __shared__ float s_T[FN_MAX_NT];
+  __shared__ float s_mod[4][SCREEN_FLOATS];
+  __shared__ float s_x[4][2 * FN_STATE];
+  for (int t = threadIdx.x; t < n_t; t += blockDim.x) s_T[t] = grid[t];
+  __syncthreads();
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t eg = (int64_t)blockIdx.x * 4 + wave;
+  if (eg >= pt.edge_off[pt.n]) return;
+  const int p = problem_of(pt, eg);
+  const EdgeArgs& a = pt.args[p];
+  const int64_t e = eg - pt.edge_off[p];
+  // a goal candidate's edges (whatever their parent: the search reports an
+  // invalid one) go to the search as they are
+  if (a.kind && a.kind[e / a.k] == 1) {
+    if (lane_id() == 0) a.tri_items[e] = 1;
+    return;
+  }
+  triage_edge<PAT, MODE>(a, e, *Ap, s_T, s_mod[wave], s_x[wave]);
+}
+
+// Phase 2: workgroup w takes the w-th edge of the sorted order (global edge
+// ids, heaviest open-slot count first); one wavefront per workgroup.
+template <int PAT, int MODE>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void
+batch_edge_open_kernel(ProbTable pt, const float* __restrict__ grid, int n_t,
+                       const ArmConst<float>* __restrict__ Ap, const int32_t* __restrict__ order,
+                       const int32_t* __restrict__ n_open) {
+  __shared__ float s_end[FN_MAX_NT];
+  __shared__ float s_T[FN_MAX_NT];
+  __shared__ float s_fix[4];
+  __shared__ float s_mod[SCREEN_FLOATS];
+  __shared__ GeoLDS<float> s_geo;
+  extern __shared__ float s_tab[];  // nsph * max_obs floats
+  if ((int64_t)blockIdx.x >= __builtin_amdgcn_readfirstlane(*n_open)) return;
+  const int64_t eg = __builtin_amdgcn_readfirstlane(order[blockIdx.x]);
+  for (int t = threadIdx.x; t < n_t; t += blockDim.x) s_T[t] = grid[t];
+  __syncthreads();
+  const int p = problem_of(pt, eg);
+  search_edge<PAT, MODE, true>(pt.args[p], eg - pt.edge_off[p], eg, *Ap, s_end, s_T, s_fix, s_mod,
+                               &s_geo, s_tab);
+}
+
 // Endpoint models of every problem's states: 8 lanes per state, first the
 // parents of all edges (global edge order), then all candidates.
 template <int PAT>
@@ -637,6 +688,7 @@ struct fn_batch {
   fn_risk risk{};
   int64_t pairs = 0, queries = 0, edges = 0;  // pairs: kNN scan work items
   int form = 1;                                // kNN scan form (fn_tuning)
+  int edge_form = 1;  // screened search: 1 one kernel, 3 ordered two-phase (fn_tuning)
   int max_obs = 0;  // most obstacles (spheres + capsules) of a problem (clearance table LDS)
   int rounds = 1;   // candidate rounds held by every problem (tables per round)
   int64_t tab_cap = 0;  // entries of knn / ins / args
@@ -787,6 +839,7 @@ extern "C" int fn_batch_prepare(fn_ctx* c, const fn_problem_set* ps) {
     a.out_work = nullptr; a.out_scr = nullptr; a.q_count = c->q_count; a.queue = c->queue;
     a.model_e = c->model_e + eo[p] * MODEL_FLOATS;
     a.model_c = c->model_c + qo[p] * MODEL_FLOATS;
+    a.tri_items = c->tri_items + eo[p];  // the problem's edges in the global range
     a.kind = q.kind; a.t_req = q.t_req; a.t_node = q.t_node; a.out_T = q.out_T;
     a.t_best = loop ? q.incumbent + 2 : nullptr;
     ip[p] = InsProb{q.tree, q.ld, q.n_nodes, q.t_node, q.parent, q.nu, q.cand, q.kind, q.v_rel,
@@ -890,6 +943,9 @@ extern "C" int fn_batch_prepare(fn_ctx* c, const fn_problem_set* ps) {
   bt->mode = ps->mode;
   bt->pairs = po[n];
   bt->form = form;
+  // the ordered two-phase search only when asked for: a small round pays
+  // three more launches for it
+  bt->edge_form = c->tune.edge_form == 3 && eo[n] <= INT32_MAX ? 3 : 1;
   bt->queries = qo[n];
   bt->edges = eo[n];
   bt->max_obs = max_obs;
@@ -922,9 +978,29 @@ static void launch_batch_search(fn_ctx* c, fn_batch* bt, const EdgeArgs* et, hip
   if (MODE != FN_SEARCH_PLAIN)
     hipLaunchKernelGGL(batch_model_kernel<PAT>, dim3((unsigned)(((bt->edges + bt->queries) * 8 + 255) / 256)),
                        dim3(256), 0, s, pt, bt->query_off, c->arm32);
-  const size_t tab = (size_t)EDGE_WAVES * c->desc.n_spheres * bt->max_obs * sizeof(float);
-  hipLaunchKernelGGL((batch_edge_kernel<PAT, MODE>), dim3((unsigned)xcd_grid(bt->queries, bt->k)),
-                     dim3(64 * EDGE_WAVES), tab, s, pt, bt->grid, bt->n_t, c->arm32, bt->max_obs);
+  if (MODE != FN_SEARCH_PLAIN && bt->edge_form == 3) {
+    // triage, counting sort of the open edges (heaviest first), search in
+    // that order; the sort's scratch is laid out as for one problem
+    const int64_t E = bt->edges;
+    int32_t* order = c->tri_items + c->caps.max_edges;
+    int32_t* hist = c->tri_items + 2 * c->caps.max_edges;
+    int32_t* n_open = hist + TRI_MAX_BLOCKS * TRI_BINS;
+    const int64_t chunk = std::max(TRI_MIN_CHUNK, (E + TRI_MAX_BLOCKS - 1) / TRI_MAX_BLOCKS);
+    const int nblk = (int)((E + chunk - 1) / chunk);
+    hipLaunchKernelGGL((batch_triage_kernel<PAT, MODE>), dim3((unsigned)((E + 3) / 4)), dim3(256), 0,
+                       s, pt, bt->grid, bt->n_t, c->arm32);
+    hipLaunchKernelGGL(tri_hist_kernel, dim3(nblk), dim3(256), 0, s, c->tri_items, E, chunk,
+                       bt->n_t, hist);
+    hipLaunchKernelGGL(tri_scatter_kernel, dim3(nblk), dim3(256), 0, s, c->tri_items, E, chunk,
+                       bt->n_t, hist, nblk, order, n_open);
+    hipLaunchKernelGGL((batch_edge_open_kernel<PAT, MODE>), dim3((unsigned)E), dim3(64),
+                       (size_t)c->desc.n_spheres * bt->max_obs * sizeof(float), s, pt, bt->grid,
+                       bt->n_t, c->arm32, order, n_open);
+  } else {
+    const size_t tab = (size_t)EDGE_WAVES * c->desc.n_spheres * bt->max_obs * sizeof(float);
+    hipLaunchKernelGGL((batch_edge_kernel<PAT, MODE>), dim3((unsigned)xcd_grid(bt->queries, bt->k)),
+                       dim3(64 * EDGE_WAVES), tab, s, pt, bt->grid, bt->n_t, c->arm32, bt->max_obs);
+  }
   const unsigned rw = (unsigned)(bt->edges < RECHECK_WAVES ? bt->edges : RECHECK_WAVES);
   hipLaunchKernelGGL(edge_recheck_kernel<PAT>, dim3(rw), dim3(64),
                      (size_t)c->desc.n_spheres * bt->max_obs * sizeof(double), s, bt->a0, pt,

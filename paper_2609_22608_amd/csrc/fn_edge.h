@@ -92,6 +92,13 @@ struct EdgeArgs {
 // default form 3 from this many edges (measured faster than forms 1 and 2 at
 // 32,768 and 1,048,576 edges), form 1 below
 constexpr int64_t TRIAGE_MIN_EDGES = 1 << 15;
+// The ordered form's counting sort (fn_edge.hip): per-block bin counts of
+// the open-slot counts, then each open edge's place in the order.
+__global__ void tri_hist_kernel(const int32_t* __restrict__ items, int64_t E, int64_t chunk,
+                                int n_t, int32_t* __restrict__ hist);
+__global__ void tri_scatter_kernel(const int32_t* __restrict__ items, int64_t E, int64_t chunk,
+                                   int n_t, const int32_t* __restrict__ hist, int nblk,
+                                   int32_t* __restrict__ order, int32_t* __restrict__ n_open);
 __device__ __forceinline__ int nodes_of(const EdgeArgs& a) {
   return a.n_nodes_dev ? *a.n_nodes_dev : a.n_nodes;
 }

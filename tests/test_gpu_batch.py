@@ -44,11 +44,11 @@ def small_set(n_problems=5, seed=3):
     return arm, [with_goal_parents(wl) for wl in probs]
 
 
-def build(arm, probs, capacity_extra=1024, mode=fn.SEARCH_SCREEN, knn_form=0):
+def build(arm, probs, capacity_extra=1024, mode=fn.SEARCH_SCREEN, knn_form=0, edge_form=0):
     sh = probs[0]["shape"]
     sumB = sum(p["shape"].batch for p in probs)
     ctx = fn.Context(arm, 70000, sumB, sh.k, max_edges=sumB * sh.k, max_problems=len(probs))
-    ctx.set_tuning(0, 0, knn_form)
+    ctx.set_tuning(0, 0, knn_form, edge_form=edge_form)
     grid = fn.dev(probs[0]["grid"])
     bt = fn.Batch(ctx, grid, sh.samples, sh.k, mode=mode)
     for wl in probs:
@@ -250,11 +250,12 @@ def test_bench_problem_set_full_size():
     ctx.close()
 
 
-@pytest.mark.parametrize("form", [0, 3])
-def test_graph_replay_equals_eager_and_is_deterministic(form):
-    """Default kNN form and the matrix-core form."""
+@pytest.mark.parametrize("form,edge_form", [(0, 0), (3, 0), (0, 3)])
+def test_graph_replay_equals_eager_and_is_deterministic(form, edge_form):
+    """Default kNN form and the matrix-core form; the one-kernel and the
+    ordered two-phase search."""
     arm, probs = small_set(6, seed=9)
-    ctx, bt = build(arm, probs, knn_form=form)
+    ctx, bt = build(arm, probs, knn_form=form, edge_form=edge_form)
     keys = ("nbr", "out_j", "out_status", "out_T", "out_node", "out_J", "n_nodes", "t_node",
             "parent", "tree")
 
@@ -314,3 +315,53 @@ def test_batch_knn_forms_agree(form):
     for P, Q in zip(b1.problems, b2.problems):
         for k in ("nbr", "out_j", "out_status", "out_node", "n_nodes"):
             assert torch.equal(P[k], Q[k]), k
+
+
+BATCH_KEYS = ("nbr", "out_j", "out_status", "out_T", "out_node", "out_J", "n_nodes", "t_node",
+              "parent", "tree", "out_best")
+
+
+def _same_rounds(b1, b2, rounds=2):
+    for _ in range(rounds):
+        b1.launch()
+        b2.launch()
+        torch.cuda.synchronize()
+        for P, Q in zip(b1.problems, b2.problems):
+            for k in BATCH_KEYS:
+                x, y = P[k], Q[k]
+                if x.dtype == torch.float32:
+                    x, y = x.view(torch.int32), y.view(torch.int32)
+                assert torch.equal(x, y), k
+
+
+def test_batch_ordered_search_equals_one_kernel():
+    """The ordered two-phase search over all problems (edge_form 3: triage,
+    counting sort of the open edges, search in that order; goal edges passed
+    to the search) gives exactly the one-kernel round: parents, decisions,
+    durations, attachments and trees, over two rounds."""
+    arm, probs = small_set(5, seed=3)
+    _, b1 = build(arm, probs, edge_form=1)
+    _, b2 = build(arm, probs, edge_form=3)
+    _same_rounds(b1, b2)
+
+
+def test_batch_ordered_search_full_size():
+    """The same on the benchmark's 32-problem round (trees of up to 65,536
+    nodes, 638,352 edges): one round, bit for bit."""
+    arm, probs = W.make_problem_set(32, 101, nodes=(1024, 65536), batch=(256, 8192))
+    sh = probs[0]["shape"]
+    sumB = sum(p["shape"].batch for p in probs)
+    outs = []
+    for ef in (1, 3):
+        ctx = fn.Context(arm, max(p["shape"].n_nodes + p["shape"].batch for p in probs), sumB,
+                         sh.k, max_edges=sumB * sh.k, max_problems=len(probs))
+        ctx.set_tuning(edge_form=ef)
+        bt = fn.Batch(ctx, fn.dev(probs[0]["grid"]), sh.samples, sh.k, mode=fn.SEARCH_SCREEN)
+        for wl in probs:
+            bt.add_problem(wl["tree_x"], wl["tree_t"], wl["cand"], wl["obs"],
+                           capacity=wl["shape"].n_nodes + wl["shape"].batch)
+        bt.prepare()
+        outs.append((ctx, bt))
+    _same_rounds(outs[0][1], outs[1][1], rounds=1)
+    for ctx, _ in outs:
+        ctx.close()

@@ -161,11 +161,12 @@ def cycle_set(arm):
     return [W.make_cycle_problem(arm, s, 400 + 150 * (s % 3), 160) for s in CYCLE_SEEDS]
 
 
-def build_cycle(arm, probs, capacity_extra=700):
+def build_cycle(arm, probs, capacity_extra=700, edge_form=0):
     k = probs[0]["k"]
     B = len(probs[0]["rounds"][0]["x"])
     ctx = fn.Context(arm, 4096, B * len(probs), k, max_edges=B * k * len(probs),
                      max_problems=len(probs))
+    ctx.set_tuning(edge_form=edge_form)
     bt = fn.Batch(ctx, fn.dev(probs[0]["grid"]), probs[0]["samples"], k)
     for c in probs:
         bt.add_problem(c["tree_x"], c["tree_t"], c["rounds"], c["obs"],
@@ -189,12 +190,15 @@ def snapshot(bt):
                                               "incumbent", "out_reach")} for P_ in bt.problems]
 
 
-def test_cycle_matches_oracle():
+@pytest.mark.parametrize("edge_form", [0, 3])
+def test_cycle_matches_oracle(edge_form):
     """Two anytime iterations of two rounds on three problems: final trees,
-    incumbents and the last Prune's reach times against the oracle's cycle."""
+    incumbents and the last Prune's reach times against the oracle's cycle;
+    with the one-kernel and the ordered two-phase search (its triage bounds
+    the free edges by t_best like the search)."""
     arm = W.make_arm(0)
     probs = cycle_set(arm)
-    ctx, bt = build_cycle(arm, probs)
+    ctx, bt = build_cycle(arm, probs, edge_form=edge_form)
     bt.cycle(2, 2, V_TIP, W.blade_midpoint(arm))
     torch.cuda.synchronize()
     A = O.make_oarm(arm)
@@ -222,12 +226,13 @@ def test_cycle_matches_oracle():
     ctx.close()
 
 
-def test_cycle_graph_replay_equals_eager():
+@pytest.mark.parametrize("edge_form", [0, 3])
+def test_cycle_graph_replay_equals_eager(edge_form):
     """The whole cycle captured as one HIP graph: three replays (trees reset
     by eager copies in between) equal the eager cycle bit for bit."""
     arm = W.make_arm(0)
     probs = cycle_set(arm)[:2]
-    ctx, bt = build_cycle(arm, probs)
+    ctx, bt = build_cycle(arm, probs, edge_form=edge_form)
     blade = W.blade_midpoint(arm)
     bt.cycle(2, 2, V_TIP, blade)
     torch.cuda.synchronize()
