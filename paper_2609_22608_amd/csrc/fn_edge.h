@@ -534,8 +534,11 @@ __device__ __forceinline__ void model_state(const EdgeArgs& a, int64_t st, int r
 // MODE is the search mode (a
 // compile-time constant, so each mode is its own kernel); GOALS: edges of
 // goal candidates (kind 1) are checked at their fixed duration.
+// Inlined into each kernel: a call would spill the live state of the search
+// to a stack frame of ~600 bytes per lane.
 template <int PAT, int MODE, bool GOALS>
-__device__ void search_edge(const EdgeArgs& a, int64_t e, int64_t eq, const ArmConst<float>& A,
+__device__ __forceinline__ void search_edge(const EdgeArgs& a, int64_t e, int64_t eq,
+                                            const ArmConst<float>& A,
                             float* s_end, const float* s_T, float* s_fix, float* s_mod,
                             GeoLDS<float>* geo, float* tab) {
   const int lane = lane_id();
