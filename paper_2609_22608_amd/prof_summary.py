@@ -66,27 +66,31 @@ def durations(args):
 
 def _counter(d, name, grid=None):
     """{kernel: [value per dispatch]} (dispatches of grid size `grid` only,
-    when given) and the copy calibration value."""
+    when given), {(kernel, grid): [value per dispatch]} and the copy
+    calibration value."""
     rows = list(csv.DictReader(open(_one(d, "counter_collection.csv"))))
     per = collections.defaultdict(list)
+    per_grid = collections.defaultdict(list)
     copy = []
     for r in rows:
         if r["Counter_Name"] != name:
             continue
         v = float(r["Counter_Value"])
+        g = int(r["Grid_Size"])
         if r["Kernel_Name"] == COPY_KERNEL:
-            copy.append((int(r["Grid_Size"]), v))
-        if grid is None or int(r["Grid_Size"]) == grid:
+            copy.append((g, v))
+        per_grid[(short(r["Kernel_Name"], 200), g)].append(v)
+        if grid is None or g == grid:
             per[short(r["Kernel_Name"], 200)].append(v)
     if not copy:
         raise SystemExit(f"no {COPY_KERNEL} dispatch in {d}")
     grid, cal = max(copy)  # the large calibration copy
-    return per, cal, grid
+    return per, per_grid, cal, grid
 
 
 def traffic(args):
-    fetch, f_cal, grid = _counter(args.fetch, "FETCH_SIZE", args.grid)
-    write, w_cal, _ = _counter(args.write, "WRITE_SIZE", args.grid)
+    fetch, fetch_g, f_cal, grid = _counter(args.fetch, "FETCH_SIZE", args.grid)
+    write, write_g, w_cal, _ = _counter(args.write, "WRITE_SIZE", args.grid)
     kib = COPY_BYTES / 1024
     f_scale = f_cal / kib  # counter KiB per KiB moved
     w_scale = w_cal / kib
@@ -96,15 +100,22 @@ def traffic(args):
     fk = wk = 0.0
     counts = []
     for kname in args.kernel:
+        # "name@grid": only that kernel's dispatches of that grid size
+        g = None
+        if "@" in kname:
+            kname, g = kname.rsplit("@", 1)
+            g = int(g)
         key = short(kname, 200)
-        if key not in fetch or key not in write:
-            raise SystemExit(f"{key} not found; kernels: {sorted(fetch)}")
-        f1, w1 = statistics.mean(fetch[key]), statistics.mean(write[key])
-        print(f"{key}: FETCH_SIZE {f1:.0f} KiB, WRITE_SIZE {w1:.0f} KiB per dispatch "
-              f"({len(fetch[key])}, {len(write[key])} dispatches)")
+        fl = fetch.get(key) if g is None else fetch_g.get((key, g))
+        wl = write.get(key) if g is None else write_g.get((key, g))
+        if not fl or not wl:
+            raise SystemExit(f"{key} (grid {g}) not found; kernels: {sorted(fetch)}")
+        f1, w1 = statistics.mean(fl), statistics.mean(wl)
+        print(f"{key}{'' if g is None else f' (grid {g})'}: FETCH_SIZE {f1:.0f} KiB, WRITE_SIZE "
+              f"{w1:.0f} KiB per dispatch ({len(fl)}, {len(wl)} dispatches)")
         fk += f1
         wk += w1
-        counts.append([len(fetch[key]), len(write[key])])
+        counts.append([len(fl), len(wl)])
     fb = fk / f_scale * 1024
     wb = wk / w_scale * 1024
     print(f"per launch: {fb / 1e6:.3f} MB read + {wb / 1e6:.3f} MB written = "
@@ -138,7 +149,8 @@ def main():
     t.add_argument("fetch")
     t.add_argument("write")
     t.add_argument("--kernel", required=True, action="append",
-                   help="kernel name; repeated: the kernels of one timed span, summed")
+                   help="kernel name, or name@grid for that grid size's dispatches only; "
+                        "repeated: the kernels of one timed span, summed")
     t.add_argument("--form", required=True)
     t.add_argument("--grid", type=int, default=None,
                    help="only dispatches of this grid size (work-items), e.g. the tuned mapping")
