@@ -135,3 +135,31 @@ def test_tuning_and_problem_set_are_validated(iteration):
     with pytest.raises(fn.FnError, match="problems"):
         bt.prepare()
     c2.close()
+
+
+def test_batch_tuner_times_both_edge_forms_and_caches(tmp_path):
+    """tune_batch times every kNN mapping in each mode with the one-kernel
+    search, then the ordered two-phase search at the screened mode's best
+    mapping; the winner is left prepared and cached, and a cache hit restores
+    it without timing."""
+    arm, probs = W.make_problem_set(3, 5, nodes=(300, 800), batch=(40, 80))
+    sh = probs[0]["shape"]
+    sumB = sum(p["shape"].batch for p in probs)
+    ctx = fn.Context(arm, 4096, sumB, sh.k, max_edges=sumB * sh.k, max_problems=len(probs))
+    bt = fn.Batch(ctx, fn.dev(probs[0]["grid"]), sh.samples, sh.k)
+    for wl in probs:
+        bt.add_problem(wl["tree_x"], wl["tree_t"], wl["cand"], wl["obs"],
+                       capacity=wl["shape"].n_nodes + 256)
+    bt.prepare()
+    cands = ((1024, 256), (2048, 512))
+    cache = autotune.Cache(str(tmp_path / "b.json"))
+    ch, times = autotune.tune_batch(bt, reps=1, cache=cache, candidates=cands)
+    n_grid = len(list(autotune.knn_grid(cands)))
+    assert len(times) == 2 * n_grid + 1  # both modes, then the ordered form once
+    assert sum(k.endswith("/e3") for k in times) == 1
+    assert ch.edge_form in (1, 3) and ch.ms == min(times.values())
+    assert ctx.edge_form == ch.edge_form and bt.mode == ch.mode
+    ch2, times2 = autotune.tune_batch(bt, cache=autotune.Cache(str(tmp_path / "b.json")),
+                                      candidates=cands)
+    assert ch2 == ch and times2 == {}
+    ctx.close()
