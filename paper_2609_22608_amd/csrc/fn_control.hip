@@ -46,16 +46,17 @@ __global__ __launch_bounds__(256) void control_kernel(
     return;
   }
   int st = 0;
-  const float invT = 1.f / T;
-  const float inv_dt = 1.f / dt;
+  // quotients and roots by the hardware reciprocal and square root (1 ulp)
+  const float invT = __builtin_amdgcn_rcpf(T);
+  const float inv_dt = __builtin_amdgcn_rcpf(dt);
   float a[NJ], sn[NJ], cs[NJ], tau[NJ];
 #pragma unroll
   for (int i = 0; i < NJ; ++i) {
     // Eq. (9): initial acceleration of the refitted cubic
     float ai = 6.f * (g[i] - x[i]) * invT * invT - (4.f * v[i] + 2.f * w[i]) * invT;
     // the velocity after one period stays inside the taper of Def. 1
-    const float vp = fminf(A.qdmax[i], sqrtf(A.two_acc[i] * fmaxf(0.f, A.qmax[i] - x[i])));
-    const float vm = fminf(A.qdmax[i], sqrtf(A.two_acc[i] * fmaxf(0.f, x[i] - A.qmin[i])));
+    const float vp = fminf(A.qdmax[i], fsqrt(A.two_acc[i] * fmaxf(0.f, A.qmax[i] - x[i])));
+    const float vm = fminf(A.qdmax[i], fsqrt(A.two_acc[i] * fmaxf(0.f, x[i] - A.qmin[i])));
     const float lo = (-vm - v[i]) * inv_dt, hi = (vp - v[i]) * inv_dt;
     if (ai < lo) {
       ai = lo;
@@ -90,7 +91,7 @@ __global__ __launch_bounds__(256) void control_kernel(
     pw += t * v[i];
   }
   const float apw = fabsf(pw);
-  const float scale = apw > A.wmax ? A.wmax / apw : 1.f;
+  const float scale = apw > A.wmax ? fdiv(A.wmax, apw) : 1.f;
   if (apw > A.wmax) st |= FN_C_POWER;
 #pragma unroll
   for (int i = 0; i < NJ; ++i) {
